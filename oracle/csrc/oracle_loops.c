@@ -1,0 +1,121 @@
+/*
+ * Oracle loops that are inherently sequential, in plain C (test infrastructure
+ * only: the eigensolver library never links or calls this file).
+ *
+ *  rs_first_pass  classical Ruge-Stueben C/F splitting, first pass only
+ *                 (Section 2.1: measure |S_i^T|, greedy choice of C points).
+ *  gs_sweep       one Gauss-Seidel sweep on a block of right-hand sides
+ *                 (the smoother of the paper's default settings, Section 4.1).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+
+/* ---- binary heap of (-measure, index): pops max measure, lowest index ---- */
+typedef struct { int64_t key; int32_t idx; } item;
+
+static int less(item a, item b) { return a.key < b.key || (a.key == b.key && a.idx < b.idx); }
+
+static void push(item *h, int64_t *n, item it) {
+    int64_t i = (*n)++;
+    h[i] = it;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!less(h[i], h[p])) break;
+        item t = h[i]; h[i] = h[p]; h[p] = t; i = p;
+    }
+}
+
+static item pop(item *h, int64_t *n) {
+    item top = h[0];
+    h[0] = h[--(*n)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *n && less(h[l], h[m])) m = l;
+        if (r < *n && less(h[r], h[m])) m = r;
+        if (m == i) break;
+        item t = h[i]; h[i] = h[m]; h[m] = t; i = m;
+    }
+    return top;
+}
+
+/*
+ * S (strong dependencies, row i lists S_i) and ST (row i lists S_i^T), both CSR.
+ * Output cf[i] = 1 for C, 0 for F.  Returns the number of C points, or -1 on
+ * allocation failure.
+ *
+ * Rule: points with S_i and S_i^T both empty are F.  Repeatedly take the
+ * undecided point with the largest measure (ties: lowest index) as C; its
+ * undecided strong influencees (S_i^T) become F, and each undecided point that
+ * such a new F point strongly depends on gains one unit of measure; undecided
+ * points that the new C point strongly depends on lose one unit.
+ */
+int64_t rs_first_pass(int64_t n, const int64_t *s_ptr, const int32_t *s_col,
+                      const int64_t *st_ptr, const int32_t *st_col, int32_t *cf) {
+    enum { UND = -1, F = 0, C = 1 };
+    int64_t *lam = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t cap = n + 8;
+    for (int64_t i = 0; i < n; ++i) cap += st_ptr[i + 1] - st_ptr[i] + s_ptr[i + 1] - s_ptr[i];
+    item *heap = (item *)malloc(sizeof(item) * (size_t)cap);
+    if (!lam || !heap) { free(lam); free(heap); return -1; }
+    int64_t hn = 0, nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        lam[i] = st_ptr[i + 1] - st_ptr[i];
+        if (lam[i] == 0 && s_ptr[i + 1] == s_ptr[i]) { cf[i] = F; continue; }
+        cf[i] = UND;
+        push(heap, &hn, (item){-lam[i], (int32_t)i});
+    }
+    while (hn > 0) {
+        item it = pop(heap, &hn);
+        int64_t i = it.idx;
+        if (cf[i] != UND || -it.key != lam[i]) continue; /* stale entry */
+        cf[i] = C; ++nc;
+        for (int64_t a = st_ptr[i]; a < st_ptr[i + 1]; ++a) {
+            int64_t j = st_col[a];
+            if (cf[j] != UND) continue;
+            cf[j] = F;
+            for (int64_t b = s_ptr[j]; b < s_ptr[j + 1]; ++b) {
+                int64_t l = s_col[b];
+                if (cf[l] != UND) continue;
+                lam[l] += 1;
+                push(heap, &hn, (item){-lam[l], (int32_t)l});
+            }
+        }
+        for (int64_t a = s_ptr[i]; a < s_ptr[i + 1]; ++a) {
+            int64_t j = s_col[a];
+            if (cf[j] != UND) continue;
+            lam[j] -= 1;
+            push(heap, &hn, (item){-lam[j], (int32_t)j});
+        }
+        if (hn + n + 8 > cap) { /* grow: bounded by total pushes, never expected */
+            cap *= 2;
+            item *nh = (item *)realloc(heap, sizeof(item) * (size_t)cap);
+            if (!nh) { free(lam); free(heap); return -1; }
+            heap = nh;
+        }
+    }
+    free(lam);
+    free(heap);
+    return nc;
+}
+
+/*
+ * One Gauss-Seidel sweep for A x = b, q right-hand sides stored row-major
+ * (x[i*q + c]).  backward != 0 runs the rows in decreasing order.
+ */
+void gs_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              int q, const double *b, double *x, int backward) {
+    double *acc = (double *)malloc(sizeof(double) * (size_t)q);
+    for (int64_t t = 0; t < n; ++t) {
+        int64_t i = backward ? n - 1 - t : t;
+        double diag = 0.0;
+        for (int c = 0; c < q; ++c) acc[c] = b[i * q + c];
+        for (int64_t a = rowptr[i]; a < rowptr[i + 1]; ++a) {
+            int64_t j = col[a];
+            if (j == i) { diag += val[a]; continue; }
+            for (int c = 0; c < q; ++c) acc[c] -= val[a] * x[j * q + c];
+        }
+        for (int c = 0; c < q; ++c) x[i * q + c] = acc[c] / diag;
+    }
+    free(acc);
+}

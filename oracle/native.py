@@ -1,0 +1,63 @@
+"""Build and load the oracle's plain-C loops (gcc, ctypes)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "csrc", "oracle_loops.c")
+LIB = os.path.join(_HERE, "csrc", "liboracle_loops.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle's C file with gcc (no GPU code involved)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(LIB)
+        p = ctypes.c_void_p
+        L.rs_first_pass.restype = ctypes.c_int64
+        L.rs_first_pass.argtypes = [ctypes.c_int64, p, p, p, p, p]
+        L.gs_sweep.restype = None
+        L.gs_sweep.argtypes = [ctypes.c_int64, p, p, p, ctypes.c_int, p, p, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def rs_first_pass(S, ST):
+    """S, ST: scipy CSR strength matrices (row i = S_i, resp. S_i^T)."""
+    n = S.shape[0]
+    sp_, sc = np.ascontiguousarray(S.indptr, np.int64), np.ascontiguousarray(S.indices, np.int32)
+    tp, tc = np.ascontiguousarray(ST.indptr, np.int64), np.ascontiguousarray(ST.indices, np.int32)
+    cf = np.empty(n, dtype=np.int32)
+    nc = lib().rs_first_pass(n, _ptr(sp_), _ptr(sc), _ptr(tp), _ptr(tc), _ptr(cf))
+    if nc < 0:
+        raise MemoryError("rs_first_pass")
+    return cf
+
+
+def gs_sweep(A, b, x, backward=False):
+    """In-place Gauss-Seidel sweep on x (n x q, C-contiguous float64)."""
+    n = A.shape[0]
+    q = x.shape[1]
+    assert x.flags.c_contiguous and x.dtype == np.float64
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    rp = np.ascontiguousarray(A.indptr, np.int64)
+    ci = np.ascontiguousarray(A.indices, np.int32)
+    va = np.ascontiguousarray(A.data, np.float64)
+    lib().gs_sweep(n, _ptr(rp), _ptr(ci), _ptr(va), q, _ptr(bb), _ptr(x), 1 if backward else 0)
+    return x

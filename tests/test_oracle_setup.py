@@ -1,0 +1,100 @@
+"""Pins of the oracle's AMG setup (Section 2) against hand derivations and
+structural facts that the paper's level sizes fix."""
+import numpy as np
+import scipy.sparse as sp
+
+from oracle import amg
+from workloads import configs
+from tests.helpers import mats
+
+
+def _lap1d(n):
+    return sp.csr_matrix(2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1))
+
+
+def test_1d_laplacian_hand_derived_hierarchy():
+    """RS first pass on tridiag(-1,2,-1), N = 7, picks every other point; direct
+    interpolation gives weights 1/2 and the Galerkin operator is tridiag(-1/2,1,-1/2)."""
+    A = _lap1d(7)
+    cf, S = amg.rs_splitting(A, 0.25)
+    assert cf.tolist() == [0, 1, 0, 1, 0, 1, 0]
+    P = amg.direct_interpolation(A, S, cf).toarray()
+    want = np.array([[.5, 0, 0], [1, 0, 0], [.5, .5, 0], [0, 1, 0], [0, .5, .5], [0, 0, 1], [0, 0, .5]])
+    assert np.array_equal(P, want)
+    A2 = amg.galerkin(sp.csr_matrix(P), A).toarray()
+    assert np.allclose(A2, np.array([[1, -.5, 0], [-.5, 1, -.5], [0, -.5, 1]]), atol=0, rtol=0)
+    M2 = amg.galerkin(sp.csr_matrix(P), sp.identity(7, format="csr")).toarray()
+    assert np.allclose(M2, np.array([[1.5, .25, 0], [.25, 1.5, .25], [0, .25, 1.5]]), atol=0, rtol=0)
+
+
+def test_strength_threshold_eq_2_1():
+    # row 0: couplings -4 (strong), -1 (= 0.25 * 4, strong by >=), -0.5 (weak), +3 (never)
+    A = sp.csr_matrix(np.array([[10., -4, -1, -.5, 3], [-4, 10, 0, 0, 0], [-1, 0, 10, 0, 0],
+                                [-.5, 0, 0, 10, 0], [3, 0, 0, 0, 10]]))
+    S = amg.strength(A, 0.25).toarray()
+    assert S[0].tolist() == [0, 1, 1, 0, 0]
+    assert S[4].tolist() == [0, 0, 0, 0, 0]  # only a positive coupling: S_i empty
+
+
+def test_level2_is_half_of_five_point_grids():
+    """The paper's level-2 sizes are (N+1)/2 (red-black split) on its 5-point grids."""
+    for p in (configs.square(64), configs.lshape(16), configs.quadrants(16)):
+        A, _ = mats(p)
+        cf, _ = amg.rs_splitting(A, 0.25)
+        assert cf.sum() == (p["n"] + 1) // 2, p["meta"]
+
+
+def test_f_points_have_strong_c_neighbour_and_constants_interpolate():
+    for p in (configs.lshape(12, jitter_seed=4), configs.cube(8), configs.oscillator(20)):
+        A, M = mats(p)
+        cf, S = amg.rs_splitting(A, 0.25)
+        P = amg.direct_interpolation(A, S, cf)
+        Sd = S.tolil().rows
+        for i in np.flatnonzero(cf == 0):
+            if Sd[i]:
+                assert cf[Sd[i]].max() == 1, i
+        # rows with zero row sum (away from the Dirichlet boundary) interpolate 1 exactly
+        rowsum = np.asarray(A.sum(axis=1)).ravel()
+        scale = np.abs(A).sum(axis=1).A.ravel()
+        zero = np.abs(rowsum) < 1e-12 * scale
+        p1 = P @ np.ones(P.shape[1])
+        if p["meta"]["family"] != "oscillator":
+            assert zero.sum() > 0
+        assert np.abs(p1[zero] - 1).max(initial=0) < 1e-13
+        # Galerkin operators stay symmetric
+        A2 = amg.galerkin(P, A)
+        M2 = amg.galerkin(P, M)
+        assert abs(A2 - A2.T).max() < 1e-12 * abs(A2).max()
+        assert abs(M2 - M2.T).max() < 1e-12 * abs(M2).max()
+
+
+def test_hierarchy_galerkin_chain_identity():
+    from oracle import Oracle
+    p = configs.lshape(10, jitter_seed=1)
+    A, M = mats(p)
+    o = Oracle(A, M, q=4, coarse_max=30)
+    assert len(o.levels) >= 3
+    dn = o.levels[-1].n
+    Q = o.prolong_from_coarsest(0, np.eye(dn))
+    assert np.abs(Q.T @ (M @ Q) - o.levels[-1].M.toarray()).max() < 1e-14
+    assert np.abs(Q.T @ (A @ Q) - o.levels[-1].A.toarray()).max() < 1e-12
+    R = o.restrict_to_coarsest(0, M @ Q)
+    assert np.abs(R - Q.T @ (M @ Q)).max() < 1e-14
+
+
+def test_rs_first_pass_measure_updates_on_asymmetric_strength():
+    """Hand-traced first pass where the decrement of the measure matters.
+
+    Strong dependencies (i -> j means j in S_i): 1,2,3 -> 0; 0 -> 4; 5 -> 4;
+    4 -> 5; 9 -> 5; 7,8 -> 6.  Measures |S^T|: 0:3, 4:2, 5:2, 6:2.
+    0 becomes C, 1,2,3 F; 0 depends on the undecided 4, whose measure drops to 1.
+    Then 5 (measure 2, lowest index) becomes C and 4, 9 become F; finally 6 is C.
+    Without the decrement 4 would win the tie and the result would be C = {0,4,6,9}.
+    """
+    edges = {1: [0], 2: [0], 3: [0], 0: [4], 5: [4], 4: [5], 9: [5], 7: [6], 8: [6]}
+    A = 10 * np.eye(10)
+    for i, js in edges.items():
+        for j in js:
+            A[i, j] = -1.0
+    cf, _ = amg.rs_splitting(sp.csr_matrix(A), 0.25)
+    assert np.flatnonzero(cf).tolist() == [0, 5, 6]

@@ -1,0 +1,145 @@
+"""Pins of the oracle's eigensolver (Algorithms 3.1 / 3.2) against results the
+mathematics fixes independently: dense brute force, a closed-form spectrum,
+fixed points, Ritz bounds and multigrid contraction."""
+import numpy as np
+import pytest
+
+from oracle import Oracle, guard_count
+from workloads import configs
+from tests.helpers import brute_force, compare_subspaces, mats
+
+SMALL = [
+    ("square16", lambda: configs.square(16, q=6)),
+    ("lshape8j", lambda: configs.lshape(8, q=6, jitter_seed=5)),
+    ("cube8", lambda: configs.cube(8, q=32)),  # the whole 32-member low cluster
+    ("osc24", lambda: configs.oscillator(24, q=6)),  # closed shells 1+2+3
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL)
+@pytest.mark.parametrize("smoother", ["gs", "l1jacobi", "chebyshev"])
+def test_converges_to_dense_brute_force(name, make, smoother):
+    p = make()
+    A, M = mats(p)
+    q = p["q"]
+    full, _ = brute_force(p, min(p["n"], 3 * q + 10))
+    qe = guard_count(full, q)
+    o = Oracle(A, M, q=q, qe=qe, coarse_max=max(40, 3 * qe), smoother=smoother)
+    lam, U, info = o.solve(tol=1e-11, max_steps=200)
+    assert info["rho"][:q].max() <= 1e-11
+    ref, Uref = brute_force(p, o.qe + 1)
+    assert np.abs(lam[:q] / ref[:q] - 1).max() < 1e-10
+    assert compare_subspaces(ref, Uref, U, M, q) < 1e-6
+    assert np.abs(U.T @ (M @ U) - np.eye(o.qe)).max() < 1e-12
+
+
+def test_lumped_mass_closed_form():
+    """M = h^2 I on the Courant mesh: lambda_kl = 4/h^2 (sin^2(k pi h/2) + sin^2(l pi h/2))."""
+    m = 32
+    p = configs.square_lumped(m, q=8)
+    A, M = mats(p)
+    h = 1.0 / m
+    k = np.arange(1, m)
+    s = np.sin(k * np.pi * h / 2) ** 2
+    exact = np.sort((4 / h ** 2) * (s[:, None] + s[None, :]).ravel())
+    o = Oracle(A, M, q=8, coarse_max=100)
+    lam, U, info = o.solve(tol=1e-11)
+    assert np.abs(lam[:8] / exact[:8] - 1).max() < 1e-11
+
+
+def test_random_start_matches_nested_start():
+    p = configs.config(0)
+    A, M = mats(p)
+    o = Oracle(A, M, q=4, coarse_max=130, smoother="l1jacobi")
+    U0 = configs.initial_block(p, o.qe)
+    l1, U1, _ = o.solve(tol=1e-11, start="random", U0=U0)
+    l2, U2, _ = o.solve(tol=1e-11, start="nested")
+    assert np.abs(l1[:4] / l2[:4] - 1).max() < 1e-12
+    ref = np.array([19.78679229, 49.55252612, 49.66736125, 79.71606372])
+    assert np.abs(l1[:4] - ref).max() < 1e-7
+
+
+def test_each_step_keeps_m_orthonormality_and_ritz_bounds():
+    p = configs.lshape(8, q=5, jitter_seed=7)
+    A, M = mats(p)
+    o = Oracle(A, M, q=5, qe=6, coarse_max=30, smoother="l1jacobi")
+    ref, _ = brute_force(p, 6)
+    lam, U = o.random_start(configs.initial_block(p, 6, seed=11))
+    prev = lam.copy()
+    for _ in range(8):
+        assert np.abs(U.T @ (M @ U) - np.eye(6)).max() < 1e-12
+        assert np.all(lam >= ref * (1 - 1e-12))  # Poincare: Ritz values bound from above
+        lam, U = o.correction(0, lam, U)
+        assert np.all(lam <= prev * (1 + 1e-12))  # non-increasing
+        prev = lam.copy()
+
+
+def test_exact_eigenpairs_are_a_fixed_point():
+    p = configs.square(12, q=4)
+    A, M = mats(p)
+    o = Oracle(A, M, q=4, qe=4, coarse_max=40)
+    ref, Uref = brute_force(p, 5)
+    lam, U = o.correction(0, ref[:4].copy(), Uref[:, :4].copy())
+    assert np.abs(lam / ref[:4] - 1).max() < 1e-13
+    assert compare_subspaces(ref, Uref, U, M, 4) < 1e-10
+
+
+@pytest.mark.parametrize("smoother,bound", [("gs", 0.25), ("l1jacobi", 0.45), ("chebyshev", 0.15)])
+def test_vcycle_is_symmetric_a_norm_contraction(smoother, bound):
+    """The V-cycle as an affine iteration x -> x + B (b - A x): B symmetric and
+    ||I - B A||_A < 1 (with textbook-sized factors for the 5-point Laplacian)."""
+    p = configs.square(32)
+    A, M = mats(p)
+    o = Oracle(A, M, q=1, coarse_max=40, smoother=smoother)
+    n = p["n"]
+    rng = np.random.default_rng(0)
+
+    def B(r):
+        return o.vcycle(0, r, np.zeros_like(r))
+
+    x = rng.standard_normal((n, 1))
+    y = rng.standard_normal((n, 1))
+    assert abs((x.T @ B(y)) - (y.T @ B(x))).max() < 1e-10 * abs(x.T @ B(x)).max()
+    e = rng.standard_normal((n, 1))
+    rate = 1.0
+    for _ in range(25):
+        e_new = e - B(A @ e)
+        rate = np.sqrt((e_new.T @ (A @ e_new)) / (e.T @ (A @ e))).item()
+        e = e_new / np.sqrt((e_new.T @ (A @ e_new)).item())
+    assert rate < bound, rate
+
+
+def test_gauss_seidel_rate_close_to_paper_example_1():
+    """Example 1 with Gauss-Seidel V(1,1): the paper reports an average
+    reduction of about 0.11 per correction (Table 1).  On a 127^2 grid with a
+    ~500-point coarse space the oracle's rate is of that order."""
+    p = configs.square(128, q=4)
+    A, M = mats(p)
+    o = Oracle(A, M, q=4, coarse_max=600, smoother="gs")
+    lam, U, info = o.solve(tol=1e-11, record=True)
+    r = [h[1][:4].max() for h in info["history"]]
+    rate = (r[-1] / r[1]) ** (1.0 / (len(r) - 2))
+    assert rate < 0.25, rate
+
+
+def test_guard_rule():
+    assert guard_count([1, 2, 3, 4, 5, 6], 3) == 3
+    assert guard_count([1, 2, 3, 3.001, 3.002, 6, 7, 8], 3) == 5
+    assert guard_count([1, 1, 1, 1, 1, 1, 1, 1, 1, 1], 2, cap=5) == 5
+
+
+def test_relative_residual_closed_form():
+    """u = e1 + eps e2 for M-orthonormal eigenvectors (lumped mass M = h^2 I):
+    theta = (l1 + eps^2 l2)/(1 + eps^2) and
+    rho = sqrt((l1 - theta)^2 + eps^2 (l2 - theta)^2) / (theta sqrt(1 + eps^2))."""
+    m = 16
+    p = configs.square_lumped(m, q=2)
+    A, M = mats(p)
+    l, E = brute_force(p, 2)
+    o = Oracle(A, M, q=2, qe=2, coarse_max=40)
+    for eps in (1e-3, 0.3):
+        u = (E[:, 0] + eps * E[:, 1])[:, None]
+        th = (l[0] + eps ** 2 * l[1]) / (1 + eps ** 2)
+        want = np.sqrt((l[0] - th) ** 2 + eps ** 2 * (l[1] - th) ** 2) / (th * np.sqrt(1 + eps ** 2))
+        got = o.residuals(0, np.array([th]), u)[0]
+        assert abs(got / want - 1) < 1e-9
