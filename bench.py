@@ -1,0 +1,181 @@
+"""Benchmark: eigenpairs/s of full solves (Algorithm 3.2 + corrections to a
+1e-8 relative residual) on one MI355X, with the dominant kernel's HBM roofline
+and the CPU oracle timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1] [--precision mixed|fp64]
+
+A step is one whole solve of the workload: nested start from the coarsest
+level, then finest-level corrections until max_{j<=q} rho_j <= 1e-8.  Inputs
+(the hierarchy) are resident in HBM before the timed region starts.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# Per-workload solver options (coarse size and block width: the paper's two
+# improvement strategies, Section 4.5)
+WORKLOADS = {
+    0: dict(name="unit square P1, 31x31 interior (N=961), q=4", coarse_max=130, qe=4),
+    1: dict(name="jittered L-shape P1, h=1/256 (N=195585), q=10", coarse_max=512, qe=12),
+    2: dict(name="3D checkerboard cube P1, 100^3 cells (N=970299), q=20", coarse_max=512, qe=32),
+    3: dict(name="oscillator -Lap+r^2 on (-6,6)^2, 2047^2 interior (N=4190209), q=64", coarse_max=700, qe=68),
+}
+
+
+def cpu_baseline(idx, qe, coarse_max, tol):
+    """The oracle (plain FP64 CPU, its own setup and Gauss-Seidel V-cycle) timed
+    on one full solve of the same workload, setup excluded, one thread."""
+    code = r"""
+import json, sys, time
+sys.path.insert(0, %r)
+from workloads import configs
+from oracle import Oracle, amg
+p = configs.config(%d)
+A = amg.csr(p["rowptr"], p["col"], p["A"], p["n"])
+M = amg.csr(p["rowptr"], p["col"], p["M"], p["n"])
+o = Oracle(A, M, q=p["q"], qe=%d, coarse_max=%d, coarse_min=2 * %d + 2, smoother="gs")
+t = time.perf_counter()
+lam, U, info = o.solve(tol=%r, max_steps=400)
+dt = time.perf_counter() - t
+print(json.dumps({"seconds": dt, "steps": info["steps"], "q": p["q"], "conv": bool(info["rho"][:p["q"]].max() <= %r)}))
+""" % (ROOT, idx, qe, coarse_max, qe, tol, tol)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["q"] / d["seconds"], "unit": "eigenpairs/s", "cores": 1, "kind": "oracle",
+            "sample": "one full oracle solve of the same workload (nested start, Gauss-Seidel V(1,1), "
+                      "%d corrections to rho<=%g, %.1f s), setup excluded, 1 thread" % (d["steps"], tol, d["seconds"])}
+
+
+def load_traffic(kernel, workload_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if any."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload_tag))
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":", 1)[1])
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus)
+        sys.exit(2)
+
+    import torch
+    import paper_1503_08462_amd as ae
+    from workloads import configs
+
+    wl = WORKLOADS[args.config]
+    p = configs.config(args.config)
+    prec = ae.PREC_MIXED if args.precision == "mixed" else ae.PREC_FP64
+    t0 = time.perf_counter()
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
+                     ae.defaults(coarse_max=wl["coarse_max"], qe=wl["qe"], precision=prec, use_graph=args.graph))
+    setup_s = time.perf_counter() - t0
+    stream = torch.cuda.Stream()
+    ctx.bind(stream=stream)
+    info = ctx.info()
+    for _ in range(args.warmup):
+        ctx.init(ae.INIT_NESTED)
+        ctx.solve(args.tol, 400)
+    ctx.timing(True)
+    lat, steps = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        ctx.init(ae.INIT_NESTED)
+        lam, ok = ctx.solve(args.tol, 400)
+        lat.append(time.perf_counter() - t)
+        pr = ctx.progress()
+        if not ok:
+            raise SystemExit("solve did not converge: %s" % pr)
+        steps.append(pr["steps"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    stats = ctx.site_stats()
+    ctx.timing(False)
+
+    q = p["q"]
+    sites = {}
+    for name, (amount, ms, n) in stats.items():
+        if n == 0:
+            continue
+        avg = ms / n * 1e-3
+        if name == "gram":
+            sites[name] = {"avg_us": avg * 1e6, "launches": n, "tflops": amount / avg / 1e12}
+        elif name == "small":
+            sites[name] = {"avg_us": avg * 1e6, "launches": n}
+        else:
+            sites[name] = {"avg_us": avg * 1e6, "launches": n, "gbs": amount / avg / 1e9}
+    hbm_sites = [s for s in sites if s not in ("gram", "small")]
+    dom = max(hbm_sites, key=lambda s: stats[s][1]) if hbm_sites else None
+    roofline = None
+    if dom:
+        amount, ms, n = stats[dom]
+        achieved = amount / (ms / n * 1e-3) / 1e9
+        kernel_name = {"residual": "k_residual", "presmooth": "k_smooth_pre", "postsmooth": "k_smooth_post",
+                       "dualspmm": "k_dual_spmm", "restrict": "k_spmm", "final": "k_final"}[dom]
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(kernel_name, "config%d_%s" % (args.config, args.precision)),
+                    "kernel": kernel_name, "site": dom, "alg_bytes_per_launch": amount,
+                    "avg_launch_us": round(ms / n * 1e3, 2)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.config, wl["qe"], wl["coarse_max"], args.tol)
+    out = {
+        "metric": "eigenpairs/sec to 1e-8 rel. residual",
+        "value": q * args.steps / elapsed,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == ae.PREC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "N": int(p["n"]), "q": q, "qe": info["qe"],
+                   "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
+                   "smoother": "l1-jacobi V(1,1)", "start": "nested (Algorithm 3.2)"},
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "corrections_per_solve": float(np.mean(steps)),
+        "setup_s": setup_s,
+        "roofline": roofline,
+        "sites": sites,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

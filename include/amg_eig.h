@@ -1,0 +1,205 @@
+/*
+ * amg_eig: AMG multilevel-correction eigensolver for A u = lambda M u on one
+ * MI355X (gfx950) GPU.
+ *
+ * Method: Zhang, Han, He, Xie, You, "An Algebraic Multigrid Method for
+ * Eigenvalue Problems in Some Different Cases" (arXiv 1503.08462).
+ *   - problem (1.1): the q smallest eigenpairs of the symmetric pencil (A, M),
+ *     A symmetric positive definite, M symmetric positive (semi)definite,
+ *     with U^T M U = I;
+ *   - hierarchy (Section 2): strength (2.1), Ruge-Stueben first-pass C/F
+ *     splitting, direct interpolation (2.2)-(2.4), Galerkin operators (2.5);
+ *   - correction step (Algorithm 3.1): one block V-cycle on A_k u = lambda M_k u
+ *     from the current iterate (3.1)-(3.2), then Rayleigh-Ritz on the coarsest
+ *     space augmented with the new block, eigenproblem (3.3);
+ *   - driver (Algorithm 3.2): coarsest eigen-solve, prolongation and one
+ *     correction per level, then corrections on the finest level.
+ *
+ * Conventions for every entry point:
+ *   - return 0 on success, > 0 for a warning, < 0 for an error (codes below);
+ *     amg_eig_strerror() names a code, amg_eig_last_error() gives the message
+ *     of the last failure on a context;
+ *   - no C++ exception crosses this interface;
+ *   - host arrays passed in are borrowed for the duration of the call only;
+ *   - device memory is owned by the caller: the library never allocates or
+ *     frees device memory; it carves everything from the workspace given to
+ *     amg_eig_bind();
+ *   - all device work of a context is enqueued on the stream given to
+ *     amg_eig_bind(); only amg_eig_progress() and amg_eig_solve() wait on it;
+ *   - one host thread at a time per context; contexts are independent.
+ * Vector blocks on the device are row-major N x ld double arrays (the values of
+ * one unknown are contiguous), ld >= the number of columns.
+ */
+#ifndef AMG_EIG_H
+#define AMG_EIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- codes */
+#define AMG_EIG_OK 0
+#define AMG_EIG_NOT_CONVERGED 1   /* warning: best-so-far results returned */
+#define AMG_EIG_EINVAL (-1)       /* malformed input or option */
+#define AMG_EIG_ENOTSPD (-2)      /* a_ii <= 0 or m_ii < 0 */
+#define AMG_EIG_EBREAKDOWN (-3)   /* projected problem lost definiteness */
+#define AMG_EIG_ENOMEM (-4)       /* host allocation failed */
+#define AMG_EIG_EWORKSPACE (-5)   /* device workspace missing or too small */
+#define AMG_EIG_EHIP (-6)         /* a HIP runtime call failed */
+#define AMG_EIG_ECANCELLED (-7)   /* cancelled by the caller */
+#define AMG_EIG_ESTATE (-8)       /* call out of order (e.g. correct before init) */
+
+/* --------------------------------------------------------------- options */
+#define AMG_EIG_SMOOTH_L1JACOBI 0  /* x += D^-1 (b - A x), d_i = sum_j |a_ij| */
+#define AMG_EIG_SMOOTH_CHEBYSHEV 1 /* Chebyshev polynomial in D^-1 A on [cheb_lo, 1] */
+
+#define AMG_EIG_PREC_FP64 0  /* everything in FP64 */
+#define AMG_EIG_PREC_MIXED 1 /* V-cycle (smoothing, transfers) in FP32 with FP32
+                                accumulation; residual, Rayleigh-Ritz and the
+                                eigenvector block in FP64 */
+
+#define AMG_EIG_INIT_NESTED 0 /* Algorithm 3.2 start from the coarsest level */
+#define AMG_EIG_INIT_RANDOM 1 /* seeded U(-1,1) block, then Rayleigh-Ritz */
+#define AMG_EIG_INIT_USER 2   /* caller's device block, then Rayleigh-Ritz */
+
+typedef struct {
+    double theta;       /* strength threshold of (2.1); paper default 0.25 */
+    int coarse_max;     /* stop coarsening once d_k <= coarse_max */
+    int coarse_min;     /* never create a level smaller than this (0: auto) */
+    int max_levels;     /* hierarchy depth limit */
+    int qe;             /* block width (wanted + extra pairs); 0: guard rule */
+    double guard_gap;   /* guard rule: block may not end inside a cluster of
+                           relative width < guard_gap */
+    int smoother;       /* AMG_EIG_SMOOTH_* */
+    int cheb_degree;    /* Chebyshev degree per smoothing step */
+    double cheb_lo;     /* lower end of the Chebyshev interval in D^-1 A */
+    int nu_pre, nu_post;/* smoothing steps before / after coarse correction */
+    int precision;      /* AMG_EIG_PREC_* */
+    double tol;         /* convergence: max_{j<=q} rho_j <= tol */
+    int max_steps;      /* finest-level corrections in amg_eig_solve */
+    int use_graph;      /* capture one correction step as a hipGraph */
+} amg_eig_opts;
+
+/* Paper defaults (Section 4.1: theta = 0.25, one V-cycle with one pre- and
+ * one post-smoothing step, n_1 = n, p_k = 1 on coarse levels) plus the GPU
+ * options: l1-Jacobi smoothing, FP64, coarse_max 512, tol 1e-8. */
+void amg_eig_opts_default(amg_eig_opts *o);
+
+/* Host CSR, borrowed for the call: rowptr[n+1] (int64, rowptr[0] = 0,
+ * non-decreasing), col[rowptr[n]] (int32, sorted, unique per row, in [0,n)),
+ * val[rowptr[n]]. */
+typedef struct {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} amg_eig_csr;
+
+typedef struct amg_eig_ctx amg_eig_ctx;
+
+/* Build the AMG hierarchy on the host (Section 2) for the q smallest
+ * eigenpairs of (A, M), plus the coarsest eigen-decomposition Z, Lambda_n with
+ * Z^T M_n Z = I, Z^T A_n Z = Lambda_n.  No device call is made.
+ * Errors: EINVAL (shapes, unsorted/duplicate/out-of-range columns, q < 1,
+ * qe + d_n > n, nnz >= 2^31), ENOTSPD (a_ii <= 0, m_ii < 0, coarsest M_n or
+ * A_n not positive definite), ENOMEM.  *out is NULL on error. */
+int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o,
+                  amg_eig_ctx **out);
+
+/* Device bytes needed by amg_eig_bind(). */
+int amg_eig_footprint(const amg_eig_ctx *c, size_t *device_bytes);
+
+/* Hand the context a caller-owned device workspace (>= footprint bytes,
+ * 256-byte aligned) and a HIP stream (hipStream_t, may be NULL for the null
+ * stream), then upload the hierarchy with asynchronous copies on that stream.
+ * The workspace must stay valid until amg_eig_destroy() or the next bind.
+ * Errors: EWORKSPACE, EHIP. */
+int amg_eig_bind(amg_eig_ctx *c, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Start the iteration on the finest level (asynchronous).
+ * NESTED: Algorithm 3.2 (coarsest eigenvectors, prolongation, one correction
+ *         per intermediate level).
+ * RANDOM: U = seeded U(-1,1) block (SplitMix64: element (i, j) is output
+ *         j*N + i of the stream seeded with `seed`), then Rayleigh-Ritz on the
+ *         coarsest space augmented with span U.
+ * USER:   U_dev (device, N x ldu row-major doubles, first qe columns used),
+ *         then Rayleigh-Ritz as for RANDOM.
+ * Errors: ESTATE (not bound), EINVAL. */
+int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, int64_t ldu);
+
+/* Enqueue `steps` correction steps (Algorithm 3.1 on the finest level).
+ * Each step first evaluates the residuals of the current iterate; once the
+ * convergence test holds, later steps do no work (device-side flag).
+ * Asynchronous. Errors: ESTATE. */
+int amg_eig_correct(amg_eig_ctx *c, int steps);
+
+/* Wait for the bound stream and report the current Ritz values theta[qe],
+ * relative residuals rho[qe] (of the iterate before the last step's update),
+ * the number of corrections done and whether the test holds.  Any output
+ * pointer may be NULL.  rho_j = ||A u_j - theta_j M u_j||_2 / (theta_j ||M u_j||_2). */
+int amg_eig_progress(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged);
+
+/* init(NESTED) unless already initialised, then correct until
+ * max_{j<=q} rho_j <= tol or max_steps corrections; copies the q wanted
+ * eigenvalues to lambda_host[q] and eigenvectors to U_dev (device, N x ldu
+ * row-major, ldu >= q) when non-NULL.  Returns NOT_CONVERGED (with the
+ * best-so-far pairs) if the step limit is reached. */
+int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host, double *U_dev,
+                  int64_t ldu);
+
+/* Enqueue `steps` correction steps for each of n bound contexts on one stream
+ * (requests of uneven N batched on the device; each context keeps its own
+ * hierarchy and block).  Errors: ESTATE, EHIP. */
+int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_stream);
+
+/* Sizes: block width qe, number of levels, and the dimension of each level
+ * (dims[nlev], may be NULL). */
+int amg_eig_info(const amg_eig_ctx *c, int *qe, int *nlevels, int64_t *dims);
+
+/* Host copies of the hierarchy, for inspection and tests: the C/F splitting
+ * of level k (cf[d_k], 1 = C), the level's A and M on the shared pattern
+ * (rowptr[d_k+1], col[nnz], a[nnz], m[nnz]; pass NULL to query nnz), the
+ * prolongation P_k (d_k x d_{k+1}), and the coarsest eigenvalues lam[d_n]. */
+int amg_eig_level_matrix(const amg_eig_ctx *c, int level, int64_t *nnz, int64_t *rowptr, int32_t *col,
+                         double *a, double *m);
+int amg_eig_level_prolongation(const amg_eig_ctx *c, int level, int64_t *nnz, int64_t *rowptr,
+                               int32_t *col, double *p);
+int amg_eig_level_splitting(const amg_eig_ctx *c, int level, int32_t *cf);
+int amg_eig_coarse_eigenvalues(const amg_eig_ctx *c, double *lam);
+
+/* Device pointer to the current FP64 iterate (N x ld row-major) and its ld. */
+int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld);
+
+/* Kernel sites on the finest level, for per-kernel timing. */
+#define AMG_EIG_SITE_RESIDUAL 0   /* outer residual + norms (FP64 dual SpMM) */
+#define AMG_EIG_SITE_PRESMOOTH 1  /* fused zero-guess smoothing + residual */
+#define AMG_EIG_SITE_POSTSMOOTH 2 /* post-smoothing fused with V = U + delta */
+#define AMG_EIG_SITE_DUALSPMM 3   /* W = [A V | M V] */
+#define AMG_EIG_SITE_GRAM 4       /* V^T [A V | M V] (counted in flops) */
+#define AMG_EIG_SITE_RESTRICT 5   /* FP64 restriction of W, level 1 -> 2 */
+#define AMG_EIG_SITE_FINAL 6      /* U = P Y + V X_v */
+#define AMG_EIG_SITE_SMALL 7      /* coarse-space Rayleigh-Ritz kernels (all) */
+#define AMG_EIG_SITE_COUNT 8
+
+/* Enable (1) or stop (0) HIP-event timing of the finest-level kernel sites
+ * for eagerly launched steps (steps replayed from a captured graph are not
+ * timed).  Enabling resets the counters. */
+int amg_eig_timing(amg_eig_ctx *c, int enable);
+
+/* Waits for the bound stream, then reports for one site: the algorithmic
+ * bytes of one launch (each operand read once, each result written once;
+ * flops for the Gram site), the summed event time in ms and the number of
+ * timed launches. */
+int amg_eig_site_stats(amg_eig_ctx *c, int site, double *alg_bytes, double *ms_total, int64_t *launches);
+
+void amg_eig_destroy(amg_eig_ctx *c);
+const char *amg_eig_strerror(int code);
+const char *amg_eig_last_error(const amg_eig_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -3,7 +3,9 @@
 Test infrastructure only: the eigensolver library never imports this.
 
   strength            eq. (2.1): S_i = {j != i : -a_ij >= theta * max_{l != i, a_il < 0} |a_il|}
-  rs_splitting        Section 2.1: classical Ruge-Stueben first pass on |S_i^T|
+  rs_splitting        Section 2.1: classical Ruge-Stueben coarsening (first pass
+                      on |S_i^T|, then the second pass giving strongly
+                      coupled F points a common strong C point)
   direct_interpolation eq. (2.2)-(2.4) with P_i = S_i intersect C
   galerkin            eq. (2.5): A_{k+1} = P^T A_k P, M_{k+1} = P^T M_k P
   build_hierarchy     the level loop of Section 2.3
@@ -45,12 +47,15 @@ def strength(A, theta=0.25):
     return S
 
 
-def rs_splitting(A, theta=0.25):
-    """C/F splitting (1 = C, 0 = F) by the Ruge-Stueben first pass."""
+def rs_splitting(A, theta=0.25, second_pass=True):
+    """C/F splitting (1 = C, 0 = F) by classical Ruge-Stueben coarsening."""
     S = strength(A, theta)
     ST = S.T.tocsr()
     ST.sort_indices()
-    return native.rs_first_pass(S, ST), S
+    cf = native.rs_first_pass(S, ST)
+    if second_pass:
+        cf = native.rs_second_pass(S, cf)
+    return cf, S
 
 
 def direct_interpolation(A, S, cf):

@@ -2,8 +2,10 @@
  * Oracle loops that are inherently sequential, in plain C (test infrastructure
  * only: the eigensolver library never links or calls this file).
  *
- *  rs_first_pass  classical Ruge-Stueben C/F splitting, first pass only
+ *  rs_first_pass  classical Ruge-Stueben C/F splitting, first pass
  *                 (Section 2.1: measure |S_i^T|, greedy choice of C points).
+ *  rs_second_pass classical second pass: strongly coupled F points must share
+ *                 a strong C point (the coarsening the paper refers to).
  *  gs_sweep       one Gauss-Seidel sweep on a block of right-hand sides
  *                 (the smoother of the paper's default settings, Section 4.1).
  */
@@ -97,6 +99,41 @@ int64_t rs_first_pass(int64_t n, const int64_t *s_ptr, const int32_t *s_col,
     free(lam);
     free(heap);
     return nc;
+}
+
+/*
+ * Second pass over the F points in increasing order.  For F point i with
+ * strong C points C_i = S_i cap C, every strong F neighbour j must strongly
+ * depend on some point of C_i; the first j that does not is added to C_i
+ * tentatively, and a second such j makes i itself a C point instead.  A
+ * tentative point that survives the scan of i becomes a C point.
+ */
+int64_t rs_second_pass(int64_t n, const int64_t *s_ptr, const int32_t *s_col, int32_t *cf) {
+    int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!stamp) return -1;
+    for (int64_t k = 0; k < n; ++k) stamp[k] = -1;
+    int64_t added = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i] != 0) continue;
+        for (int64_t a = s_ptr[i]; a < s_ptr[i + 1]; ++a)
+            if (cf[s_col[a]] == 1) stamp[s_col[a]] = i;
+        int64_t tentative = -1;
+        int became_c = 0;
+        for (int64_t a = s_ptr[i]; a < s_ptr[i + 1]; ++a) {
+            int64_t j = s_col[a];
+            if (cf[j] != 0) continue;
+            int common = 0;
+            for (int64_t b = s_ptr[j]; b < s_ptr[j + 1]; ++b)
+                if (stamp[s_col[b]] == i) { common = 1; break; }
+            if (common) continue;
+            if (tentative >= 0) { cf[i] = 1; became_c = 1; ++added; break; }
+            tentative = j;
+            stamp[j] = i;
+        }
+        if (!became_c && tentative >= 0) { cf[tentative] = 1; ++added; }
+    }
+    free(stamp);
+    return added;
 }
 
 /*

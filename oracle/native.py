@@ -28,6 +28,8 @@ def lib():
         p = ctypes.c_void_p
         L.rs_first_pass.restype = ctypes.c_int64
         L.rs_first_pass.argtypes = [ctypes.c_int64, p, p, p, p, p]
+        L.rs_second_pass.restype = ctypes.c_int64
+        L.rs_second_pass.argtypes = [ctypes.c_int64, p, p, p]
         L.gs_sweep.restype = None
         L.gs_sweep.argtypes = [ctypes.c_int64, p, p, p, ctypes.c_int, p, p, ctypes.c_int]
         _lib = L
@@ -47,6 +49,15 @@ def rs_first_pass(S, ST):
     nc = lib().rs_first_pass(n, _ptr(sp_), _ptr(sc), _ptr(tp), _ptr(tc), _ptr(cf))
     if nc < 0:
         raise MemoryError("rs_first_pass")
+    return cf
+
+
+def rs_second_pass(S, cf):
+    """Second pass on a first-pass splitting (returns a new array)."""
+    cf = np.ascontiguousarray(cf, dtype=np.int32).copy()
+    sp_, sc = np.ascontiguousarray(S.indptr, np.int64), np.ascontiguousarray(S.indices, np.int32)
+    if lib().rs_second_pass(S.shape[0], _ptr(sp_), _ptr(sc), _ptr(cf)) < 0:
+        raise MemoryError("rs_second_pass")
     return cf
 
 

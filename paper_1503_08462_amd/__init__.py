@@ -1,0 +1,259 @@
+"""Python binding of the amg_eig C ABI (include/amg_eig.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+libamg_eig.so built from csrc/ for gfx950.  PyTorch supplies the device
+workspace (a uint8 tensor of `footprint()` bytes) and the HIP stream.  There is
+no fallback: if the library is missing, importing this package raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+# PyTorch ships its own HIP runtime (same soname as /opt/rocm's).  Loading torch
+# first makes this library bind to that already-loaded runtime, so the process
+# holds a single HIP runtime that both torch (memory, streams) and the kernels use.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamg_eig.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libamg_eig.so is not built; run `python paper_1503_08462_amd/build.py` "
+                      "(hipcc for gfx950). There is no CPU fallback.")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EWORKSPACE, EHIP, ECANCELLED, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
+SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+INIT_NESTED, INIT_RANDOM, INIT_USER = 0, 1, 2
+
+EXPORTED = [
+    "amg_eig_opts_default", "amg_eig_setup", "amg_eig_footprint", "amg_eig_bind", "amg_eig_init",
+    "amg_eig_correct", "amg_eig_progress", "amg_eig_solve", "amg_eig_correct_batch", "amg_eig_info",
+    "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting",
+    "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
+    "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats",
+]
+SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("theta", ctypes.c_double), ("coarse_max", ctypes.c_int), ("coarse_min", ctypes.c_int),
+        ("max_levels", ctypes.c_int), ("qe", ctypes.c_int), ("guard_gap", ctypes.c_double),
+        ("smoother", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("cheb_lo", ctypes.c_double),
+        ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("precision", ctypes.c_int),
+        ("tol", ctypes.c_double), ("max_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
+    ]
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+_vp, _i, _i64, _d, _u64, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_size_t
+_sig = {
+    "amg_eig_opts_default": (None, [_vp]),
+    "amg_eig_setup": (_i, [_vp, _vp, _i, _vp, _vp]),
+    "amg_eig_footprint": (_i, [_vp, _vp]),
+    "amg_eig_bind": (_i, [_vp, _vp, _sz, _vp]),
+    "amg_eig_init": (_i, [_vp, _i, _u64, _vp, _i64]),
+    "amg_eig_correct": (_i, [_vp, _i]),
+    "amg_eig_progress": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "amg_eig_solve": (_i, [_vp, _d, _i, _vp, _vp, _i64]),
+    "amg_eig_correct_batch": (_i, [_vp, _i, _i, _vp]),
+    "amg_eig_info": (_i, [_vp, _vp, _vp, _vp]),
+    "amg_eig_level_matrix": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
+    "amg_eig_level_prolongation": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "amg_eig_level_splitting": (_i, [_vp, _i, _vp]),
+    "amg_eig_coarse_eigenvalues": (_i, [_vp, _vp]),
+    "amg_eig_iterate": (_i, [_vp, _vp, _vp]),
+    "amg_eig_destroy": (None, [_vp]),
+    "amg_eig_strerror": (ctypes.c_char_p, [_i]),
+    "amg_eig_last_error": (ctypes.c_char_p, [_vp]),
+    "amg_eig_timing": (_i, [_vp, _i]),
+    "amg_eig_site_stats": (_i, [_vp, _i, _vp, _vp, _vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class AmgEigError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__("%s (%d)%s" % (_lib.amg_eig_strerror(code).decode(), code, (": " + msg) if msg else ""))
+
+
+def defaults(**kw):
+    o = Opts()
+    _lib.amg_eig_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _csr(rowptr, col, val, keep):
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    va = np.ascontiguousarray(val, dtype=np.float64)
+    keep.extend([rp, ci, va])
+    return Csr(rp.size - 1, rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+
+
+class Context:
+    """One eigenproblem (A, M, q): host setup at construction, device work after bind()."""
+
+    def __init__(self, rowptr, col, a, m, q, opts=None, m_rowptr=None, m_col=None):
+        keep = []
+        A = _csr(rowptr, col, a, keep)
+        M = _csr(rowptr if m_rowptr is None else m_rowptr, col if m_col is None else m_col, m, keep)
+        self._c = ctypes.c_void_p()
+        self.opts = opts if opts is not None else defaults()
+        rc = _lib.amg_eig_setup(ctypes.byref(A), ctypes.byref(M), int(q), ctypes.byref(self.opts),
+                                ctypes.byref(self._c))
+        if rc != OK:
+            raise AmgEigError(rc)
+        self.q = int(q)
+        self.workspace = None
+        self.stream = None
+
+    # ----------------------------------------------------------- host side
+    def _check(self, rc):
+        if rc < 0:
+            raise AmgEigError(rc, _lib.amg_eig_last_error(self._c).decode())
+        return rc
+
+    def footprint(self):
+        n = ctypes.c_size_t()
+        self._check(_lib.amg_eig_footprint(self._c, ctypes.byref(n)))
+        return n.value
+
+    def info(self):
+        qe, nl = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.amg_eig_info(self._c, ctypes.byref(qe), ctypes.byref(nl), None))
+        dims = np.zeros(nl.value, dtype=np.int64)
+        self._check(_lib.amg_eig_info(self._c, None, None, _p(dims)))
+        return {"qe": qe.value, "levels": nl.value, "dims": dims}
+
+    def level_matrix(self, level):
+        nnz = ctypes.c_int64()
+        self._check(_lib.amg_eig_level_matrix(self._c, level, ctypes.byref(nnz), None, None, None, None))
+        n = int(self.info()["dims"][level])
+        rp = np.zeros(n + 1, np.int64)
+        ci = np.zeros(nnz.value, np.int32)
+        a = np.zeros(nnz.value)
+        m = np.zeros(nnz.value)
+        self._check(_lib.amg_eig_level_matrix(self._c, level, ctypes.byref(nnz), _p(rp), _p(ci), _p(a), _p(m)))
+        return rp, ci, a, m
+
+    def prolongation(self, level):
+        nnz = ctypes.c_int64()
+        self._check(_lib.amg_eig_level_prolongation(self._c, level, ctypes.byref(nnz), None, None, None))
+        n = int(self.info()["dims"][level])
+        rp = np.zeros(n + 1, np.int64)
+        ci = np.zeros(nnz.value, np.int32)
+        p = np.zeros(nnz.value)
+        self._check(_lib.amg_eig_level_prolongation(self._c, level, ctypes.byref(nnz), _p(rp), _p(ci), _p(p)))
+        return rp, ci, p
+
+    def splitting(self, level):
+        n = int(self.info()["dims"][level])
+        cf = np.zeros(n, np.int32)
+        self._check(_lib.amg_eig_level_splitting(self._c, level, _p(cf)))
+        return cf
+
+    def coarse_eigenvalues(self):
+        lam = np.zeros(int(self.info()["dims"][-1]))
+        self._check(_lib.amg_eig_coarse_eigenvalues(self._c, _p(lam)))
+        return lam
+
+    # --------------------------------------------------------- device side
+    def bind(self, device="cuda", stream=None):
+        import torch
+        self.workspace = torch.empty(self.footprint(), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        self._check(_lib.amg_eig_bind(self._c, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                      ctypes.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def init(self, mode=INIT_NESTED, seed=0, U=None):
+        ptr, ldu = None, 0
+        if U is not None:
+            ptr, ldu = ctypes.c_void_p(U.data_ptr()), U.stride(0)
+        self._check(_lib.amg_eig_init(self._c, mode, ctypes.c_uint64(seed), ptr, ldu))
+
+    def correct(self, steps=1):
+        self._check(_lib.amg_eig_correct(self._c, steps))
+
+    def progress(self):
+        qe = self.info()["qe"]
+        th, rh = np.zeros(qe), np.zeros(qe)
+        st, cv = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.amg_eig_progress(self._c, _p(th), _p(rh), ctypes.byref(st), ctypes.byref(cv)))
+        return {"theta": th, "rho": rh, "steps": st.value, "converged": bool(cv.value)}
+
+    def solve(self, tol=1e-8, max_steps=100, U_out=None):
+        lam = np.zeros(self.q)
+        ptr, ldu = None, 0
+        if U_out is not None:
+            ptr, ldu = ctypes.c_void_p(U_out.data_ptr()), U_out.stride(0)
+        rc = self._check(_lib.amg_eig_solve(self._c, tol, max_steps, _p(lam), ptr, ldu))
+        return lam, rc == OK
+
+    def iterate(self):
+        """The device iterate as a torch view (N x ld FP64, first qe columns used)."""
+        import torch
+        p = ctypes.c_void_p()
+        ld = ctypes.c_int64()
+        self._check(_lib.amg_eig_iterate(self._c, ctypes.byref(p), ctypes.byref(ld)))
+        n = int(self.info()["dims"][0])
+        off = p.value - self.workspace.data_ptr()
+        return self.workspace[off:off + n * ld.value * 8].view(torch.float64).view(n, ld.value)
+
+    def timing(self, enable=True):
+        self._check(_lib.amg_eig_timing(self._c, 1 if enable else 0))
+
+    def site_stats(self):
+        """{site: (algorithmic bytes or flops per launch, total ms, launches)}."""
+        out = {}
+        for i, name in enumerate(SITES):
+            b, ms, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+            self._check(_lib.amg_eig_site_stats(self._c, i, ctypes.byref(b), ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (b.value, ms.value, n.value)
+        return out
+
+    def close(self):
+        if self._c:
+            _lib.amg_eig_destroy(self._c)
+            self._c = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def correct_batch(contexts, steps=1, stream=None):
+    arr = (ctypes.c_void_p * len(contexts))(*[c._c.value for c in contexts])
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    rc = _lib.amg_eig_correct_batch(arr, len(contexts), steps, s)
+    if rc < 0:
+        raise AmgEigError(rc)
+
+
+def from_problem(p, **opts):
+    """Context for a workload dict (rowptr/col shared by A and M)."""
+    return Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], defaults(**opts))

@@ -1,0 +1,713 @@
+// Context, device workspace plan, upload, and the enqueue order of one
+// correction step (Algorithm 3.1) and of the driver (Algorithm 3.2); the C ABI
+// of amg_eig.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "amg_eig.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace amgeig;
+
+namespace {
+
+struct DevLevel {
+    int64_t n = 0;
+    int32_t *u_ptr = nullptr, *u_col = nullptr;
+    double *u_a = nullptr, *u_m = nullptr;
+    int32_t *v_ptr = nullptr, *v_col = nullptr;
+    void *v_val = nullptr, *dinv = nullptr;
+    int32_t *p_ptr = nullptr, *p_col = nullptr, *pt_ptr = nullptr, *pt_col = nullptr;
+    void *p_val = nullptr, *pt_val = nullptr;
+    double *p64 = nullptr, *pt64 = nullptr;
+    void *b = nullptr, *r = nullptr, *x = nullptr;
+    double *cw = nullptr;
+};
+
+// Bump allocator over the caller's workspace; with base == nullptr it only sizes.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(char *b) : base(b) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct amg_eig_ctx {
+    Hierarchy H;
+    amg_eig_opts o{};
+    int q = 0, qe = 0, ld = 0;
+    bool mixed = false;
+    std::string err;
+    // device state
+    bool bound = false, initialised = false;
+    hipStream_t stream = nullptr;
+    size_t need = 0;
+    std::vector<DevLevel> dl;
+    double *U = nullptr, *V = nullptr, *W = nullptr;
+    double *Z = nullptr, *lam = nullptr, *Yn = nullptr;
+    void *Ainv = nullptr;
+    double *theta = nullptr, *rho = nullptr, *part_res = nullptr, *part_gram = nullptr;
+    unsigned *counters = nullptr;
+    int *status = nullptr;
+    SmallWork sw;
+    // host staging kept alive until the upload completes
+    std::vector<std::vector<char>> staging;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    // optional per-site event timing of finest-level kernels (eager launches)
+    bool timing = false;
+    struct Site {
+        std::vector<hipEvent_t> ev;  // start/stop pairs
+        size_t used = 0;
+        double ms = 0.0;
+        int64_t launches = 0;
+    } sites[AMG_EIG_SITE_COUNT];
+};
+
+namespace {
+
+int fail(amg_eig_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, AMG_EIG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------ memory plan
+void plan(amg_eig_ctx *c, char *base) {
+    Carver cv(base);
+    const Hierarchy &H = c->H;
+    const int L = (int)H.lv.size(), ld = c->ld, dn = H.dn;
+    const size_t sT = c->mixed ? sizeof(float) : sizeof(double);
+    const int64_t N = H.lv[0].n;
+    c->dl.assign(L, DevLevel());
+    for (int l = 0; l < L; ++l) {
+        const Level &lv = H.lv[l];
+        DevLevel &d = c->dl[l];
+        d.n = lv.n;
+        d.u_ptr = cv.take<int32_t>(lv.n + 1);
+        d.u_col = cv.take<int32_t>(lv.col.size());
+        d.u_a = cv.take<double>(lv.col.size());
+        d.u_m = cv.take<double>(lv.col.size());
+        if (l < L - 1) {
+            d.v_ptr = cv.take<int32_t>(lv.n + 1);
+            d.v_col = cv.take<int32_t>(lv.av.col.size());
+            d.v_val = cv.take<char>(lv.av.col.size() * sT);
+            d.dinv = cv.take<char>(lv.n * sT);
+            d.p_ptr = cv.take<int32_t>(lv.n + 1);
+            d.p_col = cv.take<int32_t>(lv.P.col.size());
+            d.p_val = cv.take<char>(lv.P.col.size() * sT);
+            d.p64 = cv.take<double>(lv.P.col.size());
+            d.pt_ptr = cv.take<int32_t>(lv.Pt.nr + 1);
+            d.pt_col = cv.take<int32_t>(lv.Pt.col.size());
+            d.pt_val = cv.take<char>(lv.Pt.col.size() * sT);
+            d.pt64 = cv.take<double>(lv.Pt.col.size());
+        }
+        d.b = cv.take<char>((size_t)lv.n * ld * sT);
+        d.r = cv.take<char>((size_t)lv.n * ld * sT);
+        d.x = cv.take<char>((size_t)lv.n * ld * sT);
+        if (l >= 1) d.cw = cv.take<double>((size_t)lv.n * 2 * ld);
+    }
+    c->U = cv.take<double>((size_t)N * ld);
+    c->V = cv.take<double>((size_t)N * ld);
+    c->W = cv.take<double>((size_t)N * 2 * ld);
+    c->Z = cv.take<double>((size_t)dn * dn);
+    c->lam = cv.take<double>(dn);
+    c->Ainv = cv.take<char>((size_t)dn * dn * sT);
+    c->Yn = cv.take<double>((size_t)dn * ld);
+    c->theta = cv.take<double>(ld);
+    c->rho = cv.take<double>(ld);
+    int64_t maxn = 0;
+    for (const Level &lv : H.lv) maxn = std::max(maxn, lv.n);
+    c->part_res = cv.take<double>((size_t)residual_blocks(maxn, ld) * 2 * ld);
+    c->part_gram = cv.take<double>((size_t)gram_blocks(maxn, ld) * 2 * ld * ld);
+    c->counters = cv.take<unsigned>(16);
+    c->status = cv.take<int>(ST_COUNT);
+    SmallWork &w = c->sw;
+    w.dn = dn;
+    w.ld = ld;
+    w.lam = c->lam;
+    w.FG = cv.take<double>((size_t)dn * 2 * ld);
+    w.GAGM = cv.take<double>((size_t)2 * ld * ld);
+    w.P3 = cv.take<double>((size_t)3 * ld * ld);
+    w.Ct = cv.take<double>((size_t)dn * ld);
+    w.Dt = cv.take<double>((size_t)ld * ld);
+    w.L1 = cv.take<double>((size_t)ld * ld);
+    w.perm = cv.take<int>(ld);
+    w.X = cv.take<double>((size_t)(dn + ld) * ld);
+    w.HX = cv.take<double>((size_t)(dn + ld) * ld);
+    w.Xr = cv.take<double>((size_t)(dn + ld) * ld);
+    w.theta = cv.take<double>(ld);
+    w.Xc = cv.take<double>((size_t)dn * ld);
+    w.Xv = cv.take<double>((size_t)ld * ld);
+    w.status = c->status;
+    c->need = cv.off + 256;
+}
+
+template <typename T>
+void *stage(amg_eig_ctx *c, const std::vector<T> &v) {
+    c->staging.emplace_back(v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(c->staging.back().data(), v.data(), v.size() * sizeof(T));
+    return c->staging.back().data();
+}
+
+template <typename T>
+std::vector<T> narrow_ptr(const std::vector<int64_t> &p) {
+    std::vector<T> r(p.size());
+    for (size_t i = 0; i < p.size(); ++i) r[i] = (T)p[i];
+    return r;
+}
+
+template <typename T>
+std::vector<T> convert(const std::vector<double> &v) {
+    std::vector<T> r(v.size());
+    for (size_t i = 0; i < v.size(); ++i) r[i] = (T)v[i];
+    return r;
+}
+
+int put(amg_eig_ctx *c, void *dst, const void *host, size_t bytes) {
+    if (bytes == 0) return AMG_EIG_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, host, bytes, hipMemcpyHostToDevice, c->stream));
+    return AMG_EIG_OK;
+}
+
+template <typename T>
+int upload_vec(amg_eig_ctx *c, void *dst, const std::vector<T> &v) {
+    void *h = stage(c, v);
+    return put(c, dst, h, v.size() * sizeof(T));
+}
+
+template <typename T>
+int upload_levels(amg_eig_ctx *c) {
+    const Hierarchy &H = c->H;
+    const int L = (int)H.lv.size();
+    int rc = 0;
+    for (int l = 0; l < L && !rc; ++l) {
+        const Level &lv = H.lv[l];
+        DevLevel &d = c->dl[l];
+        rc |= upload_vec(c, d.u_ptr, narrow_ptr<int32_t>(lv.ptr));
+        rc |= upload_vec(c, d.u_col, lv.col);
+        rc |= upload_vec(c, d.u_a, lv.a);
+        rc |= upload_vec(c, d.u_m, lv.m);
+        if (l < L - 1) {
+            rc |= upload_vec(c, d.v_ptr, narrow_ptr<int32_t>(lv.av.ptr));
+            rc |= upload_vec(c, d.v_col, lv.av.col);
+            rc |= upload_vec(c, d.v_val, convert<T>(lv.av.val));
+            std::vector<double> dinv(lv.n);
+            for (int64_t i = 0; i < lv.n; ++i) dinv[i] = 1.0 / lv.l1[i];
+            rc |= upload_vec(c, d.dinv, convert<T>(dinv));
+            rc |= upload_vec(c, d.p_ptr, narrow_ptr<int32_t>(lv.P.ptr));
+            rc |= upload_vec(c, d.p_col, lv.P.col);
+            rc |= upload_vec(c, d.p_val, convert<T>(lv.P.val));
+            rc |= upload_vec(c, d.p64, lv.P.val);
+            rc |= upload_vec(c, d.pt_ptr, narrow_ptr<int32_t>(lv.Pt.ptr));
+            rc |= upload_vec(c, d.pt_col, lv.Pt.col);
+            rc |= upload_vec(c, d.pt_val, convert<T>(lv.Pt.val));
+            rc |= upload_vec(c, d.pt64, lv.Pt.val);
+        }
+    }
+    const int dn = H.dn;
+    rc |= upload_vec(c, c->Z, H.Z);
+    rc |= upload_vec(c, c->lam, H.lam);
+    rc |= upload_vec(c, c->Ainv, convert<T>(H.Ainv));
+    return rc ? AMG_EIG_EHIP : AMG_EIG_OK;
+}
+
+// ---------------------------------------------------------- site timing
+struct SiteScope {
+    amg_eig_ctx *c;
+    int site;
+    bool on;
+    SiteScope(amg_eig_ctx *ctx, int s, int level) : c(ctx), site(s), on(ctx->timing && level == 0) {
+        if (on) record();
+    }
+    ~SiteScope() {
+        if (on) record();
+    }
+    void record() {
+        auto &st = c->sites[site];
+        if (st.used == st.ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+            st.ev.push_back(e);
+        }
+        (void)hipEventRecord(st.ev[st.used++], c->stream);
+    }
+};
+
+void collect_sites(amg_eig_ctx *c) {
+    for (auto &st : c->sites) {
+        for (size_t i = 0; i + 1 < st.used; i += 2) {
+            float ms = 0.f;
+            if (hipEventSynchronize(st.ev[i + 1]) == hipSuccess && hipEventElapsedTime(&ms, st.ev[i], st.ev[i + 1]) == hipSuccess) {
+                st.ms += ms;
+                st.launches += 1;
+            }
+        }
+        st.used = 0;
+    }
+}
+
+// Algorithmic bytes (or flops for the Gram site) of one launch on the finest
+// level: every operand read once, every result written once.
+double site_bytes(const amg_eig_ctx *c, int site) {
+    const Level &L0 = c->H.lv[0];
+    const double n = (double)L0.n, ld = c->ld, sT = c->mixed ? 4.0 : 8.0;
+    const double ptr = 4.0 * (n + 1), nnz_u = (double)L0.col.size(), nnz_v = (double)L0.av.col.size();
+    const double n1 = c->H.lv.size() > 1 ? (double)c->H.lv[1].n : 0.0;
+    const double nnz_p = (double)L0.P.col.size();
+    switch (site) {
+    case AMG_EIG_SITE_RESIDUAL: return ptr + nnz_u * 20.0 + 8.0 * n * ld + sT * n * ld;
+    case AMG_EIG_SITE_PRESMOOTH: return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld;
+    case AMG_EIG_SITE_POSTSMOOTH: return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld + 16.0 * n * ld;
+    case AMG_EIG_SITE_DUALSPMM: return ptr + nnz_u * 20.0 + 8.0 * n * ld + 16.0 * n * ld;
+    case AMG_EIG_SITE_GRAM: return 4.0 * n * ld * ld;  // flops
+    case AMG_EIG_SITE_RESTRICT: return 4.0 * (n1 + 1) + nnz_p * 12.0 + 16.0 * n * ld + 16.0 * n1 * ld;
+    case AMG_EIG_SITE_FINAL: return ptr + nnz_p * 12.0 + 8.0 * n1 * ld + 16.0 * n * ld;
+    case AMG_EIG_SITE_SMALL: return 0.0;
+    default: return 0.0;
+    }
+}
+
+// ---------------------------------------------------------- step pieces
+template <typename T>
+void vcycle(amg_eig_ctx *c, int k) {
+    const int L = (int)c->dl.size(), ld = c->ld;
+    hipStream_t s = c->stream;
+    const int *st = c->status;
+    for (int l = k; l < L - 1; ++l) {
+        DevLevel &d = c->dl[l];
+        {
+            SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
+            launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                 (const T *)d.b, (T *)d.r, st);
+        }
+        DevLevel &e = c->dl[l + 1];
+        launch_spmm<T>(s, e.n, ld, d.pt_ptr, d.pt_col, (const T *)d.pt_val, (const T *)d.r, (T *)e.b, st);
+    }
+    DevLevel &cl = c->dl[L - 1];
+    launch_gemm_small<T>(s, false, (int)cl.n, ld, (int)cl.n, (const T *)c->Ainv, (int)cl.n, (const T *)cl.b, ld,
+                         (T *)cl.x, ld, st);
+    for (int l = L - 2; l >= k; --l) {
+        DevLevel &d = c->dl[l];
+        DevLevel &e = c->dl[l + 1];
+        launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.dinv,
+                              (const T *)d.b, (T *)d.r, st);
+        SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
+        launch_smooth_post<T>(s, l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                              (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st);
+    }
+}
+
+void rayleigh_ritz(amg_eig_ctx *c, int k) {
+    const int L = (int)c->dl.size(), ld = c->ld, dn = c->H.dn;
+    hipStream_t s = c->stream;
+    const int *st = c->status;
+    DevLevel &d = c->dl[k];
+    {
+        SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k);
+        launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st);
+    }
+    {
+        SiteScope sc(c, AMG_EIG_SITE_GRAM, k);
+        launch_gram(s, d.n, ld, c->V, c->W, c->part_gram, c->sw.GAGM, st);
+    }
+    const double *src = c->W;
+    for (int l = k; l < L - 1; ++l) {
+        DevLevel &a = c->dl[l];
+        DevLevel &b = c->dl[l + 1];
+        SiteScope sc(c, AMG_EIG_SITE_RESTRICT, l);
+        launch_spmm<double>(s, b.n, 2 * ld, a.pt_ptr, a.pt_col, a.pt64, src, b.cw, st);
+        src = b.cw;
+    }
+    {
+        SiteScope sc(c, AMG_EIG_SITE_SMALL, k);
+        launch_gemm_small<double>(s, true, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+        launch_small_products(s, c->sw);
+        launch_pencil(s, c->sw, 1e-13);
+        launch_arrow_eig(s, c->sw, c->qe, c->theta);
+        launch_recombine_coeffs(s, c->sw);
+        launch_gemm_small<double>(s, false, dn, ld, dn, c->Z, dn, c->sw.Xc, ld, c->Yn, ld, st);
+    }
+    const double *y = c->Yn;
+    for (int l = L - 2; l > k; --l) {
+        DevLevel &a = c->dl[l];
+        launch_spmm<double>(s, a.n, ld, a.p_ptr, a.p_col, a.p64, y, a.cw, st);
+        y = a.cw;
+    }
+    {
+        SiteScope sc(c, AMG_EIG_SITE_FINAL, k);
+        launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, y, c->V, c->sw.Xv, c->U, st);
+    }
+    launch_theta_update(s, c->sw, c->theta, k == 0 ? 1 : 0);
+}
+
+template <typename T>
+void residual(amg_eig_ctx *c, int k, int check) {
+    DevLevel &d = c->dl[k];
+    SiteScope sc(c, AMG_EIG_SITE_RESIDUAL, k);
+    launch_residual<T>(c->stream, d.n, c->ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (T *)d.b,
+                       c->part_res, c->counters, c->rho, c->q, c->o.tol, c->status, check);
+}
+
+void correction(amg_eig_ctx *c, int k) {
+    if (c->mixed) {
+        residual<float>(c, k, k == 0);
+        vcycle<float>(c, k);
+    } else {
+        residual<double>(c, k, k == 0);
+        vcycle<double>(c, k);
+    }
+    rayleigh_ritz(c, k);
+}
+
+void drop_graph(amg_eig_ctx *c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+int enqueue_steps(amg_eig_ctx *c, int steps) {
+    for (int i = 0; i < steps; ++i) {
+        if (c->o.use_graph && c->stream) {
+            if (!c->graph_exec) {
+                const bool t = c->timing;
+                c->timing = false;
+                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                correction(c, 0);
+                c->timing = t;
+                HIPCHK(c, hipStreamEndCapture(c->stream, &c->graph));
+                HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+        } else {
+            correction(c, 0);
+        }
+    }
+    HIPCHK(c, hipGetLastError());
+    return AMG_EIG_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+void amg_eig_opts_default(amg_eig_opts *o) {
+    if (!o) return;
+    o->theta = 0.25;
+    o->coarse_max = 512;
+    o->coarse_min = 0;
+    o->max_levels = 25;
+    o->qe = 0;
+    o->guard_gap = 1e-2;
+    o->smoother = AMG_EIG_SMOOTH_L1JACOBI;
+    o->cheb_degree = 2;
+    o->cheb_lo = 0.25;
+    o->nu_pre = 1;
+    o->nu_post = 1;
+    o->precision = AMG_EIG_PREC_FP64;
+    o->tol = 1e-8;
+    o->max_steps = 100;
+    o->use_graph = 0;
+}
+
+int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o, amg_eig_ctx **out) {
+    if (!out) return AMG_EIG_EINVAL;
+    *out = nullptr;
+    amg_eig_ctx *c = new (std::nothrow) amg_eig_ctx();
+    if (!c) return AMG_EIG_ENOMEM;
+    if (o)
+        c->o = *o;
+    else
+        amg_eig_opts_default(&c->o);
+    if (c->o.smoother != AMG_EIG_SMOOTH_L1JACOBI || c->o.nu_pre != 1 || c->o.nu_post != 1 ||
+        (c->o.precision != AMG_EIG_PREC_FP64 && c->o.precision != AMG_EIG_PREC_MIXED)) {
+        delete c;
+        return AMG_EIG_EINVAL;
+    }
+    int rc;
+    try {
+        rc = build_hierarchy(A, M, q, c->o, c->H, c->qe, c->err);
+    } catch (const std::bad_alloc &) {
+        rc = AMG_EIG_ENOMEM;
+    } catch (...) {
+        rc = AMG_EIG_EINVAL;
+    }
+    if (rc == AMG_EIG_OK && c->qe > kMaxWidth) rc = AMG_EIG_EINVAL;
+    if (rc != AMG_EIG_OK) {
+        delete c;
+        return rc;
+    }
+    c->q = q;
+    c->ld = c->qe;
+    c->mixed = c->o.precision == AMG_EIG_PREC_MIXED;
+    plan(c, nullptr);
+    *out = c;
+    return AMG_EIG_OK;
+}
+
+int amg_eig_footprint(const amg_eig_ctx *c, size_t *device_bytes) {
+    if (!c || !device_bytes) return AMG_EIG_EINVAL;
+    *device_bytes = c->need;
+    return AMG_EIG_OK;
+}
+
+int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (!ws || bytes < c->need || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return fail(c, AMG_EIG_EWORKSPACE, "workspace missing, unaligned or smaller than the footprint");
+    drop_graph(c);
+    c->stream = (hipStream_t)hip_stream;
+    plan(c, (char *)ws);
+    c->staging.clear();
+    int rc = c->mixed ? upload_levels<float>(c) : upload_levels<double>(c);
+    if (rc) return rc;
+    launch_fill_i32(c->stream, ST_COUNT, 0, c->status);
+    std::vector<unsigned> zero(16, 0u);
+    rc = upload_vec(c, c->counters, zero);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->staging.clear();
+    c->bound = true;
+    c->initialised = false;
+    return AMG_EIG_OK;
+}
+
+int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, int64_t ldu) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (!c->bound) return fail(c, AMG_EIG_ESTATE, "init before bind");
+    const int L = (int)c->dl.size(), ld = c->ld, qe = c->qe, dn = c->H.dn;
+    hipStream_t s = c->stream;
+    const int64_t N = c->dl[0].n;
+    launch_fill_i32(s, ST_COUNT, 0, c->status);
+    if (mode == AMG_EIG_INIT_NESTED) {
+        // coarsest eigenpairs, then one correction on each level n-1 .. 2
+        launch_copy_cols(s, dn, ld, ld, qe, c->Z, dn, c->U);
+        launch_copy_f64(s, qe, c->lam, c->theta);
+        for (int k = L - 2; k >= 0; --k) {
+            DevLevel &d = c->dl[k];
+            launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, c->U, c->V, c->status);
+            launch_copy_f64(s, d.n * (int64_t)ld, c->V, c->U);
+            if (k >= 1) correction(c, k);
+        }
+    } else if (mode == AMG_EIG_INIT_RANDOM || mode == AMG_EIG_INIT_USER) {
+        if (mode == AMG_EIG_INIT_RANDOM) {
+            launch_fill_random(s, N, ld, qe, seed, c->V);
+        } else {
+            if (!U_dev || ldu < qe) return fail(c, AMG_EIG_EINVAL, "user block missing or ldu < qe");
+            launch_copy_cols(s, N, ld, ld, qe, U_dev, ldu, c->V);
+        }
+        rayleigh_ritz(c, 0);
+    } else {
+        return fail(c, AMG_EIG_EINVAL, "unknown init mode");
+    }
+    // the step counter counts finest-level corrections only (the warm-bracket
+    // flag and the rank survive)
+    launch_fill_i32(s, 2, 0, c->status);
+    HIPCHK(c, hipGetLastError());
+    c->initialised = true;
+    return AMG_EIG_OK;
+}
+
+int amg_eig_correct(amg_eig_ctx *c, int steps) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (!c->initialised) return fail(c, AMG_EIG_ESTATE, "correct before init");
+    if (steps < 0) return fail(c, AMG_EIG_EINVAL, "negative step count");
+    return enqueue_steps(c, steps);
+}
+
+int amg_eig_progress(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (!c->bound) return fail(c, AMG_EIG_ESTATE, "progress before bind");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int st[ST_COUNT];
+    HIPCHK(c, hipMemcpy(st, c->status, sizeof(st), hipMemcpyDeviceToHost));
+    if (theta) HIPCHK(c, hipMemcpy(theta, c->theta, c->qe * sizeof(double), hipMemcpyDeviceToHost));
+    if (rho) HIPCHK(c, hipMemcpy(rho, c->rho, c->qe * sizeof(double), hipMemcpyDeviceToHost));
+    if (steps) *steps = st[ST_STEPS];
+    if (converged) *converged = st[ST_CONVERGED];
+    if (st[ST_BREAKDOWN]) return fail(c, AMG_EIG_EBREAKDOWN, "projected problem lost definiteness");
+    return AMG_EIG_OK;
+}
+
+int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host, double *U_dev, int64_t ldu) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (!c->bound) return fail(c, AMG_EIG_ESTATE, "solve before bind");
+    if (tol > 0 && tol != c->o.tol) {
+        c->o.tol = tol;
+        drop_graph(c);
+    }
+    if (!c->initialised) {
+        int rc = amg_eig_init(c, AMG_EIG_INIT_NESTED, 0, nullptr, 0);
+        if (rc) return rc;
+    }
+    int done = 0, conv = 0, steps = 0, rc;
+    while (!conv && done < max_steps) {
+        const int chunk = std::min(4, max_steps - done);
+        rc = enqueue_steps(c, chunk);
+        if (rc) return rc;
+        done += chunk;
+        rc = amg_eig_progress(c, nullptr, nullptr, &steps, &conv);
+        if (rc) return rc;
+    }
+    if (!conv) {  // residual of the last iterate
+        if (c->mixed)
+            residual<float>(c, 0, 1);
+        else
+            residual<double>(c, 0, 1);
+        rc = amg_eig_progress(c, nullptr, nullptr, &steps, &conv);
+        if (rc) return rc;
+    }
+    if (lambda_host) HIPCHK(c, hipMemcpy(lambda_host, c->theta, c->q * sizeof(double), hipMemcpyDeviceToHost));
+    if (U_dev) {
+        if (ldu < c->q) return fail(c, AMG_EIG_EINVAL, "ldu < q");
+        launch_copy_cols(c->stream, c->dl[0].n, c->q, ldu, c->q, c->U, c->ld, U_dev);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return conv ? AMG_EIG_OK : AMG_EIG_NOT_CONVERGED;
+}
+
+int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_stream) {
+    if (!cs || n < 0) return AMG_EIG_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        amg_eig_ctx *c = cs[i];
+        if (!c || !c->initialised) return c ? fail(c, AMG_EIG_ESTATE, "batch member not initialised") : AMG_EIG_EINVAL;
+        if (hip_stream && c->stream != (hipStream_t)hip_stream)
+            return fail(c, AMG_EIG_EINVAL, "batch member bound to another stream");
+    }
+    for (int s = 0; s < steps; ++s)
+        for (int i = 0; i < n; ++i) {
+            int rc = enqueue_steps(cs[i], 1);
+            if (rc) return rc;
+        }
+    return AMG_EIG_OK;
+}
+
+int amg_eig_info(const amg_eig_ctx *c, int *qe, int *nlevels, int64_t *dims) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (qe) *qe = c->qe;
+    if (nlevels) *nlevels = (int)c->H.lv.size();
+    if (dims)
+        for (size_t l = 0; l < c->H.lv.size(); ++l) dims[l] = c->H.lv[l].n;
+    return AMG_EIG_OK;
+}
+
+int amg_eig_level_matrix(const amg_eig_ctx *c, int level, int64_t *nnz, int64_t *rowptr, int32_t *col, double *a,
+                         double *m) {
+    if (!c || level < 0 || level >= (int)c->H.lv.size() || !nnz) return AMG_EIG_EINVAL;
+    const Level &L = c->H.lv[level];
+    *nnz = (int64_t)L.col.size();
+    if (rowptr) std::memcpy(rowptr, L.ptr.data(), L.ptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, L.col.data(), L.col.size() * sizeof(int32_t));
+    if (a) std::memcpy(a, L.a.data(), L.a.size() * sizeof(double));
+    if (m) std::memcpy(m, L.m.data(), L.m.size() * sizeof(double));
+    return AMG_EIG_OK;
+}
+
+int amg_eig_level_prolongation(const amg_eig_ctx *c, int level, int64_t *nnz, int64_t *rowptr, int32_t *col,
+                               double *p) {
+    if (!c || level < 0 || level + 1 >= (int)c->H.lv.size() || !nnz) return AMG_EIG_EINVAL;
+    const Csr &P = c->H.lv[level].P;
+    *nnz = P.nnz();
+    if (rowptr) std::memcpy(rowptr, P.ptr.data(), P.ptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, P.col.data(), P.col.size() * sizeof(int32_t));
+    if (p) std::memcpy(p, P.val.data(), P.val.size() * sizeof(double));
+    return AMG_EIG_OK;
+}
+
+int amg_eig_level_splitting(const amg_eig_ctx *c, int level, int32_t *cf) {
+    if (!c || level < 0 || level + 1 >= (int)c->H.lv.size() || !cf) return AMG_EIG_EINVAL;
+    const Level &L = c->H.lv[level];
+    std::memcpy(cf, L.cf.data(), L.cf.size() * sizeof(int32_t));
+    return AMG_EIG_OK;
+}
+
+int amg_eig_coarse_eigenvalues(const amg_eig_ctx *c, double *lam) {
+    if (!c || !lam) return AMG_EIG_EINVAL;
+    std::memcpy(lam, c->H.lam.data(), c->H.lam.size() * sizeof(double));
+    return AMG_EIG_OK;
+}
+
+int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld) {
+    if (!c || !U_dev || !ld) return AMG_EIG_EINVAL;
+    if (!c->bound) return AMG_EIG_ESTATE;
+    *U_dev = c->U;
+    *ld = c->ld;
+    return AMG_EIG_OK;
+}
+
+void amg_eig_destroy(amg_eig_ctx *c) {
+    if (!c) return;
+    drop_graph(c);
+    for (auto &st : c->sites)
+        for (hipEvent_t e : st.ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int amg_eig_timing(amg_eig_ctx *c, int enable) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (c->timing && !enable) collect_sites(c);
+    c->timing = enable != 0;
+    if (enable)
+        for (auto &st : c->sites) {
+            st.ms = 0.0;
+            st.launches = 0;
+            st.used = 0;
+        }
+    return AMG_EIG_OK;
+}
+
+int amg_eig_site_stats(amg_eig_ctx *c, int site, double *alg_bytes, double *ms_total, int64_t *launches) {
+    if (!c || site < 0 || site >= AMG_EIG_SITE_COUNT) return AMG_EIG_EINVAL;
+    if (c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
+    collect_sites(c);
+    if (alg_bytes) *alg_bytes = site_bytes(c, site);
+    if (ms_total) *ms_total = c->sites[site].ms;
+    if (launches) *launches = c->sites[site].launches;
+    return AMG_EIG_OK;
+}
+
+const char *amg_eig_strerror(int code) {
+    switch (code) {
+    case AMG_EIG_OK: return "ok";
+    case AMG_EIG_NOT_CONVERGED: return "not converged (best-so-far results)";
+    case AMG_EIG_EINVAL: return "invalid argument";
+    case AMG_EIG_ENOTSPD: return "matrix not positive (semi)definite";
+    case AMG_EIG_EBREAKDOWN: return "breakdown of the projected problem";
+    case AMG_EIG_ENOMEM: return "host allocation failed";
+    case AMG_EIG_EWORKSPACE: return "device workspace missing or too small";
+    case AMG_EIG_EHIP: return "HIP runtime error";
+    case AMG_EIG_ECANCELLED: return "cancelled";
+    case AMG_EIG_ESTATE: return "call out of order";
+    default: return "unknown code";
+    }
+}
+
+const char *amg_eig_last_error(const amg_eig_ctx *c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

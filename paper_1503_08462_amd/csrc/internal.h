@@ -1,0 +1,55 @@
+// Host-side structures shared by the setup (setup.cpp) and the device engine
+// (engine.hip).  Nothing here touches the GPU.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "amg_eig.h"
+
+namespace amgeig {
+
+struct Csr {
+    int64_t nr = 0, nc = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+// One level of the hierarchy, k = 0 is the finest.
+struct Level {
+    int64_t n = 0;
+    // A_k and M_k on one shared pattern (explicit zeros kept), FP64.
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> a, m;
+    // A_k without its explicit off-diagonal zeros: the V-cycle operator.
+    Csr av;
+    std::vector<double> l1;   // d_i = sum_j |a_ij|
+    std::vector<int32_t> cf;  // C/F splitting towards level k+1 (1 = C)
+    Csr P, Pt;                // prolongation n_k x n_{k+1} and its transpose
+};
+
+struct Hierarchy {
+    std::vector<Level> lv;
+    int dn = 0;
+    std::vector<double> lam;   // coarsest eigenvalues, ascending
+    std::vector<double> Z;     // dn x dn row-major, column j = eigenvector j, Z^T M_n Z = I
+    std::vector<double> Ainv;  // dn x dn row-major, A_n^-1 = Z diag(1/lam) Z^T
+};
+
+// Status codes of amg_eig.h, returned by the setup routines.
+int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts &o, Hierarchy &H,
+                    int &qe, std::string &err);
+
+// Dense symmetric-definite eigen-decomposition (host, FP64): A z = lam M z with
+// Z^T M Z = I, eigenvalues ascending.  A and M row-major n x n.  Returns false if
+// M is not positive definite.
+bool dense_sygv(int n, const std::vector<double> &A, const std::vector<double> &M, std::vector<double> &lam,
+                std::vector<double> &Z);
+
+// Choose the block width by the guard rule on approximate eigenvalues.
+int guard_width(const std::vector<double> &lam, int q, double gap, int cap);
+
+}  // namespace amgeig

@@ -1,0 +1,84 @@
+// Host-side launchers of the gfx950 kernels (all enqueue on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace amgeig {
+
+// status words (int32, device)
+enum : int {
+    ST_CONVERGED = 0,  // residual test of the finest level holds: later steps skip
+    ST_STEPS = 1,      // finest-level corrections done
+    ST_RANK = 2,       // columns of the new block kept after M-orthogonalisation
+    ST_BREAKDOWN = 3,  // set when the projected problem lost definiteness
+    ST_WARM = 4,       // the previous Ritz values may seed the eigenvalue brackets
+    ST_COUNT = 8
+};
+
+constexpr int kMaxWidth = 80;  // block width limit (LDS budget of the small kernels)
+
+// ---------------------------------------------------------- kernels_vec.hip
+int64_t residual_blocks(int64_t n, int ld);
+int64_t gram_blocks(int64_t n, int ld);
+template <typename TO>
+void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                     const double *m, const double *U, const double *theta, TO *R, double *part,
+                     unsigned *counter, double *rho, int q, double tol, int *status, int check);
+template <typename T>
+void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                       const T *dinv, const T *b, T *r, const int *status);
+template <typename T>
+void launch_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                 const T *x, T *y, const int *status);
+template <typename T>
+void launch_prolong_add(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                        const T *xc, const T *dinv, const T *b, T *y, const int *status);
+template <typename T>
+void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
+                        const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
+                        const int *status);
+template <typename T, typename TA>
+void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
+                       const int *status);
+template <typename T>
+void launch_gemm_small(hipStream_t s, bool transA, int m, int n, int K, const T *A, int lda, const T *B, int ldb,
+                       T *C, int ldc, const int *status);
+void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                      const double *m, const double *V, double *W, const int *status);
+void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
+                 const int *status);
+void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
+                  const double *Y, const double *V, const double *Xv, double *U, const int *status);
+void launch_fill_random(hipStream_t s, int64_t n, int ld, int qe, uint64_t seed, double *U);
+void launch_copy_cols(hipStream_t s, int64_t rows, int dcols, int64_t ldd, int cols, const double *src,
+                      int64_t lds, double *dst);
+void launch_copy_f64(hipStream_t s, int64_t count, const double *src, double *dst);
+void launch_fill_i32(hipStream_t s, int count, int value, int *dst);
+
+// -------------------------------------------------------- kernels_small.hip
+// Scratch of the small kernels (device, FP64 unless noted), sizes in elements:
+struct SmallWork {
+    int dn = 0, ld = 0;
+    const double *lam = nullptr;  // dn, ascending
+    double *FG = nullptr;         // dn x 2ld: row i = [(Z^T B_A)_i | (Z^T B_M)_i] = [F_i | G_i]
+    double *GAGM = nullptr;       // ld x 2ld: [V^T A V | V^T M V]
+    double *P3 = nullptr;         // ld x 3ld: G^T [F | G | Lambda G]
+    double *Ct = nullptr;         // dn x ld: coupling block of H
+    double *Dt = nullptr;         // ld x ld: trailing block of H
+    double *L1 = nullptr;         // ld x ld: Cholesky factor of the kept columns
+    int *perm = nullptr;          // ld: pivot order of the M-orthogonalisation
+    double *X = nullptr;          // (dn + ld) x ld: eigenvectors of H (inverse iteration)
+    double *HX = nullptr;         // (dn + ld) x ld scratch
+    double *Xr = nullptr;         // (dn + ld) x ld: Ritz vectors of H
+    double *theta = nullptr;      // ld: Ritz values
+    double *Xc = nullptr;         // dn x ld: coarse coefficients
+    double *Xv = nullptr;         // ld x ld: coefficients of V
+    int *status = nullptr;
+};
+void launch_small_products(hipStream_t s, const SmallWork &w);
+void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);
+void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, const double *theta_prev);
+void launch_recombine_coeffs(hipStream_t s, const SmallWork &w);
+void launch_theta_update(hipStream_t s, const SmallWork &w, double *theta_out, int final_level);
+
+}  // namespace amgeig

@@ -1,0 +1,580 @@
+// Sparse and vector-block kernels of one correction step (Algorithm 3.1) on
+// gfx950.  All blocks are row-major N x ld; a row group of ld/CPT lanes owns
+// one row (see device_common.h).  Sparse matrices are CSR with int32 indices.
+//
+//   k_residual      R = M U diag(theta) - A U (shared pattern of A and M, FP64)
+//                   and the column norms giving rho_j (eq. (3.1) residual)
+//   k_smooth_pre    V-cycle pre-smoothing from a zero guess fused with the
+//                   residual: r = b - A D^-1 b (l1-Jacobi, x1 = D^-1 b not stored)
+//   k_spmm          y = X x for a CSR X: restriction (P^T), prolongation (P),
+//                   FP64 transfer chains of the Rayleigh-Ritz step
+//   k_prolong_add   y = D^-1 b + P x_c (coarse-grid correction of x1)
+//   k_smooth_post   x = y + D^-1 (b - A y); on the correction level it writes
+//                   the FP64 block V = U + x
+//   k_dense_rows    C = A B for a small dense A (coarse solve, Z products)
+//   k_dual_spmm     W = [A V | M V] (FP64, shared pattern)
+//   k_gram          [V^T A V | V^T M V] by a two-phase deterministic reduction
+//   k_final         U = P Y + V X_v on the correction level (recombination)
+#include "device_common.h"
+#include "kernels.h"
+
+namespace amgeig {
+
+namespace {
+
+template <typename T, int C>
+__device__ __forceinline__ void fma_v(Vec<T, C> &acc, T w, const Vec<T, C> &x) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc.v[c] += w * x.v[c];
+}
+
+template <typename T, int C>
+__device__ __forceinline__ Vec<T, C> zero_v() {
+    Vec<T, C> z;
+#pragma unroll
+    for (int c = 0; c < C; ++c) z.v[c] = T(0);
+    return z;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- a1
+template <typename TO, int CPT>
+__global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ a,
+                                                  const double *__restrict__ m, const double *__restrict__ U,
+                                                  const double *__restrict__ theta, TO *__restrict__ R,
+                                                  double *__restrict__ part, unsigned *counter,
+                                                  double *__restrict__ rho, int q, double tol, int *status,
+                                                  int check) {
+    __shared__ double sm[256 * CPT * 2];
+    if (status[ST_CONVERGED]) return;
+    const int tpr = ld / CPT, rpw = kWave / tpr;
+    const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave, wpb = blockDim.x / kWave;
+    const int grp = lane / tpr, sub = lane - grp * tpr, c0 = sub * CPT;
+    const int64_t nb = gridDim.x, lb = xcd_block();
+    const int64_t waves = (n + rpw - 1) / rpw;
+    const int64_t w0 = waves * lb / nb, w1 = waves * (lb + 1) / nb;
+    double th[CPT], rr[CPT], mm[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        th[c] = grp < rpw ? theta[c0 + c] : 0.0;
+        rr[c] = mm[c] = 0.0;
+    }
+    for (int64_t w = w0 + wib; w < w1; w += wpb) {
+        const int64_t row = w * rpw + grp;
+        if (grp >= rpw || row >= n) continue;
+        Vec<double, CPT> au = zero_v<double, CPT>(), mu = zero_v<double, CPT>();
+        for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) {
+            const int64_t j = col[p];
+            const Vec<double, CPT> u = ldv<double, CPT>(U + j * ld + c0);
+            fma_v(au, a[p], u);
+            fma_v(mu, m[p], u);
+        }
+        Vec<TO, CPT> out;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const double r = th[c] * mu.v[c] - au.v[c];
+            out.v[c] = (TO)r;
+            rr[c] += r * r;
+            mm[c] += mu.v[c] * mu.v[c];
+        }
+        stv<TO, CPT>(R + row * ld + c0, out);
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        sm[(threadIdx.x * CPT + c) * 2 + 0] = rr[c];
+        sm[(threadIdx.x * CPT + c) * 2 + 1] = mm[c];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 2 * ld; idx += blockDim.x) {
+        const int cidx = idx >> 1, kind = idx & 1, s = cidx / CPT, c = cidx - s * CPT;
+        double acc = 0.0;
+        for (int w = 0; w < wpb; ++w)
+            for (int g = 0; g < rpw; ++g) acc += sm[(((w * kWave) + g * tpr + s) * CPT + c) * 2 + kind];
+        part[lb * 2 * ld + idx] = acc;
+    }
+    if (!last_block(counter)) return;
+    // last block: fixed-order sum over blocks (slot-strided, then over slots),
+    // then rho and the convergence test
+    __shared__ double fin[256];
+    {
+        const int w2 = 2 * ld, slots = (int)blockDim.x / w2;
+        const int slot = threadIdx.x / w2, cc = threadIdx.x - slot * w2;
+        double acc = 0.0;
+        if (slot < slots)
+            for (int64_t bb = slot; bb < nb; bb += slots) acc += part[bb * w2 + cc];
+        __syncthreads();
+        sm[threadIdx.x] = acc;
+        __syncthreads();
+        if ((int)threadIdx.x < w2) {
+            double t = 0.0;
+            for (int k = 0; k < slots; ++k) t += sm[k * w2 + threadIdx.x];
+            fin[threadIdx.x] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < ld) {
+        const int j = threadIdx.x;
+        const double r = sqrt(fin[2 * j]) / (fabs(theta[j]) * sqrt(fin[2 * j + 1]));
+        rho[j] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && check) {
+        double mx = 0.0;
+        for (int j = 0; j < q; ++j) mx = fmax(mx, rho[j]);
+        if (mx <= tol) status[ST_CONVERGED] = 1;
+    }
+}
+
+// ------------------------------------------------------------------- a2
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_smooth_pre(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ dinv, const T *__restrict__ b,
+                                                    T *__restrict__ r, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
+    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) {
+        const int64_t j = col[p];
+        fma_v(acc, -val[p] * dinv[j], ldv<T, CPT>(b + j * ld + c0));
+    }
+    stv<T, CPT>(r + rm.row * ld + c0, acc);
+}
+
+// ---------------------------------------------------------- a3, chains
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_spmm(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                              const int32_t *__restrict__ col, const T *__restrict__ val,
+                                              const T *__restrict__ x, T *__restrict__ y, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = zero_v<T, CPT>();
+    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) fma_v(acc, val[p], ldv<T, CPT>(x + (int64_t)col[p] * ld + c0));
+    stv<T, CPT>(y + rm.row * ld + c0, acc);
+}
+
+// ------------------------------------------------------------------- a5
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_prolong_add(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ xc, const T *__restrict__ dinv,
+                                                     const T *__restrict__ b, T *__restrict__ y, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
+    const T di = dinv[rm.row];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) acc.v[c] *= di;
+    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) fma_v(acc, val[p], ldv<T, CPT>(xc + (int64_t)col[p] * ld + c0));
+    stv<T, CPT>(y + rm.row * ld + c0, acc);
+}
+
+// ------------------------------------------------------------------- a6
+template <typename T, int CPT, bool FINAL>
+__global__ __launch_bounds__(256) void k_smooth_post(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ dinv, const T *__restrict__ b,
+                                                     const T *__restrict__ y, T *__restrict__ x,
+                                                     const double *__restrict__ U, double *__restrict__ V,
+                                                     const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
+    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p)
+        fma_v(acc, -val[p], ldv<T, CPT>(y + (int64_t)col[p] * ld + c0));
+    const Vec<T, CPT> yi = ldv<T, CPT>(y + rm.row * ld + c0);
+    const T di = dinv[rm.row];
+    if constexpr (FINAL) {
+        Vec<double, CPT> u = ldv<double, CPT>(U + rm.row * ld + c0);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) u.v[c] += (double)(yi.v[c] + di * acc.v[c]);
+        stv<double, CPT>(V + rm.row * ld + c0, u);
+    } else {
+        Vec<T, CPT> o;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) o.v[c] = yi.v[c] + di * acc.v[c];
+        stv<T, CPT>(x + rm.row * ld + c0, o);
+    }
+}
+
+// ------------------------------------------------------------ dense rows
+template <typename T, typename TA, int CPT>
+__global__ __launch_bounds__(256) void k_dense_rows(int64_t m, int64_t K, const TA *__restrict__ A, int64_t lda,
+                                                    int ld, const T *__restrict__ B, T *__restrict__ C,
+                                                    const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, m);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = zero_v<T, CPT>();
+    const TA *arow = A + rm.row * lda;
+    for (int64_t l = 0; l < K; ++l) fma_v(acc, (T)arow[l], ldv<T, CPT>(B + l * ld + c0));
+    stv<T, CPT>(C + rm.row * ld + c0, acc);
+}
+
+// ------------------------------------------------------------ small GEMM
+// C (m x n) = op(A) B with op(A) = A (m x K, row-major, lda) or A^T (A is
+// K x m).  16 x 16 output tile per block, K staged through LDS in chunks of 32.
+template <typename T, bool TA>
+__global__ __launch_bounds__(256) void k_gemm_small(int m, int n, int K, const T *__restrict__ A, int lda,
+                                                    const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
+                                                    const int *status) {
+    __shared__ T As[32][17];
+    __shared__ T Bs[32][17];
+    if (status[ST_CONVERGED]) return;
+    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+    T acc = T(0);
+    for (int l0 = 0; l0 < K; l0 += 32) {
+        for (int e = threadIdx.x; e < 32 * 16; e += blockDim.x) {
+            const int kk = e / 16, ii = e % 16, l = l0 + kk;
+            const int i = i0 + ii, j = j0 + ii;
+            T av = T(0), bv = T(0);
+            if (l < K) {
+                if (i < m) av = TA ? A[(int64_t)l * lda + i] : A[(int64_t)i * lda + l];
+                if (j < n) bv = B[(int64_t)l * ldb + j];
+            }
+            As[kk][ii] = av;
+            Bs[kk][ii] = bv;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) acc += As[kk][ty] * Bs[kk][tx];
+        __syncthreads();
+    }
+    const int i = i0 + ty, j = j0 + tx;
+    if (i < m && j < n) C[(int64_t)i * ldc + j] = acc;
+}
+
+// ------------------------------------------------------------------- a7
+template <int CPT>
+__global__ __launch_bounds__(256) void k_dual_spmm(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ a,
+                                                   const double *__restrict__ m, const double *__restrict__ V,
+                                                   double *__restrict__ W, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<double, CPT> wa = zero_v<double, CPT>(), wm = zero_v<double, CPT>();
+    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) {
+        const Vec<double, CPT> v = ldv<double, CPT>(V + (int64_t)col[p] * ld + c0);
+        fma_v(wa, a[p], v);
+        fma_v(wm, m[p], v);
+    }
+    stv<double, CPT>(W + rm.row * 2 * ld + c0, wa);
+    stv<double, CPT>(W + rm.row * 2 * ld + ld + c0, wm);
+}
+
+// Gram products G = V^T W (ld x 2ld), phase 1: each block sums its row range.
+// A thread owns a TI x TJ output tile; when tiles are fewer than threads, the
+// block's rows are split over `slices` groups of threads (fixed assignment).
+template <int TI, int TJ>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, int ld, const double *__restrict__ V,
+                                              const double *__restrict__ W, double *__restrict__ part,
+                                              const int *status) {
+    extern __shared__ double gsm[];
+    if (status[ST_CONVERGED]) return;
+    const int tj = 2 * ld / TJ, ntiles = (ld / TI) * tj;
+    const int slices = ntiles <= (int)blockDim.x ? (int)blockDim.x / ntiles : 1;
+    const int64_t nb = gridDim.x, lb = xcd_block();
+    const int64_t r0 = n * lb / nb, r1 = n * (lb + 1) / nb;
+    const int outsz = ld * 2 * ld;
+    const int nwork = ntiles * slices;
+    for (int item = threadIdx.x; item < nwork; item += blockDim.x) {
+        const int sl = item / ntiles, tt = item - sl * ntiles;
+        const int i0 = (tt / tj) * TI, j0 = (tt % tj) * TJ;
+        double acc[TI][TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = 0.0;
+        for (int64_t row = r0 + sl; row < r1; row += slices) {
+            const Vec<double, TI> v = ldv<double, TI>(V + row * ld + i0);
+            const Vec<double, TJ> w = ldv<double, TJ>(W + row * 2 * ld + j0);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) acc[i][j] += v.v[i] * w.v[j];
+        }
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) gsm[sl * outsz + (i0 + i) * 2 * ld + j0 + j] = acc[i][j];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < outsz; e += blockDim.x) {
+        double sum = 0.0;
+        for (int k = 0; k < slices; ++k) sum += gsm[k * outsz + e];
+        part[lb * outsz + e] = sum;
+    }
+}
+
+// Phase 2: G[e] = sum over blocks of part[b][e]; one wavefront per element,
+// lane l sums blocks l, l+64, ..., then a fixed butterfly over the lanes.
+__global__ __launch_bounds__(256) void k_gram_reduce(int64_t nb, int outsz, const double *__restrict__ part,
+                                                     double *__restrict__ G, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    const int e = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (e >= outsz) return;
+    double sum = 0.0;
+    for (int64_t b = lane; b < nb; b += kWave) sum += part[b * outsz + e];
+    for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+    if (lane == 0) G[e] = sum;
+}
+
+// ------------------------------------------------------------------- a11
+template <int CPT>
+__global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ col, const double *__restrict__ val,
+                                               const double *__restrict__ Y, const double *__restrict__ V,
+                                               const double *__restrict__ Xv, double *__restrict__ U,
+                                               const int *status) {
+    extern __shared__ double xv[];
+    if (status[ST_CONVERGED]) return;
+    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) xv[e] = Xv[e];
+    __syncthreads();
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<double, CPT> acc = zero_v<double, CPT>();
+    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) fma_v(acc, val[p], ldv<double, CPT>(Y + (int64_t)col[p] * ld + c0));
+    const double *vr = V + rm.row * ld;
+    for (int a = 0; a < ld; a += 4) {
+        const Vec<double, 4> v4 = ldv<double, 4>(vr + a);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) acc.v[c] += v4.v[t] * xv[(a + t) * ld + c0 + c];
+    }
+    stv<double, CPT>(U + rm.row * ld + c0, acc);
+}
+
+// ------------------------------------------------------------- init fills
+// SplitMix64 (Steele, Lea, Flood 2014): output k of the stream seeded with s is
+// mix(s + (k+1) * 0x9E3779B97F4A7C15); element (i, j) uses k = j * n + i.
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_fill_random(int64_t n, int ld, int qe, uint64_t seed, double *U) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ld) return;
+    const int64_t i = e / ld;
+    const int j = (int)(e - i * ld);
+    double v = 0.0;
+    if (j < qe) {
+        const uint64_t z = splitmix_out(seed, (uint64_t)j * (uint64_t)n + (uint64_t)i);
+        v = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+    }
+    U[e] = v;
+}
+
+// dst (rows x dcols, leading dim ldd) <- columns [0, cols) of src (leading dim
+// lds); columns [cols, dcols) are zeroed.
+__global__ void k_copy_cols(int64_t rows, int dcols, int64_t ldd, int cols, const double *src, int64_t lds,
+                            double *dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * dcols) return;
+    const int64_t i = e / dcols;
+    const int j = (int)(e - i * dcols);
+    dst[i * ldd + j] = j < cols ? src[i * lds + j] : 0.0;
+}
+
+__global__ void k_copy_f64(int64_t count, const double *src, double *dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) dst[e] = src[e];
+}
+
+__global__ void k_fill_i32(int count, int value, int *dst) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) dst[e] = value;
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+constexpr int kBlock = 256;
+
+inline int64_t row_blocks(int64_t n, int ld, int cpt) {
+    const int tpr = ld / cpt, rpw = kWave / tpr;
+    const int64_t waves = (n + rpw - 1) / rpw;
+    return (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
+}
+}  // namespace
+
+// Lanes per row = width / CPT must not exceed a wavefront: 2 columns per
+// lane up to width 128, 4 beyond.
+#define DISPATCH_CPT(width, ...)           \
+    do {                                   \
+        if ((width) <= 128) {              \
+            constexpr int CPT = 2;         \
+            __VA_ARGS__;                   \
+        } else {                           \
+            constexpr int CPT = 4;         \
+            __VA_ARGS__;                   \
+        }                                  \
+    } while (0)
+
+int64_t residual_blocks(int64_t n, int ld) {
+    const int64_t need = row_blocks(n, ld, ld <= 128 ? 2 : 4);
+    return need < 256 ? need : 256;
+}
+
+template <typename TO>
+void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                     const double *m, const double *U, const double *theta, TO *R, double *part,
+                     unsigned *counter, double *rho, int q, double tol, int *status, int check) {
+    const int64_t nb = residual_blocks(n, ld);
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
+                                        col, a, m, U, theta, R, part, counter, rho, q, tol, status, check));
+}
+
+template <typename T>
+void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                       const T *dinv, const T *b, T *r, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_smooth_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                                        0, s, n, ld, ptr, col, val, dinv, b, r, status));
+}
+
+template <typename T>
+void launch_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                 const T *x, T *y, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_spmm<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0, s,
+                                        n, ld, ptr, col, val, x, y, status));
+}
+
+template <typename T>
+void launch_prolong_add(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                        const T *xc, const T *dinv, const T *b, T *y, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_prolong_add<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                        dim3(kBlock), 0, s, n, ld, ptr, col, val, xc, dinv, b, y, status));
+}
+
+template <typename T>
+void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
+                        const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
+                        const int *status) {
+    if (final)
+        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_smooth_post<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                            dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
+    else
+        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_smooth_post<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                            dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
+}
+
+template <typename T, typename TA>
+void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
+                       const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_dense_rows<T, TA, CPT>), dim3((unsigned)row_blocks(m, ld, CPT)),
+                                        dim3(kBlock), 0, s, m, K, A, lda, ld, B, C, status));
+}
+
+void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                      const double *m, const double *V, double *W, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
+                                        s, n, ld, ptr, col, a, m, V, W, status));
+}
+
+int64_t gram_blocks(int64_t n, int ld) {
+    (void)ld;
+    int64_t nb = (n + 255) / 256;
+    return nb < 512 ? (nb < 1 ? 1 : nb) : 512;
+}
+
+void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
+                 const int *status) {
+    const int64_t nb = gram_blocks(n, ld);
+    const int outsz = 2 * ld * ld;
+    if (ld <= 16) {
+        const int ntiles = (ld / 2) * (2 * ld / 2);
+        const int slices = ntiles <= kBlock ? kBlock / ntiles : 1;
+        const size_t lds = (size_t)slices * outsz * sizeof(double);
+        hipLaunchKernelGGL((k_gram<2, 2>), dim3((unsigned)nb), dim3(kBlock), lds, s, n, ld, V, W, part, status);
+    } else {
+        const int ntiles = (ld / 4) * (2 * ld / 4);
+        const int slices = ntiles <= kBlock ? kBlock / ntiles : 1;
+        const size_t lds = (size_t)slices * outsz * sizeof(double);
+        hipLaunchKernelGGL((k_gram<4, 4>), dim3((unsigned)nb), dim3(kBlock), lds, s, n, ld, V, W, part, status);
+    }
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, part, G,
+                       status);
+}
+
+void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
+                  const double *Y, const double *V, const double *Xv, double *U, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_final<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                                        (size_t)ld * ld * sizeof(double), s, n, ld, ptr, col, val, Y, V, Xv, U,
+                                        status));
+}
+
+template <typename T>
+void launch_gemm_small(hipStream_t s, bool transA, int m, int n, int K, const T *A, int lda, const T *B, int ldb,
+                       T *C, int ldc, const int *status) {
+    const dim3 g((m + 15) / 16, (n + 15) / 16);
+    if (transA)
+        hipLaunchKernelGGL((k_gemm_small<T, true>), g, dim3(256), 0, s, m, n, K, A, lda, B, ldb, C, ldc, status);
+    else
+        hipLaunchKernelGGL((k_gemm_small<T, false>), g, dim3(256), 0, s, m, n, K, A, lda, B, ldb, C, ldc, status);
+}
+template void launch_gemm_small<float>(hipStream_t, bool, int, int, int, const float *, int, const float *, int,
+                                       float *, int, const int *);
+template void launch_gemm_small<double>(hipStream_t, bool, int, int, int, const double *, int, const double *, int,
+                                        double *, int, const int *);
+
+void launch_fill_random(hipStream_t s, int64_t n, int ld, int qe, uint64_t seed, double *U) {
+    const int64_t tot = n * ld;
+    hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, ld, qe, seed, U);
+}
+
+void launch_copy_cols(hipStream_t s, int64_t rows, int dcols, int64_t ldd, int cols, const double *src,
+                      int64_t lds, double *dst) {
+    const int64_t tot = rows * dcols;
+    if (tot == 0) return;
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, rows, dcols, ldd, cols, src,
+                       lds, dst);
+}
+
+void launch_copy_f64(hipStream_t s, int64_t count, const double *src, double *dst) {
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, src, dst);
+}
+
+void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, value, dst);
+}
+
+#define INST(T)                                                                                                      \
+    template void launch_smooth_pre<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,       \
+                                       const T *, const T *, T *, const int *);                                      \
+    template void launch_spmm<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *, const T *,  \
+                                 T *, const int *);                                                                  \
+    template void launch_prolong_add<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,      \
+                                        const T *, const T *, const T *, T *, const int *);                          \
+    template void launch_smooth_post<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *,           \
+                                        const T *, const T *, const T *, const T *, T *, const double *, double *,   \
+                                        const int *);                                                                \
+    template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
+                                     const double *, const double *, const double *, T *, double *, unsigned *,      \
+                                     double *, int, double, int *, int);
+INST(float)
+INST(double)
+#undef INST
+template void launch_dense_rows<float, float>(hipStream_t, int64_t, int64_t, const float *, int64_t, int,
+                                              const float *, float *, const int *);
+template void launch_dense_rows<double, double>(hipStream_t, int64_t, int64_t, const double *, int64_t, int,
+                                                const double *, double *, const int *);
+
+}  // namespace amgeig

@@ -1,0 +1,107 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+its host setup (an implementation independent of the oracle's) builds the same
+hierarchy.  No device call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_1503_08462_amd as ae
+from oracle import Oracle
+from workloads import configs
+from tests.helpers import mats
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "amg_eig.h")).read()
+    declared = set(re.findall(r"\b(amg_eig_[a-z_]+)\s*\(", hdr))
+    assert declared == set(ae.EXPORTED)
+    lib = ctypes.CDLL(ae.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("make,cm", [
+    (lambda: configs.config(0), 130),
+    (lambda: configs.lshape(24, q=10, jitter_seed=2), 300),
+    (lambda: configs.cube(12, q=8), 100),
+    (lambda: configs.oscillator(40, q=10), 150),
+    (lambda: configs.quadrants(16, q=6), 100),
+])
+def test_setup_matches_oracle(make, cm):
+    p = make()
+    A, M = mats(p)
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(coarse_max=cm, qe=12))
+    info = ctx.info()
+    o = Oracle(A, M, q=p["q"], qe=12, coarse_max=cm, coarse_min=26)
+    assert info["dims"].tolist() == [L.n for L in o.levels]
+    for l in range(info["levels"] - 1):
+        assert np.array_equal(ctx.splitting(l), o.levels[l].cf)
+        rp, ci, pv = ctx.prolongation(l)
+        P = sp.csr_matrix((pv, ci, rp), shape=(info["dims"][l], info["dims"][l + 1]))
+        assert abs(P - o.levels[l].P).max() <= 1e-14
+        rp, ci, a, m = ctx.level_matrix(l + 1)
+        Al, Ml = sp.csr_matrix((a, ci, rp)), sp.csr_matrix((m, ci, rp))
+        assert abs(Al - o.levels[l + 1].A).max() <= 1e-13 * abs(o.levels[l + 1].A).max()
+        assert abs(Ml - o.levels[l + 1].M).max() <= 1e-13 * abs(o.levels[l + 1].M).max()
+    lam = ctx.coarse_eigenvalues()
+    # dense symmetric eigensolvers are backward stable: errors of order eps * ||A_n||
+    assert np.abs(lam - o.lam_n).max() <= 1e-12 * np.abs(o.lam_n).max()
+    ctx.close()
+
+
+def test_guard_rule_and_width_rounding():
+    """Block width = guard rule on the coarsest eigenvalues (no block ending
+    inside a relative gap < 1e-2), rounded up to a multiple of 4."""
+    from oracle import guard_count
+    for p, q in ((configs.square(32, q=2), 2), (configs.oscillator(64, q=6), 6), (configs.cube(12, q=5), 5)):
+        ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], q, ae.defaults(coarse_max=200))
+        lam = ctx.coarse_eigenvalues()
+        want = guard_count(lam, q)
+        assert ctx.info()["qe"] == (want + 3) // 4 * 4
+        ctx.close()
+
+
+@pytest.mark.parametrize("mutate,code", [
+    ("unsorted", ae.EINVAL), ("range", ae.EINVAL), ("negdiag", ae.ENOTSPD), ("rowptr", ae.EINVAL),
+    ("q0", ae.EINVAL), ("toowide", ae.EINVAL), ("nan", ae.EINVAL),
+])
+def test_validation_errors(mutate, code):
+    p = configs.square(8, q=2)
+    rp, col, a, m = p["rowptr"].copy(), p["col"].copy(), p["A"].copy(), p["M"].copy()
+    q = 2
+    opts = ae.defaults(coarse_max=20, coarse_min=8)
+    if mutate == "unsorted":
+        col[1], col[2] = col[2], col[1]
+    elif mutate == "range":
+        col[3] = 10 ** 6
+    elif mutate == "negdiag":
+        a[0] = -1.0
+    elif mutate == "rowptr":
+        rp[5] = rp[4] - 1
+    elif mutate == "q0":
+        q = 0
+    elif mutate == "toowide":
+        opts.qe = 200
+    elif mutate == "nan":
+        m[7] = np.nan
+    with pytest.raises(ae.AmgEigError) as ei:
+        ae.Context(rp, col, a, m, q, opts)
+    assert ei.value.code == code
+
+
+def test_calls_out_of_order_are_rejected_on_the_host():
+    p = configs.square(8, q=2)
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], 2, ae.defaults(coarse_max=20, coarse_min=8))
+    with pytest.raises(ae.AmgEigError) as ei:
+        ctx.correct(1)
+    assert ei.value.code == ae.ESTATE
+    with pytest.raises(ae.AmgEigError) as ei:
+        ctx.init()
+    assert ei.value.code == ae.ESTATE
+    ctx.close()

@@ -96,5 +96,39 @@ def test_rs_first_pass_measure_updates_on_asymmetric_strength():
     for i, js in edges.items():
         for j in js:
             A[i, j] = -1.0
-    cf, _ = amg.rs_splitting(sp.csr_matrix(A), 0.25)
+    cf, _ = amg.rs_splitting(sp.csr_matrix(A), 0.25, second_pass=False)
     assert np.flatnonzero(cf).tolist() == [0, 5, 6]
+
+
+def _strong(n, deps):
+    rows = [i for i, js in deps.items() for _ in js]
+    cols = [j for i, js in deps.items() for j in js]
+    S = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    S.sort_indices()
+    return S
+
+
+def test_rs_second_pass_hand_traced():
+    """F point 1 depends on C point 0 and on F point 2, which depends only on
+    1 and C point 3: no common strong C point, so 2 becomes C.  In the second
+    case F point 1 has two such F neighbours (2 and 4): 1 itself becomes C."""
+    from oracle import native
+    S = _strong(5, {1: [0, 2], 2: [1, 3]})
+    cf = native.rs_second_pass(S, np.array([1, 0, 0, 1, 0]))
+    assert cf.tolist() == [1, 0, 1, 1, 0]
+    S = _strong(6, {1: [0, 2, 4], 2: [1, 3], 4: [1, 5]})
+    cf = native.rs_second_pass(S, np.array([1, 0, 0, 1, 0, 1]))
+    assert cf.tolist() == [1, 1, 0, 1, 0, 1]
+
+
+def test_second_pass_gives_common_c_points():
+    """After coarsening, every strongly coupled F-F pair shares a strong C point."""
+    for p in (configs.lshape(20, jitter_seed=2), configs.cube(8)):
+        A, _ = mats(p)
+        cf, S = amg.rs_splitting(A, 0.25)
+        Sl = S.tolil().rows
+        for i in np.flatnonzero(cf == 0):
+            Ci = {k for k in Sl[i] if cf[k] == 1}
+            for j in Sl[i]:
+                if cf[j] == 0:
+                    assert Ci & set(Sl[j]), (i, j)
