@@ -161,6 +161,7 @@ void plan(amg_eig_ctx *c, char *base) {
     w.Xc = cv.take<double>((size_t)dn * ld);
     w.Xv = cv.take<double>((size_t)ld * ld);
     w.status = c->status;
+    w.diag = cv.take<int>(5 * kMaxWidth + 8);
     c->need = cv.off + 256;
 }
 
@@ -488,6 +489,7 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     int rc = c->mixed ? upload_levels<float>(c) : upload_levels<double>(c);
     if (rc) return rc;
     launch_fill_i32(c->stream, ST_COUNT, 0, c->status);
+    launch_fill_i32(c->stream, 5 * kMaxWidth + 8, 0, c->sw.diag);
     std::vector<unsigned> zero(16, 0u);
     rc = upload_vec(c, c->counters, zero);
     if (rc) return rc;
@@ -709,5 +711,15 @@ const char *amg_eig_strerror(int code) {
 }
 
 const char *amg_eig_last_error(const amg_eig_ctx *c) { return c ? c->err.c_str() : ""; }
+
+// Solver statistics of the small eigensolver since bind (not part of the
+// public header): per eigenvalue index the inertia counts, warm brackets
+// used and calls, then the Jacobi sweeps and phase times.  out has 5 * 80 + 8 ints.
+int amg_eig_internal_diag(amg_eig_ctx *c, int *out) {
+    if (!c || !out || !c->bound) return AMG_EIG_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(out, c->sw.diag, (5 * kMaxWidth + 8) * sizeof(int), hipMemcpyDeviceToHost));
+    return AMG_EIG_OK;
+}
 
 }  // extern "C"

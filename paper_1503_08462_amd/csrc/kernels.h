@@ -74,6 +74,7 @@ struct SmallWork {
     double *Xc = nullptr;         // dn x ld: coarse coefficients
     double *Xv = nullptr;         // ld x ld: coefficients of V
     int *status = nullptr;
+    int *diag = nullptr;          // 4 * kMaxWidth + 8 counters (solver statistics)
 };
 void launch_small_products(hipStream_t s, const SmallWork &w);
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);

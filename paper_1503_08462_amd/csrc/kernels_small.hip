@@ -34,14 +34,10 @@ constexpr int kB = 256;  // threads per block of the small kernels
 // ipiv[p] = kp >= 0: 1x1 pivot, rows p and kp interchanged;
 // ipiv[p] = ipiv[p+1] = -(kp+1): 2x2 pivot, rows p+1 and kp interchanged.
 // Returns the number of negative eigenvalues of S (Sylvester's law).
-__device__ int bk_factor(double *S, int r, int ls, int *ipiv, double *logabs) {
+__device__ int bk_factor(double *S, int r, int ls, int *ipiv, double *mult) {
     __shared__ int s_kp, s_size, s_neg;
-    __shared__ double s_log;
     const double alpha = 0.6403882032022076;  // (1 + sqrt(17)) / 8
-    if (threadIdx.x == 0) {
-        s_neg = 0;
-        s_log = 0.0;
-    }
+    if (threadIdx.x == 0) s_neg = 0;
     __syncthreads();
     int p = 0;
     while (p < r) {
@@ -106,20 +102,31 @@ __device__ int bk_factor(double *S, int r, int ls, int *ipiv, double *logabs) {
             __syncthreads();
         }
         if (size == 1) {
+            // column p and its multipliers l_i = S[i][p] / d are staged in
+            // mult[] so that the trailing update and the store of the
+            // multipliers into column p share one pass
             const double d = S[p * ls + p];
             const double dinv = d != 0.0 ? 1.0 / d : 0.0;
             if (threadIdx.x == 0) {
                 ipiv[p] = kp;
                 if (d < 0.0) s_neg += 1;
-                s_log += log(fabs(d) + 1e-300);
             }
-            const int m = r - p - 1;
-            for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-                const int i = p + 1 + e / m, j = p + 1 + e % m;
-                S[i * ls + j] -= S[i * ls + p] * S[j * ls + p] * dinv;
+            for (int i = p + 1 + threadIdx.x; i < r; i += blockDim.x) {
+                const double c1 = S[i * ls + p];
+                mult[4 * i] = c1 * dinv;
+                mult[4 * i + 2] = c1;
             }
             __syncthreads();
-            for (int i = p + 1 + threadIdx.x; i < r; i += blockDim.x) S[i * ls + p] *= dinv;
+            const int m = r - p - 1;
+            for (int e = threadIdx.x; e < m * (m + 1); e += blockDim.x) {
+                const int i = p + 1 + e / (m + 1), jj = e % (m + 1);
+                if (jj == m) {
+                    S[i * ls + p] = mult[4 * i];
+                } else {
+                    const int j = p + 1 + jj;
+                    S[i * ls + j] -= mult[4 * i] * mult[4 * j + 2];
+                }
+            }
             __syncthreads();
             p += 1;
         } else {
@@ -128,28 +135,35 @@ __device__ int bk_factor(double *S, int r, int ls, int *ipiv, double *logabs) {
             if (threadIdx.x == 0) {
                 ipiv[p] = ipiv[p + 1] = -(kp + 1);
                 s_neg += det < 0.0 ? 1 : (a + c < 0.0 ? 2 : 0);
-                s_log += log(fabs(det) + 1e-300);
             }
             const double id = 1.0 / det;
-            const int m = r - p - 2;
-            for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-                const int i = p + 2 + e / m, j = p + 2 + e % m;
-                const double c1 = S[i * ls + p], c2 = S[i * ls + p + 1];
-                const double l1 = (c1 * c - c2 * b) * id, l2 = (c2 * a - c1 * b) * id;
-                S[i * ls + j] -= l1 * S[j * ls + p] + l2 * S[j * ls + p + 1];
-            }
-            __syncthreads();
+            // l_i = [S[i][p], S[i][p+1]] D^-1 and the two column entries
+            // themselves, staged in mult[4i .. 4i+3]
             for (int i = p + 2 + threadIdx.x; i < r; i += blockDim.x) {
                 const double c1 = S[i * ls + p], c2 = S[i * ls + p + 1];
-                S[i * ls + p] = (c1 * c - c2 * b) * id;
-                S[i * ls + p + 1] = (c2 * a - c1 * b) * id;
+                mult[4 * i] = (c1 * c - c2 * b) * id;
+                mult[4 * i + 1] = (c2 * a - c1 * b) * id;
+                mult[4 * i + 2] = c1;
+                mult[4 * i + 3] = c2;
+            }
+            __syncthreads();
+            const int m = r - p - 2;
+            for (int e = threadIdx.x; e < m * (m + 1); e += blockDim.x) {
+                const int i = p + 2 + e / (m + 1), jj = e % (m + 1);
+                const double l1 = mult[4 * i], l2 = mult[4 * i + 1];
+                if (jj == m) {
+                    S[i * ls + p] = l1;
+                    S[i * ls + p + 1] = l2;
+                } else {
+                    const int j = p + 2 + jj;
+                    S[i * ls + j] -= l1 * mult[4 * j + 2] + l2 * mult[4 * j + 3];
+                }
             }
             __syncthreads();
             p += 2;
         }
     }
     __syncthreads();
-    if (logabs) *logabs = s_log;
     return s_neg;
 }
 
@@ -204,38 +218,36 @@ __device__ void bk_solve(const double *S, int r, int ls, const int *ipiv, double
         }
     }
     __syncthreads();
-    // L^T w = y, blocks from the last one backwards: once w of a block is known,
-    // remove its contribution from the rows above.
-    int starts[kMaxWidth];
-    int nblk = 0;
-    for (int p = 0; p < r;) {
-        starts[nblk++] = p;
-        p += ipiv[p] >= 0 ? 1 : 2;
-    }
-    for (int bidx = nblk - 1; bidx >= 0; --bidx) {
-        const int p = starts[bidx];
-        if (ipiv[p] >= 0) {
+    // L^T w = y, blocks from the last one backwards (a 2x2 block has both
+    // ipiv entries negative): once w of a block is known, remove its
+    // contribution from the rows above.
+    for (int p = r - 1; p >= 0;) {
+        if (ipiv[p] < 0) {
+            const int p0 = p - 1;
+            const double w0 = f[p0], w1 = f[p];
+            for (int i = threadIdx.x; i < p0; i += blockDim.x) f[i] -= S[p0 * ls + i] * w0 + S[p * ls + i] * w1;
+            p -= 2;
+        } else {
             const double wp = f[p];
             for (int i = threadIdx.x; i < p; i += blockDim.x) f[i] -= S[p * ls + i] * wp;
-        } else {
-            const double w0 = f[p], w1 = f[p + 1];
-            for (int i = threadIdx.x; i < p; i += blockDim.x) f[i] -= S[p * ls + i] * w0 + S[(p + 1) * ls + i] * w1;
+            p -= 1;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        for (int bidx = nblk - 1; bidx >= 0; --bidx) {
-            const int p = starts[bidx];
-            if (ipiv[p] >= 0) {
+    if (threadIdx.x == 0) {  // undo the interchanges in reverse order
+        for (int p = r - 1; p >= 0;) {
+            if (ipiv[p] < 0) {
+                const int kp = -ipiv[p] - 1;
+                const double t = f[p];
+                f[p] = f[kp];
+                f[kp] = t;
+                p -= 2;
+            } else {
                 const int kp = ipiv[p];
                 const double t = f[p];
                 f[p] = f[kp];
                 f[kp] = t;
-            } else {
-                const int kp = -ipiv[p] - 1;
-                const double t = f[p + 1];
-                f[p + 1] = f[kp];
-                f[kp] = t;
+                p -= 1;
             }
         }
     }
@@ -414,17 +426,18 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol) {
 // --------------------------------------------------- eigenvalues (a10)
 // One workgroup per wanted eigenvalue k (0-based: the (k+1)-th smallest).
 // nu(s) = #{lambda_i < s} + #neg(S(s)) counts the eigenvalues of H below s
-// (Sylvester), and sign det(H - s) = (-1)^nu(s) with
-// log|det(H - s)| = sum_i log|lambda_i - s| + log|det S(s)|.
-// The eigenvalue is bracketed (warm bracket around the previous step's Ritz
-// value when it validates, else Gershgorin and the interlacing bound
-// mu_{k+1} <= lambda_{k+1}), isolated by bisection, then refined by
-// regula falsi with the Illinois modification on det(H - s).  Two steps of
-// inverse iteration at the final shift give column k of X.
-struct CountOut {
-    int nu;
-    double logdet;
-};
+// (Sylvester).  The eigenvalue is bracketed (a warm bracket around the
+// previous step's Ritz value when two counts validate it, else Gershgorin and
+// the interlacing bound mu_{k+1} <= lambda_{k+1}) and isolated by bisection.
+// Inside the isolating bracket, Rayleigh-quotient iteration with the exact
+// Schur-complement solve (H - s)^-1 refines the eigenvector: every
+// factorisation is also a count and narrows the bracket, and an iterate is
+// accepted once its Rayleigh quotient rho lies in the bracket with
+// ||H x - rho x|| <= 1e-10 |rho|, which pins it to the bracketed eigenvalue.
+// A shift leaving the bracket falls back to the bracket midpoint.
+
+constexpr int kPairGroup = 8;  // pairs of S accumulated per work item
+constexpr int kMaxItems = 4;   // work items per thread (npairs <= 4 * 256 * 8)
 
 __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
                                                       int ct_in_lds) {
@@ -433,114 +446,293 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
     const int ld = w.ld, dn = w.dn, k = blockIdx.x;
     const int r = w.status[ST_RANK];
     const int ls = r + 1;
+    const int nthr = blockDim.x;
+    const int npairs = r * (r + 1) / 2;
+    const int ngroups = (npairs + kPairGroup - 1) / kPairGroup;
+    const int slices = ngroups >= nthr ? 1 : nthr / (ngroups > 0 ? ngroups : 1);
     double *S = sm;                      // r x ls
-    double *cch = S + r * ls;            // C~ in LDS (dn x r) or a 64-row chunk
+    double *cch = S + r * ls;            // C~ (dn x r) in LDS, or a 64-row chunk
     const int chunk_rows = ct_in_lds ? dn : 64;
     double *wdn = cch + chunk_rows * r;  // dn weights 1 / (lambda_i - sigma)
-    double *vec = wdn + dn;              // dn + r
-    double *fz = vec + dn + r;           // r
+    double *vec = wdn + dn;              // dn + r : current vector
+    double *hx = vec + dn + r;           // dn + r : H x
+    double *fz = hx + dn + r;            // r
+    double *lam = fz + r;                // dn
+    double *dt = lam + dn;               // r x r
+    double *mult = dt + r * r;           // 4 r: multipliers and pivot columns of the factorisation
+    double *part = mult + 4 * r;         // slices x npairs partial sums (also reused for reductions)
     __shared__ int ipiv[kMaxWidth];
     __shared__ double red[kB];
-    __shared__ double s_log;
-    const int npairs = r * (r + 1) / 2;
-    const int nthr = blockDim.x;
-    if (ct_in_lds) {
+    const uint64_t t_start_g = wall_clock64();
+    if (ct_in_lds)
         for (int e = threadIdx.x; e < dn * r; e += nthr) cch[e] = w.Ct[(int64_t)(e / r) * ld + e % r];
-        __syncthreads();
-    }
+    for (int i = threadIdx.x; i < dn; i += nthr) lam[i] = w.lam[i];
+    for (int e = threadIdx.x; e < r * r; e += nthr) dt[e] = w.Dt[(e / r) * ld + e % r];
+    __syncthreads();
 
-    auto count = [&](double sigma) -> CountOut {
-        // #{lambda_i < sigma} (lam ascending), per thread
-        int lo_i = 0, hi_i = dn;
+    int ncount = 0;
+    __shared__ unsigned long long tim[4];  // S formation, BK, solve, Rayleigh (thread 0)
+    if (threadIdx.x == 0) tim[0] = tim[1] = tim[2] = tim[3] = 0;
+    // ---- factorisation of H - sigma through S(sigma); returns nu(sigma)
+    auto factor = [&](double sigma) -> int {
+        ++ncount;
+        const uint64_t f0 = wall_clock64();
+        int lo_i = 0, hi_i = dn;  // #{lambda_i < sigma}, lam ascending
         while (lo_i < hi_i) {
             const int mid = (lo_i + hi_i) / 2;
-            if (w.lam[mid] < sigma) lo_i = mid + 1; else hi_i = mid;
+            if (lam[mid] < sigma) lo_i = mid + 1; else hi_i = mid;
         }
         const int nlow = lo_i;
-        double lsum = 0.0;
         __syncthreads();
         for (int i = threadIdx.x; i < dn; i += nthr) {
-            double den = w.lam[i] - sigma;
+            double den = lam[i] - sigma;
             if (den == 0.0) den = 1e-300;
-            lsum += log(fabs(den));
             wdn[i] = 1.0 / den;
         }
-        __syncthreads();
-        double acc[(kMaxWidth * (kMaxWidth + 1) / 2 + 63) / 64];
-        const int per = (npairs + nthr - 1) / nthr;
-        for (int t = 0; t < per; ++t) acc[t] = 0.0;
+        // S partial sums: work item = (pair group g, row slice sl); a thread owns
+        // at most kMaxItems items, kept in registers across the row chunks
+        double acc[kMaxItems][kPairGroup];
+        int pa[kMaxItems][kPairGroup], pb[kMaxItems][kPairGroup];
+        const int nitems = ngroups * slices;
+#pragma unroll
+        for (int j = 0; j < kMaxItems; ++j) {
+            const int item = threadIdx.x + j * nthr;
+            const int g = item < nitems ? item % ngroups : 0;
+#pragma unroll
+            for (int t = 0; t < kPairGroup; ++t) {
+                int pr = g * kPairGroup + t;
+                acc[j][t] = 0.0;
+                if (pr >= npairs) pr = npairs > 0 ? npairs - 1 : 0;  // padded pairs: computed, never stored
+                int aa = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+                while (aa * (aa + 1) / 2 > pr) --aa;
+                while ((aa + 1) * (aa + 2) / 2 <= pr) ++aa;
+                pa[j][t] = aa;
+                pb[j][t] = pr - aa * (aa + 1) / 2;
+            }
+        }
+        __syncthreads();  // wdn ready
         for (int i0 = 0; i0 < dn; i0 += chunk_rows) {
             const int lim = dn - i0 < chunk_rows ? dn - i0 : chunk_rows;
-            const double *ct = ct_in_lds ? cch + (int64_t)i0 * r : cch;
             if (!ct_in_lds) {
                 __syncthreads();
                 for (int e = threadIdx.x; e < lim * r; e += nthr) cch[e] = w.Ct[(int64_t)(i0 + e / r) * ld + e % r];
                 __syncthreads();
             }
-            for (int t = 0; t < per; ++t) {
-                const int pr = threadIdx.x + t * nthr;
-                if (pr >= npairs) break;
-                int a = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
-                while (a * (a + 1) / 2 > pr) --a;
-                while ((a + 1) * (a + 2) / 2 <= pr) ++a;
-                const int b = pr - a * (a + 1) / 2;
-                double sacc = 0.0;
-                const double *wi = wdn + i0;
-                for (int ii = 0; ii < lim; ++ii) sacc += ct[ii * r + a] * ct[ii * r + b] * wi[ii];
-                acc[t] += sacc;
+            const double *ct = ct_in_lds ? cch + (int64_t)i0 * r : cch;
+#pragma unroll
+            for (int j = 0; j < kMaxItems; ++j) {
+                const int item = threadIdx.x + j * nthr;
+                if (item >= nitems) continue;
+                const int sl = item / ngroups;
+                for (int ii = sl; ii < lim; ii += slices) {
+                    const double wi = wdn[i0 + ii];
+                    const double *row = ct + ii * r;
+#pragma unroll
+                    for (int t = 0; t < kPairGroup; ++t) acc[j][t] += row[pa[j][t]] * row[pb[j][t]] * wi;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxItems; ++j) {
+            const int item = threadIdx.x + j * nthr;
+            if (item >= nitems) continue;
+            const int g = item % ngroups, sl = item / ngroups;
+            for (int t = 0; t < kPairGroup; ++t) {
+                const int pr = g * kPairGroup + t;
+                if (pr < npairs) part[sl * npairs + pr] = acc[j][t];
             }
         }
         __syncthreads();
-        for (int t = 0; t < per; ++t) {
-            const int pr = threadIdx.x + t * nthr;
-            if (pr >= npairs) break;
-            int a = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
-            while (a * (a + 1) / 2 > pr) --a;
-            while ((a + 1) * (a + 2) / 2 <= pr) ++a;
-            const int b = pr - a * (a + 1) / 2;
-            const double v = w.Dt[a * ld + b] - (a == b ? sigma : 0.0) - acc[t];
-            S[a * ls + b] = v;
-            S[b * ls + a] = v;
+        for (int pr = threadIdx.x; pr < npairs; pr += nthr) {
+            double v = 0.0;
+            for (int sl = 0; sl < slices; ++sl) v += part[sl * npairs + pr];
+            int aa = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+            while (aa * (aa + 1) / 2 > pr) --aa;
+            while ((aa + 1) * (aa + 2) / 2 <= pr) ++aa;
+            const int bb = pr - aa * (aa + 1) / 2;
+            v = dt[aa * r + bb] - (aa == bb ? sigma : 0.0) - v;
+            S[aa * ls + bb] = v;
+            S[bb * ls + aa] = v;
         }
-        lsum = block_sum(lsum, red);
-        const int neg = bk_factor(S, r, ls, ipiv, &s_log);
-        CountOut o;
-        o.nu = nlow + neg;
-        o.logdet = lsum + s_log;
         __syncthreads();
-        return o;
+        const uint64_t f1 = wall_clock64();
+        const int neg = bk_factor(S, r, ls, ipiv, mult);
+        if (threadIdx.x == 0) {
+            const uint64_t f2 = wall_clock64();
+            tim[0] += f1 - f0;
+            tim[1] += f2 - f1;
+        }
+        return nlow + neg;
     };
 
-    // ---- bracket
-    double lo, hi;
-    CountOut clo, chi;
-    bool have = false;
-    const double tp = theta_prev[k];
-    if (w.status[ST_WARM] && tp > 0.0) {
-        for (double delta = 1e-4; delta < 0.2 && !have; delta *= 100.0) {
-            const double l0 = tp * (1.0 - delta), h0 = fmin(tp * (1.0 + delta), w.lam[k] * (1.0 + 1e-14) + 1e-300);
-            if (!(l0 < h0)) break;
-            CountOut a0 = count(l0);
-            if (a0.nu > k) continue;
-            CountOut b0 = count(h0);
-            if (b0.nu < k + 1) continue;
-            lo = l0; hi = h0; clo = a0; chi = b0;
-            have = true;
+    // ---- sum over the dn coarse rows of C~_{i a} u_i, for all a (slices + LDS)
+    auto ct_t_times = [&](const double *u, double *out) {
+        const int sl2 = nthr / (r > 0 ? r : 1) > 0 ? nthr / (r > 0 ? r : 1) : 1;
+        for (int item = threadIdx.x; item < r * sl2; item += nthr) {
+            const int a2 = item % r, sl = item / r;
+            double s0 = 0.0, s1 = 0.0;
+            int i = sl;
+            for (; i + sl2 < dn; i += 2 * sl2) {
+                const double *c0 = ct_in_lds ? cch + (int64_t)i * r : w.Ct + (int64_t)i * ld;
+                const double *c1 = ct_in_lds ? cch + (int64_t)(i + sl2) * r : w.Ct + (int64_t)(i + sl2) * ld;
+                s0 += c0[a2] * u[i];
+                s1 += c1[a2] * u[i + sl2];
+            }
+            if (i < dn) s0 += (ct_in_lds ? cch[(int64_t)i * r + a2] : w.Ct[(int64_t)i * ld + a2]) * u[i];
+            part[sl * r + a2] = s0 + s1;
         }
+        __syncthreads();
+        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) {
+            double v = 0.0;
+            for (int sl = 0; sl < sl2; ++sl) v += part[sl * r + a2];
+            out[a2] = v;
+        }
+        __syncthreads();
+    };
+    auto ct_row = [&](int i, int a2) -> double { return ct_in_lds ? cch[(int64_t)i * r + a2] : w.Ct[(int64_t)i * ld + a2]; };
+
+    // ---- x <- (H - sigma)^-1 x for the factorisation in S, ipiv, wdn
+    auto solve = [&](double *x) {
+        for (int i = threadIdx.x; i < dn; i += nthr) x[i] *= wdn[i];  // t = (Lambda - sigma)^-1 b_y
+        __syncthreads();
+        ct_t_times(x, fz);
+        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) fz[a2] = x[dn + a2] - fz[a2];
+        __syncthreads();
+        bk_solve(S, r, ls, ipiv, fz);
+        for (int i = threadIdx.x; i < dn; i += nthr) {
+            double s2 = 0.0;
+            for (int a2 = 0; a2 < r; ++a2) s2 += ct_row(i, a2) * fz[a2];
+            x[i] -= s2 * wdn[i];
+        }
+        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) x[dn + a2] = fz[a2];
+        __syncthreads();
+    };
+    auto normalise = [&](double *x) {
+        double s2 = 0.0;
+        for (int i = threadIdx.x; i < dn + r; i += nthr) s2 += x[i] * x[i];
+        s2 = block_sum(s2, red);
+        const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+        for (int i = threadIdx.x; i < dn + r; i += nthr) x[i] *= inv;
+        __syncthreads();
+    };
+    // rho = x^T H x (x normalised) and ||H x - rho x||
+    auto rayleigh = [&](const double *x, double &rho, double &res) {
+        ct_t_times(x, fz);  // C~^T y
+        for (int i = threadIdx.x; i < dn; i += nthr) {
+            double s2 = lam[i] * x[i];
+            for (int a2 = 0; a2 < r; ++a2) s2 += ct_row(i, a2) * x[dn + a2];
+            hx[i] = s2;
+        }
+        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) {
+            double s2 = fz[a2];
+            for (int b2 = 0; b2 < r; ++b2) s2 += dt[a2 * r + b2] * x[dn + b2];
+            hx[dn + a2] = s2;
+        }
+        __syncthreads();
+        double q = 0.0;
+        for (int i = threadIdx.x; i < dn + r; i += nthr) q += x[i] * hx[i];
+        rho = block_sum(q, red);
+        double e2 = 0.0;
+        for (int i = threadIdx.x; i < dn + r; i += nthr) {
+            const double d = hx[i] - rho * x[i];
+            e2 += d * d;
+        }
+        res = sqrt(block_sum(e2, red));
+    };
+
+    // ---- warm start.  The corrected vector V e_k has the coordinates
+    // y = G e_k, z = L^T Pi^T e_k in the basis of H (its part outside span Z is
+    // (V - Z G) e_k = W L^T Pi^T e_k); after the first correction it is close
+    // to the wanted eigenvector, so its Rayleigh quotient is a good shift.
+    double lo = 0.0, hi = 0.0;
+    int nulo = 0, nuhi = 1 << 30;
+    bool have_lo = false, have_hi = false;
+    bool done = false;
+    const double tp = theta_prev[k];
+    const double cap = lam[k] * (1.0 + 1e-14) + 1e-300;  // interlacing: mu_k <= lambda_k
+    double rho = 0.0, res = 0.0;
+    __shared__ int s_pos;
+    const bool warm = w.status[ST_WARM] != 0;
+    if (warm) {
+        if (threadIdx.x == 0) {
+            s_pos = -1;
+            for (int a2 = 0; a2 < r; ++a2)
+                if (w.perm[a2] == k) s_pos = a2;
+        }
+        __syncthreads();
+        const int pos = s_pos;
+        for (int i = threadIdx.x; i < dn + r; i += nthr) {
+            double v;
+            if (i < dn)
+                v = w.FG[(int64_t)i * 2 * ld + ld + k];
+            else if (pos >= 0)
+                v = (i - dn) <= pos ? w.L1[pos * ld + (i - dn)] : 0.0;
+            else
+                v = start_entry(k, i);
+            vec[i] = v;
+        }
+        __syncthreads();
+        normalise(vec);
+        rayleigh(vec, rho, res);
+        const bool ok0 = rho > 0.0 && rho < cap;
+        if (ok0 && res <= 1e-10 * fabs(rho)) {
+            // already accurate: two counts around rho decide
+            const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
+            const int cl = factor(rho - span);
+            if (cl <= k) { lo = rho - span; nulo = cl; have_lo = true; }
+            const double h0 = fmin(rho + span, cap);
+            const int ch = factor(h0);
+            if (ch >= k + 1) { hi = h0; nuhi = ch; have_hi = true; }
+            done = have_lo && have_hi && nulo == k && nuhi == k + 1;
+        } else {
+            const double s0 = ok0 ? rho : (tp > 0.0 && tp < cap ? tp : -1.0);
+            if (s0 > 0.0) {
+                const double rho0 = rho;
+                const int c0 = factor(s0);
+                if (c0 <= k) { lo = s0; nulo = c0; have_lo = true; } else { hi = s0; nuhi = c0; have_hi = true; }
+                solve(vec);
+                normalise(vec);
+                rayleigh(vec, rho, res);
+                const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
+                if (have_lo && !(fabs(rho - s0) > res)) {
+                    // the shift is too close to rho to serve as the bracket end
+                    have_lo = false;
+                }
+                if (have_hi && !(fabs(rho - s0) > res)) have_hi = false;
+                if (!have_lo) {
+                    const double l0 = fmin(rho, rho0 > 0.0 ? rho0 : rho) - span;
+                    const int c1 = factor(l0);
+                    if (c1 <= k) { lo = l0; nulo = c1; have_lo = true; }
+                }
+                if (!have_hi) {
+                    const double h0 = fmin(rho + span, cap);
+                    const int c1 = factor(h0);
+                    if (c1 >= k + 1) { hi = h0; nuhi = c1; have_hi = true; }
+                }
+                if (have_lo && have_hi && nulo == k && nuhi == k + 1) {
+                    const bool inside = rho > lo && rho < hi;
+                    done = inside && res <= 1e-10 * fabs(rho) && rho - lo > res && hi - rho > res;
+                }
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
+        __syncthreads();
     }
+    const bool have = have_lo && have_hi;
     if (!have) {
         double g = 1e300;
         for (int i = threadIdx.x; i < dn; i += nthr) {
             double s2 = 0.0;
-            for (int a = 0; a < r; ++a) s2 += fabs(w.Ct[(int64_t)i * ld + a]);
-            g = fmin(g, w.lam[i] - s2);
+            for (int a2 = 0; a2 < r; ++a2) s2 += fabs(ct_row(i, a2));
+            g = fmin(g, lam[i] - s2);
         }
-        for (int a = threadIdx.x; a < r; a += nthr) {
+        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) {
             double s2 = 0.0;
-            for (int b = 0; b < r; ++b)
-                if (b != a) s2 += fabs(w.Dt[a * ld + b]);
-            for (int i = 0; i < dn; ++i) s2 += fabs(w.Ct[(int64_t)i * ld + a]);
-            g = fmin(g, w.Dt[a * ld + a] - s2);
+            for (int b2 = 0; b2 < r; ++b2)
+                if (b2 != a2) s2 += fabs(dt[a2 * r + b2]);
+            for (int i = 0; i < dn; ++i) s2 += fabs(ct_row(i, a2));
+            g = fmin(g, dt[a2 * r + a2] - s2);
         }
         red[threadIdx.x] = g;
         __syncthreads();
@@ -550,87 +742,62 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
             red[0] = mn;
         }
         __syncthreads();
-        lo = red[0];
+        const double glo = red[0];
         __syncthreads();
-        hi = w.lam[k];
-        hi = hi + fabs(hi) * 1e-14 + 1e-300;
-        lo = lo - fabs(lo) * 1e-14 - 1e-300;
-        clo = count(lo);
-        chi = count(hi);
-    }
-    // ---- isolate, then regula falsi (Illinois) on det(H - s)
-    double flo = clo.logdet, fhi = chi.logdet;  // log-magnitudes; signs from the counts
-    int side = 0;
-    for (int it = 0; it < 200; ++it) {
-        const double width = hi - lo;
-        if (width <= 1e-10 * fmax(fabs(lo), fabs(hi))) break;
-        double c;
-        const bool isolated = (clo.nu == k) && (chi.nu == k + 1);
-        if (!isolated) {
-            c = 0.5 * (lo + hi);
-        } else {
-            // f(lo) f(hi) < 0 because nu differs by one: c = hi - (hi - lo) / (1 + |f(lo)| / |f(hi)|)
-            const double q = exp(fmin(700.0, flo - fhi));
-            c = hi - width / (1.0 + q);
-            const double guard = 1e-3 * width;
-            if (!(c > lo + guard)) c = lo + guard;
-            if (!(c < hi - guard)) c = hi - guard;
+        if (!have_hi) {
+            hi = cap;
+            nuhi = 1 << 30;  // not counted yet (at least k + 1 by interlacing)
         }
-        if (c <= lo || c >= hi) break;
-        const CountOut cc = count(c);
-        if (cc.nu >= k + 1) {
-            hi = c; chi = cc; fhi = cc.logdet;
-            if (side == 1) flo += -0.69314718055994531;  // Illinois: halve the stale end
-            side = 1;
-        } else {
-            lo = c; clo = cc; flo = cc.logdet;
-            if (side == -1) fhi += -0.69314718055994531;
-            side = -1;
+        if (!have_lo) {
+            lo = glo - fabs(glo) * 1e-14 - 1e-300;
+            nulo = 0;        // Gershgorin: no eigenvalue below lo
         }
     }
-    const double sigma = 0.5 * (lo + hi);
-    (void)count(sigma);  // factorisation at sigma kept in S, ipiv
-    const int nh = dn + r;
-    for (int i = threadIdx.x; i < nh; i += nthr) vec[i] = start_entry(k, i);
-    __syncthreads();
-    for (int step = 0; step < 2; ++step) {
-        for (int i = threadIdx.x; i < dn; i += nthr) {
-            double den = w.lam[i] - sigma;
-            if (den == 0.0) den = 1e-300;
-            vec[i] = vec[i] / den;
-        }
-        __syncthreads();
-        // f = b_z - C~^T t : thread a (or a slice) per column
-        for (int a = threadIdx.x; a < r; a += nthr) {
-            double s2 = 0.0;
-            if (ct_in_lds)
-                for (int i = 0; i < dn; ++i) s2 += cch[(int64_t)i * r + a] * vec[i];
-            else
-                for (int i = 0; i < dn; ++i) s2 += w.Ct[(int64_t)i * ld + a] * vec[i];
-            fz[a] = vec[dn + a] - s2;
-        }
-        __syncthreads();
-        bk_solve(S, r, ls, ipiv, fz);
-        for (int i = threadIdx.x; i < dn; i += nthr) {
-            double s2 = 0.0;
-            if (ct_in_lds)
-                for (int a = 0; a < r; ++a) s2 += cch[(int64_t)i * r + a] * fz[a];
-            else
-                for (int a = 0; a < r; ++a) s2 += w.Ct[(int64_t)i * ld + a] * fz[a];
-            double den = w.lam[i] - sigma;
-            if (den == 0.0) den = 1e-300;
-            vec[i] -= s2 / den;
-        }
-        for (int a = threadIdx.x; a < r; a += nthr) vec[dn + a] = fz[a];
-        __syncthreads();
-        double s2 = 0.0;
-        for (int i = threadIdx.x; i < nh; i += nthr) s2 += vec[i] * vec[i];
-        s2 = block_sum(s2, red);
-        const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-        for (int i = threadIdx.x; i < nh; i += nthr) vec[i] *= inv;
-        __syncthreads();
+    // ---- isolate by bisection
+    for (int it = 0; it < 200 && !done; ++it) {
+        if (nulo == k && nuhi == k + 1) break;
+        if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;  // a cluster closer than rounding
+        const double mid = 0.5 * (lo + hi);
+        const int c = factor(mid);
+        if (c >= k + 1) { hi = mid; nuhi = c; } else { lo = mid; nulo = c; }
     }
-    for (int i = threadIdx.x; i < dn + ld; i += nthr) w.X[(int64_t)i * ld + k] = i < nh ? vec[i] : 0.0;
+    const uint64_t t_bracket = wall_clock64();
+    // ---- Rayleigh-quotient iteration inside the bracket
+    double sigma = (rho > lo && rho < hi) ? rho : ((tp > lo && tp < hi) ? tp : 0.5 * (lo + hi));
+    for (int it = 0; it < 12 && !done; ++it) {
+        const int c = factor(sigma);
+        if (c >= k + 1) { hi = fmin(hi, sigma); } else { lo = fmax(lo, sigma); }
+        const uint64_t q0 = wall_clock64();
+        solve(vec);
+        normalise(vec);
+        const uint64_t q1 = wall_clock64();
+        rayleigh(vec, rho, res);
+        if (threadIdx.x == 0) {
+            tim[2] += q1 - q0;
+            tim[3] += wall_clock64() - q1;
+        }
+        const bool inside = rho > lo && rho < hi;
+        if (inside && res <= 1e-10 * fabs(rho) && rho - lo > res && hi - rho > res) break;
+        sigma = inside ? rho : 0.5 * (lo + hi);
+        if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;
+    }
+    const uint64_t t_refine = wall_clock64();
+    if (threadIdx.x == 0 && w.diag) {
+        atomicAdd(&w.diag[k], ncount);
+        atomicAdd(&w.diag[kMaxWidth + k], done ? 1 : 0);
+        atomicAdd(&w.diag[2 * kMaxWidth + k], 1);
+    }
+    for (int i = threadIdx.x; i < dn + ld; i += nthr) w.X[(int64_t)i * ld + k] = i < dn + r ? vec[i] : 0.0;
+    const uint64_t t_end = wall_clock64();
+    if (threadIdx.x == 0 && w.diag && k == 0) {
+        atomicAdd(&w.diag[5 * kMaxWidth - 8], (int)(t_bracket - t_start_g));
+        atomicAdd(&w.diag[5 * kMaxWidth - 7], (int)(t_refine - t_bracket));
+        atomicAdd(&w.diag[5 * kMaxWidth - 6], (int)(t_end - t_refine));
+        atomicAdd(&w.diag[5 * kMaxWidth - 5], (int)tim[0]);
+        atomicAdd(&w.diag[5 * kMaxWidth - 4], (int)tim[1]);
+        atomicAdd(&w.diag[5 * kMaxWidth - 3], (int)tim[2]);
+        atomicAdd(&w.diag[5 * kMaxWidth - 2], (int)tim[3]);
+    }
 }
 
 // ------------------------------------------- Rayleigh-Ritz polish (a10)
@@ -646,11 +813,15 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     double *T = sm;          // m x m
     double *Q = T + m * m;   // m x m
     double *xs = Q + m * m;  // 32 x m staging
+    double *lamv = xs + 32 * m;  // dn
+    double *dtv = lamv + dn;     // ld x ld
+    for (int i = threadIdx.x; i < dn; i += blockDim.x) lamv[i] = w.lam[i];
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) dtv[e] = w.Dt[(e / r) * ld + e % r];
     double *Xp = w.X, *HXp = w.HX;
     const double *Ctp = w.Ct;
     int xst = ld, cst = ld;
     if (use_lds) {
-        double *Xl = xs + 32 * m;
+        double *Xl = dtv + ld * ld;
         double *HXl = Xl + nh * m;
         double *Ctl = HXl + nh * m;
         for (int e = threadIdx.x; e < nh * m; e += blockDim.x) Xl[e] = w.X[(int64_t)(e / m) * ld + e % m];
@@ -660,8 +831,8 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         Ctp = Ctl;
         xst = m;
         cst = r;
-        __syncthreads();
     }
+    __syncthreads();
     __shared__ double cs[kMaxWidth];
     __shared__ double sn[kMaxWidth];
     __shared__ int pairs[kMaxWidth];
@@ -726,7 +897,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     // ---- HX (nh x m): rows i < dn: lam_i x_i + C~_i z ; rows dn+a: C~^T y + D~ z
     for (int e = threadIdx.x; e < dn * m; e += blockDim.x) {
         const int i = e / m, c = e % m;
-        double s2 = w.lam[i] * Xp[(int64_t)i * xst + c];
+        double s2 = lamv[i] * Xp[(int64_t)i * xst + c];
         for (int a2 = 0; a2 < r; ++a2) s2 += Ctp[(int64_t)i * cst + a2] * Xp[(int64_t)(dn + a2) * xst + c];
         HXp[(int64_t)i * xst + c] = s2;
     }
@@ -734,7 +905,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         const int a2 = e / m, c = e % m;
         double s2 = 0.0;
         for (int i = 0; i < dn; ++i) s2 += Ctp[(int64_t)i * cst + a2] * Xp[(int64_t)i * xst + c];
-        for (int b2 = 0; b2 < r; ++b2) s2 += w.Dt[a2 * ld + b2] * Xp[(int64_t)(dn + b2) * xst + c];
+        for (int b2 = 0; b2 < r; ++b2) s2 += dtv[a2 * r + b2] * Xp[(int64_t)(dn + b2) * xst + c];
         HXp[(int64_t)(dn + a2) * xst + c] = s2;
     }
     __syncthreads();
@@ -807,6 +978,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
             s_off = off;
         }
         __syncthreads();
+        if (threadIdx.x == 0 && w.diag) atomicAdd(&w.diag[4 * kMaxWidth], 1);
         if (s_off < 1e-15) break;
         __syncthreads();
     }
@@ -845,16 +1017,22 @@ __global__ __launch_bounds__(256) void k_recombine_coeffs(SmallWork w) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
-    double *Xv = sm;  // ld x ld
-    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) Xv[e] = 0.0;
+    double *Xv = sm;             // ld x ld
+    double *L1 = Xv + ld * ld;   // ld x ld
+    double *z = L1 + ld * ld;    // r x ld
+    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) {
+        Xv[e] = 0.0;
+        L1[e] = w.L1[e];
+    }
+    for (int e = threadIdx.x; e < r * ld; e += blockDim.x) z[e] = w.Xr[(int64_t)(dn + e / ld) * ld + e % ld];
     __syncthreads();
     if ((int)threadIdx.x < ld) {
         const int c = threadIdx.x;
         double t[kMaxWidth];
         for (int a = r - 1; a >= 0; --a) {
-            double s = w.Xr[(int64_t)(dn + a) * ld + c];
-            for (int b = a + 1; b < r; ++b) s -= w.L1[b * ld + a] * t[b];
-            t[a] = s / w.L1[a * ld + a];
+            double s = z[a * ld + c];
+            for (int b = a + 1; b < r; ++b) s -= L1[b * ld + a] * t[b];
+            t[a] = s / L1[a * ld + a];
         }
         for (int a = 0; a < r; ++a) Xv[w.perm[a] * ld + c] = t[a];
     }
@@ -894,11 +1072,17 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, const double *t
     const int r = w.ld;  // upper bound of the rank
     const int ct_in_lds = (int64_t)w.dn * r <= 8192 ? 1 : 0;
     const size_t rows = ct_in_lds ? (size_t)w.dn : 64;
-    const size_t lds = ((size_t)r * (r + 1) + rows * r + (size_t)w.dn + (size_t)w.dn + r + r) * sizeof(double);
     const int threads = r <= 32 ? 64 : 256;
+    const size_t npairs = (size_t)r * (r + 1) / 2;
+    const size_t ngroups = (npairs + 7) / 8;
+    const size_t slices = ngroups >= (size_t)threads ? 1 : threads / ngroups;
+    size_t partsz = slices * npairs;
+    if (partsz < (size_t)threads) partsz = threads;  // also holds the C~^T u partials
+    const size_t lds = ((size_t)r * (r + 1) + rows * r + (size_t)w.dn + 2 * ((size_t)w.dn + r) + r + (size_t)w.dn +
+                        (size_t)r * r + 4 * (size_t)r + partsz) * sizeof(double);
     hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta_prev, ct_in_lds);
     // the rank is only known on the device: size the LDS path for r = ld
-    const size_t base = 2 * (size_t)qe * qe + 32 * (size_t)qe;
+    const size_t base = 2 * (size_t)qe * qe + 32 * (size_t)qe + (size_t)w.dn + (size_t)w.ld * w.ld;
     const size_t nh = (size_t)w.dn + w.ld;
     const size_t full = base + 2 * nh * qe + (size_t)w.dn * w.ld;
     const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
@@ -906,7 +1090,7 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, const double *t
 }
 
 void launch_recombine_coeffs(hipStream_t s, const SmallWork &w) {
-    hipLaunchKernelGGL(k_recombine_coeffs, dim3(1), dim3(kB), (size_t)w.ld * w.ld * sizeof(double), s, w);
+    hipLaunchKernelGGL(k_recombine_coeffs, dim3(1), dim3(kB), 3 * (size_t)w.ld * w.ld * sizeof(double), s, w);
 }
 
 void launch_theta_update(hipStream_t s, const SmallWork &w, double *theta_out, int final_level) {

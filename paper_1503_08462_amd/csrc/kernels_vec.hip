@@ -44,9 +44,7 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32
                                                   const int32_t *__restrict__ col, const double *__restrict__ a,
                                                   const double *__restrict__ m, const double *__restrict__ U,
                                                   const double *__restrict__ theta, TO *__restrict__ R,
-                                                  double *__restrict__ part, unsigned *counter,
-                                                  double *__restrict__ rho, int q, double tol, int *status,
-                                                  int check) {
+                                                  double *__restrict__ part, const int *status) {
     __shared__ double sm[256 * CPT * 2];
     if (status[ST_CONVERGED]) return;
     const int tpr = ld / CPT, rpw = kWave / tpr;
@@ -94,30 +92,28 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32
             for (int g = 0; g < rpw; ++g) acc += sm[(((w * kWave) + g * tpr + s) * CPT + c) * 2 + kind];
         part[lb * 2 * ld + idx] = acc;
     }
-    if (!last_block(counter)) return;
-    // last block: fixed-order sum over blocks (slot-strided, then over slots),
-    // then rho and the convergence test
-    __shared__ double fin[256];
-    {
-        const int w2 = 2 * ld, slots = (int)blockDim.x / w2;
-        const int slot = threadIdx.x / w2, cc = threadIdx.x - slot * w2;
-        double acc = 0.0;
-        if (slot < slots)
-            for (int64_t bb = slot; bb < nb; bb += slots) acc += part[bb * w2 + cc];
-        __syncthreads();
-        sm[threadIdx.x] = acc;
-        __syncthreads();
-        if ((int)threadIdx.x < w2) {
-            double t = 0.0;
-            for (int k = 0; k < slots; ++k) t += sm[k * w2 + threadIdx.x];
-            fin[threadIdx.x] = t;
-        }
+}
+
+// Residual norms: fin[e] = sum over blocks of part[b][e] (one wavefront per
+// sum, lanes strided over blocks, fixed butterfly), then
+// rho_j = sqrt(sum R_j^2) / (|theta_j| sqrt(sum (MU)_j^2)) and the convergence
+// test max_{j < q} rho_j <= tol.
+__global__ __launch_bounds__(256) void k_residual_finish(int64_t nb, int ld, const double *__restrict__ part,
+                                                         const double *__restrict__ theta, double *__restrict__ rho,
+                                                         int q, double tol, int *status, int check) {
+    __shared__ double fin[2 * 128];
+    if (status[ST_CONVERGED]) return;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    for (int e = wv; e < 2 * ld; e += nw) {
+        double sum = 0.0;
+        for (int64_t b = lane; b < nb; b += kWave) sum += part[b * 2 * ld + e];
+        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+        if (lane == 0) fin[e] = sum;
     }
     __syncthreads();
-    if (threadIdx.x < ld) {
+    if ((int)threadIdx.x < ld) {
         const int j = threadIdx.x;
-        const double r = sqrt(fin[2 * j]) / (fabs(theta[j]) * sqrt(fin[2 * j + 1]));
-        rho[j] = r;
+        rho[j] = sqrt(fin[2 * j]) / (fabs(theta[j]) * sqrt(fin[2 * j + 1]));
     }
     __syncthreads();
     if (threadIdx.x == 0 && check) {
@@ -431,7 +427,7 @@ inline int64_t row_blocks(int64_t n, int ld, int cpt) {
 
 int64_t residual_blocks(int64_t n, int ld) {
     const int64_t need = row_blocks(n, ld, ld <= 128 ? 2 : 4);
-    return need < 256 ? need : 256;
+    return need < 2048 ? need : 2048;
 }
 
 template <typename TO>
@@ -439,8 +435,10 @@ void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const
                      const double *m, const double *U, const double *theta, TO *R, double *part,
                      unsigned *counter, double *rho, int q, double tol, int *status, int check) {
     const int64_t nb = residual_blocks(n, ld);
+    (void)counter;
     DISPATCH_CPT(ld, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
-                                        col, a, m, U, theta, R, part, counter, rho, q, tol, status, check));
+                                        col, a, m, U, theta, R, part, status));
+    hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(kBlock), 0, s, nb, ld, part, theta, rho, q, tol, status, check);
 }
 
 template <typename T>
