@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus)
@@ -120,6 +123,14 @@ def main():
     elapsed = time.perf_counter() - t_start
     stats = ctx.site_stats()
     ctx.timing(False)
+    if args.copy_calibration:
+        n = 32 << 20  # 256 MiB of doubles read, 256 MiB written
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     q = p["q"]
     sites = {}

@@ -139,7 +139,7 @@ void plan(amg_eig_ctx *c, char *base) {
     c->rho = cv.take<double>(ld);
     int64_t maxn = 0;
     for (const Level &lv : H.lv) maxn = std::max(maxn, lv.n);
-    c->part_res = cv.take<double>((size_t)residual_blocks(maxn, ld) * 2 * ld);
+    c->part_res = cv.take<double>(((size_t)residual_blocks(maxn, ld) + 1) * 2 * ld);
     c->part_gram = cv.take<double>((size_t)gram_blocks(maxn, ld) * 2 * ld * ld);
     c->counters = cv.take<unsigned>(16);
     c->status = cv.take<int>(ST_COUNT);

@@ -29,227 +29,259 @@ namespace {
 constexpr int kB = 256;  // threads per block of the small kernels
 
 // ---------------------------------------------------------------------
-// Bunch-Kaufman symmetric indefinite LDL^T of S (r x r, LDS, row stride ls),
-// in place: multipliers below the diagonal, D on the (block) diagonal.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Value of v in lane `src` of the wavefront (src must be wave-uniform).
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    src = __builtin_amdgcn_readfirstlane(src);
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the wavefront; the xor butterfly leaves the same bits in every lane.
+__device__ __forceinline__ double wave_allsum(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// One 16 x 16 tile of X^T Y over rows [0, K) on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// D[i][j] in lane j + 16 (i mod 4), register i / 4).  X(i, c) and Y(i, c)
+// return column c (0..15) of the tile operand in row i.  One wavefront, all
+// lanes active.  Element (4u + (lane >> 4), lane & 15) of the result is in
+// component u.
+template <class FX, class FY>
+__device__ __forceinline__ dbl4 mfma_tn16(const FX &X, const FY &Y, int K) {
+    const int lane = threadIdx.x & (kWave - 1), kk = lane >> 4, c = lane & 15;
+    dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+    int base = 0;
+    for (; base + 16 <= K; base += 16) {  // operands of four steps loaded ahead of the products
+        const int i0 = base + kk;
+        const double x0 = X(i0, c), y0 = Y(i0, c), x1 = X(i0 + 4, c), y1 = Y(i0 + 4, c);
+        const double x2 = X(i0 + 8, c), y2 = Y(i0 + 8, c), x3 = X(i0 + 12, c), y3 = Y(i0 + 12, c);
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, a1, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, y2, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x3, y3, a1, 0, 0, 0);
+    }
+    for (; base < K; base += 4) {
+        const int i0 = base + kk;
+        const int ic = i0 < K ? i0 : K - 1;  // clamped: never reads past row K - 1
+        double x = X(ic, c), y = Y(ic, c);
+        if (i0 >= K) x = y = 0.0;
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, a0, 0, 0, 0);
+    }
+    return a0 + a1;
+}
+
+// Bunch-Kaufman symmetric indefinite LDL^T of S (r x r, LDS, row stride ls).
+// D (1x1 and 2x2 diagonal blocks) stays on the diagonal of S, the multipliers
+// go to the strict lower part of Lm (same stride).
 // ipiv[p] = kp >= 0: 1x1 pivot, rows p and kp interchanged;
 // ipiv[p] = ipiv[p+1] = -(kp+1): 2x2 pivot, rows p+1 and kp interchanged.
-// Returns the number of negative eigenvalues of S (Sylvester's law).
-__device__ int bk_factor(double *S, int r, int ls, int *ipiv, double *mult) {
-    __shared__ int s_kp, s_size, s_neg;
+// Returns the number of negative eigenvalues of S (Sylvester's law).  Every
+// thread evaluates the pivot choice itself from the shared column (broadcast
+// reads), so a pivot step costs one barrier, two with an interchange.  The
+// trailing update evaluates the same product for (i, j) and (j, i): the
+// active part stays exactly symmetric.
+__device__ int bk_factor(double *S, double *Lm, int r, int ls, int *ipiv) {
     const double alpha = 0.6403882032022076;  // (1 + sqrt(17)) / 8
-    if (threadIdx.x == 0) s_neg = 0;
-    __syncthreads();
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tx = tid & 15, ty = tid >> 4, nty = nthr >> 4;
+    int neg = 0;
     int p = 0;
     while (p < r) {
-        if (threadIdx.x < kWave) {
-            const int lane = threadIdx.x;
-            double best = -1.0;
-            int bi = r;
-            for (int i = p + 1 + lane; i < r; i += kWave) {
-                const double v = fabs(S[i * ls + p]);
-                if (v > best) {
-                    best = v;
-                    bi = i;
-                }
-            }
-            for (int off = kWave / 2; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(best, off, kWave);
-                const int oi = __shfl_xor(bi, off, kWave);
-                if (ov > best || (ov == best && oi < bi)) {
-                    best = ov;
-                    bi = oi;
-                }
-            }
-            const double colmax = best > 0.0 ? best : 0.0;
-            const int imax = bi;
-            const double absakk = fabs(S[p * ls + p]);
-            int kp = p, size = 1;
-            if (colmax > 0.0 && absakk < alpha * colmax) {
-                double rb = 0.0;
-                for (int j = p + lane; j < r; j += kWave)
-                    if (j != imax) rb = fmax(rb, fabs(S[imax * ls + j]));
-                for (int off = kWave / 2; off > 0; off >>= 1) rb = fmax(rb, __shfl_xor(rb, off, kWave));
-                const double rowmax = rb;
-                if (absakk * rowmax >= alpha * colmax * colmax) {
-                    kp = p;
-                } else if (fabs(S[imax * ls + imax]) >= alpha * rowmax) {
-                    kp = imax;
-                } else {
-                    kp = imax;
-                    size = 2;
-                }
-            }
-            if (lane == 0) {
-                s_kp = kp;
-                s_size = size;
+        double colmax = 0.0;
+        int imax = p;
+        for (int i = p + 1; i < r; ++i) {
+            const double v = fabs(S[i * ls + p]);
+            imax = v > colmax ? i : imax;
+            colmax = v > colmax ? v : colmax;
+        }
+        const double absakk = fabs(S[p * ls + p]);
+        int kp = p, size = 1;
+        const bool read_row = colmax > 0.0 && absakk < alpha * colmax;  // the same in every thread
+        if (read_row) {
+            double rowmax = 0.0;
+            for (int j = p; j < r; ++j)
+                if (j != imax) rowmax = fmax(rowmax, fabs(S[imax * ls + j]));
+            if (absakk * rowmax >= alpha * colmax * colmax) {
+                kp = p;
+            } else if (fabs(S[imax * ls + imax]) >= alpha * rowmax) {
+                kp = imax;
+            } else {
+                kp = imax;
+                size = 2;
             }
         }
-        __syncthreads();
-        const int kp = s_kp, size = s_size;
         const int tgt = size == 1 ? p : p + 1;
-        if (kp != tgt) {
-            for (int j = threadIdx.x; j < r; j += blockDim.x) {
-                const double t = S[tgt * ls + j];
+        if (read_row && kp == tgt) __syncthreads();  // row imax is read before the update writes it
+        if (kp != tgt) {  // symmetric interchange of tgt and kp, with the multipliers found so far
+            __syncthreads();  // every thread has read the pivot column
+            for (int j = tid; j < r; j += nthr) {
+                if (j == tgt || j == kp) continue;
+                double t = S[tgt * ls + j];
                 S[tgt * ls + j] = S[kp * ls + j];
                 S[kp * ls + j] = t;
+                t = S[j * ls + tgt];
+                S[j * ls + tgt] = S[j * ls + kp];
+                S[j * ls + kp] = t;
+                if (j < p) {
+                    t = Lm[tgt * ls + j];
+                    Lm[tgt * ls + j] = Lm[kp * ls + j];
+                    Lm[kp * ls + j] = t;
+                }
             }
-            __syncthreads();
-            for (int i = threadIdx.x; i < r; i += blockDim.x) {
-                const double t = S[i * ls + tgt];
-                S[i * ls + tgt] = S[i * ls + kp];
-                S[i * ls + kp] = t;
+            if (tid == 0) {
+                const double t = S[tgt * ls + tgt];
+                S[tgt * ls + tgt] = S[kp * ls + kp];
+                S[kp * ls + kp] = t;
             }
             __syncthreads();
         }
         if (size == 1) {
-            // column p and its multipliers l_i = S[i][p] / d are staged in
-            // mult[] so that the trailing update and the store of the
-            // multipliers into column p share one pass
             const double d = S[p * ls + p];
             const double dinv = d != 0.0 ? 1.0 / d : 0.0;
-            if (threadIdx.x == 0) {
-                ipiv[p] = kp;
-                if (d < 0.0) s_neg += 1;
-            }
-            for (int i = p + 1 + threadIdx.x; i < r; i += blockDim.x) {
-                const double c1 = S[i * ls + p];
-                mult[4 * i] = c1 * dinv;
-                mult[4 * i + 2] = c1;
-            }
-            __syncthreads();
-            const int m = r - p - 1;
-            for (int e = threadIdx.x; e < m * (m + 1); e += blockDim.x) {
-                const int i = p + 1 + e / (m + 1), jj = e % (m + 1);
-                if (jj == m) {
-                    S[i * ls + p] = mult[4 * i];
-                } else {
-                    const int j = p + 1 + jj;
-                    S[i * ls + j] -= mult[4 * i] * mult[4 * j + 2];
+            neg += d < 0.0 ? 1 : 0;
+            if (tid == 0) ipiv[p] = kp;
+            for (int i = p + 1 + ty; i < r; i += nty) {
+                const double ci = S[i * ls + p], li = ci * dinv;
+                for (int j = p + 1 + tx; j < r; j += 16) {
+                    const double cj = S[j * ls + p];
+                    S[i * ls + j] -= i >= j ? li * cj : (cj * dinv) * ci;
                 }
+                if (tx == 0) Lm[i * ls + p] = li;
             }
             __syncthreads();
             p += 1;
         } else {
             const double a = S[p * ls + p], b = S[(p + 1) * ls + p], c = S[(p + 1) * ls + p + 1];
             const double det = a * c - b * b;
-            if (threadIdx.x == 0) {
-                ipiv[p] = ipiv[p + 1] = -(kp + 1);
-                s_neg += det < 0.0 ? 1 : (a + c < 0.0 ? 2 : 0);
-            }
+            neg += det < 0.0 ? 1 : (a + c < 0.0 ? 2 : 0);
+            if (tid == 0) ipiv[p] = ipiv[p + 1] = -(kp + 1);
             const double id = 1.0 / det;
-            // l_i = [S[i][p], S[i][p+1]] D^-1 and the two column entries
-            // themselves, staged in mult[4i .. 4i+3]
-            for (int i = p + 2 + threadIdx.x; i < r; i += blockDim.x) {
-                const double c1 = S[i * ls + p], c2 = S[i * ls + p + 1];
-                mult[4 * i] = (c1 * c - c2 * b) * id;
-                mult[4 * i + 1] = (c2 * a - c1 * b) * id;
-                mult[4 * i + 2] = c1;
-                mult[4 * i + 3] = c2;
-            }
-            __syncthreads();
-            const int m = r - p - 2;
-            for (int e = threadIdx.x; e < m * (m + 1); e += blockDim.x) {
-                const int i = p + 2 + e / (m + 1), jj = e % (m + 1);
-                const double l1 = mult[4 * i], l2 = mult[4 * i + 1];
-                if (jj == m) {
-                    S[i * ls + p] = l1;
-                    S[i * ls + p + 1] = l2;
-                } else {
-                    const int j = p + 2 + jj;
-                    S[i * ls + j] -= l1 * mult[4 * j + 2] + l2 * mult[4 * j + 3];
+            for (int i = p + 2 + ty; i < r; i += nty) {
+                const double c1i = S[i * ls + p], c2i = S[i * ls + p + 1];
+                const double l1 = (c1i * c - c2i * b) * id, l2 = (c2i * a - c1i * b) * id;
+                for (int j = p + 2 + tx; j < r; j += 16) {
+                    const double c1j = S[j * ls + p], c2j = S[j * ls + p + 1];
+                    double t;
+                    if (i >= j) {
+                        t = l1 * c1j + l2 * c2j;
+                    } else {
+                        const double m1 = (c1j * c - c2j * b) * id, m2 = (c2j * a - c1j * b) * id;
+                        t = m1 * c1i + m2 * c2i;
+                    }
+                    S[i * ls + j] -= t;
+                }
+                if (tx == 0) {
+                    Lm[i * ls + p] = l1;
+                    Lm[i * ls + p + 1] = l2;
                 }
             }
             __syncthreads();
             p += 2;
         }
     }
-    __syncthreads();
-    return s_neg;
+    return neg;
 }
 
-// Solve S z = f with the factors of bk_factor (f overwritten by z, LDS).
-__device__ void bk_solve(const double *S, int r, int ls, const int *ipiv, double *f) {
-    if (threadIdx.x == 0) {
-        for (int p = 0; p < r;) {
-            if (ipiv[p] >= 0) {
-                const int kp = ipiv[p];
-                const double t = f[p];
-                f[p] = f[kp];
-                f[kp] = t;
+// Solve S z = f with the factors of bk_factor (D in S, L in Lm; f in LDS,
+// overwritten by z).
+// Wavefront 0 keeps f in registers (entry i in lane i mod 64, slot i / 64,
+// r <= 128) and exchanges values by lane reads; the other wavefronts wait at
+// the closing barrier.
+__device__ void bk_solve(const double *S, const double *Lm, int r, int ls, const int *ipiv, double *f) {
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        double f0 = lane < r ? f[lane] : 0.0;
+        double f1 = lane + kWave < r ? f[lane + kWave] : 0.0;
+        auto get = [&](int i) __attribute__((always_inline)) -> double {
+            const double src = i < kWave ? f0 : f1;  // value select: f0, f1 stay in registers
+            return lane_bcast(src, i & (kWave - 1));
+        };
+        auto put = [&](int i, double v) __attribute__((always_inline)) {
+            const bool mine = lane == (i & (kWave - 1));
+            f0 = (mine && i < kWave) ? v : f0;
+            f1 = (mine && i >= kWave) ? v : f1;
+        };
+        auto swap = [&](int a, int b) __attribute__((always_inline)) {
+            if (a == b) return;
+            const double va = get(a), vb = get(b);
+            put(a, vb);
+            put(b, va);
+        };
+        // axpy on the entries i in [lo, hi): f_i -= col(i) * s, col read from S
+        auto axpy_col = [&](int lo, int hi, int c, double s) __attribute__((always_inline)) {
+            if (lane >= lo && lane < hi) f0 -= Lm[lane * ls + c] * s;
+            if (lane + kWave >= lo && lane + kWave < hi) f1 -= Lm[(lane + kWave) * ls + c] * s;
+        };
+        auto axpy_row = [&](int hi, int rw, double s) __attribute__((always_inline)) {  // f_i -= L[rw][i] s, i < hi
+            if (lane < hi) f0 -= Lm[rw * ls + lane] * s;
+            if (lane + kWave < hi) f1 -= Lm[rw * ls + lane + kWave] * s;
+        };
+        for (int p = 0; p < r;) {  // interchanges in order
+            const int ip = ipiv[p];
+            if (ip >= 0) {
+                swap(p, ip);
                 p += 1;
             } else {
-                const int kp = -ipiv[p] - 1;
-                const double t = f[p + 1];
-                f[p + 1] = f[kp];
-                f[kp] = t;
+                swap(p + 1, -ip - 1);
                 p += 2;
             }
         }
-    }
-    __syncthreads();
-    for (int p = 0; p < r;) {  // L y = f
-        if (ipiv[p] >= 0) {
-            const double fp = f[p];
-            for (int i = p + 1 + threadIdx.x; i < r; i += blockDim.x) f[i] -= S[i * ls + p] * fp;
-            __syncthreads();
-            p += 1;
-        } else {
-            const double f0 = f[p], f1 = f[p + 1];
-            for (int i = p + 2 + threadIdx.x; i < r; i += blockDim.x) f[i] -= S[i * ls + p] * f0 + S[i * ls + p + 1] * f1;
-            __syncthreads();
-            p += 2;
+        for (int p = 0; p < r;) {  // L y = f
+            if (ipiv[p] >= 0) {
+                axpy_col(p + 1, r, p, get(p));
+                p += 1;
+            } else {
+                const double y0 = get(p), y1 = get(p + 1);
+                axpy_col(p + 2, r, p, y0);
+                axpy_col(p + 2, r, p + 1, y1);
+                p += 2;
+            }
         }
-    }
-    if (threadIdx.x == 0) {  // D solve; singular pivots are replaced by a tiny value
-        for (int p = 0; p < r;) {
+        for (int p = 0; p < r;) {  // D solve; singular pivots are replaced by a tiny value
             if (ipiv[p] >= 0) {
                 double d = S[p * ls + p];
                 if (d == 0.0) d = 1e-300;
-                f[p] /= d;
+                put(p, get(p) / d);
                 p += 1;
             } else {
                 const double a = S[p * ls + p], b = S[(p + 1) * ls + p], c = S[(p + 1) * ls + p + 1];
                 const double det = a * c - b * b;
-                const double y0 = f[p], y1 = f[p + 1];
-                f[p] = (c * y0 - b * y1) / det;
-                f[p + 1] = (a * y1 - b * y0) / det;
+                const double y0 = get(p), y1 = get(p + 1);
+                put(p, (c * y0 - b * y1) / det);
+                put(p + 1, (a * y1 - b * y0) / det);
                 p += 2;
             }
         }
-    }
-    __syncthreads();
-    // L^T w = y, blocks from the last one backwards (a 2x2 block has both
-    // ipiv entries negative): once w of a block is known, remove its
-    // contribution from the rows above.
-    for (int p = r - 1; p >= 0;) {
-        if (ipiv[p] < 0) {
-            const int p0 = p - 1;
-            const double w0 = f[p0], w1 = f[p];
-            for (int i = threadIdx.x; i < p0; i += blockDim.x) f[i] -= S[p0 * ls + i] * w0 + S[p * ls + i] * w1;
-            p -= 2;
-        } else {
-            const double wp = f[p];
-            for (int i = threadIdx.x; i < p; i += blockDim.x) f[i] -= S[p * ls + i] * wp;
-            p -= 1;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {  // undo the interchanges in reverse order
-        for (int p = r - 1; p >= 0;) {
+        for (int p = r - 1; p >= 0;) {  // L^T w = y, last block first
             if (ipiv[p] < 0) {
-                const int kp = -ipiv[p] - 1;
-                const double t = f[p];
-                f[p] = f[kp];
-                f[kp] = t;
+                const int p0 = p - 1;
+                const double w0 = get(p0), w1 = get(p);
+                axpy_row(p0, p0, w0);
+                axpy_row(p0, p, w1);
                 p -= 2;
             } else {
-                const int kp = ipiv[p];
-                const double t = f[p];
-                f[p] = f[kp];
-                f[kp] = t;
+                axpy_row(p, p, get(p));
                 p -= 1;
             }
         }
+        for (int p = r - 1; p >= 0;) {  // undo the interchanges in reverse order
+            const int ip = ipiv[p];
+            if (ip < 0) {
+                swap(p, -ip - 1);
+                p -= 2;
+            } else {
+                swap(p, ip);
+                p -= 1;
+            }
+        }
+        if (lane < r) f[lane] = f0;
+        if (lane + kWave < r) f[lane + kWave] = f1;
     }
     __syncthreads();
 }
@@ -408,71 +440,112 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol) {
     }
     if ((int)threadIdx.x < ld) w.perm[threadIdx.x] = perm[threadIdx.x];
     if (threadIdx.x == 0) w.status[ST_RANK] = r;
-    // C~ rows: c = F_i - lambda_i G_i (permuted), then L^-1 c
-    double t[kMaxWidth];
-    for (int i = threadIdx.x; i < dn; i += blockDim.x) {
-        const double li = w.lam[i];
-        const double *row = w.FG + (int64_t)i * 2 * ld;
-        for (int a = 0; a < r; ++a) {
-            const int pa = perm[a];
-            double s = row[pa] - li * row[ld + pa];
-            for (int k = 0; k < a; ++k) s -= DM[a * ld + k] * t[k];
-            t[a] = s / DM[a * ld + a];
+    // C~ = C(:, perm_r) L^-T with C = F - Lambda G: L^-1 by columns (thread c),
+    // then one dot product per entry
+    double *Li = Y;  // r x r lower, row stride ld
+    __syncthreads();
+    if ((int)threadIdx.x < r) {
+        const int c = threadIdx.x;
+        for (int i = 0; i < r; ++i) {
+            double v = 0.0;
+            if (i >= c) {
+                v = i == c ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) v -= DM[i * ld + k] * Li[k * ld + c];
+                v /= DM[i * ld + i];
+            }
+            Li[i * ld + c] = v;
         }
-        for (int a = 0; a < ld; ++a) w.Ct[(int64_t)i * ld + a] = a < r ? t[a] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < dn * ld; e += blockDim.x) {
+        const int i = e / ld, a = e - i * ld;
+        double v = 0.0;
+        if (a < r) {
+            const double li = w.lam[i];
+            const double *row = w.FG + (int64_t)i * 2 * ld;
+            for (int k = 0; k <= a; ++k) {
+                const int pk = perm[k];
+                v += Li[a * ld + k] * (row[pk] - li * row[ld + pk]);
+            }
+        }
+        w.Ct[e] = v;
     }
 }
 
 // --------------------------------------------------- eigenvalues (a10)
 // One workgroup per wanted eigenvalue k (0-based: the (k+1)-th smallest).
 // nu(s) = #{lambda_i < s} + #neg(S(s)) counts the eigenvalues of H below s
-// (Sylvester).  The eigenvalue is bracketed (a warm bracket around the
-// previous step's Ritz value when two counts validate it, else Gershgorin and
-// the interlacing bound mu_{k+1} <= lambda_{k+1}) and isolated by bisection.
-// Inside the isolating bracket, Rayleigh-quotient iteration with the exact
-// Schur-complement solve (H - s)^-1 refines the eigenvector: every
-// factorisation is also a count and narrows the bracket, and an iterate is
-// accepted once its Rayleigh quotient rho lies in the bracket with
-// ||H x - rho x|| <= 1e-10 |rho|, which pins it to the bracketed eigenvalue.
-// A shift leaving the bracket falls back to the bracket midpoint.
-
-constexpr int kPairGroup = 8;  // pairs of S accumulated per work item
-constexpr int kMaxItems = 4;   // work items per thread (npairs <= 4 * 256 * 8)
-
+// (Sylvester); S(s) is formed on the FP64 matrix cores and factored by
+// Bunch-Kaufman.  After the first correction the corrected vector V e_k,
+// expressed in the basis of H, is a close approximation of the wanted
+// eigenvector: one Rayleigh-quotient step from it and one more count around
+// the result usually isolate the eigenvalue and deliver its vector.
+// Otherwise the eigenvalue is bracketed (Gershgorin and the interlacing bound
+// mu_k <= lambda_k fill in the missing ends), isolated by bisection, and
+// Rayleigh-quotient iteration with the exact Schur-complement solve
+// (H - s)^-1 runs inside the bracket: every factorisation is also a count and
+// narrows the bracket.  An iterate is accepted once its Rayleigh quotient rho
+// lies in the isolating bracket with ||H x - rho x|| <= 1e-10 |rho| and more
+// than that residual away from both ends, which pins it to the bracketed
+// eigenvalue.
 __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
                                                       int ct_in_lds) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, k = blockIdx.x;
     const int r = w.status[ST_RANK];
-    const int ls = r + 1;
-    const int nthr = blockDim.x;
-    const int npairs = r * (r + 1) / 2;
-    const int ngroups = (npairs + kPairGroup - 1) / kPairGroup;
-    const int slices = ngroups >= nthr ? 1 : nthr / (ngroups > 0 ? ngroups : 1);
-    double *S = sm;                      // r x ls
-    double *cch = S + r * ls;            // C~ (dn x r) in LDS, or a 64-row chunk
-    const int chunk_rows = ct_in_lds ? dn : 64;
-    double *wdn = cch + chunk_rows * r;  // dn weights 1 / (lambda_i - sigma)
-    double *vec = wdn + dn;              // dn + r : current vector
-    double *hx = vec + dn + r;           // dn + r : H x
-    double *fz = hx + dn + r;            // r
-    double *lam = fz + r;                // dn
-    double *dt = lam + dn;               // r x r
-    double *mult = dt + r * r;           // 4 r: multipliers and pivot columns of the factorisation
-    double *part = mult + 4 * r;         // slices x npairs partial sums (also reused for reductions)
+    const int ldp = (ld + 15) & ~15;
+    const int ls = ldp + 1;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
+    double *S = sm;                                    // ldp x ls
+    double *ctl = S + ldp * ls;                        // dn x ldp, zero beyond column r
+    double *wdn = ctl + (ct_in_lds ? dn * ldp : 0);    // dn weights 1 / (lambda_i - sigma)
+    double *vec = wdn + dn;                            // dn + ldp: current vector
+    double *hx = vec + dn + ldp;                       // dn + ldp: H x
+    double *fz = hx + dn + ldp;                        // ldp
+    double *lam = fz + ldp;                            // dn
+    double *dt = lam + dn;                             // ldp x ldp
+    double *Lm = dt + ldp * ldp;                       // ldp x ls: multipliers of the factorisation
+    double *red = Lm + ldp * ls;                       // 4 x 256 partial tiles + 64 cross-wavefront sums
     __shared__ int ipiv[kMaxWidth];
-    __shared__ double red[kB];
-    const uint64_t t_start_g = wall_clock64();
-    if (ct_in_lds)
-        for (int e = threadIdx.x; e < dn * r; e += nthr) cch[e] = w.Ct[(int64_t)(e / r) * ld + e % r];
-    for (int i = threadIdx.x; i < dn; i += nthr) lam[i] = w.lam[i];
-    for (int e = threadIdx.x; e < r * r; e += nthr) dt[e] = w.Dt[(e / r) * ld + e % r];
+    __shared__ unsigned long long tim[8];  // solver statistics: phase clocks
+    if (tid < 8) tim[tid] = 0;
+    const uint64_t t_begin = wall_clock64();
+    if (ct_in_lds) {  // rows of ld doubles (ld a multiple of 4) as double2 pairs
+        const int hp = ldp / 2, hl = ld / 2;
+        for (int e = tid; e < dn * hp; e += nthr) {
+            const int i = e / hp, a2 = e - i * hp;
+            double2 v = make_double2(0.0, 0.0);
+            if (a2 < hl) v = reinterpret_cast<const double2 *>(w.Ct + (int64_t)i * ld)[a2];
+            if (2 * a2 >= r) v.x = 0.0;
+            if (2 * a2 + 1 >= r) v.y = 0.0;
+            reinterpret_cast<double2 *>(ctl + i * ldp)[a2] = v;
+        }
+    }
+    for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
+    for (int e = tid; e < ldp * ldp; e += nthr) {
+        const int a = e / ldp, b = e - a * ldp;
+        dt[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
+    }
     __syncthreads();
+    if (tid == 0) tim[0] += wall_clock64() - t_begin;
+    auto ct = [&](int i, int a) -> double {
+        if (ct_in_lds) return ctl[i * ldp + a];
+        return a < ld ? w.Ct[(int64_t)i * ld + a] : 0.0;  // columns r..ld-1 hold zeros
+    };
+    auto bsum = [&](double v) -> double {
+        v = wave_allsum(v);
+        if (nw == 1) return v;
+        __syncthreads();
+        if (lane == 0) red[wv] = v;
+        __syncthreads();
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += red[i];
+        return s;
+    };
 
     int ncount = 0;
-    __shared__ unsigned long long tim[4];  // S formation, BK, solve, Rayleigh (thread 0)
-    if (threadIdx.x == 0) tim[0] = tim[1] = tim[2] = tim[3] = 0;
     // ---- factorisation of H - sigma through S(sigma); returns nu(sigma)
     auto factor = [&](double sigma) -> int {
         ++ncount;
@@ -484,166 +557,153 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         }
         const int nlow = lo_i;
         __syncthreads();
-        for (int i = threadIdx.x; i < dn; i += nthr) {
+        for (int i = tid; i < dn; i += nthr) {
             double den = lam[i] - sigma;
             if (den == 0.0) den = 1e-300;
             wdn[i] = 1.0 / den;
         }
-        // S partial sums: work item = (pair group g, row slice sl); a thread owns
-        // at most kMaxItems items, kept in registers across the row chunks
-        double acc[kMaxItems][kPairGroup];
-        int pa[kMaxItems][kPairGroup], pb[kMaxItems][kPairGroup];
-        const int nitems = ngroups * slices;
+        __syncthreads();
+        const int nt = (r + 15) >> 4, ntiles = nt * (nt + 1) / 2;
+        const int ksplit = ntiles >= nw ? 1 : nw / ntiles;  // row chunks per tile
+        const int chunk = ((dn + ksplit - 1) / ksplit + 3) & ~3;
+        for (int item = wv; item < ntiles * ksplit; item += nw) {  // lower tiles of C~^T W C~
+            const int t = item % ntiles, kc = item / ntiles;
+            int ta = 0;
+            while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+            const int tb = t - ta * (ta + 1) / 2;
+            const int k0 = kc * chunk, k1 = dn < k0 + chunk ? dn : k0 + chunk;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            if (k1 > k0)
+                acc = mfma_tn16([&](int i, int c) { return wdn[k0 + i] * ct(k0 + i, 16 * ta + c); },
+                                [&](int i, int c) { return ct(k0 + i, 16 * tb + c); }, k1 - k0);
+            if (ksplit == 1) {
 #pragma unroll
-        for (int j = 0; j < kMaxItems; ++j) {
-            const int item = threadIdx.x + j * nthr;
-            const int g = item < nitems ? item % ngroups : 0;
+                for (int u = 0; u < 4; ++u) {
+                    const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
+                    if (i < r && j < r && (ta != tb || i >= j)) {
+                        const double v = dt[i * ldp + j] - (i == j ? sigma : 0.0) - acc[u];
+                        S[i * ls + j] = v;
+                        S[j * ls + i] = v;
+                    }
+                }
+            } else {
 #pragma unroll
-            for (int t = 0; t < kPairGroup; ++t) {
-                int pr = g * kPairGroup + t;
-                acc[j][t] = 0.0;
-                if (pr >= npairs) pr = npairs > 0 ? npairs - 1 : 0;  // padded pairs: computed, never stored
-                int aa = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
-                while (aa * (aa + 1) / 2 > pr) --aa;
-                while ((aa + 1) * (aa + 2) / 2 <= pr) ++aa;
-                pa[j][t] = aa;
-                pb[j][t] = pr - aa * (aa + 1) / 2;
+                for (int u = 0; u < 4; ++u) red[(item * 4 + u) * kWave + lane] = acc[u];
             }
         }
-        __syncthreads();  // wdn ready
-        for (int i0 = 0; i0 < dn; i0 += chunk_rows) {
-            const int lim = dn - i0 < chunk_rows ? dn - i0 : chunk_rows;
-            if (!ct_in_lds) {
-                __syncthreads();
-                for (int e = threadIdx.x; e < lim * r; e += nthr) cch[e] = w.Ct[(int64_t)(i0 + e / r) * ld + e % r];
-                __syncthreads();
-            }
-            const double *ct = ct_in_lds ? cch + (int64_t)i0 * r : cch;
-#pragma unroll
-            for (int j = 0; j < kMaxItems; ++j) {
-                const int item = threadIdx.x + j * nthr;
-                if (item >= nitems) continue;
-                const int sl = item / ngroups;
-                for (int ii = sl; ii < lim; ii += slices) {
-                    const double wi = wdn[i0 + ii];
-                    const double *row = ct + ii * r;
-#pragma unroll
-                    for (int t = 0; t < kPairGroup; ++t) acc[j][t] += row[pa[j][t]] * row[pb[j][t]] * wi;
+        if (ksplit > 1) {
+            __syncthreads();
+            for (int e = tid; e < ntiles * 256; e += nthr) {
+                const int t = e >> 8, u = (e >> 6) & 3, ln = e & 63;
+                double v = 0.0;
+                for (int kc = 0; kc < ksplit; ++kc) v += red[((kc * ntiles + t) * 4 + u) * kWave + ln];
+                int ta = 0;
+                while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+                const int tb = t - ta * (ta + 1) / 2;
+                const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
+                if (i < r && j < r && (ta != tb || i >= j)) {
+                    v = dt[i * ldp + j] - (i == j ? sigma : 0.0) - v;
+                    S[i * ls + j] = v;
+                    S[j * ls + i] = v;
                 }
             }
         }
-#pragma unroll
-        for (int j = 0; j < kMaxItems; ++j) {
-            const int item = threadIdx.x + j * nthr;
-            if (item >= nitems) continue;
-            const int g = item % ngroups, sl = item / ngroups;
-            for (int t = 0; t < kPairGroup; ++t) {
-                const int pr = g * kPairGroup + t;
-                if (pr < npairs) part[sl * npairs + pr] = acc[j][t];
-            }
-        }
-        __syncthreads();
-        for (int pr = threadIdx.x; pr < npairs; pr += nthr) {
-            double v = 0.0;
-            for (int sl = 0; sl < slices; ++sl) v += part[sl * npairs + pr];
-            int aa = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
-            while (aa * (aa + 1) / 2 > pr) --aa;
-            while ((aa + 1) * (aa + 2) / 2 <= pr) ++aa;
-            const int bb = pr - aa * (aa + 1) / 2;
-            v = dt[aa * r + bb] - (aa == bb ? sigma : 0.0) - v;
-            S[aa * ls + bb] = v;
-            S[bb * ls + aa] = v;
-        }
         __syncthreads();
         const uint64_t f1 = wall_clock64();
-        const int neg = bk_factor(S, r, ls, ipiv, mult);
-        if (threadIdx.x == 0) {
-            const uint64_t f2 = wall_clock64();
-            tim[0] += f1 - f0;
-            tim[1] += f2 - f1;
+        const int neg = bk_factor(S, Lm, r, ls, ipiv);
+        if (tid == 0) {
+            tim[1] += f1 - f0;
+            tim[2] += wall_clock64() - f1;
         }
         return nlow + neg;
     };
 
-    // ---- sum over the dn coarse rows of C~_{i a} u_i, for all a (slices + LDS)
+    // ---- out[a] = sum over the dn coarse rows of C~_{i a} u_i (matrix cores)
     auto ct_t_times = [&](const double *u, double *out) {
-        const int sl2 = nthr / (r > 0 ? r : 1) > 0 ? nthr / (r > 0 ? r : 1) : 1;
-        for (int item = threadIdx.x; item < r * sl2; item += nthr) {
-            const int a2 = item % r, sl = item / r;
-            double s0 = 0.0, s1 = 0.0;
-            int i = sl;
-            for (; i + sl2 < dn; i += 2 * sl2) {
-                const double *c0 = ct_in_lds ? cch + (int64_t)i * r : w.Ct + (int64_t)i * ld;
-                const double *c1 = ct_in_lds ? cch + (int64_t)(i + sl2) * r : w.Ct + (int64_t)(i + sl2) * ld;
-                s0 += c0[a2] * u[i];
-                s1 += c1[a2] * u[i + sl2];
+        const int nt = (r + 15) >> 4;
+        const int ksplit = nt >= nw ? 1 : nw / nt;
+        const int chunk = ((dn + ksplit - 1) / ksplit + 3) & ~3;
+        for (int item = wv; item < nt * ksplit; item += nw) {
+            const int ta = item % nt, kc = item / nt;
+            const int k0 = kc * chunk, k1 = dn < k0 + chunk ? dn : k0 + chunk;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            if (k1 > k0)
+                acc = mfma_tn16([&](int i, int c) { return ct(k0 + i, 16 * ta + c); },
+                                [&](int i, int c) { return c == 0 ? u[k0 + i] : 0.0; }, k1 - k0);
+            if ((lane & 15) == 0) {
+#pragma unroll
+                for (int uu = 0; uu < 4; ++uu) red[(item * 4 + uu) * 4 + (lane >> 4)] = acc[uu];
             }
-            if (i < dn) s0 += (ct_in_lds ? cch[(int64_t)i * r + a2] : w.Ct[(int64_t)i * ld + a2]) * u[i];
-            part[sl * r + a2] = s0 + s1;
         }
         __syncthreads();
-        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) {
+        for (int a = tid; a < r; a += nthr) {  // a = 16 ta + 4 uu + (lane >> 4)
+            const int ta = a >> 4, rem = a & 15, uu = rem >> 2, q4 = rem & 3;
             double v = 0.0;
-            for (int sl = 0; sl < sl2; ++sl) v += part[sl * r + a2];
-            out[a2] = v;
+            for (int kc = 0; kc < ksplit; ++kc) v += red[(((kc * nt + ta) * 4 + uu) * 4) + q4];
+            out[a] = v;
         }
         __syncthreads();
     };
-    auto ct_row = [&](int i, int a2) -> double { return ct_in_lds ? cch[(int64_t)i * r + a2] : w.Ct[(int64_t)i * ld + a2]; };
 
     // ---- x <- (H - sigma)^-1 x for the factorisation in S, ipiv, wdn
     auto solve = [&](double *x) {
-        for (int i = threadIdx.x; i < dn; i += nthr) x[i] *= wdn[i];  // t = (Lambda - sigma)^-1 b_y
+        const uint64_t s0 = wall_clock64();
+        for (int i = tid; i < dn; i += nthr) x[i] *= wdn[i];  // t = (Lambda - sigma)^-1 x_y
         __syncthreads();
         ct_t_times(x, fz);
-        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) fz[a2] = x[dn + a2] - fz[a2];
+        for (int a = tid; a < r; a += nthr) fz[a] = x[dn + a] - fz[a];
         __syncthreads();
-        bk_solve(S, r, ls, ipiv, fz);
-        for (int i = threadIdx.x; i < dn; i += nthr) {
+        bk_solve(S, Lm, r, ls, ipiv, fz);
+        for (int i = tid; i < dn; i += nthr) {
             double s2 = 0.0;
-            for (int a2 = 0; a2 < r; ++a2) s2 += ct_row(i, a2) * fz[a2];
+            for (int a = 0; a < r; ++a) s2 += ct(i, a) * fz[a];
             x[i] -= s2 * wdn[i];
         }
-        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) x[dn + a2] = fz[a2];
+        for (int a = tid; a < r; a += nthr) x[dn + a] = fz[a];
         __syncthreads();
+        if (tid == 0) tim[3] += wall_clock64() - s0;
     };
     auto normalise = [&](double *x) {
         double s2 = 0.0;
-        for (int i = threadIdx.x; i < dn + r; i += nthr) s2 += x[i] * x[i];
-        s2 = block_sum(s2, red);
+        for (int i = tid; i < dn + r; i += nthr) s2 += x[i] * x[i];
+        s2 = bsum(s2);
         const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-        for (int i = threadIdx.x; i < dn + r; i += nthr) x[i] *= inv;
+        __syncthreads();
+        for (int i = tid; i < dn + r; i += nthr) x[i] *= inv;
         __syncthreads();
     };
     // rho = x^T H x (x normalised) and ||H x - rho x||
     auto rayleigh = [&](const double *x, double &rho, double &res) {
+        const uint64_t q0 = wall_clock64();
         ct_t_times(x, fz);  // C~^T y
-        for (int i = threadIdx.x; i < dn; i += nthr) {
+        for (int i = tid; i < dn; i += nthr) {
             double s2 = lam[i] * x[i];
-            for (int a2 = 0; a2 < r; ++a2) s2 += ct_row(i, a2) * x[dn + a2];
+            for (int a = 0; a < r; ++a) s2 += ct(i, a) * x[dn + a];
             hx[i] = s2;
         }
-        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) {
-            double s2 = fz[a2];
-            for (int b2 = 0; b2 < r; ++b2) s2 += dt[a2 * r + b2] * x[dn + b2];
-            hx[dn + a2] = s2;
+        for (int a = tid; a < r; a += nthr) {
+            double s2 = fz[a];
+            for (int b = 0; b < r; ++b) s2 += dt[a * ldp + b] * x[dn + b];
+            hx[dn + a] = s2;
         }
         __syncthreads();
         double q = 0.0;
-        for (int i = threadIdx.x; i < dn + r; i += nthr) q += x[i] * hx[i];
-        rho = block_sum(q, red);
+        for (int i = tid; i < dn + r; i += nthr) q += x[i] * hx[i];
+        rho = bsum(q);
         double e2 = 0.0;
-        for (int i = threadIdx.x; i < dn + r; i += nthr) {
+        for (int i = tid; i < dn + r; i += nthr) {
             const double d = hx[i] - rho * x[i];
             e2 += d * d;
         }
-        res = sqrt(block_sum(e2, red));
+        res = sqrt(bsum(e2));
+        if (tid == 0) tim[4] += wall_clock64() - q0;
     };
 
     // ---- warm start.  The corrected vector V e_k has the coordinates
     // y = G e_k, z = L^T Pi^T e_k in the basis of H (its part outside span Z is
-    // (V - Z G) e_k = W L^T Pi^T e_k); after the first correction it is close
-    // to the wanted eigenvector, so its Rayleigh quotient is a good shift.
+    // (V - Z G) e_k = W L^T Pi^T e_k with W the M-orthonormalised columns).
+    // Up to three Rayleigh-quotient steps from it; every factorisation on the
+    // way is a count that tightens the bracket.
     double lo = 0.0, hi = 0.0;
     int nulo = 0, nuhi = 1 << 30;
     bool have_lo = false, have_hi = false;
@@ -651,17 +711,39 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
     const double tp = theta_prev[k];
     const double cap = lam[k] * (1.0 + 1e-14) + 1e-300;  // interlacing: mu_k <= lambda_k
     double rho = 0.0, res = 0.0;
+    // bracket updates are value selects (a branch on which end to write would
+    // turn the ends into addressable stack slots)
+    auto note = [&](double sg, int c) __attribute__((always_inline)) {
+        const bool is_lo = c <= k;
+        const bool up_lo = is_lo && (!have_lo || sg > lo);
+        const bool up_hi = !is_lo && (!have_hi || sg < hi);
+        lo = up_lo ? sg : lo;
+        nulo = up_lo ? c : nulo;
+        have_lo = have_lo || up_lo;
+        hi = up_hi ? sg : hi;
+        nuhi = up_hi ? c : nuhi;
+        have_hi = have_hi || up_hi;
+    };
+    auto force = [&](double sg, int c) __attribute__((always_inline)) {  // replace the end on c's side
+        const bool is_lo = c <= k;
+        lo = is_lo ? sg : lo;
+        nulo = is_lo ? c : nulo;
+        have_lo = have_lo || is_lo;
+        hi = is_lo ? hi : sg;
+        nuhi = is_lo ? nuhi : c;
+        have_hi = have_hi || !is_lo;
+    };
     __shared__ int s_pos;
     const bool warm = w.status[ST_WARM] != 0;
     if (warm) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             s_pos = -1;
-            for (int a2 = 0; a2 < r; ++a2)
-                if (w.perm[a2] == k) s_pos = a2;
+            for (int a = 0; a < r; ++a)
+                if (w.perm[a] == k) s_pos = a;
         }
         __syncthreads();
         const int pos = s_pos;
-        for (int i = threadIdx.x; i < dn + r; i += nthr) {
+        for (int i = tid; i < dn + r; i += nthr) {
             double v;
             if (i < dn)
                 v = w.FG[(int64_t)i * 2 * ld + ld + k];
@@ -674,165 +756,182 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         __syncthreads();
         normalise(vec);
         rayleigh(vec, rho, res);
-        const bool ok0 = rho > 0.0 && rho < cap;
-        if (ok0 && res <= 1e-10 * fabs(rho)) {
-            // already accurate: two counts around rho decide
+        for (int it = 0; it < 3; ++it) {
+            if (res <= 1e-10 * fabs(rho) || !(rho > 0.0 && rho < cap)) break;
+            note(rho, factor(rho));
+            solve(vec);
+            normalise(vec);
+            rayleigh(vec, rho, res);
+        }
+        if (res <= 1e-10 * fabs(rho) && rho > 0.0 && rho < cap) {
+            // ends more than the residual away from rho, counted if not yet known
             const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
-            const int cl = factor(rho - span);
-            if (cl <= k) { lo = rho - span; nulo = cl; have_lo = true; }
-            const double h0 = fmin(rho + span, cap);
-            const int ch = factor(h0);
-            if (ch >= k + 1) { hi = h0; nuhi = ch; have_hi = true; }
-            done = have_lo && have_hi && nulo == k && nuhi == k + 1;
-        } else {
-            const double s0 = ok0 ? rho : (tp > 0.0 && tp < cap ? tp : -1.0);
-            if (s0 > 0.0) {
-                const double rho0 = rho;
-                const int c0 = factor(s0);
-                if (c0 <= k) { lo = s0; nulo = c0; have_lo = true; } else { hi = s0; nuhi = c0; have_hi = true; }
-                solve(vec);
-                normalise(vec);
-                rayleigh(vec, rho, res);
-                const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
-                if (have_lo && !(fabs(rho - s0) > res)) {
-                    // the shift is too close to rho to serve as the bracket end
-                    have_lo = false;
-                }
-                if (have_hi && !(fabs(rho - s0) > res)) have_hi = false;
-                if (!have_lo) {
-                    const double l0 = fmin(rho, rho0 > 0.0 ? rho0 : rho) - span;
-                    const int c1 = factor(l0);
-                    if (c1 <= k) { lo = l0; nulo = c1; have_lo = true; }
-                }
-                if (!have_hi) {
-                    const double h0 = fmin(rho + span, cap);
-                    const int c1 = factor(h0);
-                    if (c1 >= k + 1) { hi = h0; nuhi = c1; have_hi = true; }
-                }
-                if (have_lo && have_hi && nulo == k && nuhi == k + 1) {
-                    const bool inside = rho > lo && rho < hi;
-                    done = inside && res <= 1e-10 * fabs(rho) && rho - lo > res && hi - rho > res;
-                }
+            if (!(have_lo && nulo == k && rho - lo > res)) {
+                const double l0 = rho - span;
+                const int c = factor(l0);
+                if (c <= k) force(l0, c); else note(l0, c);
             }
+            if (!(have_hi && nuhi == k + 1 && hi - rho > res)) {
+                const double h0 = fmin(rho + span, cap);
+                const int c = factor(h0);
+                if (c >= k + 1) force(h0, c); else note(h0, c);
+            }
+            done = have_lo && have_hi && nulo == k && nuhi == k + 1 && rho > lo && rho < hi && rho - lo > res &&
+                   hi - rho > res;
         }
     } else {
-        for (int i = threadIdx.x; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
+        for (int i = tid; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
         __syncthreads();
     }
-    const bool have = have_lo && have_hi;
-    if (!have) {
+    if (!(have_lo && have_hi)) {
+        // Gershgorin lower bound of H; the upper end is the interlacing bound
         double g = 1e300;
-        for (int i = threadIdx.x; i < dn; i += nthr) {
+        for (int i = tid; i < dn; i += nthr) {
             double s2 = 0.0;
-            for (int a2 = 0; a2 < r; ++a2) s2 += fabs(ct_row(i, a2));
+            for (int a = 0; a < r; ++a) s2 += fabs(ct(i, a));
             g = fmin(g, lam[i] - s2);
         }
-        for (int a2 = threadIdx.x; a2 < r; a2 += nthr) {
+        for (int a = tid; a < r; a += nthr) {
             double s2 = 0.0;
-            for (int b2 = 0; b2 < r; ++b2)
-                if (b2 != a2) s2 += fabs(dt[a2 * r + b2]);
-            for (int i = 0; i < dn; ++i) s2 += fabs(ct_row(i, a2));
-            g = fmin(g, dt[a2 * r + a2] - s2);
+            for (int b = 0; b < r; ++b)
+                if (b != a) s2 += fabs(dt[a * ldp + b]);
+            for (int i = 0; i < dn; ++i) s2 += fabs(ct(i, a));
+            g = fmin(g, dt[a * ldp + a] - s2);
         }
-        red[threadIdx.x] = g;
+        for (int off = kWave / 2; off > 0; off >>= 1) g = fmin(g, __shfl_xor(g, off, kWave));
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double mn = red[0];
-            for (int t = 1; t < nthr; ++t) mn = fmin(mn, red[t]);
-            red[0] = mn;
-        }
+        if (lane == 0) red[wv] = g;
         __syncthreads();
-        const double glo = red[0];
+        double glo = red[0];
+        for (int i = 1; i < nw; ++i) glo = fmin(glo, red[i]);
         __syncthreads();
-        if (!have_hi) {
-            hi = cap;
-            nuhi = 1 << 30;  // not counted yet (at least k + 1 by interlacing)
-        }
-        if (!have_lo) {
-            lo = glo - fabs(glo) * 1e-14 - 1e-300;
-            nulo = 0;        // Gershgorin: no eigenvalue below lo
-        }
+        hi = have_hi ? hi : cap;                // not counted yet: at least k + 1 by interlacing
+        nuhi = have_hi ? nuhi : (1 << 30);
+        lo = have_lo ? lo : glo - fabs(glo) * 1e-14 - 1e-300;
+        nulo = have_lo ? nulo : 0;              // no eigenvalue below a Gershgorin bound
     }
     // ---- isolate by bisection
     for (int it = 0; it < 200 && !done; ++it) {
         if (nulo == k && nuhi == k + 1) break;
         if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;  // a cluster closer than rounding
         const double mid = 0.5 * (lo + hi);
-        const int c = factor(mid);
-        if (c >= k + 1) { hi = mid; nuhi = c; } else { lo = mid; nulo = c; }
+        force(mid, factor(mid));
     }
-    const uint64_t t_bracket = wall_clock64();
     // ---- Rayleigh-quotient iteration inside the bracket
     double sigma = (rho > lo && rho < hi) ? rho : ((tp > lo && tp < hi) ? tp : 0.5 * (lo + hi));
     for (int it = 0; it < 12 && !done; ++it) {
         const int c = factor(sigma);
-        if (c >= k + 1) { hi = fmin(hi, sigma); } else { lo = fmax(lo, sigma); }
-        const uint64_t q0 = wall_clock64();
+        const bool up = c >= k + 1;
+        hi = up ? fmin(hi, sigma) : hi;
+        lo = up ? lo : fmax(lo, sigma);
         solve(vec);
         normalise(vec);
-        const uint64_t q1 = wall_clock64();
         rayleigh(vec, rho, res);
-        if (threadIdx.x == 0) {
-            tim[2] += q1 - q0;
-            tim[3] += wall_clock64() - q1;
-        }
         const bool inside = rho > lo && rho < hi;
         if (inside && res <= 1e-10 * fabs(rho) && rho - lo > res && hi - rho > res) break;
         sigma = inside ? rho : 0.5 * (lo + hi);
         if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;
     }
-    const uint64_t t_refine = wall_clock64();
-    if (threadIdx.x == 0 && w.diag) {
+    if (tid == 0 && w.diag && (k == 0 || k == gridDim.x - 1)) {
+        tim[5] = wall_clock64() - t_begin;
+        int *slot = w.diag + (k == 0 ? 5 * kMaxWidth - 8 : 3 * kMaxWidth);
+        for (int j = 0; j < 6; ++j) atomicAdd(&slot[j], (int)tim[j]);
+    }
+    if (tid == 0 && w.diag) {
         atomicAdd(&w.diag[k], ncount);
         atomicAdd(&w.diag[kMaxWidth + k], done ? 1 : 0);
         atomicAdd(&w.diag[2 * kMaxWidth + k], 1);
     }
-    for (int i = threadIdx.x; i < dn + ld; i += nthr) w.X[(int64_t)i * ld + k] = i < dn + r ? vec[i] : 0.0;
-    const uint64_t t_end = wall_clock64();
-    if (threadIdx.x == 0 && w.diag && k == 0) {
-        atomicAdd(&w.diag[5 * kMaxWidth - 8], (int)(t_bracket - t_start_g));
-        atomicAdd(&w.diag[5 * kMaxWidth - 7], (int)(t_refine - t_bracket));
-        atomicAdd(&w.diag[5 * kMaxWidth - 6], (int)(t_end - t_refine));
-        atomicAdd(&w.diag[5 * kMaxWidth - 5], (int)tim[0]);
-        atomicAdd(&w.diag[5 * kMaxWidth - 4], (int)tim[1]);
-        atomicAdd(&w.diag[5 * kMaxWidth - 3], (int)tim[2]);
-        atomicAdd(&w.diag[5 * kMaxWidth - 2], (int)tim[3]);
-    }
+    for (int i = tid; i < dn + ld; i += nthr) w.X[(int64_t)i * ld + k] = i < dn + r ? vec[i] : 0.0;
 }
 
 // ------------------------------------------- Rayleigh-Ritz polish (a10)
+// out = X^T Y (mi x mj, row stride ostr) over rows [0, K) in 16 x 16 tiles on
+// the matrix cores.  X(i, a) and Y(i, b) return entry a (b) of row i and zero
+// for a >= mi (b >= mj).  With fewer tiles than wavefronts the rows are split
+// over the wavefronts and the partial tiles summed in a fixed order (red holds
+// 3 * 4 * 256 doubles).  Ends with a barrier.
+template <class FX, class FY>
+__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int ti = (mi + 15) >> 4, tj = (mj + 15) >> 4, ntiles = ti * tj;
+    if (K > 0 && (ntiles >= nw || nw == 1)) {
+        for (int t = wv; t < ntiles; t += nw) {
+            const int ta = t / tj, tb = t - ta * tj;
+            const dbl4 acc = mfma_tn16([&](int i, int c) { return X(i, 16 * ta + c); },
+                                       [&](int i, int c) { return Y(i, 16 * tb + c); }, K);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
+                if (i < mi && j < mj) out[i * ostr + j] = acc[u];
+            }
+        }
+    } else if (K > 0) {
+        const int chunk = ((K + nw - 1) / nw + 3) & ~3;
+        const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
+        for (int t = 0; t < ntiles; ++t) {
+            const int ta = t / tj, tb = t - ta * tj;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            if (k1 > k0)
+                acc = mfma_tn16([&](int i, int c) { return X(k0 + i, 16 * ta + c); },
+                                [&](int i, int c) { return Y(k0 + i, 16 * tb + c); }, k1 - k0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) red[((t * nw + wv) * 4 + u) * kWave + lane] = acc[u];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ntiles * 256; e += blockDim.x) {
+            const int t = e >> 8, u = (e >> 6) & 3, ln = e & 63;
+            double s = 0.0;
+            for (int v = 0; v < nw; ++v) s += red[((t * nw + v) * 4 + u) * kWave + ln];
+            const int ta = t / tj, tb = t - ta * tj;
+            const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
+            if (i < mi && j < mj) out[i * ostr + j] = s;
+        }
+    }
+    __syncthreads();
+}
+
 // One workgroup: X <- orthonormal basis of span X (two Cholesky-QR passes),
 // T = X^T H X, T = Q diag(theta) Q^T by cyclic Jacobi, Xr = X Q sorted.
 // When they fit, X, H X and C~ are copied to LDS (use_lds); otherwise the same
 // code works on the global buffers.
+constexpr int kRed = 3 * 4 * 256;
+
 __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_lds) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
     const int nh = dn + r, m = qe;
-    double *T = sm;          // m x m
-    double *Q = T + m * m;   // m x m
-    double *xs = Q + m * m;  // 32 x m staging
-    double *lamv = xs + 32 * m;  // dn
-    double *dtv = lamv + dn;     // ld x ld
-    for (int i = threadIdx.x; i < dn; i += blockDim.x) lamv[i] = w.lam[i];
-    for (int e = threadIdx.x; e < r * r; e += blockDim.x) dtv[e] = w.Dt[(e / r) * ld + e % r];
+    const int ldp = (ld + 15) & ~15;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
+    double *T = sm;                 // ldp x ldp
+    double *Q = T + ldp * ldp;      // ldp x ldp
+    double *G = Q + ldp * ldp;      // ldp x ldp
+    double *red = G + ldp * ldp;    // kRed
+    double *lamv = red + kRed;      // dn
+    double *dtv = lamv + dn;        // ldp x ldp
+    for (int i = tid; i < dn; i += nthr) lamv[i] = w.lam[i];
+    for (int e = tid; e < ldp * ldp; e += nthr) {
+        const int a = e / ldp, b = e - a * ldp;
+        dtv[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
+    }
     double *Xp = w.X, *HXp = w.HX;
     const double *Ctp = w.Ct;
-    int xst = ld, cst = ld;
     if (use_lds) {
-        double *Xl = dtv + ld * ld;
-        double *HXl = Xl + nh * m;
-        double *Ctl = HXl + nh * m;
-        for (int e = threadIdx.x; e < nh * m; e += blockDim.x) Xl[e] = w.X[(int64_t)(e / m) * ld + e % m];
-        for (int e = threadIdx.x; e < dn * r; e += blockDim.x) Ctl[e] = w.Ct[(int64_t)(e / r) * ld + e % r];
+        double *Xl = dtv + ldp * ldp;
+        double *HXl = Xl + (dn + ld) * ld;
+        double *Ctl = HXl + (dn + ld) * ld;
+        for (int e = tid; e < nh * ld; e += nthr) Xl[e] = w.X[e];
+        for (int e = tid; e < dn * ld; e += nthr) Ctl[e] = w.Ct[e];
         Xp = Xl;
         HXp = HXl;
         Ctp = Ctl;
-        xst = m;
-        cst = r;
     }
     __syncthreads();
+    auto xa = [&](int i, int c) -> double { return c < m ? Xp[(int64_t)i * ld + c] : 0.0; };
+    auto hxa = [&](int i, int c) -> double { return c < m ? HXp[(int64_t)i * ld + c] : 0.0; };
+    auto cta = [&](int i, int a) -> double { return a < r ? Ctp[(int64_t)i * ld + a] : 0.0; };
     __shared__ double cs[kMaxWidth];
     __shared__ double sn[kMaxWidth];
     __shared__ int pairs[kMaxWidth];
@@ -841,94 +940,67 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     __shared__ double s_theta[kMaxWidth];
     // ---- two Cholesky-QR passes on X (nh x m)
     for (int pass = 0; pass < 2; ++pass) {
-        double acc[(kMaxWidth * kMaxWidth + kB - 1) / kB];
-        const int per = (m * m + kB - 1) / kB;
-        for (int t = 0; t < per; ++t) acc[t] = 0.0;
-        for (int i0 = 0; i0 < nh; i0 += 32) {
-            const int lim = nh - i0 < 32 ? nh - i0 : 32;
-            __syncthreads();
-            for (int e = threadIdx.x; e < lim * m; e += blockDim.x) xs[e] = Xp[(int64_t)(i0 + e / m) * xst + e % m];
-            __syncthreads();
-            for (int t = 0; t < per; ++t) {
-                const int e = threadIdx.x + t * kB;
-                if (e >= m * m) break;
-                const int a = e / m, b = e % m;
-                double s2 = 0.0;
-                for (int ii = 0; ii < lim; ++ii) s2 += xs[ii * m + a] * xs[ii * m + b];
-                acc[t] += s2;
-            }
-        }
-        __syncthreads();
-        for (int t = 0; t < per; ++t) {
-            const int e = threadIdx.x + t * kB;
-            if (e < m * m) T[e] = acc[t];
-        }
-        __syncthreads();
-        for (int p = 0; p < m; ++p) {  // T = L L^T in place (lower)
-            double d = T[p * m + p];
+        block_xty(xa, xa, nh, m, m, G, ldp, red);
+        for (int p = 0; p < m; ++p) {  // G = L L^T in place (lower)
+            double d = G[p * ldp + p];
             if (!(d > 0.0)) {
-                if (threadIdx.x == 0) w.status[ST_BREAKDOWN] = 1;
+                if (tid == 0) w.status[ST_BREAKDOWN] = 1;
                 d = 1e-300;
             }
             const double lpp = sqrt(d);
             __syncthreads();
-            for (int i = p + 1 + threadIdx.x; i < m; i += blockDim.x) T[i * m + p] /= lpp;
-            if (threadIdx.x == 0) T[p * m + p] = lpp;
+            for (int i = p + 1 + tid; i < m; i += nthr) G[i * ldp + p] /= lpp;
+            if (tid == 0) G[p * ldp + p] = lpp;
             __syncthreads();
             const int mm = m - p - 1;
-            for (int e = threadIdx.x; e < mm * mm; e += blockDim.x) {
+            for (int e = tid; e < mm * mm; e += nthr) {
                 const int i = p + 1 + e / mm, j = p + 1 + e % mm;
-                if (j <= i) T[i * m + j] -= T[i * m + p] * T[j * m + p];
+                if (j <= i) G[i * ldp + j] -= G[i * ldp + p] * G[j * ldp + p];
             }
             __syncthreads();
         }
-        for (int i = threadIdx.x; i < nh; i += blockDim.x) {  // x <- x L^-T
-            double z[kMaxWidth];
-            double *xr = Xp + (int64_t)i * xst;
+        for (int i = tid; i < nh; i += nthr) {  // row i <- row i L^-T, in place
+            double *xr = Xp + (int64_t)i * ld;
             for (int c = 0; c < m; ++c) {
                 double s2 = xr[c];
-                for (int a2 = 0; a2 < c; ++a2) s2 -= z[a2] * T[c * m + a2];
-                z[c] = s2 / T[c * m + c];
+                for (int a = 0; a < c; ++a) s2 -= xr[a] * G[c * ldp + a];
+                xr[c] = s2 / G[c * ldp + c];
             }
-            for (int c = 0; c < m; ++c) xr[c] = z[c];
         }
         __syncthreads();
     }
     // ---- HX (nh x m): rows i < dn: lam_i x_i + C~_i z ; rows dn+a: C~^T y + D~ z
-    for (int e = threadIdx.x; e < dn * m; e += blockDim.x) {
-        const int i = e / m, c = e % m;
-        double s2 = lamv[i] * Xp[(int64_t)i * xst + c];
-        for (int a2 = 0; a2 < r; ++a2) s2 += Ctp[(int64_t)i * cst + a2] * Xp[(int64_t)(dn + a2) * xst + c];
-        HXp[(int64_t)i * xst + c] = s2;
+    for (int e = tid; e < dn * m; e += nthr) {
+        const int i = e / m, c = e - i * m;
+        double s2 = lamv[i] * Xp[(int64_t)i * ld + c];
+        for (int a = 0; a < r; ++a) s2 += Ctp[(int64_t)i * ld + a] * Xp[(int64_t)(dn + a) * ld + c];
+        HXp[(int64_t)i * ld + c] = s2;
     }
-    for (int e = threadIdx.x; e < r * m; e += blockDim.x) {
-        const int a2 = e / m, c = e % m;
+    block_xty(cta, xa, dn, r, m, HXp + (int64_t)dn * ld, ld, red);
+    for (int e = tid; e < r * m; e += nthr) {
+        const int a = e / m, c = e - a * m;
         double s2 = 0.0;
-        for (int i = 0; i < dn; ++i) s2 += Ctp[(int64_t)i * cst + a2] * Xp[(int64_t)i * xst + c];
-        for (int b2 = 0; b2 < r; ++b2) s2 += dtv[a2 * r + b2] * Xp[(int64_t)(dn + b2) * xst + c];
-        HXp[(int64_t)(dn + a2) * xst + c] = s2;
+        for (int b = 0; b < r; ++b) s2 += dtv[a * ldp + b] * Xp[(int64_t)(dn + b) * ld + c];
+        HXp[(int64_t)(dn + a) * ld + c] += s2;
     }
     __syncthreads();
     // ---- T = X^T HX, symmetrised
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        const int a2 = e / m, b2 = e % m;
-        double s2 = 0.0;
-        for (int i = 0; i < nh; ++i) s2 += Xp[(int64_t)i * xst + a2] * HXp[(int64_t)i * xst + b2];
-        Q[e] = s2;
+    block_xty(xa, hxa, nh, m, m, Q, ldp, red);
+    for (int e = tid; e < m * m; e += nthr) {
+        const int a = e / m, b = e - a * m;
+        T[a * ldp + b] = 0.5 * (Q[a * ldp + b] + Q[b * ldp + a]);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-        const int a2 = e / m, b2 = e % m;
-        T[e] = 0.5 * (Q[a2 * m + b2] + Q[b2 * m + a2]);
+    for (int e = tid; e < m * m; e += nthr) {
+        const int a = e / m, b = e - a * m;
+        Q[a * ldp + b] = a == b ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) Q[e] = (e / m == e % m) ? 1.0 : 0.0;
     __syncthreads();
     // ---- cyclic Jacobi with the round-robin ordering (m even)
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int round = 0; round < m - 1; ++round) {
-            if ((int)threadIdx.x < m / 2) {
-                const int k2 = threadIdx.x;
+            if (tid < m / 2) {
+                const int k2 = tid;
                 auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1; };
                 int p = player(k2), q = player(m - 1 - k2);
                 if (p > q) {
@@ -938,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
                 }
                 pairs[2 * k2] = p;
                 pairs[2 * k2 + 1] = q;
-                const double apq = T[p * m + q], app = T[p * m + p], aqq = T[q * m + q];
+                const double apq = T[p * ldp + q], app = T[p * ldp + p], aqq = T[q * ldp + q];
                 double c = 1.0, sv = 0.0;
                 if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(app * aqq))) {
                     const double tau = (aqq - app) / (2.0 * apq);
@@ -950,62 +1022,68 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
                 sn[k2] = sv;
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < (m / 2) * m; e += blockDim.x) {  // rows: J^T T
-                const int k2 = e / m, j = e % m, p = pairs[2 * k2], q = pairs[2 * k2 + 1];
+            for (int e = tid; e < (m / 2) * m; e += nthr) {  // rows: J^T T
+                const int k2 = e / m, j = e - k2 * m, p = pairs[2 * k2], q = pairs[2 * k2 + 1];
                 const double c = cs[k2], sv = sn[k2];
-                const double tp = T[p * m + j], tq = T[q * m + j];
-                T[p * m + j] = c * tp - sv * tq;
-                T[q * m + j] = sv * tp + c * tq;
+                const double tp = T[p * ldp + j], tq = T[q * ldp + j];
+                T[p * ldp + j] = c * tp - sv * tq;
+                T[q * ldp + j] = sv * tp + c * tq;
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < (m / 2) * m; e += blockDim.x) {  // columns: T J, Q J
-                const int k2 = e / m, i = e % m, p = pairs[2 * k2], q = pairs[2 * k2 + 1];
+            for (int e = tid; e < (m / 2) * m; e += nthr) {  // columns: T J, Q J
+                const int k2 = e / m, i = e - k2 * m, p = pairs[2 * k2], q = pairs[2 * k2 + 1];
                 const double c = cs[k2], sv = sn[k2];
-                const double tp = T[i * m + p], tq = T[i * m + q];
-                T[i * m + p] = c * tp - sv * tq;
-                T[i * m + q] = sv * tp + c * tq;
-                const double qp = Q[i * m + p], qq = Q[i * m + q];
-                Q[i * m + p] = c * qp - sv * qq;
-                Q[i * m + q] = sv * qp + c * qq;
+                const double tp = T[i * ldp + p], tq = T[i * ldp + q];
+                T[i * ldp + p] = c * tp - sv * tq;
+                T[i * ldp + q] = sv * tp + c * tq;
+                const double qp = Q[i * ldp + p], qq = Q[i * ldp + q];
+                Q[i * ldp + p] = c * qp - sv * qq;
+                Q[i * ldp + q] = sv * qp + c * qq;
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            double off = 0.0;
-            for (int a2 = 0; a2 < m; ++a2)
-                for (int b2 = 0; b2 < m; ++b2)
-                    if (a2 != b2) off = fmax(off, fabs(T[a2 * m + b2]) / sqrt(fabs(T[a2 * m + a2] * T[b2 * m + b2]) + 1e-300));
-            s_off = off;
+        double off = 0.0;  // largest scaled off-diagonal entry
+        for (int e = tid; e < m * m; e += nthr) {
+            const int a = e / m, b = e - a * m;
+            if (a != b)
+                off = fmax(off, fabs(T[a * ldp + b]) / sqrt(fabs(T[a * ldp + a] * T[b * ldp + b]) + 1e-300));
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, kWave));
+        if (lane == 0) red[wv] = off;
+        __syncthreads();
+        if (tid == 0) {
+            double mx = red[0];
+            for (int i = 1; i < nw; ++i) mx = fmax(mx, red[i]);
+            s_off = mx;
+            if (w.diag) atomicAdd(&w.diag[4 * kMaxWidth], 1);
         }
         __syncthreads();
-        if (threadIdx.x == 0 && w.diag) atomicAdd(&w.diag[4 * kMaxWidth], 1);
         if (s_off < 1e-15) break;
-        __syncthreads();
     }
     // ---- sort Ritz values ascending and write Xr = X Q(:, order), theta
-    if (threadIdx.x == 0) {
-        for (int a2 = 0; a2 < m; ++a2) {
-            order[a2] = a2;
-            s_theta[a2] = T[a2 * m + a2];
+    if (tid == 0) {
+        for (int a = 0; a < m; ++a) {
+            order[a] = a;
+            s_theta[a] = T[a * ldp + a];
         }
-        for (int a2 = 1; a2 < m; ++a2) {  // insertion sort, stable
-            const int oa = order[a2];
-            int b2 = a2 - 1;
-            while (b2 >= 0 && s_theta[order[b2]] > s_theta[oa]) {
-                order[b2 + 1] = order[b2];
-                --b2;
+        for (int a = 1; a < m; ++a) {  // insertion sort, stable
+            const int oa = order[a];
+            int b = a - 1;
+            while (b >= 0 && s_theta[order[b]] > s_theta[oa]) {
+                order[b + 1] = order[b];
+                --b;
             }
-            order[b2 + 1] = oa;
+            order[b + 1] = oa;
         }
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < m; c += blockDim.x) w.theta[c] = s_theta[order[c]];
-    for (int e = threadIdx.x; e < (dn + ld) * ld; e += blockDim.x) {
-        const int i = e / ld, c = e % ld;
+    for (int c = tid; c < m; c += nthr) w.theta[c] = s_theta[order[c]];
+    for (int e = tid; e < (dn + ld) * ld; e += nthr) {
+        const int i = e / ld, c = e - i * ld;
         double v = 0.0;
         if (i < nh && c < m) {
             const int oc = order[c];
-            for (int a2 = 0; a2 < m; ++a2) v += Xp[(int64_t)i * xst + a2] * Q[a2 * m + oc];
+            for (int a = 0; a < m; ++a) v += Xp[(int64_t)i * ld + a] * Q[a * ldp + oc];
         }
         w.Xr[(int64_t)i * ld + c] = v;
     }
@@ -1018,23 +1096,28 @@ __global__ __launch_bounds__(256) void k_recombine_coeffs(SmallWork w) {
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
     double *Xv = sm;             // ld x ld
-    double *L1 = Xv + ld * ld;   // ld x ld
-    double *z = L1 + ld * ld;    // r x ld
-    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) {
-        Xv[e] = 0.0;
-        L1[e] = w.L1[e];
-    }
+    double *Li = Xv + ld * ld;   // ld x ld: L^-1
+    double *z = Li + ld * ld;    // r x ld
+    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) Xv[e] = 0.0;
     for (int e = threadIdx.x; e < r * ld; e += blockDim.x) z[e] = w.Xr[(int64_t)(dn + e / ld) * ld + e % ld];
-    __syncthreads();
-    if ((int)threadIdx.x < ld) {
+    if ((int)threadIdx.x < r) {  // column c of L^-1 by thread c
         const int c = threadIdx.x;
-        double t[kMaxWidth];
-        for (int a = r - 1; a >= 0; --a) {
-            double s = z[a * ld + c];
-            for (int b = a + 1; b < r; ++b) s -= L1[b * ld + a] * t[b];
-            t[a] = s / L1[a * ld + a];
+        for (int i = 0; i < r; ++i) {
+            double v = 0.0;
+            if (i >= c) {
+                v = i == c ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) v -= w.L1[i * ld + k] * Li[k * ld + c];
+                v /= w.L1[i * ld + i];
+            }
+            Li[i * ld + c] = v;
         }
-        for (int a = 0; a < r; ++a) Xv[w.perm[a] * ld + c] = t[a];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * ld; e += blockDim.x) {  // (L^-T z)[a][c]
+        const int a = e / ld, c = e - a * ld;
+        double v = 0.0;
+        for (int b = a; b < r; ++b) v += Li[b * ld + a] * z[b * ld + c];
+        Xv[w.perm[a] * ld + c] = v;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) w.Xv[e] = Xv[e];
@@ -1069,24 +1152,17 @@ void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
 }
 
 void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, const double *theta_prev) {
-    const int r = w.ld;  // upper bound of the rank
-    const int ct_in_lds = (int64_t)w.dn * r <= 8192 ? 1 : 0;
-    const size_t rows = ct_in_lds ? (size_t)w.dn : 64;
-    const int threads = r <= 32 ? 64 : 256;
-    const size_t npairs = (size_t)r * (r + 1) / 2;
-    const size_t ngroups = (npairs + 7) / 8;
-    const size_t slices = ngroups >= (size_t)threads ? 1 : threads / ngroups;
-    size_t partsz = slices * npairs;
-    if (partsz < (size_t)threads) partsz = threads;  // also holds the C~^T u partials
-    const size_t lds = ((size_t)r * (r + 1) + rows * r + (size_t)w.dn + 2 * ((size_t)w.dn + r) + r + (size_t)w.dn +
-                        (size_t)r * r + 4 * (size_t)r + partsz) * sizeof(double);
+    // the rank r <= ld is only known on the device: size for r = ld
+    const size_t ldp = ((size_t)w.ld + 15) & ~(size_t)15, dn = w.dn;
+    const int threads = kB;
+    const size_t base = 2 * ldp * (ldp + 1) + dn + 2 * (dn + ldp) + ldp + dn + ldp * ldp + 1024 + 64;
+    const int ct_in_lds = (base + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    const size_t lds = (base + (ct_in_lds ? dn * ldp : 0)) * sizeof(double);
     hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta_prev, ct_in_lds);
-    // the rank is only known on the device: size the LDS path for r = ld
-    const size_t base = 2 * (size_t)qe * qe + 32 * (size_t)qe + (size_t)w.dn + (size_t)w.ld * w.ld;
-    const size_t nh = (size_t)w.dn + w.ld;
-    const size_t full = base + 2 * nh * qe + (size_t)w.dn * w.ld;
+    const size_t rbase = 3 * ldp * ldp + kRed + dn + ldp * ldp;
+    const size_t full = rbase + 2 * (dn + w.ld) * w.ld + dn * w.ld;
     const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
-    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), (use_lds ? full : base) * sizeof(double), s, w, qe, use_lds);
+    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), (use_lds ? full : rbase) * sizeof(double), s, w, qe, use_lds);
 }
 
 void launch_recombine_coeffs(hipStream_t s, const SmallWork &w) {

@@ -94,23 +94,36 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32
     }
 }
 
-// Residual norms: fin[e] = sum over blocks of part[b][e] (one wavefront per
-// sum, lanes strided over blocks, fixed butterfly), then
-// rho_j = sqrt(sum R_j^2) / (|theta_j| sqrt(sum (MU)_j^2)) and the convergence
-// test max_{j < q} rho_j <= tol.
+// Residual norms: one workgroup per sum fin[e] = sum over blocks of
+// part[b][e] (threads strided over blocks, fixed-order tree), then the last
+// workgroup to finish forms rho_j = sqrt(sum R_j^2) / (|theta_j| sqrt(sum (MU)_j^2))
+// and the convergence test max_{j < q} rho_j <= tol.
 __global__ __launch_bounds__(256) void k_residual_finish(int64_t nb, int ld, const double *__restrict__ part,
+                                                         double *__restrict__ fin, unsigned *counter,
                                                          const double *__restrict__ theta, double *__restrict__ rho,
                                                          int q, double tol, int *status, int check) {
-    __shared__ double fin[2 * 128];
+    __shared__ double red[256 / kWave];
     if (status[ST_CONVERGED]) return;
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    for (int e = wv; e < 2 * ld; e += nw) {
-        double sum = 0.0;
-        for (int64_t b = lane; b < nb; b += kWave) sum += part[b * 2 * ld + e];
-        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-        if (lane == 0) fin[e] = sum;
+    const int e = blockIdx.x, w2 = 2 * ld;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t b = threadIdx.x;
+    for (; b + 3 * 256 < nb; b += 4 * 256) {
+        s0 += part[b * w2 + e];
+        s1 += part[(b + 256) * w2 + e];
+        s2 += part[(b + 512) * w2 + e];
+        s3 += part[(b + 768) * w2 + e];
     }
+    for (; b < nb; b += 256) s0 += part[b * w2 + e];
+    double v = (s0 + s1) + (s2 + s3);
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += red[i];
+        fin[e] = t;
+    }
+    if (!last_block(counter)) return;
     if ((int)threadIdx.x < ld) {
         const int j = threadIdx.x;
         rho[j] = sqrt(fin[2 * j]) / (fabs(theta[j]) * sqrt(fin[2 * j + 1]));
@@ -434,11 +447,13 @@ template <typename TO>
 void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                      const double *m, const double *U, const double *theta, TO *R, double *part,
                      unsigned *counter, double *rho, int q, double tol, int *status, int check) {
+    // part: 2 ld final sums, then nb x 2 ld per-block partials
     const int64_t nb = residual_blocks(n, ld);
-    (void)counter;
+    double *blocks = part + 2 * ld;
     DISPATCH_CPT(ld, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
-                                        col, a, m, U, theta, R, part, status));
-    hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(kBlock), 0, s, nb, ld, part, theta, rho, q, tol, status, check);
+                                        col, a, m, U, theta, R, blocks, status));
+    hipLaunchKernelGGL(k_residual_finish, dim3(2 * ld), dim3(kBlock), 0, s, nb, ld, blocks, part, counter, theta, rho,
+                       q, tol, status, check);
 }
 
 template <typename T>
