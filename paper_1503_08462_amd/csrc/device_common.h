@@ -127,4 +127,98 @@ __device__ __forceinline__ bool last_block(unsigned *counter) {
     return is_last;
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 tile of X^T Y over rows [0, K) on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// D[i][j] in lane j + 16 (i mod 4), register i / 4).  X(i, c) and Y(i, c)
+// return column c (0..15) of the tile operand in row i.  One wavefront, all
+// lanes active.  Element (4u + (lane >> 4), lane & 15) of the result is in
+// component u.
+template <class FX, class FY>
+__device__ __forceinline__ dbl4 mfma_tn16(const FX &X, const FY &Y, int K) {
+    const int lane = threadIdx.x & (kWave - 1), kk = lane >> 4, c = lane & 15;
+    dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+    int base = 0;
+    for (; base + 16 <= K; base += 16) {  // operands of four steps loaded ahead of the products
+        const int i0 = base + kk;
+        const double x0 = X(i0, c), y0 = Y(i0, c), x1 = X(i0 + 4, c), y1 = Y(i0 + 4, c);
+        const double x2 = X(i0 + 8, c), y2 = Y(i0 + 8, c), x3 = X(i0 + 12, c), y3 = Y(i0 + 12, c);
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, a1, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, y2, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x3, y3, a1, 0, 0, 0);
+    }
+    for (; base < K; base += 4) {
+        const int i0 = base + kk;
+        const int ic = i0 < K ? i0 : K - 1;  // clamped: never reads past row K - 1
+        double x = X(ic, c), y = Y(ic, c);
+        if (i0 >= K) x = y = 0.0;
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, a0, 0, 0, 0);
+    }
+    return a0 + a1;
+}
+
+// out = X^T Y (mi x mj, row stride ostr) over rows [0, K) in 16 x 16 tiles on
+// the matrix cores.  X(i, a) and Y(i, b) return entry a (b) of row i and zero
+// for a >= mi (b >= mj).  With fewer tiles than wavefronts the rows are split
+// over the wavefronts and the partial tiles summed in a fixed order (red holds
+// 3 * 4 * 256 doubles).  Ends with a barrier.
+template <class FX, class FY>
+__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int ti = (mi + 15) >> 4, tj = (mj + 15) >> 4, ntiles = ti * tj;
+    if (K > 0 && (ntiles >= nw || nw == 1)) {
+        for (int t = wv; t < ntiles; t += nw) {
+            const int ta = t / tj, tb = t - ta * tj;
+            const dbl4 acc = mfma_tn16([&](int i, int c) { return X(i, 16 * ta + c); },
+                                       [&](int i, int c) { return Y(i, 16 * tb + c); }, K);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
+                if (i < mi && j < mj) out[i * ostr + j] = acc[u];
+            }
+        }
+    } else if (K > 0) {
+        const int chunk = ((K + nw - 1) / nw + 3) & ~3;
+        const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
+        for (int t = 0; t < ntiles; ++t) {
+            const int ta = t / tj, tb = t - ta * tj;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            if (k1 > k0)
+                acc = mfma_tn16([&](int i, int c) { return X(k0 + i, 16 * ta + c); },
+                                [&](int i, int c) { return Y(k0 + i, 16 * tb + c); }, k1 - k0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) red[((t * nw + wv) * 4 + u) * kWave + lane] = acc[u];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ntiles * 256; e += blockDim.x) {
+            const int t = e >> 8, u = (e >> 6) & 3, ln = e & 63;
+            double s = 0.0;
+            for (int v = 0; v < nw; ++v) s += red[((t * nw + v) * 4 + u) * kWave + ln];
+            const int ta = t / tj, tb = t - ta * tj;
+            const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
+            if (i < mi && j < mj) out[i * ostr + j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Workgroup copy of n doubles (n even, both pointers 16-byte aligned) as
+// double2, four loads in flight per thread.
+__device__ __forceinline__ void block_copy(double *dst, const double *src, int n) {
+    const int n2 = n / 2, nthr = blockDim.x;
+    const double2 *s2 = reinterpret_cast<const double2 *>(src);
+    double2 *d2 = reinterpret_cast<double2 *>(dst);
+    int e = threadIdx.x;
+    for (; e + 3 * nthr < n2; e += 4 * nthr) {
+        const double2 a = s2[e], b = s2[e + nthr], c = s2[e + 2 * nthr], d = s2[e + 3 * nthr];
+        d2[e] = a;
+        d2[e + nthr] = b;
+        d2[e + 2 * nthr] = c;
+        d2[e + 3 * nthr] = d;
+    }
+    for (; e < n2; e += nthr) d2[e] = s2[e];
+}
+
 }  // namespace amgeig

@@ -60,7 +60,7 @@ struct amg_eig_ctx {
     size_t need = 0;
     std::vector<DevLevel> dl;
     double *U = nullptr, *V = nullptr, *W = nullptr;
-    double *Z = nullptr, *lam = nullptr, *Yn = nullptr;
+    double *Z = nullptr, *Zt = nullptr, *lam = nullptr, *Yn = nullptr;
     void *Ainv = nullptr;
     double *theta = nullptr, *rho = nullptr, *part_res = nullptr, *part_gram = nullptr;
     unsigned *counters = nullptr;
@@ -132,6 +132,7 @@ void plan(amg_eig_ctx *c, char *base) {
     c->V = cv.take<double>((size_t)N * ld);
     c->W = cv.take<double>((size_t)N * 2 * ld);
     c->Z = cv.take<double>((size_t)dn * dn);
+    c->Zt = cv.take<double>((size_t)dn * dn);
     c->lam = cv.take<double>(dn);
     c->Ainv = cv.take<char>((size_t)dn * dn * sT);
     c->Yn = cv.take<double>((size_t)dn * ld);
@@ -177,6 +178,13 @@ std::vector<T> narrow_ptr(const std::vector<int64_t> &p) {
     std::vector<T> r(p.size());
     for (size_t i = 0; i < p.size(); ++i) r[i] = (T)p[i];
     return r;
+}
+
+std::vector<double> transposed(const std::vector<double> &a, int n) {  // n x n row-major
+    std::vector<double> t(a.size());
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) t[(size_t)j * n + i] = a[(size_t)i * n + j];
+    return t;
 }
 
 template <typename T>
@@ -229,8 +237,9 @@ int upload_levels(amg_eig_ctx *c) {
     }
     const int dn = H.dn;
     rc |= upload_vec(c, c->Z, H.Z);
+    rc |= upload_vec(c, c->Zt, transposed(H.Z, H.dn));
     rc |= upload_vec(c, c->lam, H.lam);
-    rc |= upload_vec(c, c->Ainv, convert<T>(H.Ainv));
+    rc |= upload_vec(c, c->Ainv, convert<T>(transposed(H.Ainv, H.dn)));  // used as (A^-1)^T^T
     return rc ? AMG_EIG_EHIP : AMG_EIG_OK;
 }
 
@@ -310,8 +319,8 @@ void vcycle(amg_eig_ctx *c, int k) {
         launch_spmm<T>(s, e.n, ld, d.pt_ptr, d.pt_col, (const T *)d.pt_val, (const T *)d.r, (T *)e.b, st);
     }
     DevLevel &cl = c->dl[L - 1];
-    launch_gemm_small<T>(s, false, (int)cl.n, ld, (int)cl.n, (const T *)c->Ainv, (int)cl.n, (const T *)cl.b, ld,
-                         (T *)cl.x, ld, st);
+    launch_gemm_tn<T>(s, (int)cl.n, ld, (int)cl.n, (const T *)c->Ainv, (int)cl.n, (const T *)cl.b, ld, (T *)cl.x, ld,
+                      st);
     for (int l = L - 2; l >= k; --l) {
         DevLevel &d = c->dl[l];
         DevLevel &e = c->dl[l + 1];
@@ -346,12 +355,10 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
     }
     {
         SiteScope sc(c, AMG_EIG_SITE_SMALL, k);
-        launch_gemm_small<double>(s, true, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
-        launch_small_products(s, c->sw);
+        launch_gemm_tn<double>(s, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
         launch_pencil(s, c->sw, 1e-13);
-        launch_arrow_eig(s, c->sw, c->qe, c->theta);
-        launch_recombine_coeffs(s, c->sw);
-        launch_gemm_small<double>(s, false, dn, ld, dn, c->Z, dn, c->sw.Xc, ld, c->Yn, ld, st);
+        launch_arrow_eig(s, c->sw, c->qe, c->theta, k == 0 ? 1 : 0);
+        launch_gemm_tn<double>(s, dn, ld, dn, c->Zt, dn, c->sw.Xc, ld, c->Yn, ld, st);
     }
     const double *y = c->Yn;
     for (int l = L - 2; l > k; --l) {
@@ -363,7 +370,6 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
         SiteScope sc(c, AMG_EIG_SITE_FINAL, k);
         launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, y, c->V, c->sw.Xv, c->U, st);
     }
-    launch_theta_update(s, c->sw, c->theta, k == 0 ? 1 : 0);
 }
 
 template <typename T>

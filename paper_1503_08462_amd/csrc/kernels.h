@@ -40,9 +40,10 @@ void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int3
 template <typename T, typename TA>
 void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
                        const int *status);
+// C (m x n) = A^T B, A K x m, B K x n (row-major), FP64 matrix-core accumulation
 template <typename T>
-void launch_gemm_small(hipStream_t s, bool transA, int m, int n, int K, const T *A, int lda, const T *B, int ldb,
-                       T *C, int ldc, const int *status);
+void launch_gemm_tn(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,
+                    const int *status);
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                       const double *m, const double *V, double *W, const int *status);
 void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
@@ -76,10 +77,9 @@ struct SmallWork {
     int *status = nullptr;
     int *diag = nullptr;          // 4 * kMaxWidth + 8 counters (solver statistics)
 };
-void launch_small_products(hipStream_t s, const SmallWork &w);
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);
-void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, const double *theta_prev);
-void launch_recombine_coeffs(hipStream_t s, const SmallWork &w);
-void launch_theta_update(hipStream_t s, const SmallWork &w, double *theta_out, int final_level);
+// eigenpairs of H, Ritz polish and recombination coefficients; theta holds the
+// previous Ritz values on entry and the new ones on exit
+void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level);
 
 }  // namespace amgeig

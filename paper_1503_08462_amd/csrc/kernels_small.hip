@@ -29,8 +29,6 @@ namespace {
 constexpr int kB = 256;  // threads per block of the small kernels
 
 // ---------------------------------------------------------------------
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
 // Value of v in lane `src` of the wavefront (src must be wave-uniform).
 __device__ __forceinline__ double lane_bcast(double v, int src) {
     src = __builtin_amdgcn_readfirstlane(src);
@@ -44,36 +42,6 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 __device__ __forceinline__ double wave_allsum(double v) {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
-}
-
-// One 16 x 16 tile of X^T Y over rows [0, K) on the FP64 matrix cores
-// (v_mfma_f64_16x16x4: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
-// D[i][j] in lane j + 16 (i mod 4), register i / 4).  X(i, c) and Y(i, c)
-// return column c (0..15) of the tile operand in row i.  One wavefront, all
-// lanes active.  Element (4u + (lane >> 4), lane & 15) of the result is in
-// component u.
-template <class FX, class FY>
-__device__ __forceinline__ dbl4 mfma_tn16(const FX &X, const FY &Y, int K) {
-    const int lane = threadIdx.x & (kWave - 1), kk = lane >> 4, c = lane & 15;
-    dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
-    int base = 0;
-    for (; base + 16 <= K; base += 16) {  // operands of four steps loaded ahead of the products
-        const int i0 = base + kk;
-        const double x0 = X(i0, c), y0 = Y(i0, c), x1 = X(i0 + 4, c), y1 = Y(i0 + 4, c);
-        const double x2 = X(i0 + 8, c), y2 = Y(i0 + 8, c), x3 = X(i0 + 12, c), y3 = Y(i0 + 12, c);
-        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, a1, 0, 0, 0);
-        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, y2, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x3, y3, a1, 0, 0, 0);
-    }
-    for (; base < K; base += 4) {
-        const int i0 = base + kk;
-        const int ic = i0 < K ? i0 : K - 1;  // clamped: never reads past row K - 1
-        double x = X(ic, c), y = Y(ic, c);
-        if (i0 >= K) x = y = 0.0;
-        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, a0, 0, 0, 0);
-    }
-    return a0 + a1;
 }
 
 // Bunch-Kaufman symmetric indefinite LDL^T of S (r x r, LDS, row stride ls).
@@ -297,175 +265,153 @@ __device__ __forceinline__ double start_entry(int k, int i) {
 
 }  // namespace
 
-// ------------------------------------------------------------- products
-// P3 = G^T [F | G | Lambda G] (ld x 3ld) over the dn coarse rows.
-__global__ __launch_bounds__(256) void k_small_products(int dn, int ld, const double *__restrict__ lam,
-                                                        const double *__restrict__ FG, double *__restrict__ P3,
-                                                        const int *status) {
-    __shared__ double xs[64][17];
-    __shared__ double ys[64][17];
-    if (status[ST_CONVERGED]) return;
-    const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
-    const int ta = threadIdx.x / 16, tb = threadIdx.x % 16;
-    double acc = 0.0;
-    for (int i0 = 0; i0 < dn; i0 += 64) {
-        for (int e = threadIdx.x; e < 64 * 16; e += blockDim.x) {
-            const int ii = e / 16, cc = e % 16, i = i0 + ii;
-            double xv = 0.0, yv = 0.0;
-            if (i < dn) {
-                const int a = a0 + cc, b = b0 + cc;
-                if (a < ld) xv = FG[(int64_t)i * 2 * ld + ld + a];
-                if (b < ld)
-                    yv = FG[(int64_t)i * 2 * ld + b];
-                else if (b < 2 * ld)
-                    yv = FG[(int64_t)i * 2 * ld + ld + (b - ld)];
-                else if (b < 3 * ld)
-                    yv = lam[i] * FG[(int64_t)i * 2 * ld + ld + (b - 2 * ld)];
-            }
-            xs[ii][cc] = xv;
-            ys[ii][cc] = yv;
-        }
-        __syncthreads();
-        const int lim = dn - i0 < 64 ? dn - i0 : 64;
-        for (int ii = 0; ii < lim; ++ii) acc += xs[ii][ta] * ys[ii][tb];
-        __syncthreads();
-    }
-    const int a = a0 + ta, b = b0 + tb;
-    if (a < ld && b < 3 * ld) P3[a * 3 * ld + b] = acc;
-}
-
 // ------------------------------------------------------------- pencil (a9)
-__global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol) {
+// One workgroup.  P3 = G^T [F | G | Lambda G] on the matrix cores, the Gram
+// blocks D_M, D_A of the part of V outside the coarse space, a pivoted
+// Cholesky D_M(perm, perm) = L L^T stopped at rank r (pivot below
+// rank_tol * max diag(V^T M V)), D~ = L^-1 D_A(perm_r, perm_r) L^-T and
+// C~ = (F - Lambda G)(:, perm_r) L^-T.  The pivot choice is evaluated by every
+// thread from the shared diagonal (no broadcast through shared memory).
+constexpr int kRedSmall = 3 * 4 * 256;
+
+__global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, int fg_in_lds) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
-    const int ld = w.ld, dn = w.dn;
-    double *DM = sm;             // ld x ld, becomes L
-    double *DA = sm + ld * ld;   // ld x ld
-    double *Y = DA + ld * ld;    // ld x ld scratch
+    const int ld = w.ld, dn = w.dn, tid = threadIdx.x, nthr = blockDim.x;
+    const int tx = tid & 15, ty = tid >> 4, nty = nthr >> 4;
+    double *DM = sm;               // ld x ld
+    double *DA = DM + ld * ld;     // ld x ld
+    double *Lc = DA + ld * ld;     // ld x ld: L
+    double *Li = Lc + ld * ld;     // ld x ld: L^-1
+    double *Yb = Li + ld * ld;     // ld x ld
+    double *P3 = Yb + ld * ld;     // ld x 3 ld
+    double *red = P3 + 3 * ld * ld;
+    double *lam = red + kRedSmall;  // dn
+    double *fg = lam + ((dn + 1) & ~1);  // dn x 2 ld when fg_in_lds (16-byte aligned)
     __shared__ int perm[kMaxWidth];
-    __shared__ int s_r, s_piv;
-    __shared__ double s_scale;
-    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) {
-        const int a = e / ld, b = e % ld;
-        const double gm_ab = w.GAGM[a * 2 * ld + ld + b], gm_ba = w.GAGM[b * 2 * ld + ld + a];
-        const double ga_ab = w.GAGM[a * 2 * ld + b], ga_ba = w.GAGM[b * 2 * ld + a];
-        const double gg = 0.5 * (w.P3[a * 3 * ld + ld + b] + w.P3[b * 3 * ld + ld + a]);
-        const double gf = w.P3[a * 3 * ld + b], fg = w.P3[b * 3 * ld + a];
-        const double glg = 0.5 * (w.P3[a * 3 * ld + 2 * ld + b] + w.P3[b * 3 * ld + 2 * ld + a]);
+    for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
+    if (fg_in_lds) block_copy(fg, w.FG, dn * 2 * ld);
+    if (tid < ld) perm[tid] = tid;
+    __syncthreads();
+    const int l2 = 2 * ld;
+    auto fgv = [&](int i, int a) -> double { return fg_in_lds ? fg[i * l2 + a] : w.FG[(int64_t)i * l2 + a]; };
+    // P3 = G^T [F | G | Lambda G]   (G = FG(:, ld:2ld), F = FG(:, 0:ld))
+    block_xty([&](int i, int a) -> double { return a < ld ? fgv(i, ld + a) : 0.0; },
+              [&](int i, int b) -> double {
+                  if (b < l2) return fgv(i, b);
+                  return b < 3 * ld ? lam[i] * fgv(i, b - ld) : 0.0;
+              },
+              dn, ld, 3 * ld, P3, 3 * ld, red);
+    for (int e = tid; e < ld * ld; e += nthr) {
+        const int a = e / ld, b = e - a * ld;
+        const double gm_ab = w.GAGM[a * l2 + ld + b], gm_ba = w.GAGM[b * l2 + ld + a];
+        const double ga_ab = w.GAGM[a * l2 + b], ga_ba = w.GAGM[b * l2 + a];
+        const double gg = 0.5 * (P3[a * 3 * ld + ld + b] + P3[b * 3 * ld + ld + a]);
+        const double gf = P3[a * 3 * ld + b], fgt = P3[b * 3 * ld + a];
+        const double glg = 0.5 * (P3[a * 3 * ld + 2 * ld + b] + P3[b * 3 * ld + 2 * ld + a]);
         DM[e] = 0.5 * (gm_ab + gm_ba) - gg;
-        DA[e] = 0.5 * (ga_ab + ga_ba) - gf - fg + glg;
+        DA[e] = 0.5 * (ga_ab + ga_ba) - gf - fgt + glg;
+        Lc[e] = 0.0;
+        Li[e] = 0.0;
     }
-    if (threadIdx.x < ld) perm[threadIdx.x] = threadIdx.x;
-    if (threadIdx.x == 0) {
-        double mx = 0.0;
-        for (int a = 0; a < ld; ++a) mx = fmax(mx, w.GAGM[a * 2 * ld + ld + a]);
-        s_scale = mx;
-        s_r = 0;
-    }
+    double scale = 0.0;
+    for (int a = 0; a < ld; ++a) scale = fmax(scale, w.GAGM[a * l2 + ld + a]);
     __syncthreads();
-    // pivoted Cholesky of D_M, same symmetric permutation applied to D_A
+    // pivoted Cholesky of D_M, the same symmetric permutation applied to D_A
+    int r = 0;
     for (int p = 0; p < ld; ++p) {
-        if (threadIdx.x == 0) {
-            int best = p;
-            for (int a = p + 1; a < ld; ++a)
-                if (DM[a * ld + a] > DM[best * ld + best]) best = a;
-            s_piv = DM[best * ld + best] > rank_tol * s_scale ? best : -1;
-        }
-        __syncthreads();
-        const int piv = s_piv;
-        if (piv < 0) break;
-        if (piv != p) {
-            for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+        int best = p;
+        for (int a = p + 1; a < ld; ++a) best = DM[a * ld + a] > DM[best * ld + best] ? a : best;
+        if (!(DM[best * ld + best] > rank_tol * scale)) break;  // the same decision in every thread
+        __syncthreads();  // every thread has read the diagonal before the update below rewrites it
+        if (best != p) {
+            for (int j = tid; j < ld; j += nthr) {
+                if (j == p || j == best) continue;
                 double t = DM[p * ld + j];
-                DM[p * ld + j] = DM[piv * ld + j];
-                DM[piv * ld + j] = t;
+                DM[p * ld + j] = DM[best * ld + j];
+                DM[best * ld + j] = t;
+                t = DM[j * ld + p];
+                DM[j * ld + p] = DM[j * ld + best];
+                DM[j * ld + best] = t;
                 t = DA[p * ld + j];
-                DA[p * ld + j] = DA[piv * ld + j];
-                DA[piv * ld + j] = t;
+                DA[p * ld + j] = DA[best * ld + j];
+                DA[best * ld + j] = t;
+                t = DA[j * ld + p];
+                DA[j * ld + p] = DA[j * ld + best];
+                DA[j * ld + best] = t;
+                if (j < p) {
+                    t = Lc[p * ld + j];
+                    Lc[p * ld + j] = Lc[best * ld + j];
+                    Lc[best * ld + j] = t;
+                }
+            }
+            if (tid == 0) {
+                double t = DM[p * ld + p];
+                DM[p * ld + p] = DM[best * ld + best];
+                DM[best * ld + best] = t;
+                t = DA[p * ld + p];
+                DA[p * ld + p] = DA[best * ld + best];
+                DA[best * ld + best] = t;
+                const int ti = perm[p];
+                perm[p] = perm[best];
+                perm[best] = ti;
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-                double t = DM[i * ld + p];
-                DM[i * ld + p] = DM[i * ld + piv];
-                DM[i * ld + piv] = t;
-                t = DA[i * ld + p];
-                DA[i * ld + p] = DA[i * ld + piv];
-                DA[i * ld + piv] = t;
-            }
-            if (threadIdx.x == 0) {
-                const int t = perm[p];
-                perm[p] = perm[piv];
-                perm[piv] = t;
-            }
-            __syncthreads();
         }
-        const double lpp = sqrt(DM[p * ld + p]);
-        __syncthreads();
-        for (int i = p + 1 + threadIdx.x; i < ld; i += blockDim.x) DM[i * ld + p] /= lpp;
-        if (threadIdx.x == 0) DM[p * ld + p] = lpp;
-        __syncthreads();
-        const int m = ld - p - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int i = p + 1 + e / m, j = p + 1 + e % m;
-            DM[i * ld + j] -= DM[i * ld + p] * DM[j * ld + p];
+        const double dpp = DM[p * ld + p], lpp = sqrt(dpp), ipp = 1.0 / lpp;
+        // trailing update with the scaled column computed on the fly; column p itself is not written
+        for (int i = p + 1 + ty; i < ld; i += nty) {
+            const double li = DM[i * ld + p] * ipp;
+            for (int j = p + 1 + tx; j <= i; j += 16) {
+                const double t = li * (DM[j * ld + p] * ipp);
+                DM[i * ld + j] -= t;
+                DM[j * ld + i] = DM[i * ld + j];
+            }
+            if (tx == 0) Lc[i * ld + p] = li;
         }
-        if (threadIdx.x == 0) s_r = p + 1;
+        if (tid == 0) Lc[p * ld + p] = lpp;
+        r = p + 1;
         __syncthreads();
     }
-    const int r = s_r;
-    // Y = L^-1 D_A(perm_r, perm_r)  (column c by thread c)
-    if ((int)threadIdx.x < r) {
-        const int c = threadIdx.x;
-        for (int i = 0; i < r; ++i) {
-            double s = DA[i * ld + c];
-            for (int k = 0; k < i; ++k) s -= DM[i * ld + k] * Y[k * ld + c];
-            Y[i * ld + c] = s / DM[i * ld + i];
+    // L^-1 (column c by thread c)
+    if (tid < r) {
+        const int c = tid;
+        for (int i = c; i < r; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) v -= Lc[i * ld + k] * Li[k * ld + c];
+            Li[i * ld + c] = v / Lc[i * ld + i];
         }
     }
     __syncthreads();
-    // D~ = L^-1 Y^T (column c by thread c), symmetrised afterwards
-    if ((int)threadIdx.x < r) {
-        const int c = threadIdx.x;
-        for (int i = 0; i < r; ++i) {
-            double s = Y[c * ld + i];
-            for (int k = 0; k < i; ++k) s -= DM[i * ld + k] * DA[k * ld + c];
-            DA[i * ld + c] = s / DM[i * ld + i];
+    for (int e = tid; e < r * r; e += nthr) {  // Yb = L^-1 D_A
+        const int a = e / r, b = e - a * r;
+        double v = 0.0;
+        for (int k = 0; k <= a; ++k) v += Li[a * ld + k] * DA[k * ld + b];
+        Yb[a * ld + b] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < ld * ld; e += nthr) {
+        const int a = e / ld, b = e - a * ld;
+        double v = 0.0;
+        if (a < r && b < r) {  // D~ = Yb L^-T, symmetrised
+            double s1 = 0.0, s2 = 0.0;
+            for (int k = 0; k <= b; ++k) s1 += Yb[a * ld + k] * Li[b * ld + k];
+            for (int k = 0; k <= a; ++k) s2 += Yb[b * ld + k] * Li[a * ld + k];
+            v = 0.5 * (s1 + s2);
         }
+        w.Dt[e] = v;
+        w.L1[e] = (a < r && b <= a) ? Lc[e] : 0.0;
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) {
-        const int a = e / ld, b = e % ld;
-        w.Dt[e] = (a < r && b < r) ? 0.5 * (DA[a * ld + b] + DA[b * ld + a]) : 0.0;
-        w.L1[e] = (a < r && b <= a) ? DM[a * ld + b] : 0.0;
-    }
-    if ((int)threadIdx.x < ld) w.perm[threadIdx.x] = perm[threadIdx.x];
-    if (threadIdx.x == 0) w.status[ST_RANK] = r;
-    // C~ = C(:, perm_r) L^-T with C = F - Lambda G: L^-1 by columns (thread c),
-    // then one dot product per entry
-    double *Li = Y;  // r x r lower, row stride ld
-    __syncthreads();
-    if ((int)threadIdx.x < r) {
-        const int c = threadIdx.x;
-        for (int i = 0; i < r; ++i) {
-            double v = 0.0;
-            if (i >= c) {
-                v = i == c ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) v -= DM[i * ld + k] * Li[k * ld + c];
-                v /= DM[i * ld + i];
-            }
-            Li[i * ld + c] = v;
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < dn * ld; e += blockDim.x) {
+    if (tid < ld) w.perm[tid] = perm[tid];
+    if (tid == 0) w.status[ST_RANK] = r;
+    for (int e = tid; e < dn * ld; e += nthr) {  // C~ = (F - Lambda G)(:, perm_r) L^-T
         const int i = e / ld, a = e - i * ld;
         double v = 0.0;
         if (a < r) {
-            const double li = w.lam[i];
-            const double *row = w.FG + (int64_t)i * 2 * ld;
+            const double li = lam[i];
             for (int k = 0; k <= a; ++k) {
                 const int pk = perm[k];
-                v += Li[a * ld + k] * (row[pk] - li * row[ld + pk]);
+                v += Li[a * ld + k] * (fgv(i, pk) - li * fgv(i, ld + pk));
             }
         }
         w.Ct[e] = v;
@@ -846,58 +792,13 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
 }
 
 // ------------------------------------------- Rayleigh-Ritz polish (a10)
-// out = X^T Y (mi x mj, row stride ostr) over rows [0, K) in 16 x 16 tiles on
-// the matrix cores.  X(i, a) and Y(i, b) return entry a (b) of row i and zero
-// for a >= mi (b >= mj).  With fewer tiles than wavefronts the rows are split
-// over the wavefronts and the partial tiles summed in a fixed order (red holds
-// 3 * 4 * 256 doubles).  Ends with a barrier.
-template <class FX, class FY>
-__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red) {
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    const int ti = (mi + 15) >> 4, tj = (mj + 15) >> 4, ntiles = ti * tj;
-    if (K > 0 && (ntiles >= nw || nw == 1)) {
-        for (int t = wv; t < ntiles; t += nw) {
-            const int ta = t / tj, tb = t - ta * tj;
-            const dbl4 acc = mfma_tn16([&](int i, int c) { return X(i, 16 * ta + c); },
-                                       [&](int i, int c) { return Y(i, 16 * tb + c); }, K);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
-                if (i < mi && j < mj) out[i * ostr + j] = acc[u];
-            }
-        }
-    } else if (K > 0) {
-        const int chunk = ((K + nw - 1) / nw + 3) & ~3;
-        const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
-        for (int t = 0; t < ntiles; ++t) {
-            const int ta = t / tj, tb = t - ta * tj;
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-            if (k1 > k0)
-                acc = mfma_tn16([&](int i, int c) { return X(k0 + i, 16 * ta + c); },
-                                [&](int i, int c) { return Y(k0 + i, 16 * tb + c); }, k1 - k0);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) red[((t * nw + wv) * 4 + u) * kWave + lane] = acc[u];
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < ntiles * 256; e += blockDim.x) {
-            const int t = e >> 8, u = (e >> 6) & 3, ln = e & 63;
-            double s = 0.0;
-            for (int v = 0; v < nw; ++v) s += red[((t * nw + v) * 4 + u) * kWave + ln];
-            const int ta = t / tj, tb = t - ta * tj;
-            const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
-            if (i < mi && j < mj) out[i * ostr + j] = s;
-        }
-    }
-    __syncthreads();
-}
-
 // One workgroup: X <- orthonormal basis of span X (two Cholesky-QR passes),
 // T = X^T H X, T = Q diag(theta) Q^T by cyclic Jacobi, Xr = X Q sorted.
 // When they fit, X, H X and C~ are copied to LDS (use_lds); otherwise the same
 // code works on the global buffers.
-constexpr int kRed = 3 * 4 * 256;
+constexpr int kRed = kRedSmall;
 
-__global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_lds) {
+__global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_lds, double *theta_out, int final_level) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
@@ -910,7 +811,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     double *G = Q + ldp * ldp;      // ldp x ldp
     double *red = G + ldp * ldp;    // kRed
     double *lamv = red + kRed;      // dn
-    double *dtv = lamv + dn;        // ldp x ldp
+    double *dtv = lamv + ((dn + 1) & ~1);  // ldp x ldp (keeps the copies below 16-byte aligned)
     for (int i = tid; i < dn; i += nthr) lamv[i] = w.lam[i];
     for (int e = tid; e < ldp * ldp; e += nthr) {
         const int a = e / ldp, b = e - a * ldp;
@@ -922,8 +823,8 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         double *Xl = dtv + ldp * ldp;
         double *HXl = Xl + (dn + ld) * ld;
         double *Ctl = HXl + (dn + ld) * ld;
-        for (int e = tid; e < nh * ld; e += nthr) Xl[e] = w.X[e];
-        for (int e = tid; e < dn * ld; e += nthr) Ctl[e] = w.Ct[e];
+        block_copy(Xl, w.X, nh * ld);
+        block_copy(Ctl, w.Ct, dn * ld);
         Xp = Xl;
         HXp = HXl;
         Ctp = Ctl;
@@ -1077,100 +978,81 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         }
     }
     __syncthreads();
-    for (int c = tid; c < m; c += nthr) w.theta[c] = s_theta[order[c]];
-    for (int e = tid; e < (dn + ld) * ld; e += nthr) {
+    for (int c = tid; c < m; c += nthr) {
+        const double th = s_theta[order[c]];
+        w.theta[c] = th;
+        theta_out[c] = th;
+    }
+    // ---- Ritz vectors of H: Xr = X Q(:, order)   (H X is no longer needed)
+    double *Xr = use_lds ? HXp : w.Xr;
+    for (int e = tid; e < nh * ld; e += nthr) {
         const int i = e / ld, c = e - i * ld;
         double v = 0.0;
-        if (i < nh && c < m) {
+        if (c < m) {
             const int oc = order[c];
             for (int a = 0; a < m; ++a) v += Xp[(int64_t)i * ld + a] * Q[a * ldp + oc];
         }
-        w.Xr[(int64_t)i * ld + c] = v;
+        Xr[e] = v;
     }
-}
-
-// ---------------------------------------------- recombination coefficients
-// X_v = Pi_r L^-T z (ld x ld), X_c = y - G X_v (dn x ld).
-__global__ __launch_bounds__(256) void k_recombine_coeffs(SmallWork w) {
-    extern __shared__ double sm[];
-    if (w.status[ST_CONVERGED]) return;
-    const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
-    double *Xv = sm;             // ld x ld
-    double *Li = Xv + ld * ld;   // ld x ld: L^-1
-    double *z = Li + ld * ld;    // r x ld
-    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) Xv[e] = 0.0;
-    for (int e = threadIdx.x; e < r * ld; e += blockDim.x) z[e] = w.Xr[(int64_t)(dn + e / ld) * ld + e % ld];
-    if ((int)threadIdx.x < r) {  // column c of L^-1 by thread c
-        const int c = threadIdx.x;
-        for (int i = 0; i < r; ++i) {
-            double v = 0.0;
-            if (i >= c) {
-                v = i == c ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) v -= w.L1[i * ld + k] * Li[k * ld + c];
-                v /= w.L1[i * ld + i];
-            }
-            Li[i * ld + c] = v;
+    // ---- recombination coefficients X_v = Pi_r L^-T z, X_c = y - G X_v
+    double *Li = G;   // r x r, stride ldp
+    double *Xv = T;   // ld x ld, stride ldp
+    if (tid < r) {    // column c of L^-1 by thread c
+        const int c = tid;
+        for (int i = c; i < r; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) v -= w.L1[i * ld + k] * Li[k * ldp + c];
+            Li[i * ldp + c] = v / w.L1[i * ld + i];
         }
     }
+    for (int e = tid; e < ldp * ldp; e += nthr) Xv[e] = 0.0;
     __syncthreads();
-    for (int e = threadIdx.x; e < r * ld; e += blockDim.x) {  // (L^-T z)[a][c]
+    for (int e = tid; e < r * ld; e += nthr) {
         const int a = e / ld, c = e - a * ld;
         double v = 0.0;
-        for (int b = a; b < r; ++b) v += Li[b * ld + a] * z[b * ld + c];
-        Xv[w.perm[a] * ld + c] = v;
+        for (int b = a; b < r; ++b) v += Li[b * ldp + a] * Xr[(int64_t)(dn + b) * ld + c];
+        Xv[w.perm[a] * ldp + c] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) w.Xv[e] = Xv[e];
-    for (int e = threadIdx.x; e < dn * ld; e += blockDim.x) {
-        const int i = e / ld, c = e % ld;
-        const double *gi = w.FG + (int64_t)i * 2 * ld + ld;
-        double s = w.Xr[(int64_t)i * ld + c];
-        for (int a = 0; a < ld; ++a) s -= gi[a] * Xv[a * ld + c];
-        w.Xc[e] = s;
+    for (int e = tid; e < ld * ld; e += nthr) {
+        const int a = e / ld, c = e - a * ld;
+        w.Xv[e] = Xv[a * ldp + c];
     }
-}
-
-__global__ void k_theta_update(SmallWork w, double *theta_out, int final_level) {
-    if (w.status[ST_CONVERGED]) return;
-    const int c = threadIdx.x;
-    if (c < w.ld) theta_out[c] = w.theta[c];
-    if (c == 0) {
+    for (int e = tid; e < dn * ld; e += nthr) {
+        const int i = e / ld, c = e - i * ld;
+        const double *gi = w.FG + (int64_t)i * 2 * ld + ld;
+        double v = Xr[e];
+        for (int a = 0; a < ld; ++a) v -= gi[a] * Xv[a * ldp + c];
+        w.Xc[e] = v;
+    }
+    if (tid == 0) {
         w.status[ST_WARM] = 1;
         if (final_level) w.status[ST_STEPS] += 1;
     }
 }
 
 // ------------------------------------------------------------ launchers
-void launch_small_products(hipStream_t s, const SmallWork &w) {
-    dim3 grid((w.ld + 15) / 16, (3 * w.ld + 15) / 16);
-    hipLaunchKernelGGL(k_small_products, grid, dim3(256), 0, s, w.dn, w.ld, w.lam, w.FG, w.P3, w.status);
-}
-
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
-    const size_t lds = 3 * (size_t)w.ld * w.ld * sizeof(double);
-    hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds, s, w, rank_tol);
+    const size_t ld = w.ld, dn = w.dn;
+    const size_t base = 8 * ld * ld + kRedSmall + dn + 1;
+    const int fg_in_lds = (base + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    const size_t lds = (base + (fg_in_lds ? dn * 2 * ld : 0)) * sizeof(double);
+    hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds, s, w, rank_tol, fg_in_lds);
 }
 
-void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, const double *theta_prev) {
+void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level) {
     // the rank r <= ld is only known on the device: size for r = ld
     const size_t ldp = ((size_t)w.ld + 15) & ~(size_t)15, dn = w.dn;
     const int threads = kB;
     const size_t base = 2 * ldp * (ldp + 1) + dn + 2 * (dn + ldp) + ldp + dn + ldp * ldp + 1024 + 64;
     const int ct_in_lds = (base + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
     const size_t lds = (base + (ct_in_lds ? dn * ldp : 0)) * sizeof(double);
-    hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta_prev, ct_in_lds);
-    const size_t rbase = 3 * ldp * ldp + kRed + dn + ldp * ldp;
+    hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta, ct_in_lds);
+    const size_t rbase = 3 * ldp * ldp + kRed + dn + 1 + ldp * ldp;
     const size_t full = rbase + 2 * (dn + w.ld) * w.ld + dn * w.ld;
     const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
-    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), (use_lds ? full : rbase) * sizeof(double), s, w, qe, use_lds);
-}
-
-void launch_recombine_coeffs(hipStream_t s, const SmallWork &w) {
-    hipLaunchKernelGGL(k_recombine_coeffs, dim3(1), dim3(kB), 3 * (size_t)w.ld * w.ld * sizeof(double), s, w);
-}
-
-void launch_theta_update(hipStream_t s, const SmallWork &w, double *theta_out, int final_level) {
-    hipLaunchKernelGGL(k_theta_update, dim3(1), dim3(128), 0, s, w, theta_out, final_level);
+    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), (use_lds ? full : rbase) * sizeof(double), s, w, qe, use_lds, theta,
+                       final_level);
 }
 
 }  // namespace amgeig

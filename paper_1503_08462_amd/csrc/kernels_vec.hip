@@ -232,37 +232,40 @@ __global__ __launch_bounds__(256) void k_dense_rows(int64_t m, int64_t K, const 
 }
 
 // ------------------------------------------------------------ small GEMM
-// C (m x n) = op(A) B with op(A) = A (m x K, row-major, lda) or A^T (A is
-// K x m).  16 x 16 output tile per block, K staged through LDS in chunks of 32.
-template <typename T, bool TA>
-__global__ __launch_bounds__(256) void k_gemm_small(int m, int n, int K, const T *__restrict__ A, int lda,
-                                                    const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
-                                                    const int *status) {
-    __shared__ T As[32][17];
-    __shared__ T Bs[32][17];
+// C (m x n) = A^T B with A (K x m, row-major, lda) and B (K x n, ldb) of
+// element type T, accumulated on the FP64 matrix cores.  One workgroup per
+// 16 x 16 tile of C; its four wavefronts take a quarter of K each and the
+// partial tiles are summed in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_tn(int m, int n, int K, const T *__restrict__ A, int lda,
+                                                 const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
+                                                 const int *status) {
+    __shared__ double part[4 * 256];
     if (status[ST_CONVERGED]) return;
-    const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
-    const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-    T acc = T(0);
-    for (int l0 = 0; l0 < K; l0 += 32) {
-        for (int e = threadIdx.x; e < 32 * 16; e += blockDim.x) {
-            const int kk = e / 16, ii = e % 16, l = l0 + kk;
-            const int i = i0 + ii, j = j0 + ii;
-            T av = T(0), bv = T(0);
-            if (l < K) {
-                if (i < m) av = TA ? A[(int64_t)l * lda + i] : A[(int64_t)i * lda + l];
-                if (j < n) bv = B[(int64_t)l * ldb + j];
-            }
-            As[kk][ii] = av;
-            Bs[kk][ii] = bv;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) acc += As[kk][ty] * Bs[kk][tx];
-        __syncthreads();
-    }
-    const int i = i0 + ty, j = j0 + tx;
-    if (i < m && j < n) C[(int64_t)i * ldc + j] = acc;
+    const int ta = blockIdx.x, tb = blockIdx.y;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int chunk = ((K + 3) / 4 + 3) & ~3;
+    const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (k1 > k0)
+        acc = mfma_tn16(
+            [&](int i, int c) -> double {
+                const int col = 16 * ta + c;
+                return col < m ? (double)A[(int64_t)(k0 + i) * lda + col] : 0.0;
+            },
+            [&](int i, int c) -> double {
+                const int col = 16 * tb + c;
+                return col < n ? (double)B[(int64_t)(k0 + i) * ldb + col] : 0.0;
+            },
+            k1 - k0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) part[(wv * 4 + u) * kWave + lane] = acc[u];
+    __syncthreads();
+    const int u = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const double v = (part[(0 * 4 + u) * kWave + ln] + part[(1 * 4 + u) * kWave + ln]) +
+                     (part[(2 * 4 + u) * kWave + ln] + part[(3 * 4 + u) * kWave + ln]);
+    const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
+    if (i < m && j < n) C[(int64_t)i * ldc + j] = (T)v;
 }
 
 // ------------------------------------------------------------------- a7
@@ -535,18 +538,15 @@ void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const in
 }
 
 template <typename T>
-void launch_gemm_small(hipStream_t s, bool transA, int m, int n, int K, const T *A, int lda, const T *B, int ldb,
-                       T *C, int ldc, const int *status) {
+void launch_gemm_tn(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,
+                    const int *status) {
     const dim3 g((m + 15) / 16, (n + 15) / 16);
-    if (transA)
-        hipLaunchKernelGGL((k_gemm_small<T, true>), g, dim3(256), 0, s, m, n, K, A, lda, B, ldb, C, ldc, status);
-    else
-        hipLaunchKernelGGL((k_gemm_small<T, false>), g, dim3(256), 0, s, m, n, K, A, lda, B, ldb, C, ldc, status);
+    hipLaunchKernelGGL(k_gemm_tn<T>, g, dim3(256), 0, s, m, n, K, A, lda, B, ldb, C, ldc, status);
 }
-template void launch_gemm_small<float>(hipStream_t, bool, int, int, int, const float *, int, const float *, int,
-                                       float *, int, const int *);
-template void launch_gemm_small<double>(hipStream_t, bool, int, int, int, const double *, int, const double *, int,
-                                        double *, int, const int *);
+template void launch_gemm_tn<float>(hipStream_t, int, int, int, const float *, int, const float *, int, float *, int,
+                                    const int *);
+template void launch_gemm_tn<double>(hipStream_t, int, int, int, const double *, int, const double *, int, double *,
+                                     int, const int *);
 
 void launch_fill_random(hipStream_t s, int64_t n, int ld, int qe, uint64_t seed, double *U) {
     const int64_t tot = n * ld;
