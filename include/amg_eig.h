@@ -7,7 +7,7 @@
  *   - problem (1.1): the q smallest eigenpairs of the symmetric pencil (A, M),
  *     A symmetric positive definite, M symmetric positive (semi)definite,
  *     with U^T M U = I;
- *   - hierarchy (Section 2): strength (2.1), Ruge-Stueben first-pass C/F
+ *   - hierarchy (Section 2): strength (2.1), classical Ruge-Stueben C/F
  *     splitting, direct interpolation (2.2)-(2.4), Galerkin operators (2.5);
  *   - correction step (Algorithm 3.1): one block V-cycle on A_k u = lambda M_k u
  *     from the current iterate (3.1)-(3.2), then Rayleigh-Ritz on the coarsest

@@ -61,7 +61,7 @@ __device__ int bk_factor(double *S, double *Lm, int r, int ls, int *ipiv) {
     int neg = 0;
     int p = 0;
     while (p < r) {
-        double colmax = 0.0;
+        double colmax = 0.0;  // largest |S[i][p]|, i > p, lowest index on ties
         int imax = p;
         for (int i = p + 1; i < r; ++i) {
             const double v = fabs(S[i * ls + p]);
