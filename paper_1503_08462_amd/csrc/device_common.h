@@ -159,24 +159,25 @@ __device__ __forceinline__ dbl4 mfma_tn16(const FX &X, const FY &Y, int K) {
     return a0 + a1;
 }
 
-// out = X^T Y (mi x mj, row stride ostr) over rows [0, K) in 16 x 16 tiles on
-// the matrix cores.  X(i, a) and Y(i, b) return entry a (b) of row i and zero
-// for a >= mi (b >= mj).  With fewer tiles than wavefronts the rows are split
-// over the wavefronts and the partial tiles summed in a fixed order (red holds
-// 3 * 4 * 256 doubles).  Ends with a barrier.
-template <class FX, class FY>
-__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red) {
+// out(i, j, sum_k X(k, i) Y(k, j)) for i < mi, j < mj, k < K, in 16 x 16 tiles
+// on the matrix cores.  X(k, a) and Y(k, b) must return zero for a >= mi
+// (b >= mj); `out` receives each finished entry once.  With fewer tiles than
+// wavefronts the K range is split over the wavefronts and the partial tiles
+// summed in a fixed order (red holds 3 * 4 * 256 doubles).  Ends with a
+// barrier.
+template <class FX, class FY, class FO>
+__device__ void block_tiles(const FX &X, const FY &Y, int K, int mi, int mj, const FO &out, double *red) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int ti = (mi + 15) >> 4, tj = (mj + 15) >> 4, ntiles = ti * tj;
     if (K > 0 && (ntiles >= nw || nw == 1)) {
         for (int t = wv; t < ntiles; t += nw) {
             const int ta = t / tj, tb = t - ta * tj;
-            const dbl4 acc = mfma_tn16([&](int i, int c) { return X(i, 16 * ta + c); },
-                                       [&](int i, int c) { return Y(i, 16 * tb + c); }, K);
+            const dbl4 acc = mfma_tn16([&](int k, int c) { return X(k, 16 * ta + c); },
+                                       [&](int k, int c) { return Y(k, 16 * tb + c); }, K);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
-                if (i < mi && j < mj) out[i * ostr + j] = acc[u];
+                if (i < mi && j < mj) out(i, j, acc[u]);
             }
         }
     } else if (K > 0) {
@@ -186,8 +187,8 @@ __device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, doubl
             const int ta = t / tj, tb = t - ta * tj;
             dbl4 acc = {0.0, 0.0, 0.0, 0.0};
             if (k1 > k0)
-                acc = mfma_tn16([&](int i, int c) { return X(k0 + i, 16 * ta + c); },
-                                [&](int i, int c) { return Y(k0 + i, 16 * tb + c); }, k1 - k0);
+                acc = mfma_tn16([&](int k, int c) { return X(k0 + k, 16 * ta + c); },
+                                [&](int k, int c) { return Y(k0 + k, 16 * tb + c); }, k1 - k0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) red[((t * nw + wv) * 4 + u) * kWave + lane] = acc[u];
         }
@@ -198,10 +199,16 @@ __device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, doubl
             for (int v = 0; v < nw; ++v) s += red[((t * nw + v) * 4 + u) * kWave + ln];
             const int ta = t / tj, tb = t - ta * tj;
             const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
-            if (i < mi && j < mj) out[i * ostr + j] = s;
+            if (i < mi && j < mj) out(i, j, s);
         }
     }
     __syncthreads();
+}
+
+// out = X^T Y (mi x mj, row stride ostr): block_tiles storing into an array.
+template <class FX, class FY>
+__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red) {
+    block_tiles(X, Y, K, mi, mj, [&](int i, int j, double v) { out[i * ostr + j] = v; }, red);
 }
 
 // Workgroup copy of n doubles (n even, both pointers 16-byte aligned) as

@@ -154,6 +154,7 @@ void plan(amg_eig_ctx *c, char *base) {
     w.Ct = cv.take<double>((size_t)dn * ld);
     w.Dt = cv.take<double>((size_t)ld * ld);
     w.L1 = cv.take<double>((size_t)ld * ld);
+    w.Li = cv.take<double>((size_t)ld * ld);
     w.perm = cv.take<int>(ld);
     w.X = cv.take<double>((size_t)(dn + ld) * ld);
     w.HX = cv.take<double>((size_t)(dn + ld) * ld);

@@ -67,6 +67,7 @@ struct SmallWork {
     double *Ct = nullptr;         // dn x ld: coupling block of H
     double *Dt = nullptr;         // ld x ld: trailing block of H
     double *L1 = nullptr;         // ld x ld: Cholesky factor of the kept columns
+    double *Li = nullptr;         // ld x ld: its inverse (lower)
     int *perm = nullptr;          // ld: pivot order of the M-orthogonalisation
     double *X = nullptr;          // (dn + ld) x ld: eigenvectors of H (inverse iteration)
     double *HX = nullptr;         // (dn + ld) x ld scratch

@@ -285,16 +285,21 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
     double *Li = Lc + ld * ld;     // ld x ld: L^-1
     double *Yb = Li + ld * ld;     // ld x ld
     double *P3 = Yb + ld * ld;     // ld x 3 ld
-    double *red = P3 + 3 * ld * ld;
+    double *gag = P3 + 3 * ld * ld;  // ld x 2 ld: [V^T A V | V^T M V]
+    double *red = gag + 2 * ld * ld;
     double *lam = red + kRedSmall;  // dn
     double *fg = lam + ((dn + 1) & ~1);  // dn x 2 ld when fg_in_lds (16-byte aligned)
     __shared__ int perm[kMaxWidth];
+    uint64_t tk[8];  // solver statistics: phase clocks (thread 0)
+    tk[0] = wall_clock64();
     for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
     if (fg_in_lds) block_copy(fg, w.FG, dn * 2 * ld);
+    block_copy(gag, w.GAGM, 2 * ld * ld);
     if (tid < ld) perm[tid] = tid;
     __syncthreads();
     const int l2 = 2 * ld;
     auto fgv = [&](int i, int a) -> double { return fg_in_lds ? fg[i * l2 + a] : w.FG[(int64_t)i * l2 + a]; };
+    tk[1] = wall_clock64();
     // P3 = G^T [F | G | Lambda G]   (G = FG(:, ld:2ld), F = FG(:, 0:ld))
     block_xty([&](int i, int a) -> double { return a < ld ? fgv(i, ld + a) : 0.0; },
               [&](int i, int b) -> double {
@@ -304,8 +309,8 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
               dn, ld, 3 * ld, P3, 3 * ld, red);
     for (int e = tid; e < ld * ld; e += nthr) {
         const int a = e / ld, b = e - a * ld;
-        const double gm_ab = w.GAGM[a * l2 + ld + b], gm_ba = w.GAGM[b * l2 + ld + a];
-        const double ga_ab = w.GAGM[a * l2 + b], ga_ba = w.GAGM[b * l2 + a];
+        const double gm_ab = gag[a * l2 + ld + b], gm_ba = gag[b * l2 + ld + a];
+        const double ga_ab = gag[a * l2 + b], ga_ba = gag[b * l2 + a];
         const double gg = 0.5 * (P3[a * 3 * ld + ld + b] + P3[b * 3 * ld + ld + a]);
         const double gf = P3[a * 3 * ld + b], fgt = P3[b * 3 * ld + a];
         const double glg = 0.5 * (P3[a * 3 * ld + 2 * ld + b] + P3[b * 3 * ld + 2 * ld + a]);
@@ -315,14 +320,20 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
         Li[e] = 0.0;
     }
     double scale = 0.0;
-    for (int a = 0; a < ld; ++a) scale = fmax(scale, w.GAGM[a * l2 + ld + a]);
+    for (int a = 0; a < ld; ++a) scale = fmax(scale, gag[a * l2 + ld + a]);
     __syncthreads();
+    tk[2] = wall_clock64();
     // pivoted Cholesky of D_M, the same symmetric permutation applied to D_A
     int r = 0;
     for (int p = 0; p < ld; ++p) {
         int best = p;
-        for (int a = p + 1; a < ld; ++a) best = DM[a * ld + a] > DM[best * ld + best] ? a : best;
-        if (!(DM[best * ld + best] > rank_tol * scale)) break;  // the same decision in every thread
+        double bv = DM[p * ld + p];
+        for (int a = p + 1; a < ld; ++a) {
+            const double v = DM[a * ld + a];
+            best = v > bv ? a : best;
+            bv = v > bv ? v : bv;
+        }
+        if (!(bv > rank_tol * scale)) break;  // the same decision in every thread
         __syncthreads();  // every thread has read the diagonal before the update below rewrites it
         if (best != p) {
             for (int j = tid; j < ld; j += nthr) {
@@ -373,6 +384,7 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
         r = p + 1;
         __syncthreads();
     }
+    tk[3] = wall_clock64();
     // L^-1 (column c by thread c)
     if (tid < r) {
         const int c = tid;
@@ -401,20 +413,23 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
         }
         w.Dt[e] = v;
         w.L1[e] = (a < r && b <= a) ? Lc[e] : 0.0;
+        w.Li[e] = Li[e];
     }
     if (tid < ld) w.perm[tid] = perm[tid];
     if (tid == 0) w.status[ST_RANK] = r;
-    for (int e = tid; e < dn * ld; e += nthr) {  // C~ = (F - Lambda G)(:, perm_r) L^-T
-        const int i = e / ld, a = e - i * ld;
-        double v = 0.0;
-        if (a < r) {
-            const double li = lam[i];
-            for (int k = 0; k <= a; ++k) {
-                const int pk = perm[k];
-                v += Li[a * ld + k] * (fgv(i, pk) - li * fgv(i, ld + pk));
-            }
-        }
-        w.Ct[e] = v;
+    tk[4] = wall_clock64();
+    // C~ = (F - Lambda G)(:, perm_r) L^-T on the matrix cores
+    block_tiles(
+        [&](int k, int i) -> double {
+            if (i >= dn || k >= r) return 0.0;
+            const int pk = perm[k];
+            return fgv(i, pk) - lam[i] * fgv(i, ld + pk);
+        },
+        [&](int k, int a) -> double { return a < r ? Li[a * ld + k] : 0.0; }, r, dn, ld,
+        [&](int i, int a, double v) { w.Ct[(int64_t)i * ld + a] = v; }, red);
+    if (tid == 0 && w.diag) {
+        tk[5] = wall_clock64();
+        for (int j = 0; j < 5; ++j) atomicAdd(&w.diag[330 + j], (int)(tk[j + 1] - tk[j]));
     }
 }
 
@@ -806,6 +821,8 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     const int ldp = (ld + 15) & ~15;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
+    uint64_t tk[9];  // solver statistics: phase clocks (thread 0)
+    tk[0] = wall_clock64();
     double *T = sm;                 // ldp x ldp
     double *Q = T + ldp * ldp;      // ldp x ldp
     double *G = Q + ldp * ldp;      // ldp x ldp
@@ -839,11 +856,16 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     __shared__ double s_off;
     __shared__ int order[kMaxWidth];
     __shared__ double s_theta[kMaxWidth];
-    // ---- two Cholesky-QR passes on X (nh x m)
+    tk[1] = wall_clock64();
+    // ---- Cholesky-QR on X (nh x m); a second pass unless every pivot of the
+    // first was within 10% of 1 (then X was already orthonormal to a few
+    // units of rounding and one pass leaves it so)
     for (int pass = 0; pass < 2; ++pass) {
+        bool near_identity = true;  // the same in every thread
         block_xty(xa, xa, nh, m, m, G, ldp, red);
         for (int p = 0; p < m; ++p) {  // G = L L^T in place (lower)
             double d = G[p * ldp + p];
+            near_identity = near_identity && d > 0.9 && d < 1.1;
             if (!(d > 0.0)) {
                 if (tid == 0) w.status[ST_BREAKDOWN] = 1;
                 d = 1e-300;
@@ -860,23 +882,34 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
             }
             __syncthreads();
         }
-        for (int i = tid; i < nh; i += nthr) {  // row i <- row i L^-T, in place
-            double *xr = Xp + (int64_t)i * ld;
-            for (int c = 0; c < m; ++c) {
-                double s2 = xr[c];
-                for (int a = 0; a < c; ++a) s2 -= xr[a] * G[c * ldp + a];
-                xr[c] = s2 / G[c * ldp + c];
+        if (tid < m) {  // L^-1 into Q, column c by thread c (zero above the diagonal)
+            const int c = tid;
+            for (int i = 0; i < m; ++i) {
+                double v = 0.0;
+                if (i >= c) {
+                    v = i == c ? 1.0 : 0.0;
+                    for (int k = c; k < i; ++k) v -= G[i * ldp + k] * Q[k * ldp + c];
+                    v /= G[i * ldp + i];
+                }
+                Q[i * ldp + c] = v;
             }
         }
         __syncthreads();
+        // X L^-T on the matrix cores into the other buffer, then swap
+        block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
+                    [&](int a, int c) -> double { return c < m ? Q[c * ldp + a] : 0.0; }, m, nh, m,
+                    [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = v; }, red);
+        double *t = Xp;
+        Xp = HXp;
+        HXp = t;
+        if (near_identity) break;
     }
+    tk[2] = wall_clock64();
     // ---- HX (nh x m): rows i < dn: lam_i x_i + C~_i z ; rows dn+a: C~^T y + D~ z
-    for (int e = tid; e < dn * m; e += nthr) {
-        const int i = e / m, c = e - i * m;
-        double s2 = lamv[i] * Xp[(int64_t)i * ld + c];
-        for (int a = 0; a < r; ++a) s2 += Ctp[(int64_t)i * ld + a] * Xp[(int64_t)(dn + a) * ld + c];
-        HXp[(int64_t)i * ld + c] = s2;
-    }
+    block_tiles([&](int a, int i) -> double { return (i < dn && a < r) ? Ctp[(int64_t)i * ld + a] : 0.0; },
+                [&](int a, int c) -> double { return c < m ? Xp[(int64_t)(dn + a) * ld + c] : 0.0; }, r, dn, m,
+                [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = lamv[i] * Xp[(int64_t)i * ld + c] + v; },
+                red);
     block_xty(cta, xa, dn, r, m, HXp + (int64_t)dn * ld, ld, red);
     for (int e = tid; e < r * m; e += nthr) {
         const int a = e / m, c = e - a * m;
@@ -885,6 +918,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         HXp[(int64_t)(dn + a) * ld + c] += s2;
     }
     __syncthreads();
+    tk[3] = wall_clock64();
     // ---- T = X^T HX, symmetrised
     block_xty(xa, hxa, nh, m, m, Q, ldp, red);
     for (int e = tid; e < m * m; e += nthr) {
@@ -897,6 +931,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         Q[a * ldp + b] = a == b ? 1.0 : 0.0;
     }
     __syncthreads();
+    tk[4] = wall_clock64();
     // ---- cyclic Jacobi with the round-robin ordering (m even)
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int round = 0; round < m - 1; ++round) {
@@ -961,6 +996,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         __syncthreads();
         if (s_off < 1e-15) break;
     }
+    tk[5] = wall_clock64();
     // ---- sort Ritz values ascending and write Xr = X Q(:, order), theta
     if (tid == 0) {
         for (int a = 0; a < m; ++a) {
@@ -983,27 +1019,19 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         w.theta[c] = th;
         theta_out[c] = th;
     }
+    tk[6] = wall_clock64();
     // ---- Ritz vectors of H: Xr = X Q(:, order)   (H X is no longer needed)
     double *Xr = use_lds ? HXp : w.Xr;
-    for (int e = tid; e < nh * ld; e += nthr) {
-        const int i = e / ld, c = e - i * ld;
-        double v = 0.0;
-        if (c < m) {
-            const int oc = order[c];
-            for (int a = 0; a < m; ++a) v += Xp[(int64_t)i * ld + a] * Q[a * ldp + oc];
-        }
-        Xr[e] = v;
-    }
+    block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
+                [&](int a, int c) -> double { return c < m ? Q[a * ldp + order[c]] : 0.0; }, m, nh, ld,
+                [&](int i, int c, double v) { Xr[(int64_t)i * ld + c] = v; }, red);
+    tk[7] = wall_clock64();
     // ---- recombination coefficients X_v = Pi_r L^-T z, X_c = y - G X_v
-    double *Li = G;   // r x r, stride ldp
+    double *Li = G;   // r x r, stride ldp (only the lower triangle is read)
     double *Xv = T;   // ld x ld, stride ldp
-    if (tid < r) {    // column c of L^-1 by thread c
-        const int c = tid;
-        for (int i = c; i < r; ++i) {
-            double v = i == c ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) v -= w.L1[i * ld + k] * Li[k * ldp + c];
-            Li[i * ldp + c] = v / w.L1[i * ld + i];
-        }
+    for (int e = tid; e < r * r; e += nthr) {  // L^-1 from the pencil kernel
+        const int a = e / r, b = e - a * r;
+        Li[a * ldp + b] = w.Li[a * ld + b];
     }
     for (int e = tid; e < ldp * ldp; e += nthr) Xv[e] = 0.0;
     __syncthreads();
@@ -1018,23 +1046,23 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         const int a = e / ld, c = e - a * ld;
         w.Xv[e] = Xv[a * ldp + c];
     }
-    for (int e = tid; e < dn * ld; e += nthr) {
-        const int i = e / ld, c = e - i * ld;
-        const double *gi = w.FG + (int64_t)i * 2 * ld + ld;
-        double v = Xr[e];
-        for (int a = 0; a < ld; ++a) v -= gi[a] * Xv[a * ldp + c];
-        w.Xc[e] = v;
-    }
+    block_tiles([&](int a, int i) -> double { return (i < dn && a < ld) ? w.FG[(int64_t)i * 2 * ld + ld + a] : 0.0; },
+                [&](int a, int c) -> double { return c < ld ? Xv[a * ldp + c] : 0.0; }, ld, dn, ld,
+                [&](int i, int c, double v) { w.Xc[(int64_t)i * ld + c] = Xr[(int64_t)i * ld + c] - v; }, red);
     if (tid == 0) {
         w.status[ST_WARM] = 1;
         if (final_level) w.status[ST_STEPS] += 1;
+        if (w.diag) {
+            tk[8] = wall_clock64();
+            for (int j = 0; j < 8; ++j) atomicAdd(&w.diag[321 + j], (int)(tk[j + 1] - tk[j]));
+        }
     }
 }
 
 // ------------------------------------------------------------ launchers
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
     const size_t ld = w.ld, dn = w.dn;
-    const size_t base = 8 * ld * ld + kRedSmall + dn + 1;
+    const size_t base = 10 * ld * ld + kRedSmall + dn + 1;
     const int fg_in_lds = (base + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
     const size_t lds = (base + (fg_in_lds ? dn * 2 * ld : 0)) * sizeof(double);
     hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds, s, w, rank_tol, fg_in_lds);
