@@ -859,16 +859,24 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     tk[1] = wall_clock64();
     // ---- Cholesky-QR on X (nh x m); a second pass unless every pivot of the
     // first was within 10% of 1 (then X was already orthonormal to a few
-    // units of rounding and one pass leaves it so)
-    for (int pass = 0; pass < 2; ++pass) {
+    // units of rounding and one pass leaves it so).  A column whose pivot
+    // falls below 1e-10 (columns have unit norm) repeats a direction of the
+    // columns before it, as two vectors of a multiple eigenvalue can: it is
+    // replaced by the coordinates of the corrected vector V e_p (then, if
+    // that fails too, by a pseudo-random vector) and the pass restarts.
+    __shared__ int tries[kMaxWidth];
+    if (tid < m) tries[tid] = 0;
+    int passes = 0;
+    for (int it = 0; it < 2 + 2 * m && passes < 2; ++it) {
         bool near_identity = true;  // the same in every thread
+        int bad = -1;
         block_xty(xa, xa, nh, m, m, G, ldp, red);
         for (int p = 0; p < m; ++p) {  // G = L L^T in place (lower)
-            double d = G[p * ldp + p];
+            const double d = G[p * ldp + p];
             near_identity = near_identity && d > 0.9 && d < 1.1;
-            if (!(d > 0.0)) {
-                if (tid == 0) w.status[ST_BREAKDOWN] = 1;
-                d = 1e-300;
+            if (!(d > 1e-10)) {
+                bad = p;
+                break;
             }
             const double lpp = sqrt(d);
             __syncthreads();
@@ -881,6 +889,44 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
                 if (j <= i) G[i * ldp + j] -= G[i * ldp + p] * G[j * ldp + p];
             }
             __syncthreads();
+        }
+        if (bad >= 0) {
+            const int tr = tries[bad];
+            __syncthreads();
+            if (tr >= 2) {  // no independent direction found
+                if (tid == 0) w.status[ST_BREAKDOWN] = 1;
+                break;
+            }
+            __shared__ int s_pos;
+            if (tid == 0) {
+                s_pos = -1;
+                for (int a2 = 0; a2 < r; ++a2)
+                    if (w.perm[a2] == bad) s_pos = a2;
+                tries[bad] = tr + 1;
+            }
+            __syncthreads();
+            const int pos = tr == 0 ? s_pos : -1;
+            double s2 = 0.0;
+            for (int i = tid; i < nh; i += nthr) {
+                double v;
+                if (i < dn && tr == 0)
+                    v = w.FG[(int64_t)i * 2 * ld + ld + bad];
+                else if (i >= dn && pos >= 0)
+                    v = (i - dn) <= pos ? w.L1[pos * ld + (i - dn)] : 0.0;
+                else
+                    v = start_entry(bad + 7 * (tr + 1), i);
+                Xp[(int64_t)i * ld + bad] = v;
+                s2 += v * v;
+            }
+            for (int o = kWave / 2; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, kWave);
+            if (lane == 0) red[wv] = s2;
+            __syncthreads();
+            double nrm = 0.0;
+            for (int i = 0; i < nw; ++i) nrm += red[i];
+            const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+            for (int i = tid; i < nh; i += nthr) Xp[(int64_t)i * ld + bad] *= inv;
+            __syncthreads();
+            continue;
         }
         if (tid < m) {  // L^-1 into Q, column c by thread c (zero above the diagonal)
             const int c = tid;
@@ -902,6 +948,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         double *t = Xp;
         Xp = HXp;
         HXp = t;
+        ++passes;
         if (near_identity) break;
     }
     tk[2] = wall_clock64();

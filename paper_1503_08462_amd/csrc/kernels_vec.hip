@@ -288,47 +288,50 @@ __global__ __launch_bounds__(256) void k_dual_spmm(int64_t n, int ld, const int3
     stv<double, CPT>(W + rm.row * 2 * ld + ld + c0, wm);
 }
 
-// Gram products G = V^T W (ld x 2ld), phase 1: each block sums its row range.
-// A thread owns a TI x TJ output tile; when tiles are fewer than threads, the
-// block's rows are split over `slices` groups of threads (fixed assignment).
-template <int TI, int TJ>
+// Phase 1 of [V^T A V | V^T M V] = V^T W on the FP64 matrix cores: workgroup
+// b takes the contiguous rows [n b / nb, n (b+1) / nb), each wavefront a
+// quarter of them; per 16 x 16 tile of the ld x 2ld result the four partial
+// tiles are summed in a fixed order and written to part[b].  The rows of a
+// wavefront (a few KB) are re-read from cache for the later tiles.
 __global__ __launch_bounds__(256) void k_gram(int64_t n, int ld, const double *__restrict__ V,
                                               const double *__restrict__ W, double *__restrict__ part,
                                               const int *status) {
-    extern __shared__ double gsm[];
+    __shared__ double red[4 * 256];
     if (status[ST_CONVERGED]) return;
-    const int tj = 2 * ld / TJ, ntiles = (ld / TI) * tj;
-    const int slices = ntiles <= (int)blockDim.x ? (int)blockDim.x / ntiles : 1;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int64_t nb = gridDim.x, lb = xcd_block();
     const int64_t r0 = n * lb / nb, r1 = n * (lb + 1) / nb;
-    const int outsz = ld * 2 * ld;
-    const int nwork = ntiles * slices;
-    for (int item = threadIdx.x; item < nwork; item += blockDim.x) {
-        const int sl = item / ntiles, tt = item - sl * ntiles;
-        const int i0 = (tt / tj) * TI, j0 = (tt % tj) * TJ;
-        double acc[TI][TJ];
+    const int64_t per = (r1 - r0 + 3) / 4;
+    const int64_t w0 = r0 + wv * per < r1 ? r0 + wv * per : r1;
+    const int64_t w1 = w0 + per < r1 ? w0 + per : r1;
+    const int K = (int)(w1 - w0);
+    const int l2 = 2 * ld, ti = (ld + 15) / 16, tj = (l2 + 15) / 16;
+    const int outsz = ld * l2;
+    for (int t = 0; t < ti * tj; ++t) {
+        const int ta = t / tj, tb = t - ta * tj;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        if (K > 0)
+            acc = mfma_tn16(
+                [&](int k, int c) -> double {
+                    const int col = 16 * ta + c;
+                    return col < ld ? V[(w0 + k) * ld + col] : 0.0;
+                },
+                [&](int k, int c) -> double {
+                    const int col = 16 * tb + c;
+                    return col < l2 ? W[(w0 + k) * l2 + col] : 0.0;
+                },
+                K);
 #pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) acc[i][j] = 0.0;
-        for (int64_t row = r0 + sl; row < r1; row += slices) {
-            const Vec<double, TI> v = ldv<double, TI>(V + row * ld + i0);
-            const Vec<double, TJ> w = ldv<double, TJ>(W + row * 2 * ld + j0);
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-                for (int j = 0; j < TJ; ++j) acc[i][j] += v.v[i] * w.v[j];
+        for (int u = 0; u < 4; ++u) red[(wv * 4 + u) * kWave + lane] = acc[u];
+        __syncthreads();
+        {
+            const int u = threadIdx.x >> 6, ln = threadIdx.x & 63;
+            const double v = (red[(0 * 4 + u) * kWave + ln] + red[(1 * 4 + u) * kWave + ln]) +
+                             (red[(2 * 4 + u) * kWave + ln] + red[(3 * 4 + u) * kWave + ln]);
+            const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
+            if (i < ld && j < l2) part[lb * outsz + i * l2 + j] = v;
         }
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) gsm[sl * outsz + (i0 + i) * 2 * ld + j0 + j] = acc[i][j];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < outsz; e += blockDim.x) {
-        double sum = 0.0;
-        for (int k = 0; k < slices; ++k) sum += gsm[k * outsz + e];
-        part[lb * outsz + e] = sum;
+        __syncthreads();
     }
 }
 
@@ -505,27 +508,17 @@ void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, cons
                                         s, n, ld, ptr, col, a, m, V, W, status));
 }
 
-int64_t gram_blocks(int64_t n, int ld) {
+int64_t gram_blocks(int64_t n, int ld) {  // about 64 rows per wavefront, at most 1024 workgroups
     (void)ld;
     int64_t nb = (n + 255) / 256;
-    return nb < 512 ? (nb < 1 ? 1 : nb) : 512;
+    return nb < 1024 ? (nb < 1 ? 1 : nb) : 1024;
 }
 
 void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
                  const int *status) {
     const int64_t nb = gram_blocks(n, ld);
     const int outsz = 2 * ld * ld;
-    if (ld <= 16) {
-        const int ntiles = (ld / 2) * (2 * ld / 2);
-        const int slices = ntiles <= kBlock ? kBlock / ntiles : 1;
-        const size_t lds = (size_t)slices * outsz * sizeof(double);
-        hipLaunchKernelGGL((k_gram<2, 2>), dim3((unsigned)nb), dim3(kBlock), lds, s, n, ld, V, W, part, status);
-    } else {
-        const int ntiles = (ld / 4) * (2 * ld / 4);
-        const int slices = ntiles <= kBlock ? kBlock / ntiles : 1;
-        const size_t lds = (size_t)slices * outsz * sizeof(double);
-        hipLaunchKernelGGL((k_gram<4, 4>), dim3((unsigned)nb), dim3(kBlock), lds, s, n, ld, V, W, part, status);
-    }
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, part, G,
                        status);
 }
