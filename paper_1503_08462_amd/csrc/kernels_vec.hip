@@ -36,6 +36,30 @@ __device__ __forceinline__ Vec<T, C> zero_v() {
     return z;
 }
 
+// Gathers x[col[p]] (CPT values from column c0) for p in [p0, p1) and hands
+// each to consume(p, j, x_j) in ascending p; the loads of four neighbours are
+// issued before the first of them is consumed.
+template <typename T, int CPT, class F>
+__device__ __forceinline__ void gather4(int32_t p0, int32_t p1, const int32_t *__restrict__ col,
+                                        const T *__restrict__ x, int ld, int c0, const F &consume) {
+    int32_t p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        const int64_t j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
+        const Vec<T, CPT> x0 = ldv<T, CPT>(x + j0 * ld + c0);
+        const Vec<T, CPT> x1 = ldv<T, CPT>(x + j1 * ld + c0);
+        const Vec<T, CPT> x2 = ldv<T, CPT>(x + j2 * ld + c0);
+        const Vec<T, CPT> x3 = ldv<T, CPT>(x + j3 * ld + c0);
+        consume(p, j0, x0);
+        consume(p + 1, j1, x1);
+        consume(p + 2, j2, x2);
+        consume(p + 3, j3, x3);
+    }
+    for (; p < p1; ++p) {
+        const int64_t j = col[p];
+        consume(p, j, ldv<T, CPT>(x + j * ld + c0));
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- a1
@@ -63,12 +87,11 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32
         const int64_t row = w * rpw + grp;
         if (grp >= rpw || row >= n) continue;
         Vec<double, CPT> au = zero_v<double, CPT>(), mu = zero_v<double, CPT>();
-        for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) {
-            const int64_t j = col[p];
-            const Vec<double, CPT> u = ldv<double, CPT>(U + j * ld + c0);
-            fma_v(au, a[p], u);
-            fma_v(mu, m[p], u);
-        }
+        gather4<double, CPT>(ptr[row], ptr[row + 1], col, U, ld, c0,
+                             [&](int32_t p, int64_t, const Vec<double, CPT> &u) {
+                                 fma_v(au, a[p], u);
+                                 fma_v(mu, m[p], u);
+                             });
         Vec<TO, CPT> out;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -147,10 +170,8 @@ __global__ __launch_bounds__(256) void k_smooth_pre(int64_t n, int ld, const int
     if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) {
-        const int64_t j = col[p];
-        fma_v(acc, -val[p] * dinv[j], ldv<T, CPT>(b + j * ld + c0));
-    }
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, b, ld, c0,
+                    [&](int32_t p, int64_t j, const Vec<T, CPT> &xj) { fma_v(acc, -val[p] * dinv[j], xj); });
     stv<T, CPT>(r + rm.row * ld + c0, acc);
 }
 
@@ -164,7 +185,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, int ld, const int32_t *
     if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> acc = zero_v<T, CPT>();
-    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) fma_v(acc, val[p], ldv<T, CPT>(x + (int64_t)col[p] * ld + c0));
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, x, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, val[p], xj); });
     stv<T, CPT>(y + rm.row * ld + c0, acc);
 }
 
@@ -182,7 +204,8 @@ __global__ __launch_bounds__(256) void k_prolong_add(int64_t n, int ld, const in
     const T di = dinv[rm.row];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) acc.v[c] *= di;
-    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) fma_v(acc, val[p], ldv<T, CPT>(xc + (int64_t)col[p] * ld + c0));
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, xc, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, val[p], xj); });
     stv<T, CPT>(y + rm.row * ld + c0, acc);
 }
 
@@ -199,8 +222,8 @@ __global__ __launch_bounds__(256) void k_smooth_post(int64_t n, int ld, const in
     if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p)
-        fma_v(acc, -val[p], ldv<T, CPT>(y + (int64_t)col[p] * ld + c0));
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, y, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -val[p], xj); });
     const Vec<T, CPT> yi = ldv<T, CPT>(y + rm.row * ld + c0);
     const T di = dinv[rm.row];
     if constexpr (FINAL) {
@@ -279,11 +302,11 @@ __global__ __launch_bounds__(256) void k_dual_spmm(int64_t n, int ld, const int3
     if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<double, CPT> wa = zero_v<double, CPT>(), wm = zero_v<double, CPT>();
-    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) {
-        const Vec<double, CPT> v = ldv<double, CPT>(V + (int64_t)col[p] * ld + c0);
-        fma_v(wa, a[p], v);
-        fma_v(wm, m[p], v);
-    }
+    gather4<double, CPT>(ptr[rm.row], ptr[rm.row + 1], col, V, ld, c0,
+                         [&](int32_t p, int64_t, const Vec<double, CPT> &v) {
+                             fma_v(wa, a[p], v);
+                             fma_v(wm, m[p], v);
+                         });
     stv<double, CPT>(W + rm.row * 2 * ld + c0, wa);
     stv<double, CPT>(W + rm.row * 2 * ld + ld + c0, wm);
 }
@@ -364,7 +387,8 @@ __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t 
     if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<double, CPT> acc = zero_v<double, CPT>();
-    for (int32_t p = ptr[rm.row]; p < ptr[rm.row + 1]; ++p) fma_v(acc, val[p], ldv<double, CPT>(Y + (int64_t)col[p] * ld + c0));
+    gather4<double, CPT>(ptr[rm.row], ptr[rm.row + 1], col, Y, ld, c0,
+                         [&](int32_t p, int64_t, const Vec<double, CPT> &yj) { fma_v(acc, val[p], yj); });
     const double *vr = V + rm.row * ld;
     for (int a = 0; a < ld; a += 4) {
         const Vec<double, 4> v4 = ldv<double, 4>(vr + a);
