@@ -174,7 +174,7 @@ int amg_eig_coarse_eigenvalues(const amg_eig_ctx *c, double *lam);
 int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld);
 
 /* Kernel sites on the finest level, for per-kernel timing. */
-#define AMG_EIG_SITE_RESIDUAL 0   /* outer residual + norms (FP64 dual SpMM) */
+#define AMG_EIG_SITE_RESIDUAL 0   /* outer residual R = M U Theta - A U (FP64 dual SpMM) */
 #define AMG_EIG_SITE_PRESMOOTH 1  /* fused zero-guess smoothing + residual */
 #define AMG_EIG_SITE_POSTSMOOTH 2 /* post-smoothing fused with V = U + delta */
 #define AMG_EIG_SITE_DUALSPMM 3   /* W = [A V | M V] */

@@ -376,9 +376,13 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
 template <typename T>
 void residual(amg_eig_ctx *c, int k, int check) {
     DevLevel &d = c->dl[k];
-    SiteScope sc(c, AMG_EIG_SITE_RESIDUAL, k);
-    launch_residual<T>(c->stream, d.n, c->ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (T *)d.b,
-                       c->part_res, c->counters, c->rho, c->q, c->o.tol, c->status, check);
+    {
+        SiteScope sc(c, AMG_EIG_SITE_RESIDUAL, k);
+        launch_residual<T>(c->stream, d.n, c->ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (T *)d.b,
+                           c->part_res, c->status);
+    }
+    launch_residual_finish(c->stream, d.n, c->ld, c->part_res, c->counters, c->theta, c->rho, c->q, c->o.tol,
+                           c->status, check);
 }
 
 void correction(amg_eig_ctx *c, int k) {

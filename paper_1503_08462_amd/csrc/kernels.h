@@ -22,8 +22,10 @@ int64_t residual_blocks(int64_t n, int ld);
 int64_t gram_blocks(int64_t n, int ld);
 template <typename TO>
 void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
-                     const double *m, const double *U, const double *theta, TO *R, double *part,
-                     unsigned *counter, double *rho, int q, double tol, int *status, int check);
+                     const double *m, const double *U, const double *theta, TO *R, double *part, const int *status);
+// the norms rho_j and the convergence flag from the partial sums of launch_residual
+void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
+                            double *rho, int q, double tol, int *status, int check);
 template <typename T>
 void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
                        const T *dinv, const T *b, T *r, const int *status);

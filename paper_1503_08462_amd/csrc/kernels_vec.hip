@@ -475,15 +475,19 @@ int64_t residual_blocks(int64_t n, int ld) {
 
 template <typename TO>
 void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
-                     const double *m, const double *U, const double *theta, TO *R, double *part,
-                     unsigned *counter, double *rho, int q, double tol, int *status, int check) {
+                     const double *m, const double *U, const double *theta, TO *R, double *part, const int *status) {
     // part: 2 ld final sums, then nb x 2 ld per-block partials
     const int64_t nb = residual_blocks(n, ld);
     double *blocks = part + 2 * ld;
     DISPATCH_CPT(ld, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
                                         col, a, m, U, theta, R, blocks, status));
-    hipLaunchKernelGGL(k_residual_finish, dim3(2 * ld), dim3(kBlock), 0, s, nb, ld, blocks, part, counter, theta, rho,
-                       q, tol, status, check);
+}
+
+void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
+                            double *rho, int q, double tol, int *status, int check) {
+    const int64_t nb = residual_blocks(n, ld);
+    hipLaunchKernelGGL(k_residual_finish, dim3(2 * ld), dim3(kBlock), 0, s, nb, ld, part + 2 * ld, part, counter,
+                       theta, rho, q, tol, status, check);
 }
 
 template <typename T>
@@ -597,8 +601,7 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
                                         const T *, const T *, const T *, const T *, T *, const double *, double *,   \
                                         const int *);                                                                \
     template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
-                                     const double *, const double *, const double *, T *, double *, unsigned *,      \
-                                     double *, int, double, int *, int);
+                                     const double *, const double *, const double *, T *, double *, const int *);
 INST(float)
 INST(double)
 #undef INST
