@@ -54,7 +54,7 @@ extern "C" {
 
 /* --------------------------------------------------------------- options */
 #define AMG_EIG_SMOOTH_L1JACOBI 0  /* x += D^-1 (b - A x), d_i = sum_j |a_ij| */
-#define AMG_EIG_SMOOTH_CHEBYSHEV 1 /* Chebyshev polynomial in D^-1 A on [cheb_lo, 1] */
+#define AMG_EIG_SMOOTH_CHEBYSHEV 1 /* degree-2 Chebyshev polynomial in D^-1 A on [cheb_lo, 1] (cheb_degree must be 2) */
 
 #define AMG_EIG_PREC_FP64 0  /* everything in FP64 */
 #define AMG_EIG_PREC_MIXED 1 /* V-cycle (smoothing, transfers) in FP32 with FP32
@@ -85,7 +85,8 @@ typedef struct {
 
 /* Paper defaults (Section 4.1: theta = 0.25, one V-cycle with one pre- and
  * one post-smoothing step, n_1 = n, p_k = 1 on coarse levels) plus the GPU
- * options: l1-Jacobi smoothing, FP64, coarse_max 512, tol 1e-8. */
+ * options: degree-2 Chebyshev smoothing on [0.25, 1] in D^-1 A (D the l1
+ * diagonal), FP64, coarse_max 512, tol 1e-8. */
 void amg_eig_opts_default(amg_eig_opts *o);
 
 /* Host CSR, borrowed for the call: rowptr[n+1] (int64, rowptr[0] = 0,

@@ -28,7 +28,7 @@ struct DevLevel {
     int32_t *p_ptr = nullptr, *p_col = nullptr, *pt_ptr = nullptr, *pt_col = nullptr;
     void *p_val = nullptr, *pt_val = nullptr;
     double *p64 = nullptr, *pt64 = nullptr;
-    void *b = nullptr, *r = nullptr, *x = nullptr;
+    void *b = nullptr, *r = nullptr, *x = nullptr, *t = nullptr;  // t: Chebyshev scratch
     double *cw = nullptr;
 };
 
@@ -126,6 +126,7 @@ void plan(amg_eig_ctx *c, char *base) {
         d.b = cv.take<char>((size_t)lv.n * ld * sT);
         d.r = cv.take<char>((size_t)lv.n * ld * sT);
         d.x = cv.take<char>((size_t)lv.n * ld * sT);
+        if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV && l < L - 1) d.t = cv.take<char>((size_t)lv.n * ld * sT);
         if (l >= 1) d.cw = cv.take<double>((size_t)lv.n * 2 * ld);
     }
     c->U = cv.take<double>((size_t)N * ld);
@@ -293,7 +294,10 @@ double site_bytes(const amg_eig_ctx *c, int site) {
     switch (site) {
     case AMG_EIG_SITE_RESIDUAL: return ptr + nnz_u * 20.0 + 8.0 * n * ld + sT * n * ld;
     case AMG_EIG_SITE_PRESMOOTH: return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld;
-    case AMG_EIG_SITE_POSTSMOOTH: return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld + 16.0 * n * ld;
+    case AMG_EIG_SITE_POSTSMOOTH:
+        if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV)  // two products: d0 from (b, y); x from (d0, y), U -> V
+            return 2.0 * (ptr + nnz_v * (4.0 + sT) + sT * n) + 3.0 * sT * n * ld + 2.0 * sT * n * ld + 16.0 * n * ld;
+        return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_DUALSPMM: return ptr + nnz_u * 20.0 + 8.0 * n * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_GRAM: return 4.0 * n * ld * ld;  // flops
     case AMG_EIG_SITE_RESTRICT: return 4.0 * (n1 + 1) + nnz_p * 12.0 + 16.0 * n * ld + 16.0 * n1 * ld;
@@ -309,9 +313,19 @@ void vcycle(amg_eig_ctx *c, int k) {
     const int L = (int)c->dl.size(), ld = c->ld;
     hipStream_t s = c->stream;
     const int *st = c->status;
+    const bool cheb = c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV;
+    const double lo = c->o.cheb_lo;
     for (int l = k; l < L - 1; ++l) {
         DevLevel &d = c->dl[l];
-        {
+        if (cheb) {
+            {
+                SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
+                launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                   (const T *)d.b, (T *)d.x, lo, st);
+            }
+            launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
+                                     (const T *)d.x, (T *)d.r, st);
+        } else {
             SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
             launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                  (const T *)d.b, (T *)d.r, st);
@@ -325,11 +339,20 @@ void vcycle(amg_eig_ctx *c, int k) {
     for (int l = L - 2; l >= k; --l) {
         DevLevel &d = c->dl[l];
         DevLevel &e = c->dl[l + 1];
-        launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.dinv,
-                              (const T *)d.b, (T *)d.r, st);
-        SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
-        launch_smooth_post<T>(s, l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
-                              (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st);
+        if (cheb) {
+            // y = x + P x_{l+1} into r (free after the restriction), then x = smoothed y
+            launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.x,
+                                (T *)d.r, st);
+            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
+            launch_cheb_post<T>(s, l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                (const T *)d.b, (const T *)d.r, (T *)d.t, (T *)d.x, c->U, c->V, lo, st);
+        } else {
+            launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
+                                  (const T *)d.dinv, (const T *)d.b, (T *)d.r, st);
+            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
+            launch_smooth_post<T>(s, l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                  (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st);
+        }
     }
 }
 
@@ -437,7 +460,7 @@ void amg_eig_opts_default(amg_eig_opts *o) {
     o->max_levels = 25;
     o->qe = 0;
     o->guard_gap = 1e-2;
-    o->smoother = AMG_EIG_SMOOTH_L1JACOBI;
+    o->smoother = AMG_EIG_SMOOTH_CHEBYSHEV;
     o->cheb_degree = 2;
     o->cheb_lo = 0.25;
     o->nu_pre = 1;
@@ -457,7 +480,9 @@ int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_e
         c->o = *o;
     else
         amg_eig_opts_default(&c->o);
-    if (c->o.smoother != AMG_EIG_SMOOTH_L1JACOBI || c->o.nu_pre != 1 || c->o.nu_post != 1 ||
+    const bool cheb_ok = c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV && c->o.cheb_degree == 2 && c->o.cheb_lo > 0.0 &&
+                         c->o.cheb_lo < 1.0;
+    if ((c->o.smoother != AMG_EIG_SMOOTH_L1JACOBI && !cheb_ok) || c->o.nu_pre != 1 || c->o.nu_post != 1 ||
         (c->o.precision != AMG_EIG_PREC_FP64 && c->o.precision != AMG_EIG_PREC_MIXED)) {
         delete c;
         return AMG_EIG_EINVAL;

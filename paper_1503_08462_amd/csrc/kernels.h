@@ -39,6 +39,23 @@ template <typename T>
 void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
                         const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
                         const int *status);
+// Degree-2 Chebyshev smoothing on D^-1 A over [lo, 1] (D the l1 diagonal):
+// pre-smoothing from a zero guess (x), the level residual r = b - A x, the
+// prolongation y = x + P xc, and post-smoothing of y (scratch d0; x, or on
+// the correction level V = U + x in FP64).
+template <typename T>
+void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                     const T *dinv, const T *b, T *x, double lo, const int *status);
+template <typename T>
+void launch_level_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                           const T *b, const T *x, T *r, const int *status);
+template <typename T>
+void launch_prolong_x(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                      const T *xc, const T *x, T *y, const int *status);
+template <typename T>
+void launch_cheb_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
+                      const T *val, const T *dinv, const T *b, const T *y, T *d0, T *x, const double *U, double *V,
+                      double lo, const int *status);
 template <typename T, typename TA>
 void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
                        const int *status);

@@ -239,6 +239,153 @@ __global__ __launch_bounds__(256) void k_smooth_post(int64_t n, int ld, const in
     }
 }
 
+// ---------------------------------------------- Chebyshev smoothing (a2, a6)
+// Degree-2 Chebyshev smoothing on D^-1 A over [lo, 1] (D the l1 diagonal):
+// with theta = (1 + lo) / 2, delta = (1 - lo) / 2, sigma = theta / delta,
+// rho0 = 1 / sigma, rho1 = 1 / (2 sigma - rho0), c1 = rho1 rho0, c2 = 2 rho1 / delta,
+//   r0 = D^-1 (b - A x0), d0 = r0 / theta, r1 = r0 - D^-1 A d0,
+//   d1 = c1 d0 + c2 r1, x = x0 + d0 + d1.
+struct ChebCoef {
+    float itheta, theta, c1, c2;     // FP32 copies for the mixed-precision V-cycle
+    double ditheta, dtheta, dc1, dc2;
+};
+
+template <typename T>
+__device__ __forceinline__ void cheb_coef(const ChebCoef &k, T &itheta, T &theta, T &c1, T &c2) {
+    if constexpr (sizeof(T) == 4) {
+        itheta = k.itheta;
+        theta = k.theta;
+        c1 = k.c1;
+        c2 = k.c2;
+    } else {
+        itheta = k.ditheta;
+        theta = k.dtheta;
+        c1 = k.dc1;
+        c2 = k.dc2;
+    }
+}
+
+// Pre-smoothing from x0 = 0: r0 = D^-1 b, so one product A (D^-1 b) gives x.
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_cheb_pre(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                  const T *__restrict__ dinv, const T *__restrict__ b,
+                                                  T *__restrict__ x, ChebCoef kc, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    T itheta, theta, c1, c2;
+    cheb_coef(kc, itheta, theta, c1, c2);
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> az = zero_v<T, CPT>();  // A D^-1 b
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, b, ld, c0,
+                    [&](int32_t p, int64_t j, const Vec<T, CPT> &bj) { fma_v(az, val[p] * dinv[j], bj); });
+    const Vec<T, CPT> bi = ldv<T, CPT>(b + rm.row * ld + c0);
+    const T di = dinv[rm.row];
+    Vec<T, CPT> o;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const T r0 = di * bi.v[c];
+        const T d0 = r0 * itheta;
+        const T r1 = r0 - di * (az.v[c] * itheta);
+        const T d1 = c1 * d0 + c2 * r1;
+        o.v[c] = d0 + d1;
+    }
+    stv<T, CPT>(x + rm.row * ld + c0, o);
+}
+
+// r = b - A x on one level
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_level_residual(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                        const T *__restrict__ b, const T *__restrict__ x,
+                                                        T *__restrict__ r, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, x, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -val[p], xj); });
+    stv<T, CPT>(r + rm.row * ld + c0, acc);
+}
+
+// y = x + P xc (prolongation onto the stored pre-smoothed iterate)
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_prolong_x(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                   const T *__restrict__ xc, const T *__restrict__ x,
+                                                   T *__restrict__ y, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(x + rm.row * ld + c0);
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, xc, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, val[p], xj); });
+    stv<T, CPT>(y + rm.row * ld + c0, acc);
+}
+
+// Post-smoothing, first product: d0 = D^-1 (b - A y) / theta
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_cheb_post1(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ dinv, const T *__restrict__ b,
+                                                    const T *__restrict__ y, T *__restrict__ d0, ChebCoef kc,
+                                                    const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    T itheta, theta, c1, c2;
+    cheb_coef(kc, itheta, theta, c1, c2);
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, y, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &yj) { fma_v(acc, -val[p], yj); });
+    const T di = dinv[rm.row];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) acc.v[c] = (di * acc.v[c]) * itheta;
+    stv<T, CPT>(d0 + rm.row * ld + c0, acc);
+}
+
+// Post-smoothing, second product: r1 = theta d0 - D^-1 A d0, d1 = c1 d0 + c2 r1,
+// x = y + d0 + d1; on the correction level V = U + x in FP64 instead.
+template <typename T, int CPT, bool FINAL>
+__global__ __launch_bounds__(256) void k_cheb_post2(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ dinv, const T *__restrict__ y,
+                                                    const T *__restrict__ d0, T *__restrict__ x,
+                                                    const double *__restrict__ U, double *__restrict__ V,
+                                                    ChebCoef kc, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    if (!rm.active) return;
+    T itheta, theta, c1, c2;
+    cheb_coef(kc, itheta, theta, c1, c2);
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> ad = zero_v<T, CPT>();
+    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, d0, ld, c0,
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &dj) { fma_v(ad, val[p], dj); });
+    const Vec<T, CPT> di0 = ldv<T, CPT>(d0 + rm.row * ld + c0);
+    const Vec<T, CPT> yi = ldv<T, CPT>(y + rm.row * ld + c0);
+    const T di = dinv[rm.row];
+    Vec<T, CPT> o;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const T r1 = theta * di0.v[c] - di * ad.v[c];
+        const T d1 = c1 * di0.v[c] + c2 * r1;
+        o.v[c] = yi.v[c] + di0.v[c] + d1;
+    }
+    if constexpr (FINAL) {
+        Vec<double, CPT> u = ldv<double, CPT>(U + rm.row * ld + c0);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) u.v[c] += (double)o.v[c];
+        stv<double, CPT>(V + rm.row * ld + c0, u);
+    } else {
+        stv<T, CPT>(x + rm.row * ld + c0, o);
+    }
+}
+
 // ------------------------------------------------------------ dense rows
 template <typename T, typename TA, int CPT>
 __global__ __launch_bounds__(256) void k_dense_rows(int64_t m, int64_t K, const TA *__restrict__ A, int64_t lda,
@@ -569,6 +716,60 @@ template void launch_gemm_tn<float>(hipStream_t, int, int, int, const float *, i
 template void launch_gemm_tn<double>(hipStream_t, int, int, int, const double *, int, const double *, int, double *,
                                      int, const int *);
 
+ChebCoef cheb_coefficients(double lo) {
+    const double theta = 0.5 * (1.0 + lo), delta = 0.5 * (1.0 - lo);
+    const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    ChebCoef k;
+    k.ditheta = 1.0 / theta;
+    k.dtheta = theta;
+    k.dc1 = rho1 * rho0;
+    k.dc2 = 2.0 * rho1 / delta;
+    k.itheta = (float)k.ditheta;
+    k.theta = (float)k.dtheta;
+    k.c1 = (float)k.dc1;
+    k.c2 = (float)k.dc2;
+    return k;
+}
+
+template <typename T>
+void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                     const T *dinv, const T *b, T *x, double lo, const int *status) {
+    const ChebCoef kc = cheb_coefficients(lo);
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                                        0, s, n, ld, ptr, col, val, dinv, b, x, kc, status));
+}
+
+template <typename T>
+void launch_level_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                           const T *b, const T *x, T *r, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_level_residual<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                        dim3(kBlock), 0, s, n, ld, ptr, col, val, b, x, r, status));
+}
+
+template <typename T>
+void launch_prolong_x(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                      const T *xc, const T *x, T *y, const int *status) {
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_prolong_x<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                                        0, s, n, ld, ptr, col, val, xc, x, y, status));
+}
+
+template <typename T>
+void launch_cheb_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
+                      const T *val, const T *dinv, const T *b, const T *y, T *d0, T *x, const double *U, double *V,
+                      double lo, const int *status) {
+    const ChebCoef kc = cheb_coefficients(lo);
+    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_post1<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                                        0, s, n, ld, ptr, col, val, dinv, b, y, d0, kc, status));
+    if (final)
+        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_post2<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                            dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
+                                            status));
+    else
+        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_post2<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                            dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
+                                            status));
+}
+
 void launch_fill_random(hipStream_t s, int64_t n, int ld, int qe, uint64_t seed, double *U) {
     const int64_t tot = n * ld;
     hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, ld, qe, seed, U);
@@ -601,7 +802,16 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
                                         const T *, const T *, const T *, const T *, T *, const double *, double *,   \
                                         const int *);                                                                \
     template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
-                                     const double *, const double *, const double *, T *, double *, const int *);
+                                     const double *, const double *, const double *, T *, double *, const int *);     \
+    template void launch_cheb_pre<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,         \
+                                     const T *, const T *, T *, double, const int *);                                \
+    template void launch_level_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,   \
+                                           const T *, const T *, T *, const int *);                                  \
+    template void launch_prolong_x<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,        \
+                                      const T *, const T *, T *, const int *);                                       \
+    template void launch_cheb_post<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *, const T *,  \
+                                      const T *, const T *, const T *, T *, T *, const double *, double *, double,    \
+                                      const int *);
 INST(float)
 INST(double)
 #undef INST

@@ -41,7 +41,7 @@ def make_ctx(p, **kw):
     return ctx
 
 
-def oracle_for(p, ctx, smoother="l1jacobi"):
+def oracle_for(p, ctx, smoother="chebyshev"):
     A, M = mats(p)
     info = ctx.info()
     o = Oracle(A, M, q=p["q"], qe=info["qe"], coarse_max=ctx.opts.coarse_max,
@@ -58,8 +58,8 @@ def test_random_start_and_step_parity_config0():
     _torch()
     p = configs.config(0)
     _say("config0 random start, step parity, FP64")
-    ctx = make_ctx(p, coarse_max=130)
-    o, A, M = oracle_for(p, ctx)
+    ctx = make_ctx(p, coarse_max=130, smoother=ae.SMOOTH_L1JACOBI)
+    o, A, M = oracle_for(p, ctx, smoother="l1jacobi")
     qe = ctx.info()["qe"]
     ctx.init(ae.INIT_RANDOM, seed=1)
     th, U, _ = gpu_state(ctx)
@@ -118,6 +118,35 @@ def test_nested_solve_matches_oracle(name, make, cm, prec):
     # the device residuals agree with a CPU evaluation of the returned pairs
     rho_cpu = o.residuals(0, th, U)
     assert rho_cpu[:q].max() <= 1e-10 * 1.01
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [ae.PREC_FP64, ae.PREC_MIXED])
+def test_chebyshev_smoother_step_parity_and_solve(prec):
+    """Degree-2 Chebyshev smoothing on [0.25, 1]: each correction agrees with
+    the oracle's Chebyshev V-cycle step by step (FP64), and the converged pairs
+    agree with the oracle's (both precisions) on a jittered L-shape."""
+    _torch()
+    p = configs.lshape(24, q=6, jitter_seed=5)
+    _say("chebyshev smoother prec=%d" % prec)
+    ctx = make_ctx(p, coarse_max=150, precision=prec, smoother=ae.SMOOTH_CHEBYSHEV, cheb_degree=2, cheb_lo=0.25)
+    o, A, M = oracle_for(p, ctx, smoother="chebyshev")
+    q, qe = p["q"], ctx.info()["qe"]
+    ctx.init(ae.INIT_RANDOM, seed=11)
+    lam_o, U_o = o.random_start(prng.random_block(11, p["n"], qe))
+    for step in range(3):
+        ctx.correct(1)
+        th, U, pr = gpu_state(ctx)
+        lam_o, U_o = o.correction(0, lam_o, U_o)
+        tol = 1e-10 if prec == ae.PREC_FP64 else 1e-5
+        assert np.abs(th / lam_o - 1).max() < tol, (step, th, lam_o)
+    lam, ok = ctx.solve(tol=1e-10, max_steps=300)
+    th, U, pr = gpu_state(ctx)
+    assert ok, pr
+    lo, Uo, info = o.solve(tol=1e-11, max_steps=400)
+    assert np.abs(lam / lo[:q] - 1).max() < (1e-10 if prec == ae.PREC_FP64 else 1e-6)
+    assert compare_subspaces(lo, Uo, U, M, q) < 1e-6
+    assert o.residuals(0, th, U)[:q].max() <= 1e-10 * 1.01
     ctx.close()
 
 

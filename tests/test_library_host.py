@@ -69,7 +69,7 @@ def test_guard_rule_and_width_rounding():
 
 @pytest.mark.parametrize("mutate,code", [
     ("unsorted", ae.EINVAL), ("range", ae.EINVAL), ("negdiag", ae.ENOTSPD), ("rowptr", ae.EINVAL),
-    ("q0", ae.EINVAL), ("toowide", ae.EINVAL), ("nan", ae.EINVAL),
+    ("q0", ae.EINVAL), ("toowide", ae.EINVAL), ("nan", ae.EINVAL), ("chebdeg3", ae.EINVAL), ("nu2", ae.EINVAL),
 ])
 def test_validation_errors(mutate, code):
     p = configs.square(8, q=2)
@@ -90,9 +90,21 @@ def test_validation_errors(mutate, code):
         opts.qe = 200
     elif mutate == "nan":
         m[7] = np.nan
+    elif mutate == "chebdeg3":  # the device smoother implements degree 2 only
+        opts.smoother, opts.cheb_degree = ae.SMOOTH_CHEBYSHEV, 3
+    elif mutate == "nu2":
+        opts.nu_pre = 2
     with pytest.raises(ae.AmgEigError) as ei:
         ae.Context(rp, col, a, m, q, opts)
     assert ei.value.code == code
+
+
+def test_chebyshev_degree_two_is_accepted():
+    p = configs.square(8, q=2)
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], 2,
+                     ae.defaults(coarse_max=20, coarse_min=8, smoother=ae.SMOOTH_CHEBYSHEV, cheb_degree=2))
+    assert ctx.info()["qe"] >= 2
+    ctx.close()
 
 
 def test_calls_out_of_order_are_rejected_on_the_host():
