@@ -163,13 +163,14 @@ __device__ __forceinline__ dbl4 mfma_tn16(const FX &X, const FY &Y, int K) {
 // on the matrix cores.  X(k, a) and Y(k, b) must return zero for a >= mi
 // (b >= mj); `out` receives each finished entry once.  With fewer tiles than
 // wavefronts the K range is split over the wavefronts and the partial tiles
-// summed in a fixed order (red holds 3 * 4 * 256 doubles).  Ends with a
-// barrier.
+// summed in a fixed order, provided red (red_cap doubles) holds
+// ntiles * wavefronts * 256 doubles.  Ends with a barrier.
 template <class FX, class FY, class FO>
-__device__ void block_tiles(const FX &X, const FY &Y, int K, int mi, int mj, const FO &out, double *red) {
+__device__ void block_tiles(const FX &X, const FY &Y, int K, int mi, int mj, const FO &out, double *red,
+                            int red_cap) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int ti = (mi + 15) >> 4, tj = (mj + 15) >> 4, ntiles = ti * tj;
-    if (K > 0 && (ntiles >= nw || nw == 1)) {
+    if (K > 0 && (ntiles >= nw || nw == 1 || ntiles * nw * 256 > red_cap)) {
         for (int t = wv; t < ntiles; t += nw) {
             const int ta = t / tj, tb = t - ta * tj;
             const dbl4 acc = mfma_tn16([&](int k, int c) { return X(k, 16 * ta + c); },
@@ -207,8 +208,9 @@ __device__ void block_tiles(const FX &X, const FY &Y, int K, int mi, int mj, con
 
 // out = X^T Y (mi x mj, row stride ostr): block_tiles storing into an array.
 template <class FX, class FY>
-__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red) {
-    block_tiles(X, Y, K, mi, mj, [&](int i, int j, double v) { out[i * ostr + j] = v; }, red);
+__device__ void block_xty(const FX &X, const FY &Y, int K, int mi, int mj, double *out, int ostr, double *red,
+                          int red_cap) {
+    block_tiles(X, Y, K, mi, mj, [&](int i, int j, double v) { out[i * ostr + j] = v; }, red, red_cap);
 }
 
 // Workgroup copy of n doubles (n even, both pointers 16-byte aligned) as

@@ -279,22 +279,29 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, tid = threadIdx.x, nthr = blockDim.x;
     const int tx = tid & 15, ty = tid >> 4, nty = nthr >> 4;
+    // ld <= 32: everything in LDS; wider: D_M, D_A, L^-1 in LDS, L and the
+    // scratch product in the (then consumed) P3 buffer, P3 and [V^T A V | V^T M V]
+    // in global memory
+    const bool small = ld <= 32;
     double *DM = sm;               // ld x ld
     double *DA = DM + ld * ld;     // ld x ld
-    double *Lc = DA + ld * ld;     // ld x ld: L
-    double *Li = Lc + ld * ld;     // ld x ld: L^-1
-    double *Yb = Li + ld * ld;     // ld x ld
-    double *P3 = Yb + ld * ld;     // ld x 3 ld
-    double *gag = P3 + 3 * ld * ld;  // ld x 2 ld: [V^T A V | V^T M V]
-    double *red = gag + 2 * ld * ld;
-    double *lam = red + kRedSmall;  // dn
+    double *Li = DA + ld * ld;     // ld x ld: L^-1
+    double *ext = Li + ld * ld;    // small: L, Yb, P3, gag
+    double *Lc = small ? ext : w.P3;                          // ld x ld: L
+    double *Yb = small ? ext + ld * ld : w.P3 + ld * ld;      // ld x ld
+    double *P3 = small ? ext + 2 * ld * ld : w.P3;            // ld x 3 ld
+    double *gagl = ext + 5 * ld * ld;                          // ld x 2 ld when small
+    double *red = small ? ext + 7 * ld * ld : ext;             // kRedSmall or 64
+    double *lam = red + (small ? kRedSmall : 64);              // dn
     double *fg = lam + ((dn + 1) & ~1);  // dn x 2 ld when fg_in_lds (16-byte aligned)
+    const double *gag = small ? gagl : w.GAGM;
+    const int rcap = small ? kRedSmall : 64;
     __shared__ int perm[kMaxWidth];
     uint64_t tk[8];  // solver statistics: phase clocks (thread 0)
     tk[0] = wall_clock64();
     for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
     if (fg_in_lds) block_copy(fg, w.FG, dn * 2 * ld);
-    block_copy(gag, w.GAGM, 2 * ld * ld);
+    if (small) block_copy(gagl, w.GAGM, 2 * ld * ld);
     if (tid < ld) perm[tid] = tid;
     __syncthreads();
     const int l2 = 2 * ld;
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
                   if (b < l2) return fgv(i, b);
                   return b < 3 * ld ? lam[i] * fgv(i, b - ld) : 0.0;
               },
-              dn, ld, 3 * ld, P3, 3 * ld, red);
+              dn, ld, 3 * ld, P3, 3 * ld, red, rcap);
     for (int e = tid; e < ld * ld; e += nthr) {
         const int a = e / ld, b = e - a * ld;
         const double gm_ab = gag[a * l2 + ld + b], gm_ba = gag[b * l2 + ld + a];
@@ -316,11 +323,14 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
         const double glg = 0.5 * (P3[a * 3 * ld + 2 * ld + b] + P3[b * 3 * ld + 2 * ld + a]);
         DM[e] = 0.5 * (gm_ab + gm_ba) - gg;
         DA[e] = 0.5 * (ga_ab + ga_ba) - gf - fgt + glg;
-        Lc[e] = 0.0;
-        Li[e] = 0.0;
     }
     double scale = 0.0;
     for (int a = 0; a < ld; ++a) scale = fmax(scale, gag[a * l2 + ld + a]);
+    __syncthreads();  // P3 consumed: its buffer may now hold L
+    for (int e = tid; e < ld * ld; e += nthr) {
+        Lc[e] = 0.0;
+        Li[e] = 0.0;
+    }
     __syncthreads();
     tk[2] = wall_clock64();
     // pivoted Cholesky of D_M, the same symmetric permutation applied to D_A
@@ -426,7 +436,7 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
             return fgv(i, pk) - lam[i] * fgv(i, ld + pk);
         },
         [&](int k, int a) -> double { return a < r ? Li[a * ld + k] : 0.0; }, r, dn, ld,
-        [&](int i, int a, double v) { w.Ct[(int64_t)i * ld + a] = v; }, red);
+        [&](int i, int a, double v) { w.Ct[(int64_t)i * ld + a] = v; }, red, rcap);
     if (tid == 0 && w.diag) {
         tk[5] = wall_clock64();
         for (int j = 0; j < 5; ++j) atomicAdd(&w.diag[330 + j], (int)(tk[j + 1] - tk[j]));
@@ -456,19 +466,22 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
     const int ld = w.ld, dn = w.dn, k = blockIdx.x;
     const int r = w.status[ST_RANK];
     const int ldp = (ld + 15) & ~15;
-    const int ls = ldp + 1;
+    const int ls = ld + 1;
+    const bool dt_in_lds = ld <= 32;  // wider D~ is read from global memory (L2)
+    const int dts = dt_in_lds ? ldp : ld;
     const int nthr = blockDim.x, tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
-    double *S = sm;                                    // ldp x ls
-    double *ctl = S + ldp * ls;                        // dn x ldp, zero beyond column r
+    double *S = sm;                                    // ld x ls
+    double *ctl = S + ld * ls;                         // dn x ldp, zero beyond column r
     double *wdn = ctl + (ct_in_lds ? dn * ldp : 0);    // dn weights 1 / (lambda_i - sigma)
     double *vec = wdn + dn;                            // dn + ldp: current vector
     double *hx = vec + dn + ldp;                       // dn + ldp: H x
     double *fz = hx + dn + ldp;                        // ldp
     double *lam = fz + ldp;                            // dn
-    double *dt = lam + dn;                             // ldp x ldp
-    double *Lm = dt + ldp * ldp;                       // ldp x ls: multipliers of the factorisation
-    double *red = Lm + ldp * ls;                       // 4 x 256 partial tiles + 64 cross-wavefront sums
+    double *dtl = lam + dn;                            // ldp x ldp when dt_in_lds
+    double *Lm = dtl + (dt_in_lds ? ldp * ldp : 0);    // ld x ls: multipliers of the factorisation
+    double *red = Lm + ld * ls;                        // 4 x 256 partial tiles + 64 cross-wavefront sums
+    const double *dt = dt_in_lds ? dtl : w.Dt;
     __shared__ int ipiv[kMaxWidth];
     __shared__ unsigned long long tim[8];  // solver statistics: phase clocks
     if (tid < 8) tim[tid] = 0;
@@ -485,10 +498,11 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         }
     }
     for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
-    for (int e = tid; e < ldp * ldp; e += nthr) {
-        const int a = e / ldp, b = e - a * ldp;
-        dt[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
-    }
+    if (dt_in_lds)
+        for (int e = tid; e < ldp * ldp; e += nthr) {
+            const int a = e / ldp, b = e - a * ldp;
+            dtl[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
+        }
     __syncthreads();
     if (tid == 0) tim[0] += wall_clock64() - t_begin;
     auto ct = [&](int i, int a) -> double {
@@ -542,7 +556,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
                 for (int u = 0; u < 4; ++u) {
                     const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
                     if (i < r && j < r && (ta != tb || i >= j)) {
-                        const double v = dt[i * ldp + j] - (i == j ? sigma : 0.0) - acc[u];
+                        const double v = dt[i * dts + j] - (i == j ? sigma : 0.0) - acc[u];
                         S[i * ls + j] = v;
                         S[j * ls + i] = v;
                     }
@@ -563,7 +577,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
                 const int tb = t - ta * (ta + 1) / 2;
                 const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
                 if (i < r && j < r && (ta != tb || i >= j)) {
-                    v = dt[i * ldp + j] - (i == j ? sigma : 0.0) - v;
+                    v = dt[i * dts + j] - (i == j ? sigma : 0.0) - v;
                     S[i * ls + j] = v;
                     S[j * ls + i] = v;
                 }
@@ -644,7 +658,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         }
         for (int a = tid; a < r; a += nthr) {
             double s2 = fz[a];
-            for (int b = 0; b < r; ++b) s2 += dt[a * ldp + b] * x[dn + b];
+            for (int b = 0; b < r; ++b) s2 += dt[a * dts + b] * x[dn + b];
             hx[dn + a] = s2;
         }
         __syncthreads();
@@ -755,9 +769,9 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         for (int a = tid; a < r; a += nthr) {
             double s2 = 0.0;
             for (int b = 0; b < r; ++b)
-                if (b != a) s2 += fabs(dt[a * ldp + b]);
+                if (b != a) s2 += fabs(dt[a * dts + b]);
             for (int i = 0; i < dn; ++i) s2 += fabs(ct(i, a));
-            g = fmin(g, dt[a * ldp + a] - s2);
+            g = fmin(g, dt[a * dts + a] - s2);
         }
         for (int off = kWave / 2; off > 0; off >>= 1) g = fmin(g, __shfl_xor(g, off, kWave));
         __syncthreads();
@@ -818,26 +832,30 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
     const int nh = dn + r, m = qe;
-    const int ldp = (ld + 15) & ~15;
+    const int ldp = ld;                   // row stride of the m x m matrices below
+    const bool small = ld <= 32;          // wider: D~ from global memory, no split-K partials
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
     uint64_t tk[9];  // solver statistics: phase clocks (thread 0)
     tk[0] = wall_clock64();
-    double *T = sm;                 // ldp x ldp
-    double *Q = T + ldp * ldp;      // ldp x ldp
-    double *G = Q + ldp * ldp;      // ldp x ldp
-    double *red = G + ldp * ldp;    // kRed
-    double *lamv = red + kRed;      // dn
-    double *dtv = lamv + ((dn + 1) & ~1);  // ldp x ldp (keeps the copies below 16-byte aligned)
+    double *T = sm;                 // ld x ld
+    double *Q = T + ldp * ldp;      // ld x ld
+    double *G = Q + ldp * ldp;      // ld x ld
+    double *red = G + ldp * ldp;    // kRed (small) or 64
+    double *lamv = red + (small ? kRed : 64);  // dn
+    double *dtl = lamv + ((dn + 1) & ~1);      // ld x ld when small (keeps the copies below 16-byte aligned)
     for (int i = tid; i < dn; i += nthr) lamv[i] = w.lam[i];
-    for (int e = tid; e < ldp * ldp; e += nthr) {
-        const int a = e / ldp, b = e - a * ldp;
-        dtv[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
-    }
+    if (small)
+        for (int e = tid; e < ldp * ldp; e += nthr) {
+            const int a = e / ldp, b = e - a * ldp;
+            dtl[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
+        }
+    const double *dtv = small ? dtl : w.Dt;
+    const int rcap = small ? kRed : 64;
     double *Xp = w.X, *HXp = w.HX;
     const double *Ctp = w.Ct;
     if (use_lds) {
-        double *Xl = dtv + ldp * ldp;
+        double *Xl = dtl + (small ? ldp * ldp : 0);
         double *HXl = Xl + (dn + ld) * ld;
         double *Ctl = HXl + (dn + ld) * ld;
         block_copy(Xl, w.X, nh * ld);
@@ -870,7 +888,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     for (int it = 0; it < 2 + 2 * m && passes < 2; ++it) {
         bool near_identity = true;  // the same in every thread
         int bad = -1;
-        block_xty(xa, xa, nh, m, m, G, ldp, red);
+        block_xty(xa, xa, nh, m, m, G, ldp, red, rcap);
         for (int p = 0; p < m; ++p) {  // G = L L^T in place (lower)
             const double d = G[p * ldp + p];
             near_identity = near_identity && d > 0.9 && d < 1.1;
@@ -944,7 +962,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
         // X L^-T on the matrix cores into the other buffer, then swap
         block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
                     [&](int a, int c) -> double { return c < m ? Q[c * ldp + a] : 0.0; }, m, nh, m,
-                    [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = v; }, red);
+                    [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = v; }, red, rcap);
         double *t = Xp;
         Xp = HXp;
         HXp = t;
@@ -956,18 +974,14 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     block_tiles([&](int a, int i) -> double { return (i < dn && a < r) ? Ctp[(int64_t)i * ld + a] : 0.0; },
                 [&](int a, int c) -> double { return c < m ? Xp[(int64_t)(dn + a) * ld + c] : 0.0; }, r, dn, m,
                 [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = lamv[i] * Xp[(int64_t)i * ld + c] + v; },
-                red);
-    block_xty(cta, xa, dn, r, m, HXp + (int64_t)dn * ld, ld, red);
-    for (int e = tid; e < r * m; e += nthr) {
-        const int a = e / m, c = e - a * m;
-        double s2 = 0.0;
-        for (int b = 0; b < r; ++b) s2 += dtv[a * ldp + b] * Xp[(int64_t)(dn + b) * ld + c];
-        HXp[(int64_t)(dn + a) * ld + c] += s2;
-    }
-    __syncthreads();
+                red, rcap);
+    block_xty(cta, xa, dn, r, m, HXp + (int64_t)dn * ld, ld, red, rcap);
+    block_tiles([&](int b, int a) -> double { return (a < r && b < r) ? dtv[b * ldp + a] : 0.0; },  // D~ symmetric
+                [&](int b, int c) -> double { return c < m ? Xp[(int64_t)(dn + b) * ld + c] : 0.0; }, r, r, m,
+                [&](int a, int c, double v) { HXp[(int64_t)(dn + a) * ld + c] += v; }, red, rcap);
     tk[3] = wall_clock64();
     // ---- T = X^T HX, symmetrised
-    block_xty(xa, hxa, nh, m, m, Q, ldp, red);
+    block_xty(xa, hxa, nh, m, m, Q, ldp, red, rcap);
     for (int e = tid; e < m * m; e += nthr) {
         const int a = e / m, b = e - a * m;
         T[a * ldp + b] = 0.5 * (Q[a * ldp + b] + Q[b * ldp + a]);
@@ -1071,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     double *Xr = use_lds ? HXp : w.Xr;
     block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
                 [&](int a, int c) -> double { return c < m ? Q[a * ldp + order[c]] : 0.0; }, m, nh, ld,
-                [&](int i, int c, double v) { Xr[(int64_t)i * ld + c] = v; }, red);
+                [&](int i, int c, double v) { Xr[(int64_t)i * ld + c] = v; }, red, rcap);
     tk[7] = wall_clock64();
     // ---- recombination coefficients X_v = Pi_r L^-T z, X_c = y - G X_v
     double *Li = G;   // r x r, stride ldp (only the lower triangle is read)
@@ -1095,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     }
     block_tiles([&](int a, int i) -> double { return (i < dn && a < ld) ? w.FG[(int64_t)i * 2 * ld + ld + a] : 0.0; },
                 [&](int a, int c) -> double { return c < ld ? Xv[a * ldp + c] : 0.0; }, ld, dn, ld,
-                [&](int i, int c, double v) { w.Xc[(int64_t)i * ld + c] = Xr[(int64_t)i * ld + c] - v; }, red);
+                [&](int i, int c, double v) { w.Xc[(int64_t)i * ld + c] = Xr[(int64_t)i * ld + c] - v; }, red, rcap);
     if (tid == 0) {
         w.status[ST_WARM] = 1;
         if (final_level) w.status[ST_STEPS] += 1;
@@ -1109,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
 // ------------------------------------------------------------ launchers
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
     const size_t ld = w.ld, dn = w.dn;
-    const size_t base = 10 * ld * ld + kRedSmall + dn + 1;
+    const size_t base = ld <= 32 ? 10 * ld * ld + kRedSmall + dn + 1 : 3 * ld * ld + 64 + dn + 1;
     const int fg_in_lds = (base + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
     const size_t lds = (base + (fg_in_lds ? dn * 2 * ld : 0)) * sizeof(double);
     hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds, s, w, rank_tol, fg_in_lds);
@@ -1119,11 +1133,13 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, 
     // the rank r <= ld is only known on the device: size for r = ld
     const size_t ldp = ((size_t)w.ld + 15) & ~(size_t)15, dn = w.dn;
     const int threads = kB;
-    const size_t base = 2 * ldp * (ldp + 1) + dn + 2 * (dn + ldp) + ldp + dn + ldp * ldp + 1024 + 64;
+    const size_t ld = w.ld, dtl = ld <= 32 ? ldp * ldp : 0;  // the kernel's layout
+    const size_t base = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64;
     const int ct_in_lds = (base + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
     const size_t lds = (base + (ct_in_lds ? dn * ldp : 0)) * sizeof(double);
     hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta, ct_in_lds);
-    const size_t rbase = 3 * ldp * ldp + kRed + dn + 1 + ldp * ldp;
+    const size_t rsmall = ld <= 32;
+    const size_t rbase = 3 * ld * ld + (rsmall ? kRed : 64) + dn + 1 + (rsmall ? ld * ld : 0);
     const size_t full = rbase + 2 * (dn + w.ld) * w.ld + dn * w.ld;
     const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
     hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), (use_lds ? full : rbase) * sizeof(double), s, w, qe, use_lds, theta,

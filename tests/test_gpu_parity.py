@@ -150,6 +150,39 @@ def test_chebyshev_smoother_step_parity_and_solve(prec):
     ctx.close()
 
 
+WIDE = [
+    # (name, problem, explicit q_e, precision): widths beyond one 16-column tile and
+    # beyond 32 columns (the kernels' wide layouts)
+    ("cube24_qe32", lambda: configs.cube(24, q=20), 32, ae.PREC_FP64),
+    ("lshape40j_qe36", lambda: configs.lshape(40, q=10, jitter_seed=3), 36, ae.PREC_FP64),
+    ("osc96_q64", lambda: configs.oscillator(96, q=64), 0, ae.PREC_MIXED),
+]
+
+
+@pytest.mark.parametrize("name,make,qe,prec", WIDE)
+def test_wide_blocks_match_oracle(name, make, qe, prec):
+    _torch()
+    p = make()
+    _say("%s wide block qe=%d prec=%d" % (name, qe, prec))
+    ctx = make_ctx(p, qe=qe, precision=prec)
+    o, A, M = oracle_for(p, ctx)
+    q = p["q"]
+    assert ctx.info()["qe"] == (qe if qe else o.qe)
+    lam, ok = ctx.solve(tol=1e-9, max_steps=300)
+    th, U, pr = gpu_state(ctx)
+    assert ok, pr
+    lo, Uo, info = o.solve(tol=1e-11, max_steps=400)
+    if prec == ae.PREC_FP64:
+        kap = np.abs(A).sum(axis=1).max() / M.diagonal().min() / lo[:q]
+        tol = np.maximum(1e-10, 10 * np.finfo(float).eps * kap)
+    else:
+        tol = 1e-6
+    assert np.all(np.abs(lam / lo[:q] - 1) < tol)
+    assert compare_subspaces(lo, Uo, U, M, q) < 1e-6
+    assert o.residuals(0, th, U)[:q].max() <= 1e-9 * 1.01
+    ctx.close()
+
+
 def test_user_start_equals_random_start():
     torch = _torch()
     p = configs.lshape(16, q=4, jitter_seed=3)
