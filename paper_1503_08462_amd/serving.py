@@ -1,0 +1,146 @@
+"""Serving form of the solver: many eigenproblems of uneven size on one GPU.
+
+Requests are set up on the host when they are submitted (the AMG hierarchy,
+Section 2), admitted to the device in arrival order while their device
+footprint fits the memory budget, and then advanced together: every
+scheduling round enqueues a few correction steps (Algorithm 3.1) for each
+active request on its own stream from a small pool, so the short, latency-bound
+kernels of different requests overlap on the device.  Requests join at a
+round boundary (after their Algorithm 3.2 start) and leave as soon as their
+convergence test holds or their step limit is reached, which frees their
+memory for the next arrivals (continuous batching).  Latency is measured from
+submission (or the given arrival time) to completion.
+
+The scheduler only orders host calls into the library; every step of a solve
+runs in the library's kernels.
+"""
+import time
+
+import numpy as np
+
+from . import INIT_NESTED, Context, correct_batch, defaults
+
+
+class Request:
+    __slots__ = ("id", "ctx", "q", "tol", "max_steps", "footprint", "arrival", "admitted", "done", "stream",
+                 "result")
+
+    def __init__(self, rid, ctx, q, tol, max_steps, arrival):
+        self.id, self.ctx, self.q, self.tol, self.max_steps = rid, ctx, q, tol, max_steps
+        self.footprint = ctx.footprint()
+        self.arrival = arrival
+        self.admitted = self.done = None
+        self.stream = None
+        self.result = None
+
+
+class Server:
+    """Admission by footprint, continuous batching at step boundaries.
+
+    budget_bytes:     device memory the admitted requests may hold together
+    n_streams:        stream pool; request k of a round uses stream k mod n_streams
+    steps_per_round:  corrections enqueued per request between convergence checks
+    context_factory:  (problem dict, opts) -> context; the default builds a
+                      library Context (tests pass stand-ins)
+    batch_fn:         (contexts, steps) -> None; the default is correct_batch
+                      with each context on its own stream
+    """
+
+    def __init__(self, budget_bytes, n_streams=4, steps_per_round=2, opts=None, context_factory=None,
+                 batch_fn=None, stream_factory=None, clock=time.perf_counter):
+        if budget_bytes <= 0 or n_streams < 1 or steps_per_round < 1:
+            raise ValueError("budget, stream count and steps per round must be positive")
+        self.budget = int(budget_bytes)
+        self.steps_per_round = int(steps_per_round)
+        self.opts = opts
+        self.clock = clock
+        self._make = context_factory or (lambda p, o: Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], o))
+        self._batch = batch_fn or (lambda cs, steps: correct_batch(cs, steps))
+        if stream_factory is None:
+            def stream_factory():
+                import torch
+                return torch.cuda.Stream()  # default priority
+        self.streams = [stream_factory() for _ in range(n_streams)]
+        self.queue = []       # submitted, waiting for memory, in arrival order
+        self.active = []      # on the device
+        self.finished = {}    # id -> Request
+        self.in_use = 0       # bytes held by active requests
+        self.peak_in_use = 0
+        self.rounds = 0
+        self._next_id = 0
+        self._next_stream = 0
+
+    # ------------------------------------------------------------- requests
+    def submit(self, problem, tol=1e-8, max_steps=200, opts=None, arrival=None):
+        """Host setup now; returns the request id.  A request larger than the
+        whole budget is rejected (ValueError) rather than queued forever."""
+        base = opts if opts is not None else (self.opts if self.opts is not None else defaults())
+        o = type(base).from_buffer_copy(base) if hasattr(type(base), "from_buffer_copy") else base
+        if hasattr(o, "tol"):
+            o.tol = tol  # the device-side convergence test of each step
+        ctx = self._make(problem, o)
+        rid = self._next_id
+        self._next_id += 1
+        req = Request(rid, ctx, int(problem["q"]), tol, max_steps, self.clock() if arrival is None else arrival)
+        if req.footprint > self.budget:
+            ctx.close()
+            raise ValueError("request %d needs %d bytes, more than the budget of %d" % (rid, req.footprint,
+                                                                                        self.budget))
+        self.queue.append(req)
+        return rid
+
+    def _admit(self):
+        while self.queue and self.in_use + self.queue[0].footprint <= self.budget:
+            req = self.queue.pop(0)
+            req.stream = self.streams[self._next_stream % len(self.streams)]
+            self._next_stream += 1
+            req.ctx.bind(stream=req.stream)
+            req.ctx.init(INIT_NESTED)
+            req.admitted = self.clock()
+            self.in_use += req.footprint
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.active.append(req)
+
+    def _retire(self):
+        still = []
+        for req in self.active:
+            pr = req.ctx.progress()
+            if pr["converged"] or pr["steps"] >= req.max_steps:
+                req.done = self.clock()
+                req.result = {"lam": np.asarray(pr["theta"][:req.q]).copy(), "rho": np.asarray(pr["rho"][:req.q]).copy(),
+                              "steps": pr["steps"], "converged": bool(pr["converged"]),
+                              "latency_s": req.done - req.arrival}
+                req.ctx.close()
+                if hasattr(req.ctx, "workspace"):
+                    req.ctx.workspace = None  # back to the allocator for the next admissions
+                self.in_use -= req.footprint
+                self.finished[req.id] = req
+            else:
+                still.append(req)
+        self.active = still
+
+    def round(self):
+        """One scheduling round; returns the number of requests still pending."""
+        self._admit()
+        if not self.active and self.queue:  # cannot happen while every request fits the budget
+            raise RuntimeError("no request can be admitted")
+        if self.active:
+            self._batch([r.ctx for r in self.active], self.steps_per_round)
+            self.rounds += 1
+            self._retire()
+        return len(self.queue) + len(self.active)
+
+    def run(self):
+        while self.round():
+            pass
+        return self.results()
+
+    # -------------------------------------------------------------- reports
+    def results(self):
+        return {rid: r.result for rid, r in sorted(self.finished.items())}
+
+    def latency(self):
+        lat = np.array([r.result["latency_s"] for r in self.finished.values()])
+        if lat.size == 0:
+            return {"p50_s": None, "p99_s": None, "count": 0}
+        return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)), "count": int(lat.size)}

@@ -1,0 +1,99 @@
+"""Host logic of the serving form (admission by footprint, continuous batching),
+driven with stand-in contexts so that it runs without a GPU."""
+import numpy as np
+import pytest
+
+from paper_1503_08462_amd.serving import Server
+
+
+class FakeCtx:
+    """Converges after `need` corrections; records its life cycle."""
+    log = []
+
+    def __init__(self, p, opts):
+        self.q, self.need, self.fp, self.name = p["q"], p["need"], p["fp"], p["name"]
+        self.steps = 0
+        self.bound = self.closed = False
+
+    def footprint(self):
+        return self.fp
+
+    def bind(self, stream=None):
+        self.bound = True
+        self.stream = stream
+        FakeCtx.log.append(("bind", self.name))
+
+    def init(self, mode):
+        assert self.bound
+
+    def correct(self, steps):
+        self.steps = min(self.need, self.steps + steps)
+
+    def progress(self):
+        return {"theta": np.arange(1.0, self.q + 3), "rho": np.zeros(self.q + 2), "steps": self.steps,
+                "converged": self.steps >= self.need}
+
+    def close(self):
+        self.closed = True
+        FakeCtx.log.append(("close", self.name))
+
+
+def make_server(budget, **kw):
+    tick = iter(range(10 ** 6))
+    batches = []
+
+    def batch(cs, steps):
+        batches.append([c.name for c in cs])
+        for c in cs:
+            c.correct(steps)
+    srv = Server(budget, context_factory=FakeCtx, batch_fn=batch, stream_factory=lambda: object(),
+                 clock=lambda: float(next(tick)), **kw)
+    return srv, batches
+
+
+def prob(name, fp, need, q=2):
+    return {"name": name, "fp": fp, "need": need, "q": q}
+
+
+def test_admission_respects_budget_and_arrival_order():
+    FakeCtx.log = []
+    srv, batches = make_server(100, steps_per_round=1)
+    for name, fp, need in [("a", 60, 3), ("b", 50, 1), ("c", 30, 2), ("d", 40, 1)]:
+        srv.submit(prob(name, fp, need))
+    res = srv.run()
+    assert sorted(res) == [0, 1, 2, 3]
+    # b cannot join a (60 + 50 > 100); c and d wait behind b (first come, first served)
+    assert batches[0] == ["a"]
+    assert all(r["converged"] for r in res.values())
+    assert srv.peak_in_use <= 100 and srv.in_use == 0
+    binds = [n for k, n in FakeCtx.log if k == "bind"]
+    assert binds == ["a", "b", "c", "d"]
+
+
+def test_requests_join_and_leave_at_round_boundaries():
+    FakeCtx.log = []
+    srv, batches = make_server(100, steps_per_round=2)
+    srv.submit(prob("long", 50, 8))
+    srv.submit(prob("short", 40, 2))
+    srv.submit(prob("late", 40, 2))  # fits once "short" has left
+    srv.run()
+    assert batches[0] == ["long", "short"]
+    assert batches[1] == ["long", "late"]  # joined while "long" keeps running
+    assert srv.finished[0].result["steps"] == 8
+    lat = srv.latency()
+    assert lat["count"] == 3 and lat["p50_s"] <= lat["p99_s"]
+
+
+def test_oversized_request_is_rejected_and_closed():
+    srv, _ = make_server(10)
+    with pytest.raises(ValueError):
+        srv.submit(prob("huge", 11, 1))
+    assert srv.queue == []
+
+
+def test_step_limit_ends_a_request_unconverged():
+    srv, _ = make_server(100, steps_per_round=3)
+    rid = srv.submit(prob("slow", 10, 100), max_steps=6)
+    res = srv.run()
+    assert res[rid]["steps"] == 6 and not res[rid]["converged"]
+    assert res[rid]["lam"].shape == (2,)
