@@ -505,6 +505,64 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int ld, const double *_
     }
 }
 
+// Phase 1 for wide blocks (more than 8 tiles): the workgroup stages 16 rows
+// of V and W at a time in LDS (coalesced loads by all threads); the tiles of
+// the ld x 2ld result are dealt round-robin to its four wavefronts, which
+// accumulate them from LDS and finally write them to part[b] directly.
+constexpr int kGramTilesPerWave = 12;  // covers ld <= 68 (5 x 9 tiles)
+constexpr int kGramRows = 16;
+
+__global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const double *__restrict__ V,
+                                                   const double *__restrict__ W, double *__restrict__ part,
+                                                   const int *status) {
+    extern __shared__ double stage[];  // kGramRows x ld, then kGramRows x 2 ld
+    if (status[ST_CONVERGED]) return;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t nb = gridDim.x, lb = xcd_block();
+    const int64_t r0 = n * lb / nb, r1 = n * (lb + 1) / nb;
+    const int l2 = 2 * ld, ti = (ld + 15) / 16, tj = (l2 + 15) / 16, ntiles = ti * tj;
+    const int outsz = ld * l2;
+    const int kk = lane >> 4, c = lane & 15;
+    dbl4 acc[kGramTilesPerWave];
+#pragma unroll
+    for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) acc[s2] = dbl4{0.0, 0.0, 0.0, 0.0};
+    double *sv = stage, *sw = stage + kGramRows * ld;  // 16 rows of V, then 16 rows of W
+    for (int64_t base = r0; base < r1; base += kGramRows) {
+        const int rows = r1 - base < kGramRows ? (int)(r1 - base) : kGramRows;
+        __syncthreads();  // the previous chunk is consumed
+        block_copy(sv, V + base * ld, rows * ld);  // contiguous rows, double2 loads, four in flight
+        block_copy(sw, W + base * l2, rows * l2);
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
+            const int t = wv + s2 * nw;
+            if (t < ntiles) {  // wave-uniform
+                const int ta = t / tj, tb = t - ta * tj;
+                const int ca = 16 * ta + c, cb = 16 * tb + c;
+#pragma unroll
+                for (int k0 = 0; k0 < kGramRows; k0 += 4) {
+                    const int rr = k0 + kk;
+                    double x = (ca < ld && rr < rows) ? sv[rr * ld + ca] : 0.0;
+                    double y = (cb < l2 && rr < rows) ? sw[rr * l2 + cb] : 0.0;
+                    acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[s2], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
+        const int t = wv + s2 * nw;
+        if (t < ntiles) {
+            const int ta = t / tj, tb = t - ta * tj;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
+                if (i < ld && j < l2) part[lb * outsz + i * l2 + j] = acc[s2][u];
+            }
+        }
+    }
+}
+
 // Phase 2: G[e] = sum over blocks of part[b][e]; one wavefront per element,
 // lane l sums blocks l, l+64, ..., then a fixed butterfly over the lanes.
 __global__ __launch_bounds__(256) void k_gram_reduce(int64_t nb, int outsz, const double *__restrict__ part,
@@ -520,8 +578,10 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int64_t nb, int outsz, cons
 }
 
 // ------------------------------------------------------------------- a11
+// Narrow blocks (ld <= 32): one row group per row, X_v in LDS, the
+// prolongation gathered four neighbours at a time.
 template <int CPT>
-__global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int32_t *__restrict__ ptr,
                                                const int32_t *__restrict__ col, const double *__restrict__ val,
                                                const double *__restrict__ Y, const double *__restrict__ V,
                                                const double *__restrict__ Xv, double *__restrict__ U,
@@ -545,6 +605,47 @@ __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t 
             for (int c = 0; c < CPT; ++c) acc.v[c] += v4.v[t] * xv[(a + t) * ld + c0 + c];
     }
     stv<double, CPT>(U + rm.row * ld + c0, acc);
+}
+
+// Wide blocks: U = P Y + V X_v on the correction level.  One wavefront per
+// 16 consecutive rows: V X_v as 16 x 16 tiles on the FP64 matrix cores (X_v
+// staged in LDS), then each lane adds the prolongation P Y for its four
+// (row, column) entries of the tile and writes them.
+__global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ col, const double *__restrict__ val,
+                                               const double *__restrict__ Y, const double *__restrict__ V,
+                                               const double *__restrict__ Xv, double *__restrict__ U,
+                                               const int *status) {
+    extern __shared__ double xv[];
+    if (status[ST_CONVERGED]) return;
+    for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) xv[e] = Xv[e];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t r0 = (xcd_block() * (blockDim.x / kWave) + wv) * 16;
+    if (r0 >= n) return;  // the whole wavefront
+    const int tj = (ld + 15) / 16;
+    for (int tb = 0; tb < tj; ++tb) {
+        const dbl4 acc = mfma_tn16(
+            [&](int k, int c) -> double {
+                const int64_t row = r0 + c;
+                return row < n ? V[row * ld + k] : 0.0;
+            },
+            [&](int k, int c) -> double {
+                const int j = 16 * tb + c;
+                return j < ld ? xv[k * ld + j] : 0.0;
+            },
+            ld);
+        const int j = 16 * tb + (lane & 15);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = r0 + (lane >> 4) + 4 * u;
+            if (row < n && j < ld) {
+                double v = acc[u];
+                for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) v += val[p] * Y[(int64_t)col[p] * ld + j];
+                U[row * ld + j] = v;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------- init fills
@@ -602,21 +703,42 @@ inline int64_t row_blocks(int64_t n, int ld, int cpt) {
 }
 }  // namespace
 
-// Lanes per row = width / CPT must not exceed a wavefront: 2 columns per
-// lane up to width 128, 4 beyond.
-#define DISPATCH_CPT(width, ...)           \
-    do {                                   \
-        if ((width) <= 128) {              \
-            constexpr int CPT = 2;         \
-            __VA_ARGS__;                   \
-        } else {                           \
-            constexpr int CPT = 4;         \
-            __VA_ARGS__;                   \
-        }                                  \
+// Columns per lane for a row-major block of the given width: the choice among
+// 2, 4 and 8 that leaves the fewest idle lanes in a wavefront (rows of
+// width / CPT lanes each; ties to fewer columns per lane).
+int cpt_for(int width) {
+    int best = 0;
+    double bu = -1.0;
+    for (int c = 2; c <= 8; c *= 2) {
+        if (width % c) continue;
+        const int tpr = width / c;
+        if (tpr > kWave) continue;
+        const double u = (double)((kWave / tpr) * tpr) / kWave;
+        if (u > bu + 0.02) {
+            bu = u;
+            best = c;
+        }
+    }
+    return best ? best : 8;
+}
+
+#define DISPATCH_CPT(width, ...)             \
+    do {                                     \
+        const int cpt_sel = cpt_for(width);  \
+        if (cpt_sel == 2) {                  \
+            constexpr int CPT = 2;           \
+            __VA_ARGS__;                     \
+        } else if (cpt_sel == 4) {           \
+            constexpr int CPT = 4;           \
+            __VA_ARGS__;                     \
+        } else {                             \
+            constexpr int CPT = 8;           \
+            __VA_ARGS__;                     \
+        }                                    \
     } while (0)
 
 int64_t residual_blocks(int64_t n, int ld) {
-    const int64_t need = row_blocks(n, ld, ld <= 128 ? 2 : 4);
+    const int64_t need = row_blocks(n, ld, cpt_for(ld));
     return need < 2048 ? need : 2048;
 }
 
@@ -693,16 +815,27 @@ void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double
                  const int *status) {
     const int64_t nb = gram_blocks(n, ld);
     const int outsz = 2 * ld * ld;
-    hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
+    const int ntiles = ((ld + 15) / 16) * ((2 * ld + 15) / 16);
+    if (ntiles > 8 && ntiles <= 4 * kGramTilesPerWave)
+        hipLaunchKernelGGL(k_gram_wide, dim3((unsigned)nb), dim3(kBlock),
+                           (size_t)kGramRows * 3 * ld * sizeof(double), s, n, ld, V, W, part, status);
+    else
+        hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, part, G,
                        status);
 }
 
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
                   const double *Y, const double *V, const double *Xv, double *U, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_final<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
-                                        (size_t)ld * ld * sizeof(double), s, n, ld, ptr, col, val, Y, V, Xv, U,
-                                        status));
+    if (ld <= 32) {
+        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_final_rows<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                                            dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr, col, val,
+                                            Y, V, Xv, U, status));
+        return;
+    }
+    const int64_t tiles = (n + 15) / 16, nb = (tiles + (kBlock / kWave) - 1) / (kBlock / kWave);
+    hipLaunchKernelGGL(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr,
+                       col, val, Y, V, Xv, U, status);
 }
 
 template <typename T>
