@@ -62,6 +62,13 @@ struct amg_eig_ctx {
     double *U = nullptr, *V = nullptr, *W = nullptr;
     double *Z = nullptr, *Zt = nullptr, *lam = nullptr, *Yn = nullptr;
     void *Ainv = nullptr;
+    // dense coarse tail: from level `tail` down, the V-cycle is applied as its
+    // matrix Bt (built on the device at bind), and the coarse basis as
+    // Zk = I_tail^n Z (n_tail x d_n) with its transpose Zkt
+    int tail = -1;
+    std::vector<double> Zk_host;
+    void *Bt = nullptr;
+    double *Zk = nullptr, *Zkt = nullptr;
     double *theta = nullptr, *rho = nullptr, *part_res = nullptr, *part_gram = nullptr;
     unsigned *counters = nullptr;
     int *status = nullptr;
@@ -92,6 +99,38 @@ int fail(amg_eig_ctx *c, int code, const std::string &msg) {
         hipError_t e_ = (call);                                                                  \
         if (e_ != hipSuccess) return fail(ctx, AMG_EIG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// ------------------------------------------------------------ dense tail
+// The first level t >= 1 with at most kTailRows unknowns and at least one level
+// below it becomes the dense tail; Zk = P_t P_{t+1} ... P_{n-1} Z on the host.
+constexpr int64_t kTailRows = 3000;
+
+void choose_tail(amg_eig_ctx *c) {
+    const Hierarchy &H = c->H;
+    const int L = (int)H.lv.size(), dn = H.dn;
+    c->tail = -1;
+    c->Zk_host.clear();
+    for (int l = 1; l <= L - 2; ++l)
+        if (H.lv[l].n <= kTailRows) {
+            c->tail = l;
+            break;
+        }
+    if (c->tail < 0) return;
+    std::vector<double> Y = H.Z;  // level L-1, d_n x d_n
+    for (int l = L - 2; l >= c->tail; --l) {
+        const Csr &P = H.lv[l].P;  // n_l x n_{l+1}
+        std::vector<double> X((size_t)H.lv[l].n * dn, 0.0);
+        for (int64_t i = 0; i < H.lv[l].n; ++i)
+            for (int64_t p = P.ptr[i]; p < P.ptr[i + 1]; ++p) {
+                const double w = P.val[p];
+                const double *yr = &Y[(size_t)P.col[p] * dn];
+                double *xr = &X[(size_t)i * dn];
+                for (int j = 0; j < dn; ++j) xr[j] += w * yr[j];
+            }
+        Y.swap(X);
+    }
+    c->Zk_host.swap(Y);
+}
 
 // ------------------------------------------------------------ memory plan
 void plan(amg_eig_ctx *c, char *base) {
@@ -144,6 +183,12 @@ void plan(amg_eig_ctx *c, char *base) {
     c->part_res = cv.take<double>(((size_t)residual_blocks(maxn, ld) + 1) * 2 * ld);
     c->part_gram = cv.take<double>((size_t)gram_blocks(maxn, ld) * 2 * ld * ld);
     c->counters = cv.take<unsigned>(16);
+    if (c->tail >= 0) {
+        const int nt = (int)H.lv[c->tail].n;
+        c->Bt = cv.take<char>((size_t)nt * nt * sT);
+        c->Zk = cv.take<double>((size_t)nt * dn);
+        c->Zkt = cv.take<double>((size_t)nt * dn);
+    }
     c->status = cv.take<int>(ST_COUNT);
     SmallWork &w = c->sw;
     w.dn = dn;
@@ -242,6 +287,14 @@ int upload_levels(amg_eig_ctx *c) {
     rc |= upload_vec(c, c->Zt, transposed(H.Z, H.dn));
     rc |= upload_vec(c, c->lam, H.lam);
     rc |= upload_vec(c, c->Ainv, convert<T>(transposed(H.Ainv, H.dn)));  // used as (A^-1)^T^T
+    if (c->tail >= 0) {
+        const int64_t nt = H.lv[c->tail].n;
+        rc |= upload_vec(c, c->Zk, c->Zk_host);
+        std::vector<double> zt((size_t)nt * dn);
+        for (int64_t i = 0; i < nt; ++i)
+            for (int j = 0; j < dn; ++j) zt[(size_t)j * nt + i] = c->Zk_host[(size_t)i * dn + j];
+        rc |= upload_vec(c, c->Zkt, zt);
+    }
     return rc ? AMG_EIG_EHIP : AMG_EIG_OK;
 }
 
@@ -308,14 +361,18 @@ double site_bytes(const amg_eig_ctx *c, int site) {
 }
 
 // ---------------------------------------------------------- step pieces
+// One V-cycle from level k (right-hand side in dl[k].b, zero initial guess)
+// down to `bottom`, where the coarse problem is solved by A_n^-1 (bottom = n)
+// or by the dense tail operator Bt.  The post-smoothing on level k writes
+// V = U + x when final_at_k, else x.
 template <typename T>
-void vcycle(amg_eig_ctx *c, int k) {
+void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
     const int L = (int)c->dl.size(), ld = c->ld;
     hipStream_t s = c->stream;
     const int *st = c->status;
     const bool cheb = c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV;
     const double lo = c->o.cheb_lo;
-    for (int l = k; l < L - 1; ++l) {
+    for (int l = k; l < bottom; ++l) {
         DevLevel &d = c->dl[l];
         if (cheb) {
             {
@@ -333,10 +390,14 @@ void vcycle(amg_eig_ctx *c, int k) {
         DevLevel &e = c->dl[l + 1];
         launch_spmm<T>(s, e.n, ld, d.pt_ptr, d.pt_col, (const T *)d.pt_val, (const T *)d.r, (T *)e.b, st);
     }
-    DevLevel &cl = c->dl[L - 1];
-    launch_gemm_tn<T>(s, (int)cl.n, ld, (int)cl.n, (const T *)c->Ainv, (int)cl.n, (const T *)cl.b, ld, (T *)cl.x, ld,
-                      st);
-    for (int l = L - 2; l >= k; --l) {
+    DevLevel &cl = c->dl[bottom];
+    if (bottom == L - 1)
+        launch_gemm_tn<T>(s, (int)cl.n, ld, (int)cl.n, (const T *)c->Ainv, (int)cl.n, (const T *)cl.b, ld,
+                          (T *)cl.x, ld, st);
+    else  // x_t = Bt b_t with Bt stored transposed
+        launch_gemm_tn_long<T>(s, (int)cl.n, ld, (int)cl.n, (const T *)c->Bt, (int)cl.n, (const T *)cl.b, ld,
+                               (T *)cl.x, ld, st);
+    for (int l = bottom - 1; l >= k; --l) {
         DevLevel &d = c->dl[l];
         DevLevel &e = c->dl[l + 1];
         if (cheb) {
@@ -344,15 +405,34 @@ void vcycle(amg_eig_ctx *c, int k) {
             launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.x,
                                 (T *)d.r, st);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
-            launch_cheb_post<T>(s, l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+            launch_cheb_post<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                 (const T *)d.b, (const T *)d.r, (T *)d.t, (T *)d.x, c->U, c->V, lo, st);
         } else {
             launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
                                   (const T *)d.dinv, (const T *)d.b, (T *)d.r, st);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
-            launch_smooth_post<T>(s, l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+            launch_smooth_post<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                   (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st);
         }
+    }
+}
+
+template <typename T>
+void vcycle(amg_eig_ctx *c, int k) {
+    const int bottom = (c->tail >= 0 && k < c->tail) ? c->tail : (int)c->dl.size() - 1;
+    vcycle_levels<T>(c, k, bottom, true);
+}
+
+// Bt (stored transposed) = the V-cycle from the tail level, one identity block
+// of ld columns at a time, with the same kernels as every later V-cycle.
+template <typename T>
+void build_tail(amg_eig_ctx *c) {
+    const int t = c->tail, L = (int)c->dl.size(), ld = c->ld;
+    DevLevel &d = c->dl[t];
+    for (int64_t j0 = 0; j0 < d.n; j0 += ld) {
+        launch_identity_block<T>(c->stream, d.n, ld, j0, (T *)d.b);
+        vcycle_levels<T>(c, t, L - 1, false);
+        launch_rows_from_block<T>(c->stream, d.n, ld, j0, (const T *)d.x, (T *)c->Bt);
     }
 }
 
@@ -369,23 +449,39 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
         SiteScope sc(c, AMG_EIG_SITE_GRAM, k);
         launch_gram(s, d.n, ld, c->V, c->W, c->part_gram, c->sw.GAGM, st);
     }
+    // restrict W to the tail level (then Zk^T) or to the coarsest level (then Z^T)
+    const bool tail = c->tail >= 0 && k < c->tail;
+    const int bottom = tail ? c->tail : L - 1;
     const double *src = c->W;
-    for (int l = k; l < L - 1; ++l) {
+    for (int l = k; l < bottom; ++l) {
         DevLevel &a = c->dl[l];
         DevLevel &b = c->dl[l + 1];
         SiteScope sc(c, AMG_EIG_SITE_RESTRICT, l);
         launch_spmm<double>(s, b.n, 2 * ld, a.pt_ptr, a.pt_col, a.pt64, src, b.cw, st);
         src = b.cw;
     }
+    const double *y;
     {
         SiteScope sc(c, AMG_EIG_SITE_SMALL, k);
-        launch_gemm_tn<double>(s, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+        if (tail) {
+            const int nt = (int)c->dl[bottom].n;
+            launch_gemm_tn_long<double>(s, dn, 2 * ld, nt, c->Zk, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+        } else {
+            launch_gemm_tn<double>(s, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+        }
         launch_pencil(s, c->sw, 1e-13);
         launch_arrow_eig(s, c->sw, c->qe, c->theta, k == 0 ? 1 : 0);
-        launch_gemm_tn<double>(s, dn, ld, dn, c->Zt, dn, c->sw.Xc, ld, c->Yn, ld, st);
+        if (tail) {  // Y on the tail level = Zk X_c
+            double *yt = c->dl[bottom].cw;
+            launch_gemm_tn_long<double>(s, (int)c->dl[bottom].n, ld, dn, c->Zkt, (int)c->dl[bottom].n, c->sw.Xc,
+                                        ld, yt, ld, st);
+            y = yt;
+        } else {
+            launch_gemm_tn<double>(s, dn, ld, dn, c->Zt, dn, c->sw.Xc, ld, c->Yn, ld, st);
+            y = c->Yn;
+        }
     }
-    const double *y = c->Yn;
-    for (int l = L - 2; l > k; --l) {
+    for (int l = bottom - 1; l > k; --l) {
         DevLevel &a = c->dl[l];
         launch_spmm<double>(s, a.n, ld, a.p_ptr, a.p_col, a.p64, y, a.cw, st);
         y = a.cw;
@@ -503,6 +599,7 @@ int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_e
     c->q = q;
     c->ld = c->qe;
     c->mixed = c->o.precision == AMG_EIG_PREC_MIXED;
+    choose_tail(c);
     plan(c, nullptr);
     *out = c;
     return AMG_EIG_OK;
@@ -529,6 +626,12 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     std::vector<unsigned> zero(16, 0u);
     rc = upload_vec(c, c->counters, zero);
     if (rc) return rc;
+    if (c->tail >= 0) {
+        if (c->mixed)
+            build_tail<float>(c);
+        else
+            build_tail<double>(c);
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->staging.clear();
     c->bound = true;

@@ -69,6 +69,16 @@ void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double
                  const int *status);
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
                   const double *Y, const double *V, const double *Xv, double *U, const int *status);
+// launch_gemm_tn for long K: sixteen wavefronts per tile of C
+template <typename T>
+void launch_gemm_tn_long(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,
+                         const int *status);
+// columns j0 .. j0 + ld - 1 of the n x n identity as an n x ld block
+template <typename T>
+void launch_identity_block(hipStream_t s, int64_t n, int ld, int64_t j0, T *b);
+// rows j0 .. of the n x n matrix Bt from the columns of the n x ld block x
+template <typename T>
+void launch_rows_from_block(hipStream_t s, int64_t n, int ld, int64_t j0, const T *x, T *Bt);
 void launch_fill_random(hipStream_t s, int64_t n, int ld, int qe, uint64_t seed, double *U);
 void launch_copy_cols(hipStream_t s, int64_t rows, int dcols, int64_t ldd, int cols, const double *src,
                       int64_t lds, double *dst);

@@ -438,6 +438,61 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int m, int n, int K, const T *_
     if (i < m && j < n) C[(int64_t)i * ldc + j] = (T)v;
 }
 
+// C (m x n) = A^T B as k_gemm_tn for long K: one workgroup of 16 wavefronts
+// per 16 x 16 tile of C, each wavefront a sixteenth of K, the partial tiles
+// summed in a fixed order in LDS.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gemm_tn_long(int m, int n, int K, const T *__restrict__ A, int lda,
+                                                       const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
+                                                       const int *status) {
+    __shared__ double red[16 * 256];
+    if (status[ST_CONVERGED]) return;
+    const int ta = blockIdx.x, tb = blockIdx.y;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int chunk = ((K + nw - 1) / nw + 3) & ~3;
+    const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (k1 > k0)
+        acc = mfma_tn16(
+            [&](int i, int c) -> double {
+                const int col = 16 * ta + c;
+                return col < m ? (double)A[(int64_t)(k0 + i) * lda + col] : 0.0;
+            },
+            [&](int i, int c) -> double {
+                const int col = 16 * tb + c;
+                return col < n ? (double)B[(int64_t)(k0 + i) * ldb + col] : 0.0;
+            },
+            k1 - k0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) red[(wv * 4 + u) * kWave + lane] = acc[u];
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int u = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        double v = 0.0;
+        for (int w = 0; w < nw; ++w) v += red[(w * 4 + u) * kWave + ln];
+        const int i = 16 * ta + (ln >> 4) + 4 * u, j = 16 * tb + (ln & 15);
+        if (i < m && j < n) C[(int64_t)i * ldc + j] = (T)v;
+    }
+}
+
+// b (n x ld) = columns j0 .. j0 + ld - 1 of the identity
+template <typename T>
+__global__ void k_identity_block(int64_t n, int ld, int64_t j0, T *__restrict__ b) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ld) return;
+    const int64_t i = e / ld, c = e - i * ld;
+    b[e] = i == j0 + c ? T(1) : T(0);
+}
+
+// rows j0 .. j0 + ld - 1 of Bt (n x n) = the columns of x (n x ld)
+template <typename T>
+__global__ void k_rows_from_block(int64_t n, int ld, int64_t j0, const T *__restrict__ x, T *__restrict__ Bt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ld) return;
+    const int64_t c = e / n, i = e - c * n;  // consecutive threads: consecutive i of one column
+    if (j0 + c < n) Bt[(j0 + c) * n + i] = x[i * ld + c];
+}
+
 // ------------------------------------------------------------------- a7
 template <int CPT>
 __global__ __launch_bounds__(256) void k_dual_spmm(int64_t n, int ld, const int32_t *__restrict__ ptr,
@@ -902,6 +957,34 @@ void launch_cheb_post(hipStream_t s, bool final, int64_t n, int ld, const int32_
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
                                             status));
 }
+
+template <typename T>
+void launch_gemm_tn_long(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,
+                         const int *status) {
+    const dim3 g((m + 15) / 16, (n + 15) / 16);
+    hipLaunchKernelGGL(k_gemm_tn_long<T>, g, dim3(1024), 0, s, m, n, K, A, lda, B, ldb, C, ldc, status);
+}
+template void launch_gemm_tn_long<float>(hipStream_t, int, int, int, const float *, int, const float *, int, float *,
+                                         int, const int *);
+template void launch_gemm_tn_long<double>(hipStream_t, int, int, int, const double *, int, const double *, int,
+                                          double *, int, const int *);
+
+template <typename T>
+void launch_identity_block(hipStream_t s, int64_t n, int ld, int64_t j0, T *b) {
+    const int64_t tot = n * ld;
+    hipLaunchKernelGGL(k_identity_block<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, ld, j0, b);
+}
+template void launch_identity_block<float>(hipStream_t, int64_t, int, int64_t, float *);
+template void launch_identity_block<double>(hipStream_t, int64_t, int, int64_t, double *);
+
+template <typename T>
+void launch_rows_from_block(hipStream_t s, int64_t n, int ld, int64_t j0, const T *x, T *Bt) {
+    const int64_t tot = n * ld;
+    hipLaunchKernelGGL(k_rows_from_block<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, ld, j0, x,
+                       Bt);
+}
+template void launch_rows_from_block<float>(hipStream_t, int64_t, int, int64_t, const float *, float *);
+template void launch_rows_from_block<double>(hipStream_t, int64_t, int, int64_t, const double *, double *);
 
 void launch_fill_random(hipStream_t s, int64_t n, int ld, int qe, uint64_t seed, double *U) {
     const int64_t tot = n * ld;
