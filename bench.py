@@ -3,6 +3,7 @@
 and the CPU oracle timed beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1] [--precision mixed|fp64]
+    python bench.py --config 4 [--requests R] [--rate HZ] [--n-hi N]     (serving stream)
 
 A step is one whole solve of the workload: nested start from the coarsest
 level, then finest-level corrections until max_{j<=q} rho_j <= 1e-8.  Inputs
@@ -60,6 +61,117 @@ print(json.dumps({"seconds": dt, "steps": info["steps"], "q": p["q"], "conv": bo
                       "%d corrections to rho<=%g, %.1f s), setup excluded, 1 thread" % (d["steps"], tol, d["seconds"])}
 
 
+def serving(args):
+    """Serving stream: seeded requests from the three mesh families with uneven N
+    and q, Poisson arrivals at a fixed rate, admission by device footprint and
+    continuous batching over a stream pool (mixed precision).  Beside it, the
+    same requests solved one after another as plain single-instance solves, in
+    FP64 and in mixed precision.  Host setup (the AMG hierarchy) is done before
+    each timed pass; binding (device workspace) and the solve are inside."""
+    import torch
+    import paper_1503_08462_amd as ae
+    from paper_1503_08462_amd.serving import Server
+    from workloads import configs
+
+    reqs = configs.request_stream(args.requests, seed=5, n_lo=10_000, n_hi=args.n_hi)
+    probs = [configs.build_request(r) for r in reqs]
+    qs = np.array([p["q"] for p in probs])
+    gaps = -np.log1p(-np.array([r["u_arrival"] for r in reqs])) / args.rate
+    arrivals = np.cumsum(gaps) - gaps[0]
+    tol = args.tol
+
+    def contexts(prec):
+        return [ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
+                           ae.defaults(coarse_max=512, qe=p["qe"], precision=prec, tol=tol)) for p in probs]
+
+    def solo(prec):
+        cs = contexts(prec)
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lat, bad = [], []
+        for k, c in enumerate(cs):
+            t1 = time.perf_counter()
+            c.bind(stream=stream)
+            c.init(ae.INIT_NESTED)
+            _, ok = c.solve(tol, 400)
+            if not ok:
+                bad.append(k)
+            c.close()
+            c.workspace = None
+            lat.append(time.perf_counter() - t1)
+        torch.cuda.synchronize()
+        if bad:
+            raise SystemExit("solo solves of requests %s did not converge" % bad)
+        return qs.sum() / (time.perf_counter() - t), lat
+
+    # warm-up: one request end to end
+    c = contexts(ae.PREC_MIXED)[0]
+    c.bind()
+    c.init(ae.INIT_NESTED)
+    c.solve(tol, 400)
+    c.close()
+    del c
+    solo64, _ = solo(ae.PREC_FP64)
+    solo32, _ = solo(ae.PREC_MIXED)
+
+    cs = contexts(ae.PREC_MIXED)
+    fps = sorted(c.footprint() for c in cs)
+    budget = int(args.budget_gb * 2 ** 30)
+    srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=2,
+                 context_factory=lambda p, o: cs[p["_k"]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(probs) or srv.queue or srv.active:
+        now = time.perf_counter() - t0
+        while i < len(probs) and arrivals[i] <= now:
+            srv.submit(dict(probs[i], _k=i), tol=tol, max_steps=400, arrival=t0 + arrivals[i])
+            i += 1
+        if srv.queue or srv.active:
+            srv.round()
+        elif i < len(probs):
+            time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
+    torch.cuda.synchronize()
+    makespan = time.perf_counter() - t0
+    res = srv.results()
+    bad = [k for k, r in res.items() if not r["converged"]]
+    if bad:
+        raise SystemExit("served requests %s did not converge" % bad)
+    lat = srv.latency()
+    served = qs.sum() / makespan
+    ns = [p["n"] for p in probs]
+    out = {
+        "metric": "eigenpairs/sec to 1e-8 rel. residual (served stream)",
+        "value": served,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": makespan * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "serving stream: %d seeded requests (L-shape, checkerboard cube, oscillator), "
+                               "N in [%d, %d], q in {4, 8, 16, 32}, Poisson arrivals at %g/s"
+                               % (len(probs), min(ns), max(ns), args.rate),
+                   "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
+                   "streams": args.streams, "steps_per_round": 2, "tol": tol},
+        "p50_ms": lat["p50_s"] * 1e3,
+        "p99_ms": lat["p99_s"] * 1e3,
+        "peak_resident_gb": srv.peak_in_use / 2 ** 30,
+        "rounds": srv.rounds,
+        "solo_fp64_eigenpairs_per_s": solo64,
+        "solo_mixed_eigenpairs_per_s": solo32,
+        "served_vs_solo_fp64": served / solo64,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def load_traffic(kernel, workload_tag):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if any."""
     path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload_tag))
@@ -81,7 +193,14 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--tune", type=int, default=1,
+                    help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev"])
+    ap.add_argument("--requests", type=int, default=24, help="serving stream (config 4): number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving stream: Poisson arrival rate, 1/s")
+    ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
+    ap.add_argument("--budget-gb", type=float, default=8.0, help="serving stream: device memory budget")
+    ap.add_argument("--streams", type=int, default=4, help="serving stream: stream pool size")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -89,6 +208,10 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus)
         sys.exit(2)
+
+    if args.config == 4:
+        serving(args)
+        return
 
     import torch
     import paper_1503_08462_amd as ae
@@ -106,6 +229,13 @@ def main():
     stream = torch.cuda.Stream()
     ctx.bind(stream=stream)
     info = ctx.info()
+    tuning = None
+    if args.tune:
+        from paper_1503_08462_amd import autotune
+        t1 = time.perf_counter()
+        rep = autotune.tune(ctx)
+        tuning = {"seconds": round(time.perf_counter() - t1, 3),
+                  "cpt": {"%s@%d" % (v["kind"], v["level"]): v["cpt"] for v in rep.values()}}
     for _ in range(args.warmup):
         ctx.init(ae.INIT_NESTED)
         ctx.solve(args.tol, 400)
@@ -156,8 +286,11 @@ def main():
     if dom:
         amount, ms, n = stats[dom]
         achieved = amount / (ms / n * 1e-3) / 1e9
-        kernel_name = {"residual": "k_residual", "presmooth": "k_smooth_pre", "postsmooth": "k_smooth_post",
-                       "dualspmm": "k_dual_spmm", "restrict": "k_spmm", "final": "k_final"}[dom]
+        cheb = args.smoother == "chebyshev"
+        kernel_name = {"residual": "k_residual", "presmooth": "k_cheb_pre" if cheb else "k_smooth_pre",
+                       "postsmooth": "k_cheb_post2" if cheb else "k_smooth_post",
+                       "dualspmm": "k_dual_spmm", "restrict": "k_spmm",
+                       "final": "k_final" if wl["qe"] > 32 else "k_final_rows"}[dom]
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": load_traffic(kernel_name, "config%d_%s" % (args.config, args.precision)),
@@ -192,6 +325,7 @@ def main():
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "corrections_per_solve": float(np.mean(steps)),
         "setup_s": setup_s,
+        "tuning": tuning,
         "roofline": roofline,
         "small_solver": small,
         "sites": sites,

@@ -176,8 +176,8 @@ int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld);
 
 /* Kernel sites on the finest level, for per-kernel timing. */
 #define AMG_EIG_SITE_RESIDUAL 0   /* outer residual R = M U Theta - A U (FP64 dual SpMM) */
-#define AMG_EIG_SITE_PRESMOOTH 1  /* fused zero-guess smoothing + residual */
-#define AMG_EIG_SITE_POSTSMOOTH 2 /* post-smoothing fused with V = U + delta */
+#define AMG_EIG_SITE_PRESMOOTH 1  /* zero-guess pre-smoothing (l1-Jacobi: fused with the residual) */
+#define AMG_EIG_SITE_POSTSMOOTH 2 /* last post-smoothing product, fused with V = U + delta */
 #define AMG_EIG_SITE_DUALSPMM 3   /* W = [A V | M V] */
 #define AMG_EIG_SITE_GRAM 4       /* V^T [A V | M V] (counted in flops) */
 #define AMG_EIG_SITE_RESTRICT 5   /* FP64 restriction of W, level 1 -> 2 */
@@ -195,6 +195,34 @@ int amg_eig_timing(amg_eig_ctx *c, int enable);
  * flops for the Gram site), the summed event time in ms and the number of
  * timed launches. */
 int amg_eig_site_stats(amg_eig_ctx *c, int site, double *alg_bytes, double *ms_total, int64_t *launches);
+
+/* Launch shape of the row kernels (batching form: per-level choice by a
+ * timing autotuner).  A row kernel gives each row of its block width / cpt
+ * lanes, every lane cpt consecutive columns; cpt is 2, 4 or 8, must divide the
+ * width and leave at most 64 lanes per row, and 0 selects the built-in rule
+ * (fewest idle lanes, then fewest columns per lane).  Each output entry is the
+ * same ordered sum for every cpt, so the choice changes timing, not results.
+ * Kinds, by the rows a kernel produces on `level`:
+ *   VCYCLE     smoothing, level residual and transfers of the V-cycle, in the
+ *              working precision, width q_e (levels 0 .. nlev-2);
+ *   FP64       dual SpMM [A V | M V], prolongation of the coarse part of the
+ *              Ritz vectors and the final update, width q_e (0 .. nlev-2);
+ *   FP64_WIDE  restriction of [A V | M V], width 2 q_e (1 .. nlev-2).
+ * set_cpt: EINVAL for an invalid kind, level or cpt; drops a captured step.
+ * get_cpt: the cpt in effect (the built-in rule's when none is set). */
+#define AMG_EIG_TUNE_VCYCLE 0
+#define AMG_EIG_TUNE_FP64 1
+#define AMG_EIG_TUNE_FP64_WIDE 2
+int amg_eig_set_cpt(amg_eig_ctx *c, int kind, int level, int cpt);
+int amg_eig_get_cpt(const amg_eig_ctx *c, int kind, int level, int *cpt);
+
+/* Time the row kernels of one kind on one level with the given cpt (0: the
+ * built-in rule): one untimed pass, then `reps` passes between two HIP events
+ * on the bound stream; waits for them and returns the microseconds per pass.
+ * The kernels work on the context's scratch (never on the iterate U) and the
+ * solve state is cleared, so init() must follow before the next correction.
+ * Errors: EINVAL (kind, level, cpt, reps < 1), ESTATE (not bound), EHIP. */
+int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, double *us_per_rep);
 
 void amg_eig_destroy(amg_eig_ctx *c);
 const char *amg_eig_strerror(int code);

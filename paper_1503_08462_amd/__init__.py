@@ -35,8 +35,10 @@ EXPORTED = [
     "amg_eig_correct", "amg_eig_progress", "amg_eig_solve", "amg_eig_correct_batch", "amg_eig_info",
     "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting",
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
-    "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats",
+    "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
+    "amg_eig_tune_time",
 ]
+TUNE_VCYCLE, TUNE_FP64, TUNE_FP64_WIDE = 0, 1, 2
 SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
 
 
@@ -77,6 +79,9 @@ _sig = {
     "amg_eig_last_error": (ctypes.c_char_p, [_vp]),
     "amg_eig_timing": (_i, [_vp, _i]),
     "amg_eig_site_stats": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "amg_eig_set_cpt": (_i, [_vp, _i, _i, _i]),
+    "amg_eig_get_cpt": (_i, [_vp, _i, _i, _vp]),
+    "amg_eig_tune_time": (_i, [_vp, _i, _i, _i, _i, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -233,6 +238,26 @@ class Context:
             self._check(_lib.amg_eig_site_stats(self._c, i, ctypes.byref(b), ctypes.byref(ms), ctypes.byref(n)))
             out[name] = (b.value, ms.value, n.value)
         return out
+
+    def level_nnz(self, level):
+        nnz = ctypes.c_int64()
+        self._check(_lib.amg_eig_level_matrix(self._c, level, ctypes.byref(nnz), None, None, None, None))
+        return nnz.value
+
+    def set_cpt(self, kind, level, cpt):
+        """Columns per lane of the row kernels of one kind on one level (0: built-in rule)."""
+        self._check(_lib.amg_eig_set_cpt(self._c, kind, level, cpt))
+
+    def get_cpt(self, kind, level):
+        v = ctypes.c_int()
+        self._check(_lib.amg_eig_get_cpt(self._c, kind, level, ctypes.byref(v)))
+        return v.value
+
+    def tune_time(self, kind, level, cpt, reps=10):
+        """Microseconds per pass of the row kernels of (kind, level) launched with cpt; clears the solve state."""
+        us = ctypes.c_double()
+        self._check(_lib.amg_eig_tune_time(self._c, kind, level, cpt, reps, ctypes.byref(us)))
+        return us.value
 
     def close(self):
         if self._c:

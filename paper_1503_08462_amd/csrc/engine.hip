@@ -9,6 +9,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "amg_eig.h"
@@ -30,6 +31,7 @@ struct DevLevel {
     double *p64 = nullptr, *pt64 = nullptr;
     void *b = nullptr, *r = nullptr, *x = nullptr, *t = nullptr;  // t: Chebyshev scratch
     double *cw = nullptr;
+    int cpt[3] = {0, 0, 0};  // columns per lane of the row kernels on this level's rows, by tuning kind (0: built-in)
 };
 
 // Bump allocator over the caller's workspace; with base == nullptr it only sizes.
@@ -77,6 +79,8 @@ struct amg_eig_ctx {
     std::vector<std::vector<char>> staging;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // tuned columns per lane by (level, kind); copied into dl at bind
+    std::vector<std::array<int, 3>> cpt_tab;
     // optional per-site event timing of finest-level kernels (eager launches)
     bool timing = false;
     struct Site {
@@ -103,7 +107,10 @@ int fail(amg_eig_ctx *c, int code, const std::string &msg) {
 // ------------------------------------------------------------ dense tail
 // The first level t >= 1 with at most kTailRows unknowns and at least one level
 // below it becomes the dense tail; Zk = P_t P_{t+1} ... P_{n-1} Z on the host.
-constexpr int64_t kTailRows = 3000;
+#ifndef AMG_EIG_TAIL_ROWS
+#define AMG_EIG_TAIL_ROWS 3000
+#endif
+constexpr int64_t kTailRows = AMG_EIG_TAIL_ROWS;
 
 void choose_tail(amg_eig_ctx *c) {
     const Hierarchy &H = c->H;
@@ -140,6 +147,9 @@ void plan(amg_eig_ctx *c, char *base) {
     const size_t sT = c->mixed ? sizeof(float) : sizeof(double);
     const int64_t N = H.lv[0].n;
     c->dl.assign(L, DevLevel());
+    if ((int)c->cpt_tab.size() != L) c->cpt_tab.assign(L, std::array<int, 3>{0, 0, 0});
+    for (int l = 0; l < L; ++l)
+        for (int k = 0; k < 3; ++k) c->dl[l].cpt[k] = c->cpt_tab[l][k];
     for (int l = 0; l < L; ++l) {
         const Level &lv = H.lv[l];
         DevLevel &d = c->dl[l];
@@ -348,8 +358,7 @@ double site_bytes(const amg_eig_ctx *c, int site) {
     case AMG_EIG_SITE_RESIDUAL: return ptr + nnz_u * 20.0 + 8.0 * n * ld + sT * n * ld;
     case AMG_EIG_SITE_PRESMOOTH: return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld;
     case AMG_EIG_SITE_POSTSMOOTH:
-        if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV)  // two products: d0 from (b, y); x from (d0, y), U -> V
-            return 2.0 * (ptr + nnz_v * (4.0 + sT) + sT * n) + 3.0 * sT * n * ld + 2.0 * sT * n * ld + 16.0 * n * ld;
+        // l1-Jacobi: (b, r) -> U + x; Chebyshev, second product: (y, d0) -> U + x
         return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_DUALSPMM: return ptr + nnz_u * 20.0 + 8.0 * n * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_GRAM: return 4.0 * n * ld * ld;  // flops
@@ -378,17 +387,17 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
             {
                 SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
                 launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
-                                   (const T *)d.b, (T *)d.x, lo, st);
+                                   (const T *)d.b, (T *)d.x, lo, st, d.cpt[0]);
             }
             launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
-                                     (const T *)d.x, (T *)d.r, st);
+                                     (const T *)d.x, (T *)d.r, st, d.cpt[0]);
         } else {
             SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
             launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
-                                 (const T *)d.b, (T *)d.r, st);
+                                 (const T *)d.b, (T *)d.r, st, d.cpt[0]);
         }
         DevLevel &e = c->dl[l + 1];
-        launch_spmm<T>(s, e.n, ld, d.pt_ptr, d.pt_col, (const T *)d.pt_val, (const T *)d.r, (T *)e.b, st);
+        launch_spmm<T>(s, e.n, ld, d.pt_ptr, d.pt_col, (const T *)d.pt_val, (const T *)d.r, (T *)e.b, st, e.cpt[0]);
     }
     DevLevel &cl = c->dl[bottom];
     if (bottom == L - 1)
@@ -403,16 +412,19 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
         if (cheb) {
             // y = x + P x_{l+1} into r (free after the restriction), then x = smoothed y
             launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.x,
-                                (T *)d.r, st);
+                                (T *)d.r, st, d.cpt[0]);
+            launch_cheb_post1<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv, (const T *)d.b,
+                                 (const T *)d.r, (T *)d.t, lo, st, d.cpt[0]);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
-            launch_cheb_post<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
-                                (const T *)d.b, (const T *)d.r, (T *)d.t, (T *)d.x, c->U, c->V, lo, st);
+            launch_cheb_post2<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val,
+                                 (const T *)d.dinv, (const T *)d.r, (const T *)d.t, (T *)d.x, c->U, c->V, lo, st,
+                                 d.cpt[0]);
         } else {
             launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
-                                  (const T *)d.dinv, (const T *)d.b, (T *)d.r, st);
+                                  (const T *)d.dinv, (const T *)d.b, (T *)d.r, st, d.cpt[0]);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
             launch_smooth_post<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
-                                  (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st);
+                                  (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st, d.cpt[0]);
         }
     }
 }
@@ -443,7 +455,7 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
     DevLevel &d = c->dl[k];
     {
         SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k);
-        launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st);
+        launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, d.cpt[1]);
     }
     {
         SiteScope sc(c, AMG_EIG_SITE_GRAM, k);
@@ -457,7 +469,7 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
         DevLevel &a = c->dl[l];
         DevLevel &b = c->dl[l + 1];
         SiteScope sc(c, AMG_EIG_SITE_RESTRICT, l);
-        launch_spmm<double>(s, b.n, 2 * ld, a.pt_ptr, a.pt_col, a.pt64, src, b.cw, st);
+        launch_spmm<double>(s, b.n, 2 * ld, a.pt_ptr, a.pt_col, a.pt64, src, b.cw, st, b.cpt[2]);
         src = b.cw;
     }
     const double *y;
@@ -483,12 +495,12 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
     }
     for (int l = bottom - 1; l > k; --l) {
         DevLevel &a = c->dl[l];
-        launch_spmm<double>(s, a.n, ld, a.p_ptr, a.p_col, a.p64, y, a.cw, st);
+        launch_spmm<double>(s, a.n, ld, a.p_ptr, a.p_col, a.p64, y, a.cw, st, a.cpt[1]);
         y = a.cw;
     }
     {
         SiteScope sc(c, AMG_EIG_SITE_FINAL, k);
-        launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, y, c->V, c->sw.Xv, c->U, st);
+        launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, y, c->V, c->sw.Xv, c->U, st, d.cpt[1]);
     }
 }
 
@@ -652,7 +664,7 @@ int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, i
         launch_copy_f64(s, qe, c->lam, c->theta);
         for (int k = L - 2; k >= 0; --k) {
             DevLevel &d = c->dl[k];
-            launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, c->U, c->V, c->status);
+            launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, c->U, c->V, c->status, d.cpt[1]);
             launch_copy_f64(s, d.n * (int64_t)ld, c->V, c->U);
             if (k >= 1) correction(c, k);
         }
@@ -830,6 +842,104 @@ int amg_eig_site_stats(amg_eig_ctx *c, int site, double *alg_bytes, double *ms_t
     if (alg_bytes) *alg_bytes = site_bytes(c, site);
     if (ms_total) *ms_total = c->sites[site].ms;
     if (launches) *launches = c->sites[site].launches;
+    return AMG_EIG_OK;
+}
+
+int amg_eig_set_cpt(amg_eig_ctx *c, int kind, int level, int cpt) {
+    if (!c || kind < 0 || kind > 2 || level < 0 || level >= (int)c->H.lv.size())
+        return c ? fail(c, AMG_EIG_EINVAL, "tuning kind or level out of range") : AMG_EIG_EINVAL;
+    const int width = kind == AMG_EIG_TUNE_FP64_WIDE ? 2 * c->ld : c->ld;
+    if (cpt != 0 && !cpt_valid(width, cpt))
+        return fail(c, AMG_EIG_EINVAL, "columns per lane must be 2, 4 or 8, divide the block width and leave at "
+                                       "most 64 lanes per row");
+    if ((int)c->cpt_tab.size() != (int)c->H.lv.size()) c->cpt_tab.assign(c->H.lv.size(), std::array<int, 3>{0, 0, 0});
+    c->cpt_tab[level][kind] = cpt;
+    if (level < (int)c->dl.size()) c->dl[level].cpt[kind] = cpt;
+    drop_graph(c);  // a captured step holds the old launch shapes
+    return AMG_EIG_OK;
+}
+
+int amg_eig_get_cpt(const amg_eig_ctx *c, int kind, int level, int *cpt) {
+    if (!c || !cpt || kind < 0 || kind > 2 || level < 0 || level >= (int)c->H.lv.size()) return AMG_EIG_EINVAL;
+    const int width = kind == AMG_EIG_TUNE_FP64_WIDE ? 2 * c->ld : c->ld;
+    const int hint = (int)c->cpt_tab.size() > level ? c->cpt_tab[level][kind] : 0;
+    *cpt = pick_cpt(width, hint);
+    return AMG_EIG_OK;
+}
+
+int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, double *us_per_rep) {
+    if (!c || !us_per_rep || kind < 0 || kind > 2 || reps < 1) return AMG_EIG_EINVAL;
+    if (!c->bound) return fail(c, AMG_EIG_ESTATE, "tuning before bind");
+    const int L = (int)c->dl.size(), ld = c->ld;
+    if (level < 0 || level > L - 2) return fail(c, AMG_EIG_EINVAL, "no row kernels of this kind on that level");
+    if (kind == AMG_EIG_TUNE_FP64_WIDE && level < 1)
+        return fail(c, AMG_EIG_EINVAL, "the restriction of W produces levels 1 and below");
+    const int width = kind == AMG_EIG_TUNE_FP64_WIDE ? 2 * ld : ld;
+    if (cpt != 0 && !cpt_valid(width, cpt)) return fail(c, AMG_EIG_EINVAL, "invalid columns per lane");
+    hipStream_t s = c->stream;
+    const int *st = c->status;
+    launch_fill_i32(s, ST_COUNT, 0, c->status);  // the kernels run only while the converged flag is clear
+    DevLevel &d = c->dl[level];
+    DevLevel &e = c->dl[level + 1];
+    const double lo = c->o.cheb_lo;
+    auto group = [&](auto tag) {
+        using T = decltype(tag);
+        if (kind == AMG_EIG_TUNE_VCYCLE) {
+            if (level >= 1) {
+                DevLevel &f = c->dl[level - 1];
+                launch_spmm<T>(s, d.n, ld, f.pt_ptr, f.pt_col, (const T *)f.pt_val, (const T *)f.r, (T *)d.b, st, cpt);
+            }
+            if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV) {
+                launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                   (const T *)d.b, (T *)d.x, lo, st, cpt);
+                launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
+                                         (const T *)d.x, (T *)d.r, st, cpt);
+                launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
+                                    (const T *)d.x, (T *)d.r, st, cpt);
+                launch_cheb_post1<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                     (const T *)d.b, (const T *)d.r, (T *)d.t, lo, st, cpt);
+                launch_cheb_post2<T>(s, false, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                     (const T *)d.r, (const T *)d.t, (T *)d.x, c->U, c->V, lo, st, cpt);
+            } else {
+                launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                     (const T *)d.b, (T *)d.r, st, cpt);
+                launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
+                                      (const T *)d.dinv, (const T *)d.b, (T *)d.r, st, cpt);
+                launch_smooth_post<T>(s, false, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                                      (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st, cpt);
+            }
+        } else if (kind == AMG_EIG_TUNE_FP64) {
+            // the final update writes into W here, never into the iterate U
+            launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, cpt);
+            if (level >= 1) launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, e.cw, d.cw, st, cpt);
+            launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, e.cw, c->V, c->sw.Xv, c->W, st, cpt);
+        } else {
+            DevLevel &f = c->dl[level - 1];
+            launch_spmm<double>(s, d.n, 2 * ld, f.pt_ptr, f.pt_col, f.pt64, level == 1 ? c->W : f.cw, d.cw, st,
+                                cpt);
+        }
+    };
+    hipEvent_t ev[2];
+    HIPCHK(c, hipEventCreate(&ev[0]));
+    HIPCHK(c, hipEventCreate(&ev[1]));
+    auto run = [&]() {
+        if (c->mixed)
+            group(float());
+        else
+            group(double());
+    };
+    run();  // warm
+    (void)hipEventRecord(ev[0], s);
+    for (int i = 0; i < reps; ++i) run();
+    (void)hipEventRecord(ev[1], s);
+    hipError_t err = hipEventSynchronize(ev[1]);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (err != hipSuccess) return fail(c, AMG_EIG_EHIP, std::string("tuning: ") + hipGetErrorString(err));
+    *us_per_rep = 1e3 * (double)ms / reps;
+    c->initialised = false;  // the scratch and flags were overwritten: init before the next correction
     return AMG_EIG_OK;
 }
 

@@ -28,34 +28,37 @@ void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsi
                             double *rho, int q, double tol, int *status, int check);
 template <typename T>
 void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                       const T *dinv, const T *b, T *r, const int *status);
+                       const T *dinv, const T *b, T *r, const int *status, int cpt = 0);
 template <typename T>
 void launch_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                 const T *x, T *y, const int *status);
+                 const T *x, T *y, const int *status, int cpt = 0);
 template <typename T>
 void launch_prolong_add(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                        const T *xc, const T *dinv, const T *b, T *y, const int *status);
+                        const T *xc, const T *dinv, const T *b, T *y, const int *status, int cpt = 0);
 template <typename T>
 void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
                         const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
-                        const int *status);
+                        const int *status, int cpt = 0);
 // Degree-2 Chebyshev smoothing on D^-1 A over [lo, 1] (D the l1 diagonal):
 // pre-smoothing from a zero guess (x), the level residual r = b - A x, the
 // prolongation y = x + P xc, and post-smoothing of y (scratch d0; x, or on
 // the correction level V = U + x in FP64).
 template <typename T>
 void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                     const T *dinv, const T *b, T *x, double lo, const int *status);
+                     const T *dinv, const T *b, T *x, double lo, const int *status, int cpt = 0);
 template <typename T>
 void launch_level_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                           const T *b, const T *x, T *r, const int *status);
+                           const T *b, const T *x, T *r, const int *status, int cpt = 0);
 template <typename T>
 void launch_prolong_x(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                      const T *xc, const T *x, T *y, const int *status);
+                      const T *xc, const T *x, T *y, const int *status, int cpt = 0);
 template <typename T>
-void launch_cheb_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
-                      const T *val, const T *dinv, const T *b, const T *y, T *d0, T *x, const double *U, double *V,
-                      double lo, const int *status);
+void launch_cheb_post1(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                       const T *dinv, const T *b, const T *y, T *d0, double lo, const int *status, int cpt = 0);
+template <typename T>
+void launch_cheb_post2(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
+                       const T *val, const T *dinv, const T *y, const T *d0, T *x, const double *U, double *V,
+                       double lo, const int *status, int cpt = 0);
 template <typename T, typename TA>
 void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
                        const int *status);
@@ -64,11 +67,14 @@ template <typename T>
 void launch_gemm_tn(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,
                     const int *status);
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
-                      const double *m, const double *V, double *W, const int *status);
+                      const double *m, const double *V, double *W, const int *status, int cpt = 0);
 void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
                  const int *status);
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
-                  const double *Y, const double *V, const double *Xv, double *U, const int *status);
+                  const double *Y, const double *V, const double *Xv, double *U, const int *status, int cpt = 0);
+// columns-per-lane choice of the row kernels: `hint` when valid for the width, else the built-in rule
+bool cpt_valid(int width, int cpt);
+int pick_cpt(int width, int hint);
 // launch_gemm_tn for long K: sixteen wavefronts per tile of C
 template <typename T>
 void launch_gemm_tn_long(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,

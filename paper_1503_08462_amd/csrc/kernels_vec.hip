@@ -777,9 +777,16 @@ int cpt_for(int width) {
     return best ? best : 8;
 }
 
-#define DISPATCH_CPT(width, ...)             \
-    do {                                     \
-        const int cpt_sel = cpt_for(width);  \
+bool cpt_valid(int width, int cpt) {
+    return (cpt == 2 || cpt == 4 || cpt == 8) && width % cpt == 0 && width / cpt <= kWave;
+}
+
+// `hint` when it is a valid choice for the width (a tuned value), else cpt_for.
+int pick_cpt(int width, int hint) { return cpt_valid(width, hint) ? hint : cpt_for(width); }
+
+#define DISPATCH_CPT(width, hint, ...)             \
+    do {                                           \
+        const int cpt_sel = pick_cpt(width, hint); \
         if (cpt_sel == 2) {                  \
             constexpr int CPT = 2;           \
             __VA_ARGS__;                     \
@@ -803,7 +810,7 @@ void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const
     // part: 2 ld final sums, then nb x 2 ld per-block partials
     const int64_t nb = residual_blocks(n, ld);
     double *blocks = part + 2 * ld;
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
+    DISPATCH_CPT(ld, 0, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
                                         col, a, m, U, theta, R, blocks, status));
 }
 
@@ -816,47 +823,47 @@ void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsi
 
 template <typename T>
 void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                       const T *dinv, const T *b, T *r, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_smooth_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                       const T *dinv, const T *b, T *r, const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_smooth_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
                                         0, s, n, ld, ptr, col, val, dinv, b, r, status));
 }
 
 template <typename T>
 void launch_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                 const T *x, T *y, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_spmm<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0, s,
+                 const T *x, T *y, const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_spmm<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0, s,
                                         n, ld, ptr, col, val, x, y, status));
 }
 
 template <typename T>
 void launch_prolong_add(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                        const T *xc, const T *dinv, const T *b, T *y, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_prolong_add<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                        const T *xc, const T *dinv, const T *b, T *y, const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_prolong_add<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                         dim3(kBlock), 0, s, n, ld, ptr, col, val, xc, dinv, b, y, status));
 }
 
 template <typename T>
 void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
                         const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
-                        const int *status) {
+                        const int *status, int cpt) {
     if (final)
-        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_smooth_post<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_smooth_post<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
     else
-        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_smooth_post<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_smooth_post<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
 }
 
 template <typename T, typename TA>
 void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
                        const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_dense_rows<T, TA, CPT>), dim3((unsigned)row_blocks(m, ld, CPT)),
+    DISPATCH_CPT(ld, 0, hipLaunchKernelGGL((k_dense_rows<T, TA, CPT>), dim3((unsigned)row_blocks(m, ld, CPT)),
                                         dim3(kBlock), 0, s, m, K, A, lda, ld, B, C, status));
 }
 
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
-                      const double *m, const double *V, double *W, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
+                      const double *m, const double *V, double *W, const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
                                         s, n, ld, ptr, col, a, m, V, W, status));
 }
 
@@ -881,9 +888,9 @@ void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double
 }
 
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
-                  const double *Y, const double *V, const double *Xv, double *U, const int *status) {
+                  const double *Y, const double *V, const double *Xv, double *U, const int *status, int cpt) {
     if (ld <= 32) {
-        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_final_rows<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_final_rows<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr, col, val,
                                             Y, V, Xv, U, status));
         return;
@@ -921,39 +928,45 @@ ChebCoef cheb_coefficients(double lo) {
 
 template <typename T>
 void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                     const T *dinv, const T *b, T *x, double lo, const int *status) {
+                     const T *dinv, const T *b, T *x, double lo, const int *status, int cpt) {
     const ChebCoef kc = cheb_coefficients(lo);
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
                                         0, s, n, ld, ptr, col, val, dinv, b, x, kc, status));
 }
 
 template <typename T>
 void launch_level_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                           const T *b, const T *x, T *r, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_level_residual<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+                           const T *b, const T *x, T *r, const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_level_residual<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                         dim3(kBlock), 0, s, n, ld, ptr, col, val, b, x, r, status));
 }
 
 template <typename T>
 void launch_prolong_x(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
-                      const T *xc, const T *x, T *y, const int *status) {
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_prolong_x<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                      const T *xc, const T *x, T *y, const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_prolong_x<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
                                         0, s, n, ld, ptr, col, val, xc, x, y, status));
 }
 
 template <typename T>
-void launch_cheb_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
-                      const T *val, const T *dinv, const T *b, const T *y, T *d0, T *x, const double *U, double *V,
-                      double lo, const int *status) {
+void launch_cheb_post1(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+                       const T *dinv, const T *b, const T *y, T *d0, double lo, const int *status, int cpt) {
     const ChebCoef kc = cheb_coefficients(lo);
-    DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_post1<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_post1<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
                                         0, s, n, ld, ptr, col, val, dinv, b, y, d0, kc, status));
+}
+
+template <typename T>
+void launch_cheb_post2(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
+                       const T *val, const T *dinv, const T *y, const T *d0, T *x, const double *U, double *V,
+                       double lo, const int *status, int cpt) {
+    const ChebCoef kc = cheb_coefficients(lo);
     if (final)
-        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_post2<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_post2<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
                                             status));
     else
-        DISPATCH_CPT(ld, hipLaunchKernelGGL((k_cheb_post2<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_post2<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
                                             status));
 }
@@ -1009,25 +1022,27 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
 
 #define INST(T)                                                                                                      \
     template void launch_smooth_pre<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,       \
-                                       const T *, const T *, T *, const int *);                                      \
+                                       const T *, const T *, T *, const int *, int);                                      \
     template void launch_spmm<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *, const T *,  \
-                                 T *, const int *);                                                                  \
+                                 T *, const int *, int);                                                                  \
     template void launch_prolong_add<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,      \
-                                        const T *, const T *, const T *, T *, const int *);                          \
+                                        const T *, const T *, const T *, T *, const int *, int);                          \
     template void launch_smooth_post<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *,           \
                                         const T *, const T *, const T *, const T *, T *, const double *, double *,   \
-                                        const int *);                                                                \
+                                        const int *, int);                                                                \
     template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
                                      const double *, const double *, const double *, T *, double *, const int *);     \
     template void launch_cheb_pre<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,         \
-                                     const T *, const T *, T *, double, const int *);                                \
+                                     const T *, const T *, T *, double, const int *, int);                                \
     template void launch_level_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,   \
-                                           const T *, const T *, T *, const int *);                                  \
+                                           const T *, const T *, T *, const int *, int);                                  \
     template void launch_prolong_x<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,        \
-                                      const T *, const T *, T *, const int *);                                       \
-    template void launch_cheb_post<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *, const T *,  \
-                                      const T *, const T *, const T *, T *, T *, const double *, double *, double,    \
-                                      const int *);
+                                      const T *, const T *, T *, const int *, int);                                       \
+    template void launch_cheb_post1<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,       \
+                                       const T *, const T *, const T *, T *, double, const int *, int);                   \
+    template void launch_cheb_post2<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *, const T *, \
+                                       const T *, const T *, const T *, T *, const double *, double *, double,       \
+                                       const int *, int);
 INST(float)
 INST(double)
 #undef INST

@@ -106,8 +106,28 @@ def lshape_m_for(n_target):
     return max(4, int(round((4 + np.sqrt(16 - 12 * (1 - n_target))) / 6)))
 
 
+def guard_width(family, q):
+    """Block width a client asks for so that the block never ends inside a
+    cluster of the family's spectrum (extra pairs computed beside the wanted
+    ones): the oscillator's eigenvalues 2(k+1) have multiplicity k+1, so the
+    width is the end of the cluster holding the q-th; the checkerboard cube has
+    a low cluster of 32 (one mode per kappa = 1 block), so widths below 32 take
+    the whole cluster; the L-shape has no multiple eigenvalues, and a quarter
+    more pairs keep the convergence factor lambda_q / lambda_{qe+1} small."""
+    if family == "oscillator":
+        k, total = 0, 0
+        while total < q:
+            k += 1
+            total += k
+        return total
+    if family == "cube":
+        return 32 if q < 32 else q + 4
+    return q + max(2, (q + 3) // 4)
+
+
 def request_stream(n_requests=256, seed=5, n_lo=10_000, n_hi=1_000_000):
-    """Seeded request descriptors: family, mesh parameter, q, per-request seed."""
+    """Seeded request descriptors: family, mesh parameter, q, block width qe,
+    per-request seed."""
     out = []
     for r in range(n_requests):
         rs = prng.derive_seed(seed, r)
@@ -122,7 +142,8 @@ def request_stream(n_requests=256, seed=5, n_lo=10_000, n_hi=1_000_000):
             m = 4 * max(2, int(round(m / 4)))  # checkerboard blocks stay whole cells
         else:
             m = max(16, int(round(np.sqrt(nt))) + 1)
-        out.append({"id": r, "family": fam, "m": m, "q": q, "seed": rs, "u_arrival": float(u[3])})
+        out.append({"id": r, "family": fam, "m": m, "q": q, "qe": guard_width(fam, q), "seed": rs,
+                    "u_arrival": float(u[3])})
     return out
 
 
@@ -135,4 +156,5 @@ def build_request(req):
     else:
         p = oscillator(m, q=q)
     p["seed"] = req["seed"]
+    p["qe"] = req["qe"]
     return p
