@@ -82,7 +82,8 @@ def serving(args):
 
     def contexts(prec):
         return [ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
-                           ae.defaults(coarse_max=512, qe=p["qe"], precision=prec, tol=tol)) for p in probs]
+                           ae.defaults(coarse_max=512, qe=p["qe"], precision=prec, tol=tol,
+                                       use_graph=args.graph if prec == ae.PREC_MIXED else 0)) for p in probs]
 
     def solo(prec):
         cs = contexts(prec)
@@ -118,7 +119,7 @@ def serving(args):
     cs = contexts(ae.PREC_MIXED)
     fps = sorted(c.footprint() for c in cs)
     budget = int(args.budget_gb * 2 ** 30)
-    srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=2,
+    srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=args.steps_per_round,
                  context_factory=lambda p, o: cs[p["_k"]])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,7 +159,8 @@ def serving(args):
                                "N in [%d, %d], q in {4, 8, 16, 32}, Poisson arrivals at %g/s"
                                % (len(probs), min(ns), max(ns), args.rate),
                    "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
-                   "streams": args.streams, "steps_per_round": 2, "tol": tol},
+                   "streams": args.streams, "steps_per_round": args.steps_per_round, "tol": tol,
+                   "graph_steps": bool(args.graph)},
         "p50_ms": lat["p50_s"] * 1e3,
         "p99_ms": lat["p99_s"] * 1e3,
         "peak_resident_gb": srv.peak_in_use / 2 ** 30,
@@ -191,6 +193,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--coarse-max", type=int, default=0, help="override the workload's coarsest-level bound")
+    ap.add_argument("--qe", type=int, default=0, help="override the workload's block width")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--tune", type=int, default=1,
@@ -200,7 +204,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serving stream: Poisson arrival rate, 1/s")
     ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
     ap.add_argument("--budget-gb", type=float, default=8.0, help="serving stream: device memory budget")
-    ap.add_argument("--streams", type=int, default=4, help="serving stream: stream pool size")
+    ap.add_argument("--streams", type=int, default=8, help="serving stream: stream pool size")
+    ap.add_argument("--steps-per-round", type=int, default=2, help="serving stream: corrections per round")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -217,7 +222,11 @@ def main():
     import paper_1503_08462_amd as ae
     from workloads import configs
 
-    wl = WORKLOADS[args.config]
+    wl = dict(WORKLOADS[args.config])
+    if args.coarse_max:
+        wl["coarse_max"] = args.coarse_max
+    if args.qe:
+        wl["qe"] = args.qe
     p = configs.config(args.config)
     prec = ae.PREC_MIXED if args.precision == "mixed" else ae.PREC_FP64
     t0 = time.perf_counter()
