@@ -27,6 +27,10 @@ namespace amgeig {
 namespace {
 
 constexpr int kB = 256;  // threads per block of the small kernels
+// Rayleigh-quotient iteration stops at ||H x - rho x|| <= kRqiTol |rho|.  The
+// Rayleigh-Ritz polish over the span of all accepted vectors then leaves the
+// Ritz values with errors of the order of the squared residual over the gap.
+constexpr double kRqiTol = 1e-8;
 
 // ---------------------------------------------------------------------
 // Value of v in lane `src` of the wavefront (src must be wave-uniform).
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
 // Rayleigh-quotient iteration with the exact Schur-complement solve
 // (H - s)^-1 runs inside the bracket: every factorisation is also a count and
 // narrows the bracket.  An iterate is accepted once its Rayleigh quotient rho
-// lies in the isolating bracket with ||H x - rho x|| <= 1e-10 |rho| and more
+// lies in the isolating bracket with ||H x - rho x|| <= kRqiTol |rho| and more
 // than that residual away from both ends, which pins it to the bracketed
 // eigenvalue.
 __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
@@ -732,13 +736,13 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         normalise(vec);
         rayleigh(vec, rho, res);
         for (int it = 0; it < 3; ++it) {
-            if (res <= 1e-10 * fabs(rho) || !(rho > 0.0 && rho < cap)) break;
+            if (res <= kRqiTol * fabs(rho) || !(rho > 0.0 && rho < cap)) break;
             note(rho, factor(rho));
             solve(vec);
             normalise(vec);
             rayleigh(vec, rho, res);
         }
-        if (res <= 1e-10 * fabs(rho) && rho > 0.0 && rho < cap) {
+        if (res <= kRqiTol * fabs(rho) && rho > 0.0 && rho < cap) {
             // ends more than the residual away from rho, counted if not yet known
             const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
             if (!(have_lo && nulo == k && rho - lo > res)) {
@@ -803,7 +807,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         normalise(vec);
         rayleigh(vec, rho, res);
         const bool inside = rho > lo && rho < hi;
-        if (inside && res <= 1e-10 * fabs(rho) && rho - lo > res && hi - rho > res) break;
+        if (inside && res <= kRqiTol * fabs(rho) && rho - lo > res && hi - rho > res) break;
         sigma = inside ? rho : 0.5 * (lo + hi);
         if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;
     }
