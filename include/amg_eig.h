@@ -200,13 +200,16 @@ int amg_eig_site_stats(amg_eig_ctx *c, int site, double *alg_bytes, double *ms_t
  * timing autotuner).  A row kernel gives each row of its block width / cpt
  * lanes, every lane cpt consecutive columns; cpt is 2, 4 or 8, must divide the
  * width and leave at most 64 lanes per row, and 0 selects the built-in rule
- * (fewest idle lanes, then fewest columns per lane).  Each output entry is the
- * same ordered sum for every cpt, so the choice changes timing, not results.
+ * (fewest idle lanes, then fewest columns per lane).  Each vector entry is the
+ * same ordered sum for every cpt, so the iterates do not depend on the choice;
+ * only the residual norms rho_j, summed over rows in an order that follows the
+ * launch shape, can differ in the last bits.
  * Kinds, by the rows a kernel produces on `level`:
  *   VCYCLE     smoothing, level residual and transfers of the V-cycle, in the
  *              working precision, width q_e (levels 0 .. nlev-2);
- *   FP64       dual SpMM [A V | M V], prolongation of the coarse part of the
- *              Ritz vectors and the final update, width q_e (0 .. nlev-2);
+ *   FP64       outer residual, dual SpMM [A V | M V], prolongation of the
+ *              coarse part of the Ritz vectors and the final update, width q_e
+ *              (0 .. nlev-2);
  *   FP64_WIDE  restriction of [A V | M V], width 2 q_e (1 .. nlev-2).
  * set_cpt: EINVAL for an invalid kind, level or cpt; drops a captured step.
  * get_cpt: the cpt in effect (the built-in rule's when none is set). */

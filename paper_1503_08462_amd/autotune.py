@@ -5,13 +5,15 @@ each lane cpt consecutive columns.  Which cpt is fastest depends on the level
 (rows, nonzeros per row, how much of the gathered block stays in cache), the
 block width and the precision, so it is chosen per (kind, level) by timing the
 candidates on the bound context: the V-cycle kernels of a level, the FP64
-kernels of the correction level (dual SpMM, prolongation, final update) and the
+kernels of the correction level (outer residual, dual SpMM, prolongation, final
+update) and the
 FP64 restriction of [A V | M V].  The winner must beat the built-in choice by a
 margin, otherwise the built-in choice stays.  Results go to an on-disk JSON
 cache keyed by device architecture, precision, smoother, kind, level size,
 nonzeros and width, so a later context of the same shape is configured without
-timing.  The choice never changes results (each output entry is the same
-ordered sum for every cpt), only speed.
+timing.  The choice never changes the iterates (each vector entry is the same
+ordered sum for every cpt); only the residual norms can differ in the last
+bits, through the order of their row sums.
 """
 import json
 import os

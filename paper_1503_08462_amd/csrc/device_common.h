@@ -159,6 +159,36 @@ __device__ __forceinline__ dbl4 mfma_tn16(const FX &X, const FY &Y, int K) {
     return a0 + a1;
 }
 
+// mfma_tn16 with the operands of eight steps (32 rows) loaded ahead of the
+// products: for long K read from memory, where load latency dominates.
+template <class FX, class FY>
+__device__ __forceinline__ dbl4 mfma_tn16_deep(const FX &X, const FY &Y, int K) {
+    const int lane = threadIdx.x & (kWave - 1), kk = lane >> 4, c = lane & 15;
+    dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+    int base = 0;
+    for (; base + 32 <= K; base += 32) {
+        double x[8], y[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            x[t] = X(base + kk + 4 * t, c);
+            y[t] = Y(base + kk + 4 * t, c);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t], y[t], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x[t + 1], y[t + 1], a1, 0, 0, 0);
+        }
+    }
+    for (; base < K; base += 4) {
+        const int i0 = base + kk;
+        const int ic = i0 < K ? i0 : K - 1;  // clamped: never reads past row K - 1
+        double x = X(ic, c), y = Y(ic, c);
+        if (i0 >= K) x = y = 0.0;
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, a0, 0, 0, 0);
+    }
+    return a0 + a1;
+}
+
 // out(i, j, sum_k X(k, i) Y(k, j)) for i < mi, j < mj, k < K, in 16 x 16 tiles
 // on the matrix cores.  X(k, a) and Y(k, b) must return zero for a >= mi
 // (b >= mj); `out` receives each finished entry once.  With fewer tiles than

@@ -190,7 +190,7 @@ void plan(amg_eig_ctx *c, char *base) {
     c->rho = cv.take<double>(ld);
     int64_t maxn = 0;
     for (const Level &lv : H.lv) maxn = std::max(maxn, lv.n);
-    c->part_res = cv.take<double>(((size_t)residual_blocks(maxn, ld) + 1) * 2 * ld);
+    c->part_res = cv.take<double>(((size_t)residual_blocks_max(maxn, ld) + 1) * 2 * ld);
     c->part_gram = cv.take<double>((size_t)gram_blocks(maxn, ld) * 2 * ld * ld);
     c->counters = cv.take<unsigned>(16);
     if (c->tail >= 0) {
@@ -510,10 +510,10 @@ void residual(amg_eig_ctx *c, int k, int check) {
     {
         SiteScope sc(c, AMG_EIG_SITE_RESIDUAL, k);
         launch_residual<T>(c->stream, d.n, c->ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (T *)d.b,
-                           c->part_res, c->status);
+                           c->part_res, c->status, d.cpt[1]);
     }
     launch_residual_finish(c->stream, d.n, c->ld, c->part_res, c->counters, c->theta, c->rho, c->q, c->o.tol,
-                           c->status, check);
+                           c->status, check, d.cpt[1]);
 }
 
 void correction(amg_eig_ctx *c, int k) {
@@ -909,7 +909,14 @@ int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, do
                                       (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st, cpt);
             }
         } else if (kind == AMG_EIG_TUNE_FP64) {
-            // the final update writes into W here, never into the iterate U
+            // the residual reads U and writes the level's right-hand side; the
+            // final update writes into W here, never into the iterate U
+            if (c->mixed)
+                launch_residual<float>(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (float *)d.b,
+                                       c->part_res, st, cpt);
+            else
+                launch_residual<double>(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (double *)d.b,
+                                        c->part_res, st, cpt);
             launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, cpt);
             if (level >= 1) launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, e.cw, d.cw, st, cpt);
             launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, e.cw, c->V, c->sw.Xv, c->W, st, cpt);

@@ -18,14 +18,16 @@ enum : int {
 constexpr int kMaxWidth = 80;  // block width limit (LDS budget of the small kernels)
 
 // ---------------------------------------------------------- kernels_vec.hip
-int64_t residual_blocks(int64_t n, int ld);
+int64_t residual_blocks(int64_t n, int ld, int cpt);
+int64_t residual_blocks_max(int64_t n, int ld);  // the most over the columns-per-lane choices
 int64_t gram_blocks(int64_t n, int ld);
 template <typename TO>
 void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
-                     const double *m, const double *U, const double *theta, TO *R, double *part, const int *status);
+                     const double *m, const double *U, const double *theta, TO *R, double *part, const int *status,
+                     int cpt = 0);
 // the norms rho_j and the convergence flag from the partial sums of launch_residual
 void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
-                            double *rho, int q, double tol, int *status, int check);
+                            double *rho, int q, double tol, int *status, int check, int cpt = 0);
 template <typename T>
 void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
                        const T *dinv, const T *b, T *r, const int *status, int cpt = 0);

@@ -15,6 +15,8 @@
 //   k_dual_spmm     W = [A V | M V] (FP64, shared pattern)
 //   k_gram          [V^T A V | V^T M V] by a two-phase deterministic reduction
 //   k_final         U = P Y + V X_v on the correction level (recombination)
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int m, int n, int K, const T *_
     const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     if (k1 > k0)
-        acc = mfma_tn16(
+        acc = mfma_tn16_deep(
             [&](int i, int c) -> double {
                 const int col = 16 * ta + c;
                 return col < m ? (double)A[(int64_t)(k0 + i) * lda + col] : 0.0;
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(1024) void k_gemm_tn_long(int m, int n, int K, cons
     const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     if (k1 > k0)
-        acc = mfma_tn16(
+        acc = mfma_tn16_deep(
             [&](int i, int c) -> double {
                 const int col = 16 * ta + c;
                 return col < m ? (double)A[(int64_t)(k0 + i) * lda + col] : 0.0;
@@ -799,24 +801,32 @@ int pick_cpt(int width, int hint) { return cpt_valid(width, hint) ? hint : cpt_f
         }                                    \
     } while (0)
 
-int64_t residual_blocks(int64_t n, int ld) {
-    const int64_t need = row_blocks(n, ld, cpt_for(ld));
+int64_t residual_blocks(int64_t n, int ld, int cpt) {
+    const int64_t need = row_blocks(n, ld, pick_cpt(ld, cpt));
     return need < 2048 ? need : 2048;
+}
+
+int64_t residual_blocks_max(int64_t n, int ld) {  // over every columns-per-lane choice
+    int64_t best = residual_blocks(n, ld, 0);
+    for (int c = 2; c <= 8; c *= 2)
+        if (cpt_valid(ld, c)) best = std::max(best, residual_blocks(n, ld, c));
+    return best;
 }
 
 template <typename TO>
 void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
-                     const double *m, const double *U, const double *theta, TO *R, double *part, const int *status) {
+                     const double *m, const double *U, const double *theta, TO *R, double *part, const int *status,
+                     int cpt) {
     // part: 2 ld final sums, then nb x 2 ld per-block partials
-    const int64_t nb = residual_blocks(n, ld);
+    const int64_t nb = residual_blocks(n, ld, cpt);
     double *blocks = part + 2 * ld;
-    DISPATCH_CPT(ld, 0, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, ptr,
-                                        col, a, m, U, theta, R, blocks, status));
+    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld,
+                                             ptr, col, a, m, U, theta, R, blocks, status));
 }
 
 void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
-                            double *rho, int q, double tol, int *status, int check) {
-    const int64_t nb = residual_blocks(n, ld);
+                            double *rho, int q, double tol, int *status, int check, int cpt) {
+    const int64_t nb = residual_blocks(n, ld, cpt);
     hipLaunchKernelGGL(k_residual_finish, dim3(2 * ld), dim3(kBlock), 0, s, nb, ld, part + 2 * ld, part, counter,
                        theta, rho, q, tol, status, check);
 }
@@ -1031,7 +1041,8 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
                                         const T *, const T *, const T *, const T *, T *, const double *, double *,   \
                                         const int *, int);                                                                \
     template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
-                                     const double *, const double *, const double *, T *, double *, const int *);     \
+                                     const double *, const double *, const double *, T *, double *, const int *,      \
+                                     int);                                                                            \
     template void launch_cheb_pre<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,         \
                                      const T *, const T *, T *, double, const int *, int);                                \
     template void launch_level_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const T *,   \
