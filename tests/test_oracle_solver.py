@@ -143,3 +143,41 @@ def test_relative_residual_closed_form():
         want = np.sqrt((l[0] - th) ** 2 + eps ** 2 * (l[1] - th) ** 2) / (th * np.sqrt(1 + eps ** 2))
         got = o.residuals(0, np.array([th]), u)[0]
         assert abs(got / want - 1) < 1e-9
+
+
+@pytest.mark.parametrize("degree,lo", [(1, 0.25), (2, 0.25), (3, 0.1)])
+def test_chebyshev_smoother_is_the_scaled_chebyshev_polynomial(degree, lo):
+    """With b = 0 the Chebyshev smoother maps the error e to p(D^-1 A) e, where
+    p(t) = T_s((theta - t) / delta) / T_s(theta / delta) on [lo, 1] (theta, delta
+    the interval's centre and half-width, T_s the Chebyshev polynomial of the
+    first kind).  Checked against that closed form through the eigendecomposition
+    of the symmetric D^-1/2 A D^-1/2, with T_s evaluated by cos / cosh."""
+    p = configs.square(8)
+    A, M = mats(p)
+    o = Oracle(A, M, q=1, coarse_max=20, smoother="chebyshev", cheb_degree=degree, cheb_lo=lo)
+    L = o.levels[0]
+    n = p["n"]
+    E = o._smooth(L, np.zeros((n, n)), np.eye(n), backward=False)
+    Ad = L.A.toarray()
+    d = np.asarray(L.l1, dtype=float).ravel()
+    S = Ad / np.sqrt(d)[:, None] / np.sqrt(d)[None, :]
+    lam, Q = np.linalg.eigh(S)
+    assert lam.max() <= 1.0 + 1e-12 and lam.min() > 0  # the l1 scaling bounds the spectrum by 1
+
+    def cheb_t(s, x):
+        x = np.asarray(x, dtype=float)
+        out = np.empty_like(x)
+        inside = np.abs(x) <= 1
+        out[inside] = np.cos(s * np.arccos(x[inside]))
+        xo = x[~inside]
+        out[~inside] = np.sign(xo) ** s * np.cosh(s * np.arccosh(np.abs(xo)))
+        return out
+
+    theta, delta = 0.5 * (1 + lo), 0.5 * (1 - lo)
+    pl = cheb_t(degree, (theta - lam) / delta) / cheb_t(degree, np.array([theta / delta]))[0]
+    E_ref = (Q * pl) @ Q.T
+    E_ref = E_ref / np.sqrt(d)[:, None] * np.sqrt(d)[None, :]  # D^-1/2 p(S) D^1/2
+    assert np.abs(E - E_ref).max() < 1e-12
+    # the scaled polynomial is bounded by 1 / T_s(theta / delta) on [lo, 1]
+    on = (lam >= lo)
+    assert np.abs(pl[on]).max() <= 1.0 / cheb_t(degree, np.array([theta / delta]))[0] + 1e-14
