@@ -659,6 +659,10 @@ int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, i
     const int64_t N = c->dl[0].n;
     launch_fill_i32(s, ST_COUNT, 0, c->status);
     if (mode == AMG_EIG_INIT_NESTED) {
+        // the prolongated coarsest eigenvectors already approximate the wanted
+        // ones, so the first Rayleigh-Ritz step may start from them (the
+        // inertia counts still certify every eigenvalue it accepts)
+        launch_fill_i32(s, 1, 1, c->status + ST_WARM);
         // coarsest eigenpairs, then one correction on each level n-1 .. 2
         launch_copy_cols(s, dn, ld, ld, qe, c->Z, dn, c->U);
         launch_copy_f64(s, qe, c->lam, c->theta);
@@ -720,13 +724,30 @@ int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host
         if (rc) return rc;
     }
     int done = 0, conv = 0, steps = 0, rc;
+    // Steps go out in chunks between synchronisations.  Convergence of the
+    // iterate after step s shows in the residual at the start of step s + 1,
+    // and the steps after it return at once; so from the observed decay of
+    // max_{j<q} rho_j the next chunk is sized to end at the predicted step.
+    std::vector<double> rho(c->qe);
+    double rho_prev = -1.0;
+    int steps_prev = 0;
+    int chunk = 4;
     while (!conv && done < max_steps) {
-        const int chunk = std::min(4, max_steps - done);
+        chunk = std::max(1, std::min(chunk, max_steps - done));
         rc = enqueue_steps(c, chunk);
         if (rc) return rc;
         done += chunk;
-        rc = amg_eig_progress(c, nullptr, nullptr, &steps, &conv);
+        rc = amg_eig_progress(c, nullptr, rho.data(), &steps, &conv);
         if (rc) return rc;
+        const double r = *std::max_element(rho.begin(), rho.begin() + c->q);
+        chunk = 4;
+        if (rho_prev > 0.0 && r > 0.0 && r < rho_prev && steps > steps_prev) {
+            const double rate = std::pow(r / rho_prev, 1.0 / (steps - steps_prev));
+            const double need = std::log(c->o.tol / r) / std::log(rate);  // steps until rho <= tol
+            if (need < 4.0) chunk = std::max(1, (int)std::ceil(need));
+        }
+        rho_prev = r;
+        steps_prev = steps;
     }
     if (!conv) {  // residual of the last iterate
         if (c->mixed)
