@@ -485,6 +485,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
     double *dtl = lam + dn;                            // ldp x ldp when dt_in_lds
     double *Lm = dtl + (dt_in_lds ? ldp * ldp : 0);    // ld x ls: multipliers of the factorisation
     double *red = Lm + ld * ls;                        // 4 x 256 partial tiles + 64 cross-wavefront sums
+    double *vec0 = red + 1024 + 64;                    // dn + ldp: the starting vector
     const double *dt = dt_in_lds ? dtl : w.Dt;
     __shared__ int ipiv[kMaxWidth];
     __shared__ unsigned long long tim[8];  // solver statistics: phase clocks
@@ -734,29 +735,54 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         }
         __syncthreads();
         normalise(vec);
-        rayleigh(vec, rho, res);
-        for (int it = 0; it < 3; ++it) {
-            if (res <= kRqiTol * fabs(rho) || !(rho > 0.0 && rho < cap)) break;
-            note(rho, factor(rho));
-            solve(vec);
-            normalise(vec);
+        for (int i = tid; i < dn + r; i += nthr) vec0[i] = vec[i];
+        // up to two attempts: the second from the starting vector with the
+        // eigenvector found by the first projected out, when the first settled
+        // on a neighbouring eigenvalue (a close pair whose starting vector
+        // mixed both)
+        for (int attempt = 0; attempt < 2 && !done; ++attempt) {
             rayleigh(vec, rho, res);
-        }
-        if (res <= kRqiTol * fabs(rho) && rho > 0.0 && rho < cap) {
+            for (int it = 0; it < 3; ++it) {
+                if (res <= kRqiTol * fabs(rho) || !(rho > 0.0 && rho < cap)) break;
+                note(rho, factor(rho));
+                solve(vec);
+                normalise(vec);
+                rayleigh(vec, rho, res);
+            }
+            if (!(res <= kRqiTol * fabs(rho) && rho > 0.0 && rho < cap)) break;
             // ends more than the residual away from rho, counted if not yet known
             const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
+            // (an end that would not isolate eigenvalue k only tightens the bracket)
             if (!(have_lo && nulo == k && rho - lo > res)) {
                 const double l0 = rho - span;
                 const int c = factor(l0);
-                if (c <= k) force(l0, c); else note(l0, c);
+                if (c == k) force(l0, c); else note(l0, c);
             }
             if (!(have_hi && nuhi == k + 1 && hi - rho > res)) {
                 const double h0 = fmin(rho + span, cap);
                 const int c = factor(h0);
-                if (c >= k + 1) force(h0, c); else note(h0, c);
+                if (c == k + 1) force(h0, c); else note(h0, c);
             }
             done = have_lo && have_hi && nulo == k && nuhi == k + 1 && rho > lo && rho < hi && rho - lo > res &&
                    hi - rho > res;
+            if (done || attempt == 1 || !((have_hi && hi < rho) || (have_lo && lo > rho))) break;
+            double d = 0.0;
+            for (int i = tid; i < dn + r; i += nthr) d += vec[i] * vec0[i];
+            d = bsum(d);
+            __syncthreads();
+            double s2 = 0.0;
+            for (int i = tid; i < dn + r; i += nthr) {
+                const double v = vec0[i] - d * vec[i];
+                vec[i] = v;
+                s2 += v * v;
+            }
+            s2 = bsum(s2);
+            if (!(s2 > 1e-12)) {  // nothing left: a pseudo-random start instead
+                __syncthreads();
+                for (int i = tid; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
+            }
+            __syncthreads();
+            normalise(vec);
         }
     } else {
         for (int i = tid; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
@@ -786,8 +812,11 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         __syncthreads();
         hi = have_hi ? hi : cap;                // not counted yet: at least k + 1 by interlacing
         nuhi = have_hi ? nuhi : (1 << 30);
-        lo = have_lo ? lo : glo - fabs(glo) * 1e-14 - 1e-300;
-        nulo = have_lo ? nulo : 0;              // no eigenvalue below a Gershgorin bound
+        // no eigenvalue below a Gershgorin bound, nor below 0: H is the
+        // projection of the positive definite A in an M-orthonormal basis
+        const double g0 = glo - fabs(glo) * 1e-14 - 1e-300;
+        lo = have_lo ? lo : (g0 > 0.0 ? g0 : 0.0);
+        nulo = have_lo ? nulo : 0;
     }
     // ---- isolate by bisection
     for (int it = 0; it < 200 && !done; ++it) {
@@ -1138,7 +1167,7 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, 
     const size_t ldp = ((size_t)w.ld + 15) & ~(size_t)15, dn = w.dn;
     const int threads = kB;
     const size_t ld = w.ld, dtl = ld <= 32 ? ldp * ldp : 0;  // the kernel's layout
-    const size_t base = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64;
+    const size_t base = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64 + dn + ldp;
     const int ct_in_lds = (base + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
     const size_t lds = (base + (ct_in_lds ? dn * ldp : 0)) * sizeof(double);
     hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta, ct_in_lds);
