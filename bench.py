@@ -83,7 +83,7 @@ def serving(args):
     def contexts(prec):
         return [ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
                            ae.defaults(coarse_max=512, qe=p["qe"], precision=prec, tol=tol,
-                                       use_graph=args.graph if prec == ae.PREC_MIXED else 0)) for p in probs]
+                                       use_graph=args.serve_graph if prec == ae.PREC_MIXED else 0)) for p in probs]
 
     def solo(prec):
         cs = contexts(prec)
@@ -160,7 +160,7 @@ def serving(args):
                                % (len(probs), min(ns), max(ns), args.rate),
                    "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
                    "streams": args.streams, "steps_per_round": args.steps_per_round, "tol": tol,
-                   "graph_steps": bool(args.graph)},
+                   "graph_steps": bool(args.serve_graph)},
         "p50_ms": lat["p50_s"] * 1e3,
         "p99_ms": lat["p99_s"] * 1e3,
         "peak_resident_gb": srv.peak_in_use / 2 ** 30,
@@ -196,7 +196,9 @@ def main():
     ap.add_argument("--coarse-max", type=int, default=0, help="override the workload's coarsest-level bound")
     ap.add_argument("--qe", type=int, default=0, help="override the workload's block width")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1,
+                    help="replay captured correction steps (the second step of each chunk of three or more runs "
+                         "eagerly and carries the per-kernel event timing)")
     ap.add_argument("--tune", type=int, default=1,
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev"])
@@ -206,6 +208,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=8.0, help="serving stream: device memory budget")
     ap.add_argument("--streams", type=int, default=8, help="serving stream: stream pool size")
     ap.add_argument("--steps-per-round", type=int, default=2, help="serving stream: corrections per round")
+    ap.add_argument("--serve-graph", type=int, default=0, help="serving stream: replay captured steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")
@@ -329,7 +332,9 @@ def main():
         "config": {"workload": wl["name"], "N": int(p["n"]), "q": q, "qe": info["qe"],
                    "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
                    "smoother": ("l1-jacobi" if args.smoother == "l1jacobi" else "chebyshev degree 2 on [0.25, 1]")
-                               + " V(1,1)", "start": "nested (Algorithm 3.2)"},
+                               + " V(1,1)", "start": "nested (Algorithm 3.2)",
+                   "steps_launch": ("captured hipGraph replays; the second step of each enqueued chunk of three "
+                                    "or more eager and event-timed" if args.graph else "eager")},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "corrections_per_solve": float(np.mean(steps)),

@@ -536,7 +536,12 @@ void drop_graph(amg_eig_ctx *c) {
 
 int enqueue_steps(amg_eig_ctx *c, int steps) {
     for (int i = 0; i < steps; ++i) {
-        if (c->o.use_graph && c->stream) {
+        // with site timing on, the second step of each enqueued chunk of three or
+        // more runs eagerly (HIP events cannot be captured into the graph): it
+        // follows a replay, so the device is busy, and it is never the step that
+        // only detects convergence at the end of a solve
+        const bool timed_eager = c->timing && steps >= 3 && i == 1;
+        if (c->o.use_graph && c->stream && !timed_eager) {
             if (!c->graph_exec) {
                 const bool t = c->timing;
                 c->timing = false;
