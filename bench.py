@@ -120,6 +120,7 @@ def serving(args):
     fps = sorted(c.footprint() for c in cs)
     budget = int(args.budget_gb * 2 ** 30)
     srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=args.steps_per_round,
+                 max_active=args.max_active if args.max_active > 0 else None,
                  context_factory=lambda p, o: cs[p["_k"]])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -160,6 +161,7 @@ def serving(args):
                                % (len(probs), min(ns), max(ns), args.rate),
                    "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
                    "streams": args.streams, "steps_per_round": args.steps_per_round, "tol": tol,
+                   "max_active": args.max_active or None,
                    "graph_steps": bool(args.serve_graph)},
         "p50_ms": lat["p50_s"] * 1e3,
         "p99_ms": lat["p99_s"] * 1e3,
@@ -209,6 +211,8 @@ def main():
     ap.add_argument("--streams", type=int, default=8, help="serving stream: stream pool size")
     ap.add_argument("--steps-per-round", type=int, default=2, help="serving stream: corrections per round")
     ap.add_argument("--serve-graph", type=int, default=0, help="serving stream: replay captured steps")
+    ap.add_argument("--max-active", type=int, default=0, help="serving stream: requests on the device at once "
+                                                                 "(0: the memory budget alone decides)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")

@@ -39,6 +39,9 @@ class Server:
 
     budget_bytes:     device memory the admitted requests may hold together
     n_streams:        stream pool; request k of a round uses stream k mod n_streams
+    max_active:       at most this many requests on the device at once (None: only
+                      the budget limits admission); fewer concurrent requests
+                      finish sooner each, which lowers the latency percentiles
     steps_per_round:  corrections enqueued per request between convergence checks
     context_factory:  (problem dict, opts) -> context; the default builds a
                       library Context (tests pass stand-ins)
@@ -47,9 +50,10 @@ class Server:
     """
 
     def __init__(self, budget_bytes, n_streams=4, steps_per_round=2, opts=None, context_factory=None,
-                 batch_fn=None, stream_factory=None, clock=time.perf_counter):
-        if budget_bytes <= 0 or n_streams < 1 or steps_per_round < 1:
-            raise ValueError("budget, stream count and steps per round must be positive")
+                 batch_fn=None, stream_factory=None, clock=time.perf_counter, max_active=None):
+        if budget_bytes <= 0 or n_streams < 1 or steps_per_round < 1 or (max_active is not None and max_active < 1):
+            raise ValueError("budget, stream count, steps per round and active limit must be positive")
+        self.max_active = max_active
         self.budget = int(budget_bytes)
         self.steps_per_round = int(steps_per_round)
         self.opts = opts
@@ -90,7 +94,8 @@ class Server:
         return rid
 
     def _admit(self):
-        while self.queue and self.in_use + self.queue[0].footprint <= self.budget:
+        while (self.queue and self.in_use + self.queue[0].footprint <= self.budget
+               and (self.max_active is None or len(self.active) < self.max_active)):
             req = self.queue.pop(0)
             req.stream = self.streams[self._next_stream % len(self.streams)]
             self._next_stream += 1

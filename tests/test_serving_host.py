@@ -97,3 +97,17 @@ def test_step_limit_ends_a_request_unconverged():
     res = srv.run()
     assert res[rid]["steps"] == 6 and not res[rid]["converged"]
     assert res[rid]["lam"].shape == (2,)
+
+
+def test_active_limit_caps_concurrency_and_keeps_order():
+    FakeCtx.log = []
+    srv, batches = make_server(1000, steps_per_round=1, max_active=2)
+    for name, need in [("a", 3), ("b", 1), ("c", 2), ("d", 1)]:
+        srv.submit(prob(name, 10, need))
+    res = srv.run()
+    assert all(len(b) <= 2 for b in batches)
+    assert batches[0] == ["a", "b"]
+    assert batches[1] == ["a", "c"]  # c joins when b leaves
+    binds = [n for k, n in FakeCtx.log if k == "bind"]
+    assert binds == ["a", "b", "c", "d"]
+    assert all(r["converged"] for r in res.values())
