@@ -194,8 +194,24 @@ __device__ void bk_solve(const double *S, const double *Lm, int r, int ls, const
             if (lane < hi) f0 -= Lm[rw * ls + lane] * s;
             if (lane + kWave < hi) f1 -= Lm[rw * ls + lane + kWave] * s;
         };
+        // the pivot record and the diagonal blocks in registers (entry p in lane
+        // p mod 64), read by lane reads instead of one shared-memory load per step
+        const int iv0 = lane < r ? ipiv[lane] : 0, iv1 = lane + kWave < r ? ipiv[lane + kWave] : 0;
+        const double dg0 = lane < r ? S[lane * ls + lane] : 0.0;
+        const double dg1 = lane + kWave < r ? S[(lane + kWave) * ls + lane + kWave] : 0.0;
+        const double sb0 = lane + 1 < r ? S[(lane + 1) * ls + lane] : 0.0;
+        const double sb1 = lane + kWave + 1 < r ? S[(lane + kWave + 1) * ls + lane + kWave] : 0.0;
+        auto piv = [&](int p) __attribute__((always_inline)) -> int {
+            return __builtin_amdgcn_readlane(p < kWave ? iv0 : iv1, p & (kWave - 1));
+        };
+        auto diag = [&](int p) __attribute__((always_inline)) -> double {  // S[p][p]
+            return lane_bcast(p < kWave ? dg0 : dg1, p & (kWave - 1));
+        };
+        auto subd = [&](int p) __attribute__((always_inline)) -> double {  // S[p + 1][p]
+            return lane_bcast(p < kWave ? sb0 : sb1, p & (kWave - 1));
+        };
         for (int p = 0; p < r;) {  // interchanges in order
-            const int ip = ipiv[p];
+            const int ip = piv(p);
             if (ip >= 0) {
                 swap(p, ip);
                 p += 1;
@@ -205,7 +221,7 @@ __device__ void bk_solve(const double *S, const double *Lm, int r, int ls, const
             }
         }
         for (int p = 0; p < r;) {  // L y = f
-            if (ipiv[p] >= 0) {
+            if (piv(p) >= 0) {
                 axpy_col(p + 1, r, p, get(p));
                 p += 1;
             } else {
@@ -216,13 +232,13 @@ __device__ void bk_solve(const double *S, const double *Lm, int r, int ls, const
             }
         }
         for (int p = 0; p < r;) {  // D solve; singular pivots are replaced by a tiny value
-            if (ipiv[p] >= 0) {
-                double d = S[p * ls + p];
+            if (piv(p) >= 0) {
+                double d = diag(p);
                 if (d == 0.0) d = 1e-300;
                 put(p, get(p) / d);
                 p += 1;
             } else {
-                const double a = S[p * ls + p], b = S[(p + 1) * ls + p], c = S[(p + 1) * ls + p + 1];
+                const double a = diag(p), b = subd(p), c = diag(p + 1);
                 const double det = a * c - b * b;
                 const double y0 = get(p), y1 = get(p + 1);
                 put(p, (c * y0 - b * y1) / det);
@@ -231,7 +247,7 @@ __device__ void bk_solve(const double *S, const double *Lm, int r, int ls, const
             }
         }
         for (int p = r - 1; p >= 0;) {  // L^T w = y, last block first
-            if (ipiv[p] < 0) {
+            if (piv(p) < 0) {
                 const int p0 = p - 1;
                 const double w0 = get(p0), w1 = get(p);
                 axpy_row(p0, p0, w0);
@@ -243,7 +259,7 @@ __device__ void bk_solve(const double *S, const double *Lm, int r, int ls, const
             }
         }
         for (int p = r - 1; p >= 0;) {  // undo the interchanges in reverse order
-            const int ip = ipiv[p];
+            const int ip = piv(p);
             if (ip < 0) {
                 swap(p, -ip - 1);
                 p -= 2;
