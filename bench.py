@@ -121,7 +121,8 @@ def serving(args):
     budget = int(args.budget_gb * 2 ** 30)
     srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=args.steps_per_round,
                  max_active=args.max_active if args.max_active > 0 else None,
-                 context_factory=lambda p, o: cs[p["_k"]])
+                 context_factory=lambda p, o: cs[p["_k"]],
+                 batch_fn=(lambda cs_, steps: ae.correct_batch_joint(cs_, steps)) if args.joint else None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
@@ -162,7 +163,7 @@ def serving(args):
                    "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
                    "streams": args.streams, "steps_per_round": args.steps_per_round, "tol": tol,
                    "max_active": args.max_active or None,
-                   "graph_steps": bool(args.serve_graph)},
+                   "graph_steps": bool(args.serve_graph), "joint_small_solves": bool(args.joint)},
         "p50_ms": lat["p50_s"] * 1e3,
         "p99_ms": lat["p99_s"] * 1e3,
         "peak_resident_gb": srv.peak_in_use / 2 ** 30,
@@ -213,6 +214,8 @@ def main():
     ap.add_argument("--serve-graph", type=int, default=0, help="serving stream: replay captured steps")
     ap.add_argument("--max-active", type=int, default=0, help="serving stream: requests on the device at once "
                                                                  "(0: the memory budget alone decides)")
+    ap.add_argument("--joint", type=int, default=0, help="serving stream: solve the members' small eigenproblems "
+                                                         "in shared launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")

@@ -156,6 +156,21 @@ int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host
  * hierarchy and block).  Errors: ESTATE, EHIP. */
 int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_stream);
 
+/* Batching form of the correction (Algorithm 3.1, steps of eq (3.3)): enqueue
+ * `steps` correction steps for each of n initialised contexts, with the small
+ * eigenproblem of every member solved jointly.  Per step, each member's
+ * residual, V-cycle and projection products run on its own stream; the lead
+ * stream (that of cs[0]) then waits for all of them and solves the n small
+ * pencils in three launches over a device-side table of per-request
+ * descriptors (one workgroup per member for the pencil and the Ritz polish, qe
+ * workgroups per member for the eigenvalues, members of different d_n and qe
+ * side by side, up to 64 per launch); the members' streams wait for that and
+ * recombine.  Results are bitwise those of amg_eig_correct on each member.
+ * Launches are eager (no graph); members may share streams.  A context may
+ * appear once.  Errors: EINVAL (NULL, duplicate), ESTATE (not initialised),
+ * EHIP. */
+int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps);
+
 /* Sizes: block width qe, number of levels, and the dimension of each level
  * (dims[nlev], may be NULL). */
 int amg_eig_info(const amg_eig_ctx *c, int *qe, int *nlevels, int64_t *dims);

@@ -32,7 +32,8 @@ INIT_NESTED, INIT_RANDOM, INIT_USER = 0, 1, 2
 
 EXPORTED = [
     "amg_eig_opts_default", "amg_eig_setup", "amg_eig_footprint", "amg_eig_bind", "amg_eig_init",
-    "amg_eig_correct", "amg_eig_progress", "amg_eig_solve", "amg_eig_correct_batch", "amg_eig_info",
+    "amg_eig_correct", "amg_eig_progress", "amg_eig_solve", "amg_eig_correct_batch", "amg_eig_correct_batch_joint",
+    "amg_eig_info",
     "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting",
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
@@ -68,6 +69,7 @@ _sig = {
     "amg_eig_progress": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "amg_eig_solve": (_i, [_vp, _d, _i, _vp, _vp, _i64]),
     "amg_eig_correct_batch": (_i, [_vp, _i, _i, _vp]),
+    "amg_eig_correct_batch_joint": (_i, [_vp, _i, _i]),
     "amg_eig_info": (_i, [_vp, _vp, _vp, _vp]),
     "amg_eig_level_matrix": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "amg_eig_level_prolongation": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
@@ -275,6 +277,15 @@ def correct_batch(contexts, steps=1, stream=None):
     arr = (ctypes.c_void_p * len(contexts))(*[c._c.value for c in contexts])
     s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
     rc = _lib.amg_eig_correct_batch(arr, len(contexts), steps, s)
+    if rc < 0:
+        raise AmgEigError(rc)
+
+
+def correct_batch_joint(contexts, steps=1):
+    """Correction steps for several requests with their small eigenproblems
+    solved in shared launches (each member on its own bound stream)."""
+    arr = (ctypes.c_void_p * max(1, len(contexts)))(*[c._c.value for c in contexts])
+    rc = _lib.amg_eig_correct_batch_joint(arr, len(contexts), steps)
     if rc < 0:
         raise AmgEigError(rc)
 

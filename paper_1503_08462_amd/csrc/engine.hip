@@ -75,6 +75,12 @@ struct amg_eig_ctx {
     unsigned *counters = nullptr;
     int *status = nullptr;
     SmallWork sw;
+    // the small-eigensolver descriptor of this request (device copy for the
+    // batched launches) and its LDS sizes; an event for joining batch streams
+    SmallItem *item_dev = nullptr;
+    SmallItem item_host;
+    SmallLds small_lds;
+    hipEvent_t join_ev = nullptr;
     // host staging kept alive until the upload completes
     std::vector<std::vector<char>> staging;
     hipGraph_t graph = nullptr;
@@ -220,6 +226,7 @@ void plan(amg_eig_ctx *c, char *base) {
     w.Xv = cv.take<double>((size_t)ld * ld);
     w.status = c->status;
     w.diag = cv.take<int>(5 * kMaxWidth + 8);
+    c->item_dev = cv.take<SmallItem>(1);
     c->need = cv.off + 256;
 }
 
@@ -332,6 +339,11 @@ struct SiteScope {
         (void)hipEventRecord(st.ev[st.used++], c->stream);
     }
 };
+
+// one event of a start/stop pair, for a site that spans several functions
+void site_mark(amg_eig_ctx *c, int site, int level) {
+    if (c->timing && level == 0) SiteScope(c, site, -1).record();
+}
 
 void collect_sites(amg_eig_ctx *c) {
     for (auto &st : c->sites) {
@@ -448,7 +460,9 @@ void build_tail(amg_eig_ctx *c) {
     }
 }
 
-void rayleigh_ritz(amg_eig_ctx *c, int k) {
+// Rayleigh-Ritz on level k in three parts: the products that form the small
+// pencil (up to Z^T B), the small eigensolver, and the recombination
+void rr_front(amg_eig_ctx *c, int k) {
     const int L = (int)c->dl.size(), ld = c->ld, dn = c->H.dn;
     hipStream_t s = c->stream;
     const int *st = c->status;
@@ -472,17 +486,31 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
         launch_spmm<double>(s, b.n, 2 * ld, a.pt_ptr, a.pt_col, a.pt64, src, b.cw, st, b.cpt[2]);
         src = b.cw;
     }
+    site_mark(c, AMG_EIG_SITE_SMALL, k);  // the small site spans Z^T B .. Z X_c
+    if (tail) {
+        const int nt = (int)c->dl[bottom].n;
+        launch_gemm_tn_long<double>(s, dn, 2 * ld, nt, c->Zk, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+    } else {
+        launch_gemm_tn<double>(s, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+    }
+}
+
+constexpr double kRankTol = 1e-13;
+
+void rr_small(amg_eig_ctx *c, int k) {
+    launch_pencil(c->stream, c->sw, kRankTol);
+    launch_arrow_eig(c->stream, c->sw, c->qe, c->theta, k == 0 ? 1 : 0);
+}
+
+void rr_back(amg_eig_ctx *c, int k) {
+    const int L = (int)c->dl.size(), ld = c->ld, dn = c->H.dn;
+    hipStream_t s = c->stream;
+    const int *st = c->status;
+    DevLevel &d = c->dl[k];
+    const bool tail = c->tail >= 0 && k < c->tail;
+    const int bottom = tail ? c->tail : L - 1;
     const double *y;
     {
-        SiteScope sc(c, AMG_EIG_SITE_SMALL, k);
-        if (tail) {
-            const int nt = (int)c->dl[bottom].n;
-            launch_gemm_tn_long<double>(s, dn, 2 * ld, nt, c->Zk, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
-        } else {
-            launch_gemm_tn<double>(s, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
-        }
-        launch_pencil(s, c->sw, 1e-13);
-        launch_arrow_eig(s, c->sw, c->qe, c->theta, k == 0 ? 1 : 0);
         if (tail) {  // Y on the tail level = Zk X_c
             double *yt = c->dl[bottom].cw;
             launch_gemm_tn_long<double>(s, (int)c->dl[bottom].n, ld, dn, c->Zkt, (int)c->dl[bottom].n, c->sw.Xc,
@@ -492,6 +520,7 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
             launch_gemm_tn<double>(s, dn, ld, dn, c->Zt, dn, c->sw.Xc, ld, c->Yn, ld, st);
             y = c->Yn;
         }
+        site_mark(c, AMG_EIG_SITE_SMALL, k);
     }
     for (int l = bottom - 1; l > k; --l) {
         DevLevel &a = c->dl[l];
@@ -502,6 +531,12 @@ void rayleigh_ritz(amg_eig_ctx *c, int k) {
         SiteScope sc(c, AMG_EIG_SITE_FINAL, k);
         launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, y, c->V, c->sw.Xv, c->U, st, d.cpt[1]);
     }
+}
+
+void rayleigh_ritz(amg_eig_ctx *c, int k) {
+    rr_front(c, k);
+    rr_small(c, k);
+    rr_back(c, k);
 }
 
 template <typename T>
@@ -516,7 +551,7 @@ void residual(amg_eig_ctx *c, int k, int check) {
                            c->status, check, d.cpt[1]);
 }
 
-void correction(amg_eig_ctx *c, int k) {
+void correction_front(amg_eig_ctx *c, int k) {
     if (c->mixed) {
         residual<float>(c, k, k == 0);
         vcycle<float>(c, k);
@@ -524,7 +559,13 @@ void correction(amg_eig_ctx *c, int k) {
         residual<double>(c, k, k == 0);
         vcycle<double>(c, k);
     }
-    rayleigh_ritz(c, k);
+    rr_front(c, k);
+}
+
+void correction(amg_eig_ctx *c, int k) {
+    correction_front(c, k);
+    rr_small(c, k);
+    rr_back(c, k);
 }
 
 void drop_graph(amg_eig_ctx *c) {
@@ -640,6 +681,9 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     if (rc) return rc;
     launch_fill_i32(c->stream, ST_COUNT, 0, c->status);
     launch_fill_i32(c->stream, 5 * kMaxWidth + 8, 0, c->sw.diag);
+    small_layout(c->sw, c->qe, c->theta, 1, &c->item_host, &c->small_lds);
+    rc = put(c, c->item_dev, &c->item_host, sizeof(SmallItem));
+    if (rc) return rc;
     std::vector<unsigned> zero(16, 0u);
     rc = upload_vec(c, c->counters, zero);
     if (rc) return rc;
@@ -787,6 +831,56 @@ int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_st
     return AMG_EIG_OK;
 }
 
+int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps) {
+    if (!cs || n < 0 || steps < 0) return AMG_EIG_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        amg_eig_ctx *c = cs[i];
+        if (!c) return AMG_EIG_EINVAL;
+        if (!c->initialised) return fail(c, AMG_EIG_ESTATE, "batch member not initialised");
+        for (int j = 0; j < i; ++j)
+            if (cs[j] == c) return fail(c, AMG_EIG_EINVAL, "context listed twice in a batch");
+        if (!c->join_ev) HIPCHK(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    if (n == 0 || steps == 0) return AMG_EIG_OK;
+    amg_eig_ctx *lead = cs[0];
+    hipStream_t ls = lead->stream;
+    // the other streams of the batch, each once
+    std::vector<amg_eig_ctx *> others;
+    for (int i = 0; i < n; ++i) {
+        bool seen = cs[i]->stream == ls;
+        for (amg_eig_ctx *o : others) seen = seen || o->stream == cs[i]->stream;
+        if (!seen) others.push_back(cs[i]);
+    }
+    for (int step = 0; step < steps; ++step) {
+        for (int i = 0; i < n; ++i) correction_front(cs[i], 0);
+        for (amg_eig_ctx *o : others) {  // the lead stream waits for every front part
+            HIPCHK(o, hipEventRecord(o->join_ev, o->stream));
+            HIPCHK(lead, hipStreamWaitEvent(ls, o->join_ev, 0));
+        }
+        for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+            const int m = std::min(n - i0, kMaxBatch);
+            SmallTable t{};
+            SmallLds lds;
+            t.n = m;
+            t.first[0] = 0;
+            for (int j = 0; j < m; ++j) {
+                const amg_eig_ctx *c = cs[i0 + j];
+                t.item[j] = c->item_dev;
+                t.first[j + 1] = t.first[j] + c->qe;
+                lds.pencil = std::max(lds.pencil, c->small_lds.pencil);
+                lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
+                lds.rr = std::max(lds.rr, c->small_lds.rr);
+            }
+            launch_small_batch(ls, t, lds, kRankTol);
+        }
+        HIPCHK(lead, hipEventRecord(lead->join_ev, ls));
+        for (amg_eig_ctx *o : others) HIPCHK(o, hipStreamWaitEvent(o->stream, lead->join_ev, 0));
+        for (int i = 0; i < n; ++i) rr_back(cs[i], 0);
+    }
+    HIPCHK(lead, hipGetLastError());
+    return AMG_EIG_OK;
+}
+
 int amg_eig_info(const amg_eig_ctx *c, int *qe, int *nlevels, int64_t *dims) {
     if (!c) return AMG_EIG_EINVAL;
     if (qe) *qe = c->qe;
@@ -843,6 +937,7 @@ int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld) {
 void amg_eig_destroy(amg_eig_ctx *c) {
     if (!c) return;
     drop_graph(c);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto &st : c->sites)
         for (hipEvent_t e : st.ev) (void)hipEventDestroy(e);
     delete c;

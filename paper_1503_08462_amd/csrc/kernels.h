@@ -116,6 +116,27 @@ struct SmallWork {
     int *diag = nullptr;          // 4 * kMaxWidth + 8 counters (solver statistics)
 };
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);
+// one request's small-eigensolver launch parameters, kept in device memory for
+// the batched launches
+struct SmallItem {
+    SmallWork w;
+    double *theta = nullptr;  // Ritz values: previous on entry, new on exit
+    int qe = 0, final_level = 0;
+    int fg_in_lds = 0, ct_in_lds = 0, use_lds = 0;
+};
+struct SmallLds {
+    size_t pencil = 0, bisect = 0, rr = 0;  // dynamic LDS bytes per kernel
+};
+void small_layout(const SmallWork &w, int qe, double *theta, int final_level, SmallItem *it, SmallLds *lds);
+constexpr int kMaxBatch = 64;
+struct SmallTable {
+    const SmallItem *item[kMaxBatch];  // device addresses
+    int first[kMaxBatch + 1];          // eigenvalue workgroups of member m: first[m] .. first[m+1]-1
+    int n;
+};
+// pencil, eigenpairs and Ritz polish of every member of the table, three
+// launches in all; lds holds the largest size over the members
+void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol);
 // eigenpairs of H, Ritz polish and recombination coefficients; theta holds the
 // previous Ritz values on entry and the new ones on exit
 void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level);

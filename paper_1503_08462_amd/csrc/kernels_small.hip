@@ -294,7 +294,7 @@ __device__ __forceinline__ double start_entry(int k, int i) {
 // thread from the shared diagonal (no broadcast through shared memory).
 constexpr int kRedSmall = 3 * 4 * 256;
 
-__global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, int fg_in_lds) {
+__device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg_in_lds) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, tid = threadIdx.x, nthr = blockDim.x;
@@ -479,11 +479,11 @@ __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, in
 // lies in the isolating bracket with ||H x - rho x|| <= kRqiTol |rho| and more
 // than that residual away from both ends, which pins it to the bracketed
 // eigenvalue.
-__global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
-                                                      int ct_in_lds) {
+__device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__restrict__ theta_prev, int ct_in_lds,
+                                                  int k, int nk) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
-    const int ld = w.ld, dn = w.dn, k = blockIdx.x;
+    const int ld = w.ld, dn = w.dn;
     const int r = w.status[ST_RANK];
     const int ldp = (ld + 15) & ~15;
     const int ls = ld + 1;
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
         sigma = inside ? rho : 0.5 * (lo + hi);
         if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;
     }
-    if (tid == 0 && w.diag && (k == 0 || k == gridDim.x - 1)) {
+    if (tid == 0 && w.diag && (k == 0 || k == nk - 1)) {
         tim[5] = wall_clock64() - t_begin;
         int *slot = w.diag + (k == 0 ? 5 * kMaxWidth - 8 : 3 * kMaxWidth);
         for (int j = 0; j < 6; ++j) atomicAdd(&slot[j], (int)tim[j]);
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
 // code works on the global buffers.
 constexpr int kRed = kRedSmall;
 
-__global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_lds, double *theta_out, int final_level) {
+__device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, double *theta_out, int final_level) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
@@ -1169,30 +1169,88 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
     }
 }
 
+// ------------------------------------------------------------ kernels
+__global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, int fg_in_lds) {
+    pencil_body(w, rank_tol, fg_in_lds);
+}
+
+__global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
+                                                      int ct_in_lds) {
+    arrow_bisect_body(w, theta_prev, ct_in_lds, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_lds, double *theta_out, int final_level) {
+    arrow_rr_body(w, qe, use_lds, theta_out, final_level);
+}
+
+// The same three steps for several requests in one launch each: workgroup b of
+// the pencil and Rayleigh-Ritz kernels serves member b of the table, and the
+// eigenvalue workgroups of member m are blocks first[m] .. first[m + 1] - 1.
+// Every member's descriptor (pointers into its own workspace, widths, LDS
+// layout flags) lives in device memory; the launch takes the largest LDS size
+// any member needs.
+__global__ __launch_bounds__(256) void k_pencil_batch(SmallTable t, double rank_tol) {
+    const SmallItem *it = t.item[blockIdx.x];
+    pencil_body(it->w, rank_tol, it->fg_in_lds);
+}
+
+__global__ __launch_bounds__(256) void k_arrow_bisect_batch(SmallTable t) {
+    int m = 0;
+    while (m + 1 < t.n && t.first[m + 1] <= (int)blockIdx.x) ++m;
+    const SmallItem *it = t.item[m];
+    arrow_bisect_body(it->w, it->theta, it->ct_in_lds, (int)blockIdx.x - t.first[m], it->qe);
+}
+
+__global__ __launch_bounds__(256) void k_arrow_rr_batch(SmallTable t) {
+    const SmallItem *it = t.item[blockIdx.x];
+    arrow_rr_body(it->w, it->qe, it->use_lds, it->theta, it->final_level);
+}
+
 // ------------------------------------------------------------ launchers
-void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
+void small_layout(const SmallWork &w, int qe, double *theta, int final_level, SmallItem *it, SmallLds *lds) {
     const size_t ld = w.ld, dn = w.dn;
-    const size_t base = ld <= 32 ? 10 * ld * ld + kRedSmall + dn + 1 : 3 * ld * ld + 64 + dn + 1;
-    const int fg_in_lds = (base + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
-    const size_t lds = (base + (fg_in_lds ? dn * 2 * ld : 0)) * sizeof(double);
-    hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds, s, w, rank_tol, fg_in_lds);
+    const size_t pbase = ld <= 32 ? 10 * ld * ld + kRedSmall + dn + 1 : 3 * ld * ld + 64 + dn + 1;
+    const int fg_in_lds = (pbase + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    // the rank r <= ld is only known on the device: size for r = ld
+    const size_t ldp = (ld + 15) & ~(size_t)15, dtl = ld <= 32 ? ldp * ldp : 0;  // the kernel's layout
+    const size_t bbase = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64 + dn + ldp;
+    const int ct_in_lds = (bbase + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    const size_t rsmall = ld <= 32;
+    const size_t rbase = 3 * ld * ld + (rsmall ? kRed : 64) + dn + 1 + (rsmall ? ld * ld : 0);
+    const size_t full = rbase + 2 * (dn + ld) * ld + dn * ld;
+    const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    it->w = w;
+    it->theta = theta;
+    it->qe = qe;
+    it->final_level = final_level;
+    it->fg_in_lds = fg_in_lds;
+    it->ct_in_lds = ct_in_lds;
+    it->use_lds = use_lds;
+    lds->pencil = (pbase + (fg_in_lds ? dn * 2 * ld : 0)) * sizeof(double);
+    lds->bisect = (bbase + (ct_in_lds ? dn * ldp : 0)) * sizeof(double);
+    lds->rr = (use_lds ? full : rbase) * sizeof(double);
+}
+
+void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
+    SmallItem it;
+    SmallLds lds;
+    small_layout(w, 1, nullptr, 0, &it, &lds);
+    hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds.pencil, s, w, rank_tol, it.fg_in_lds);
 }
 
 void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level) {
-    // the rank r <= ld is only known on the device: size for r = ld
-    const size_t ldp = ((size_t)w.ld + 15) & ~(size_t)15, dn = w.dn;
-    const int threads = kB;
-    const size_t ld = w.ld, dtl = ld <= 32 ? ldp * ldp : 0;  // the kernel's layout
-    const size_t base = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64 + dn + ldp;
-    const int ct_in_lds = (base + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
-    const size_t lds = (base + (ct_in_lds ? dn * ldp : 0)) * sizeof(double);
-    hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(threads), lds, s, w, theta, ct_in_lds);
-    const size_t rsmall = ld <= 32;
-    const size_t rbase = 3 * ld * ld + (rsmall ? kRed : 64) + dn + 1 + (rsmall ? ld * ld : 0);
-    const size_t full = rbase + 2 * (dn + w.ld) * w.ld + dn * w.ld;
-    const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
-    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), (use_lds ? full : rbase) * sizeof(double), s, w, qe, use_lds, theta,
-                       final_level);
+    SmallItem it;
+    SmallLds lds;
+    small_layout(w, qe, theta, final_level, &it, &lds);
+    hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(kB), lds.bisect, s, w, theta, it.ct_in_lds);
+    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), lds.rr, s, w, qe, it.use_lds, theta, final_level);
+}
+
+void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol) {
+    if (t.n <= 0) return;
+    hipLaunchKernelGGL(k_pencil_batch, dim3(t.n), dim3(kB), lds.pencil, s, t, rank_tol);
+    hipLaunchKernelGGL(k_arrow_bisect_batch, dim3(t.first[t.n]), dim3(kB), lds.bisect, s, t);
+    hipLaunchKernelGGL(k_arrow_rr_batch, dim3(t.n), dim3(kB), lds.rr, s, t);
 }
 
 }  // namespace amgeig
