@@ -122,7 +122,7 @@ def serving(args):
     srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=args.steps_per_round,
                  max_active=args.max_active if args.max_active > 0 else None,
                  context_factory=lambda p, o: cs[p["_k"]],
-                 batch_fn=(lambda cs_, steps: ae.correct_batch_joint(cs_, steps)) if args.joint else None)
+                 batch_fn=None if args.joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
@@ -211,10 +211,11 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=8.0, help="serving stream: device memory budget")
     ap.add_argument("--streams", type=int, default=8, help="serving stream: stream pool size")
     ap.add_argument("--steps-per-round", type=int, default=2, help="serving stream: corrections per round")
-    ap.add_argument("--serve-graph", type=int, default=0, help="serving stream: replay captured steps")
+    ap.add_argument("--serve-graph", type=int, default=1, help="serving stream: replay captured steps (or, with "
+                                                                "--joint, each request's own parts of a step)")
     ap.add_argument("--max-active", type=int, default=0, help="serving stream: requests on the device at once "
                                                                  "(0: the memory budget alone decides)")
-    ap.add_argument("--joint", type=int, default=0, help="serving stream: solve the members' small eigenproblems "
+    ap.add_argument("--joint", type=int, default=1, help="serving stream: solve the members' small eigenproblems "
                                                          "in shared launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "

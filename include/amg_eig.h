@@ -166,8 +166,10 @@ int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_st
  * workgroups per member for the eigenvalues, members of different d_n and qe
  * side by side, up to 64 per launch); the members' streams wait for that and
  * recombine.  Results are bitwise those of amg_eig_correct on each member.
- * Launches are eager (no graph); members may share streams.  A context may
- * appear once.  Errors: EINVAL (NULL, duplicate), ESTATE (not initialised),
+ * A member whose options ask for graphs (and whose site timing is off)
+ * replays its two own parts from graphs captured on its first joint step; the
+ * joint launches are eager.  Members may share streams.  A context may appear
+ * once.  Errors: EINVAL (NULL, duplicate), ESTATE (not initialised),
  * EHIP. */
 int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps);
 

@@ -85,6 +85,9 @@ struct amg_eig_ctx {
     std::vector<std::vector<char>> staging;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // the two per-request parts of a joint batch step, captured separately
+    hipGraph_t part_graph[2] = {nullptr, nullptr};
+    hipGraphExec_t part_exec[2] = {nullptr, nullptr};
     // tuned columns per lane by (level, kind); copied into dl at bind
     std::vector<std::array<int, 3>> cpt_tab;
     // optional per-site event timing of finest-level kernels (eager launches)
@@ -573,6 +576,35 @@ void drop_graph(amg_eig_ctx *c) {
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->graph_exec = nullptr;
     c->graph = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (c->part_exec[i]) (void)hipGraphExecDestroy(c->part_exec[i]);
+        if (c->part_graph[i]) (void)hipGraphDestroy(c->part_graph[i]);
+        c->part_exec[i] = nullptr;
+        c->part_graph[i] = nullptr;
+    }
+}
+
+// part 0: residual, V-cycle and the products up to Z^T B; part 1: the
+// recombination.  Replayed from a captured graph when the context asks for
+// graphs and no site timing is on.
+int enqueue_part(amg_eig_ctx *c, int part) {
+    if (c->o.use_graph && c->stream && !c->timing) {
+        if (!c->part_exec[part]) {
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            if (part == 0)
+                correction_front(c, 0);
+            else
+                rr_back(c, 0);
+            HIPCHK(c, hipStreamEndCapture(c->stream, &c->part_graph[part]));
+            HIPCHK(c, hipGraphInstantiate(&c->part_exec[part], c->part_graph[part], nullptr, nullptr, 0));
+        }
+        HIPCHK(c, hipGraphLaunch(c->part_exec[part], c->stream));
+    } else if (part == 0) {
+        correction_front(c, 0);
+    } else {
+        rr_back(c, 0);
+    }
+    return AMG_EIG_OK;
 }
 
 int enqueue_steps(amg_eig_ctx *c, int steps) {
@@ -852,7 +884,10 @@ int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps) {
         if (!seen) others.push_back(cs[i]);
     }
     for (int step = 0; step < steps; ++step) {
-        for (int i = 0; i < n; ++i) correction_front(cs[i], 0);
+        for (int i = 0; i < n; ++i) {
+            const int rc = enqueue_part(cs[i], 0);
+            if (rc) return rc;
+        }
         for (amg_eig_ctx *o : others) {  // the lead stream waits for every front part
             HIPCHK(o, hipEventRecord(o->join_ev, o->stream));
             HIPCHK(lead, hipStreamWaitEvent(ls, o->join_ev, 0));
@@ -875,7 +910,10 @@ int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps) {
         }
         HIPCHK(lead, hipEventRecord(lead->join_ev, ls));
         for (amg_eig_ctx *o : others) HIPCHK(o, hipStreamWaitEvent(o->stream, lead->join_ev, 0));
-        for (int i = 0; i < n; ++i) rr_back(cs[i], 0);
+        for (int i = 0; i < n; ++i) {
+            const int rc = enqueue_part(cs[i], 1);
+            if (rc) return rc;
+        }
     }
     HIPCHK(lead, hipGetLastError());
     return AMG_EIG_OK;

@@ -472,13 +472,14 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
 // eigenvector: one Rayleigh-quotient step from it and one more count around
 // the result usually isolate the eigenvalue and deliver its vector.
 // Otherwise the eigenvalue is bracketed (Gershgorin and the interlacing bound
-// mu_k <= lambda_k fill in the missing ends), isolated by bisection, and
+// mu_k <= lambda_k fill in the missing ends), isolated by bisection (or
+// narrowed to a cluster of relative width kRqiTol that holds it), and
 // Rayleigh-quotient iteration with the exact Schur-complement solve
 // (H - s)^-1 runs inside the bracket: every factorisation is also a count and
 // narrows the bracket.  An iterate is accepted once its Rayleigh quotient rho
-// lies in the isolating bracket with ||H x - rho x|| <= kRqiTol |rho| and more
-// than that residual away from both ends, which pins it to the bracketed
-// eigenvalue.
+// lies in the bracket with ||H x - rho x|| <= kRqiTol |rho| and more than
+// that residual away from both ends, which pins it to the bracketed
+// eigenvalue (or cluster).
 __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__restrict__ theta_prev, int ct_in_lds,
                                                   int k, int nk) {
     extern __shared__ double sm[];
@@ -704,7 +705,10 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
     int nulo = 0, nuhi = 1 << 30;
     bool have_lo = false, have_hi = false;
     bool done = false;
-    const double tp = theta_prev[k];
+    // the previous Ritz values are meaningful only after a first Rayleigh-Ritz
+    // step (or from the coarsest eigenvalues in the nested start)
+    const bool warm = w.status[ST_WARM] != 0;
+    const double tp = warm ? theta_prev[k] : 0.0;
     const double cap = lam[k] * (1.0 + 1e-14) + 1e-300;  // interlacing: mu_k <= lambda_k
     double rho = 0.0, res = 0.0;
     // bracket updates are value selects (a branch on which end to write would
@@ -730,7 +734,6 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         have_hi = have_hi || !is_lo;
     };
     __shared__ int s_pos;
-    const bool warm = w.status[ST_WARM] != 0;
     if (warm) {
         if (tid == 0) {
             s_pos = -1;
@@ -769,18 +772,34 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
             // ends more than the residual away from rho, counted if not yet known
             const double span = fmax(4.0 * res, 1e-12 * fabs(rho));
             // (an end that would not isolate eigenvalue k only tightens the bracket)
+            const double l0 = rho - span, h0 = fmin(rho + span, cap);
+            int cl = -1, ch = -1;  // counts at l0 and h0, where taken
             if (!(have_lo && nulo == k && rho - lo > res)) {
-                const double l0 = rho - span;
-                const int c = factor(l0);
-                if (c == k) force(l0, c); else note(l0, c);
+                cl = factor(l0);
+                if (cl == k) force(l0, cl); else note(l0, cl);
             }
             if (!(have_hi && nuhi == k + 1 && hi - rho > res)) {
-                const double h0 = fmin(rho + span, cap);
-                const int c = factor(h0);
-                if (c == k + 1) force(h0, c); else note(h0, c);
+                ch = factor(h0);
+                if (ch == k + 1) force(h0, ch); else note(h0, ch);
             }
             done = have_lo && have_hi && nulo == k && nuhi == k + 1 && rho > lo && rho < hi && rho - lo > res &&
                    hi - rho > res;
+            // a cluster: eigenvalue k lies in [l0, h0) together with others that
+            // no count can separate from it at this residual.  Then rho is within
+            // span of eigenvalue k, and x lies in the cluster's invariant subspace
+            // up to the residual over the gap to the rest of the spectrum; the
+            // cluster members start from different corrected vectors, and the
+            // Ritz polish that follows resolves the subspace they span
+            if (!done && (cl >= 0) != (ch >= 0)) {  // count the end not taken in this attempt
+                if (cl < 0) {
+                    cl = factor(l0);
+                    note(l0, cl);
+                } else {
+                    ch = factor(h0);
+                    note(h0, ch);
+                }
+            }
+            done = done || (cl >= 0 && ch >= 0 && cl <= k && k < ch);
             if (done || attempt == 1 || !((have_hi && hi < rho) || (have_lo && lo > rho))) break;
             double d = 0.0;
             for (int i = tid; i < dn + r; i += nthr) d += vec[i] * vec0[i];
@@ -803,6 +822,19 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
     } else {
         for (int i = tid; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
         __syncthreads();
+    }
+    // ---- the previous Ritz value theta_prev[k] is close to eigenvalue k once
+    // the iteration has settled: counts at widening windows around it give a
+    // narrow bracket in a few factorisations (any count is a valid bracket
+    // end, so a poor guess only costs the counts)
+    if (!done && warm && tp > 0.0 && tp < cap) {
+        double d = 1e-7 * tp;
+        for (int t = 0; t < 3; ++t, d *= 100.0) {
+            const double a = tp - d, b = fmin(tp + d, cap);
+            if (!(have_lo && lo >= a) && !(have_hi && hi <= a)) note(a, factor(a));
+            if (!(have_hi && hi <= b) && !(have_lo && lo >= b)) note(b, factor(b));
+            if (have_lo && have_hi && hi - lo <= 2.0 * d) break;
+        }
     }
     if (!(have_lo && have_hi)) {
         // Gershgorin lower bound of H; the upper end is the interlacing bound
@@ -834,14 +866,23 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         lo = have_lo ? lo : (g0 > 0.0 ? g0 : 0.0);
         nulo = have_lo ? nulo : 0;
     }
-    // ---- isolate by bisection
+    // ---- isolate by bisection, or narrow to a cluster no wider than the
+    // acceptance residual: then every eigenvalue in the bracket is within
+    // kRqiTol |rho| of eigenvalue k, and the iteration below settles on one
+    // of them with its vector in the cluster's invariant subspace
     for (int it = 0; it < 200 && !done; ++it) {
         if (nulo == k && nuhi == k + 1) break;
-        if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;  // a cluster closer than rounding
+        if (hi - lo <= kRqiTol * fmax(fabs(lo), fabs(hi))) break;
         const double mid = 0.5 * (lo + hi);
         force(mid, factor(mid));
     }
-    // ---- Rayleigh-quotient iteration inside the bracket
+    // ---- Rayleigh-quotient iteration inside the bracket, from the corrected
+    // vector when there is one (the warm attempts may have left a neighbour's
+    // eigenvector in vec)
+    if (!done && warm) {
+        for (int i = tid; i < dn + r; i += nthr) vec[i] = vec0[i];
+        __syncthreads();
+    }
     double sigma = (rho > lo && rho < hi) ? rho : ((tp > lo && tp < hi) ? tp : 0.5 * (lo + hi));
     for (int it = 0; it < 12 && !done; ++it) {
         const int c = factor(sigma);

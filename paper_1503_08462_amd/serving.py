@@ -4,8 +4,9 @@ Requests are set up on the host when they are submitted (the AMG hierarchy,
 Section 2), admitted to the device in arrival order while their device
 footprint fits the memory budget, and then advanced together: every
 scheduling round enqueues a few correction steps (Algorithm 3.1) for each
-active request on its own stream from a small pool, so the short, latency-bound
-kernels of different requests overlap on the device.  Requests join at a
+active request on its own stream from a small pool, so the streaming kernels
+of different requests overlap on the device, and by default solves the small
+eigenproblems (3.3) of all of them in shared launches.  Requests join at a
 round boundary (after their Algorithm 3.2 start) and leave as soon as their
 convergence test holds or their step limit is reached, which frees their
 memory for the next arrivals (continuous batching).  Latency is measured from
@@ -18,7 +19,7 @@ import time
 
 import numpy as np
 
-from . import INIT_NESTED, Context, correct_batch, defaults
+from . import INIT_NESTED, Context, correct_batch_joint, defaults
 
 
 class Request:
@@ -45,8 +46,9 @@ class Server:
     steps_per_round:  corrections enqueued per request between convergence checks
     context_factory:  (problem dict, opts) -> context; the default builds a
                       library Context (tests pass stand-ins)
-    batch_fn:         (contexts, steps) -> None; the default is correct_batch
-                      with each context on its own stream
+    batch_fn:         (contexts, steps) -> None; the default is
+                      correct_batch_joint (each context on its own stream, the
+                      small eigenproblems of all of them in shared launches)
     """
 
     def __init__(self, budget_bytes, n_streams=4, steps_per_round=2, opts=None, context_factory=None,
@@ -59,7 +61,7 @@ class Server:
         self.opts = opts
         self.clock = clock
         self._make = context_factory or (lambda p, o: Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], o))
-        self._batch = batch_fn or (lambda cs, steps: correct_batch(cs, steps))
+        self._batch = batch_fn or (lambda cs, steps: correct_batch_joint(cs, steps))
         if stream_factory is None:
             def stream_factory():
                 import torch

@@ -127,3 +127,29 @@ def test_joint_batch_rejects_bad_lists():
     ae.correct_batch_joint([], 1)
     c.close()
     u.close()
+
+
+def test_joint_graph_parts_equal_eager_joint():
+    """Members that replay their own parts from captured graphs (replays
+    interleaved with host reads) match members launched eagerly, bitwise."""
+    torch = _torch()
+    probs = [(make(), kw) for make, kw in MEMBERS[:4]]
+    _say("joint batch, graph parts vs eager parts, 4 members, 2 streams")
+    res = {}
+    for g in (0, 1):
+        streams = [torch.cuda.Stream() for _ in range(2)]
+        cs = []
+        for i, (p, kw) in enumerate(probs):
+            ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(use_graph=g, **kw))
+            ctx.bind(stream=streams[i % 2])
+            ctx.init(ae.INIT_NESTED)
+            cs.append(ctx)
+        res[g] = []
+        for _ in range(4):
+            ae.correct_batch_joint(cs, 1)
+            res[g].append([_state(c) for c in cs])
+        for c in cs:
+            c.close()
+    for e_round, g_round in zip(res[0], res[1]):
+        for (te, Ue), (tg, Ug) in zip(e_round, g_round):
+            assert np.array_equal(te, tg) and np.array_equal(Ue, Ug)
