@@ -122,7 +122,8 @@ def serving(args):
     srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=args.steps_per_round,
                  max_active=args.max_active if args.max_active > 0 else None,
                  context_factory=lambda p, o: cs[p["_k"]],
-                 batch_fn=None if args.joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)))
+                 batch_fn=None if args.joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)),
+                 init_fn=(lambda cs_: ae.init_batch_joint(cs_)) if args.joint_init else None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
@@ -163,7 +164,8 @@ def serving(args):
                    "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
                    "streams": args.streams, "steps_per_round": args.steps_per_round, "tol": tol,
                    "max_active": args.max_active or None,
-                   "graph_steps": bool(args.serve_graph), "joint_small_solves": bool(args.joint)},
+                   "graph_steps": bool(args.serve_graph), "joint_small_solves": bool(args.joint),
+                   "joint_starts": bool(args.joint_init)},
         "p50_ms": lat["p50_s"] * 1e3,
         "p99_ms": lat["p99_s"] * 1e3,
         "peak_resident_gb": srv.peak_in_use / 2 ** 30,
@@ -217,6 +219,8 @@ def main():
                                                                  "(0: the memory budget alone decides)")
     ap.add_argument("--joint", type=int, default=1, help="serving stream: solve the members' small eigenproblems "
                                                          "in shared launches")
+    ap.add_argument("--joint-init", type=int, default=0, help="serving stream: start the requests admitted in a "
+                                                              "round together (init_batch_joint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one plain 256 MiB device copy whose HBM counters "
                          "calibrate FETCH_SIZE / WRITE_SIZE")

@@ -173,6 +173,15 @@ int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_st
  * EHIP. */
 int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps);
 
+/* Nested start (Algorithm 3.2) of n bound contexts together: every member's
+ * coarse-level corrections run on its own stream with their small
+ * eigenproblems (eq (3.3)) solved jointly per level, as in
+ * amg_eig_correct_batch_joint; a member with fewer levels joins at the later
+ * rounds, so all reach the finest level together.  Results are bitwise those
+ * of amg_eig_init(NESTED) on each member.  Eager launches.  Errors: EINVAL
+ * (NULL, duplicate), ESTATE (not bound), EHIP. */
+int amg_eig_init_batch_joint(amg_eig_ctx *const *cs, int n);
+
 /* Sizes: block width qe, number of levels, and the dimension of each level
  * (dims[nlev], may be NULL). */
 int amg_eig_info(const amg_eig_ctx *c, int *qe, int *nlevels, int64_t *dims);

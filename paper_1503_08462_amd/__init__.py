@@ -33,7 +33,7 @@ INIT_NESTED, INIT_RANDOM, INIT_USER = 0, 1, 2
 EXPORTED = [
     "amg_eig_opts_default", "amg_eig_setup", "amg_eig_footprint", "amg_eig_bind", "amg_eig_init",
     "amg_eig_correct", "amg_eig_progress", "amg_eig_solve", "amg_eig_correct_batch", "amg_eig_correct_batch_joint",
-    "amg_eig_info",
+    "amg_eig_init_batch_joint", "amg_eig_info",
     "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting",
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
@@ -70,6 +70,7 @@ _sig = {
     "amg_eig_solve": (_i, [_vp, _d, _i, _vp, _vp, _i64]),
     "amg_eig_correct_batch": (_i, [_vp, _i, _i, _vp]),
     "amg_eig_correct_batch_joint": (_i, [_vp, _i, _i]),
+    "amg_eig_init_batch_joint": (_i, [_vp, _i]),
     "amg_eig_info": (_i, [_vp, _vp, _vp, _vp]),
     "amg_eig_level_matrix": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "amg_eig_level_prolongation": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
@@ -286,6 +287,15 @@ def correct_batch_joint(contexts, steps=1):
     solved in shared launches (each member on its own bound stream)."""
     arr = (ctypes.c_void_p * max(1, len(contexts)))(*[c._c.value for c in contexts])
     rc = _lib.amg_eig_correct_batch_joint(arr, len(contexts), steps)
+    if rc < 0:
+        raise AmgEigError(rc)
+
+
+def init_batch_joint(contexts):
+    """Nested start of several bound requests with the small eigenproblems of
+    their coarse-level corrections solved in shared launches."""
+    arr = (ctypes.c_void_p * max(1, len(contexts)))(*[c._c.value for c in contexts])
+    rc = _lib.amg_eig_init_batch_joint(arr, len(contexts))
     if rc < 0:
         raise AmgEigError(rc)
 

@@ -584,6 +584,31 @@ void drop_graph(amg_eig_ctx *c) {
     }
 }
 
+// Algorithm 3.2: the coarsest eigenpairs start the block; the prolongated
+// coarsest eigenvectors already approximate the wanted ones, so the first
+// Rayleigh-Ritz step may start from them (the inertia counts still certify
+// every eigenvalue it accepts)
+void nested_head(amg_eig_ctx *c) {
+    hipStream_t s = c->stream;
+    const int ld = c->ld, qe = c->qe, dn = c->H.dn;
+    launch_fill_i32(s, ST_COUNT, 0, c->status);
+    launch_fill_i32(s, 1, 1, c->status + ST_WARM);
+    launch_copy_cols(s, dn, ld, ld, qe, c->Z, dn, c->U);
+    launch_copy_f64(s, qe, c->lam, c->theta);
+}
+
+// the block prolongated from level k + 1 to level k (a correction on level k
+// follows for k >= 1)
+void nested_prolong(amg_eig_ctx *c, int k) {
+    DevLevel &d = c->dl[k];
+    launch_spmm<double>(c->stream, d.n, c->ld, d.p_ptr, d.p_col, d.p64, c->U, c->V, c->status, d.cpt[1]);
+    launch_copy_f64(c->stream, d.n * (int64_t)c->ld, c->V, c->U);
+}
+
+// after a start: the step counter counts finest-level corrections only (the
+// warm-bracket flag and the rank survive)
+void reset_step_count(amg_eig_ctx *c) { launch_fill_i32(c->stream, 2, 0, c->status); }
+
 // part 0: residual, V-cycle and the products up to Z^T B; part 1: the
 // recombination.  Replayed from a captured graph when the context asks for
 // graphs and no site timing is on.
@@ -630,6 +655,60 @@ int enqueue_steps(amg_eig_ctx *c, int steps) {
         }
     }
     HIPCHK(c, hipGetLastError());
+    return AMG_EIG_OK;
+}
+
+// Arguments of the joint batch entry points: members non-NULL, bound (and
+// initialised when `initialised`), listed once; creates their join events.
+int check_joint(amg_eig_ctx *const *cs, int n, bool initialised) {
+    for (int i = 0; i < n; ++i) {
+        amg_eig_ctx *c = cs[i];
+        if (!c) return AMG_EIG_EINVAL;
+        if (!c->bound) return fail(c, AMG_EIG_ESTATE, "batch member not bound");
+        if (initialised && !c->initialised) return fail(c, AMG_EIG_ESTATE, "batch member not initialised");
+        for (int j = 0; j < i; ++j)
+            if (cs[j] == c) return fail(c, AMG_EIG_EINVAL, "context listed twice in a batch");
+        if (!c->join_ev) HIPCHK(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    return AMG_EIG_OK;
+}
+
+// The small eigenproblems of n members whose front parts are enqueued: the
+// stream of cs[0] waits for the others (one event per distinct stream), runs
+// the three batched kernels over their descriptors, and the others wait for it.
+int joint_small(amg_eig_ctx *const *cs, int n, int final_level) {
+    if (n <= 0) return AMG_EIG_OK;
+    amg_eig_ctx *lead = cs[0];
+    hipStream_t ls = lead->stream;
+    std::vector<amg_eig_ctx *> others;  // the other streams, each once
+    for (int i = 0; i < n; ++i) {
+        bool seen = cs[i]->stream == ls;
+        for (amg_eig_ctx *o : others) seen = seen || o->stream == cs[i]->stream;
+        if (!seen) others.push_back(cs[i]);
+    }
+    for (amg_eig_ctx *o : others) {
+        HIPCHK(o, hipEventRecord(o->join_ev, o->stream));
+        HIPCHK(lead, hipStreamWaitEvent(ls, o->join_ev, 0));
+    }
+    for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+        const int m = std::min(n - i0, kMaxBatch);
+        SmallTable t{};
+        SmallLds lds;
+        t.n = m;
+        t.final_level = final_level;
+        t.first[0] = 0;
+        for (int j = 0; j < m; ++j) {
+            const amg_eig_ctx *c = cs[i0 + j];
+            t.item[j] = c->item_dev;
+            t.first[j + 1] = t.first[j] + c->qe;
+            lds.pencil = std::max(lds.pencil, c->small_lds.pencil);
+            lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
+            lds.rr = std::max(lds.rr, c->small_lds.rr);
+        }
+        launch_small_batch(ls, t, lds, kRankTol);
+    }
+    HIPCHK(lead, hipEventRecord(lead->join_ev, ls));
+    for (amg_eig_ctx *o : others) HIPCHK(o, hipStreamWaitEvent(o->stream, lead->join_ev, 0));
     return AMG_EIG_OK;
 }
 
@@ -713,7 +792,7 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     if (rc) return rc;
     launch_fill_i32(c->stream, ST_COUNT, 0, c->status);
     launch_fill_i32(c->stream, 5 * kMaxWidth + 8, 0, c->sw.diag);
-    small_layout(c->sw, c->qe, c->theta, 1, &c->item_host, &c->small_lds);
+    small_layout(c->sw, c->qe, c->theta, &c->item_host, &c->small_lds);
     rc = put(c, c->item_dev, &c->item_host, sizeof(SmallItem));
     if (rc) return rc;
     std::vector<unsigned> zero(16, 0u);
@@ -735,25 +814,17 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
 int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, int64_t ldu) {
     if (!c) return AMG_EIG_EINVAL;
     if (!c->bound) return fail(c, AMG_EIG_ESTATE, "init before bind");
-    const int L = (int)c->dl.size(), ld = c->ld, qe = c->qe, dn = c->H.dn;
+    const int L = (int)c->dl.size(), ld = c->ld, qe = c->qe;
     hipStream_t s = c->stream;
     const int64_t N = c->dl[0].n;
-    launch_fill_i32(s, ST_COUNT, 0, c->status);
     if (mode == AMG_EIG_INIT_NESTED) {
-        // the prolongated coarsest eigenvectors already approximate the wanted
-        // ones, so the first Rayleigh-Ritz step may start from them (the
-        // inertia counts still certify every eigenvalue it accepts)
-        launch_fill_i32(s, 1, 1, c->status + ST_WARM);
-        // coarsest eigenpairs, then one correction on each level n-1 .. 2
-        launch_copy_cols(s, dn, ld, ld, qe, c->Z, dn, c->U);
-        launch_copy_f64(s, qe, c->lam, c->theta);
+        nested_head(c);
         for (int k = L - 2; k >= 0; --k) {
-            DevLevel &d = c->dl[k];
-            launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, c->U, c->V, c->status, d.cpt[1]);
-            launch_copy_f64(s, d.n * (int64_t)ld, c->V, c->U);
+            nested_prolong(c, k);
             if (k >= 1) correction(c, k);
         }
     } else if (mode == AMG_EIG_INIT_RANDOM || mode == AMG_EIG_INIT_USER) {
+        launch_fill_i32(s, ST_COUNT, 0, c->status);
         if (mode == AMG_EIG_INIT_RANDOM) {
             launch_fill_random(s, N, ld, qe, seed, c->V);
         } else {
@@ -764,9 +835,7 @@ int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, i
     } else {
         return fail(c, AMG_EIG_EINVAL, "unknown init mode");
     }
-    // the step counter counts finest-level corrections only (the warm-bracket
-    // flag and the rank survive)
-    launch_fill_i32(s, 2, 0, c->status);
+    reset_step_count(c);
     HIPCHK(c, hipGetLastError());
     c->initialised = true;
     return AMG_EIG_OK;
@@ -865,57 +934,49 @@ int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_st
 
 int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps) {
     if (!cs || n < 0 || steps < 0) return AMG_EIG_EINVAL;
+    int rc = check_joint(cs, n, true);
+    if (rc) return rc;
+    for (int step = 0; step < steps && n > 0; ++step) {
+        for (int i = 0; i < n; ++i)
+            if ((rc = enqueue_part(cs[i], 0))) return rc;
+        if ((rc = joint_small(cs, n, 1))) return rc;
+        for (int i = 0; i < n; ++i)
+            if ((rc = enqueue_part(cs[i], 1))) return rc;
+    }
+    if (n > 0) HIPCHK(cs[0], hipGetLastError());
+    return AMG_EIG_OK;
+}
+
+int amg_eig_init_batch_joint(amg_eig_ctx *const *cs, int n) {
+    if (!cs || n < 0) return AMG_EIG_EINVAL;
+    int rc = check_joint(cs, n, false);
+    if (rc) return rc;
+    // members finish together: a member with L levels runs levels L-2 .. 0
+    // in the last L-1 of the rounds
+    int rounds = 0;
     for (int i = 0; i < n; ++i) {
-        amg_eig_ctx *c = cs[i];
-        if (!c) return AMG_EIG_EINVAL;
-        if (!c->initialised) return fail(c, AMG_EIG_ESTATE, "batch member not initialised");
-        for (int j = 0; j < i; ++j)
-            if (cs[j] == c) return fail(c, AMG_EIG_EINVAL, "context listed twice in a batch");
-        if (!c->join_ev) HIPCHK(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+        nested_head(cs[i]);
+        rounds = std::max(rounds, (int)cs[i]->dl.size() - 1);
     }
-    if (n == 0 || steps == 0) return AMG_EIG_OK;
-    amg_eig_ctx *lead = cs[0];
-    hipStream_t ls = lead->stream;
-    // the other streams of the batch, each once
-    std::vector<amg_eig_ctx *> others;
+    std::vector<amg_eig_ctx *> act;
+    for (int t = 0; t < rounds; ++t) {
+        const int k = rounds - 1 - t;
+        act.clear();
+        for (int i = 0; i < n; ++i)
+            if (k <= (int)cs[i]->dl.size() - 2) act.push_back(cs[i]);
+        for (amg_eig_ctx *c : act) {
+            nested_prolong(c, k);
+            if (k >= 1) correction_front(c, k);
+        }
+        if (k == 0) break;
+        if ((rc = joint_small(act.data(), (int)act.size(), 0))) return rc;
+        for (amg_eig_ctx *c : act) rr_back(c, k);
+    }
     for (int i = 0; i < n; ++i) {
-        bool seen = cs[i]->stream == ls;
-        for (amg_eig_ctx *o : others) seen = seen || o->stream == cs[i]->stream;
-        if (!seen) others.push_back(cs[i]);
+        reset_step_count(cs[i]);
+        HIPCHK(cs[i], hipGetLastError());
+        cs[i]->initialised = true;
     }
-    for (int step = 0; step < steps; ++step) {
-        for (int i = 0; i < n; ++i) {
-            const int rc = enqueue_part(cs[i], 0);
-            if (rc) return rc;
-        }
-        for (amg_eig_ctx *o : others) {  // the lead stream waits for every front part
-            HIPCHK(o, hipEventRecord(o->join_ev, o->stream));
-            HIPCHK(lead, hipStreamWaitEvent(ls, o->join_ev, 0));
-        }
-        for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
-            const int m = std::min(n - i0, kMaxBatch);
-            SmallTable t{};
-            SmallLds lds;
-            t.n = m;
-            t.first[0] = 0;
-            for (int j = 0; j < m; ++j) {
-                const amg_eig_ctx *c = cs[i0 + j];
-                t.item[j] = c->item_dev;
-                t.first[j + 1] = t.first[j] + c->qe;
-                lds.pencil = std::max(lds.pencil, c->small_lds.pencil);
-                lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
-                lds.rr = std::max(lds.rr, c->small_lds.rr);
-            }
-            launch_small_batch(ls, t, lds, kRankTol);
-        }
-        HIPCHK(lead, hipEventRecord(lead->join_ev, ls));
-        for (amg_eig_ctx *o : others) HIPCHK(o, hipStreamWaitEvent(o->stream, lead->join_ev, 0));
-        for (int i = 0; i < n; ++i) {
-            const int rc = enqueue_part(cs[i], 1);
-            if (rc) return rc;
-        }
-    }
-    HIPCHK(lead, hipGetLastError());
     return AMG_EIG_OK;
 }
 

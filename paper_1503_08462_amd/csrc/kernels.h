@@ -121,18 +121,19 @@ void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);
 struct SmallItem {
     SmallWork w;
     double *theta = nullptr;  // Ritz values: previous on entry, new on exit
-    int qe = 0, final_level = 0;
+    int qe = 0;
     int fg_in_lds = 0, ct_in_lds = 0, use_lds = 0;
 };
 struct SmallLds {
     size_t pencil = 0, bisect = 0, rr = 0;  // dynamic LDS bytes per kernel
 };
-void small_layout(const SmallWork &w, int qe, double *theta, int final_level, SmallItem *it, SmallLds *lds);
+void small_layout(const SmallWork &w, int qe, double *theta, SmallItem *it, SmallLds *lds);
 constexpr int kMaxBatch = 64;
 struct SmallTable {
     const SmallItem *item[kMaxBatch];  // device addresses
     int first[kMaxBatch + 1];          // eigenvalue workgroups of member m: first[m] .. first[m+1]-1
     int n;
+    int final_level;                   // finest-level step (counted) or a step of the nested start
 };
 // pencil, eigenpairs and Ritz polish of every member of the table, three
 // launches in all; lds holds the largest size over the members

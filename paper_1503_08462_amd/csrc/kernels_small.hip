@@ -1244,11 +1244,11 @@ __global__ __launch_bounds__(256) void k_arrow_bisect_batch(SmallTable t) {
 
 __global__ __launch_bounds__(256) void k_arrow_rr_batch(SmallTable t) {
     const SmallItem *it = t.item[blockIdx.x];
-    arrow_rr_body(it->w, it->qe, it->use_lds, it->theta, it->final_level);
+    arrow_rr_body(it->w, it->qe, it->use_lds, it->theta, t.final_level);
 }
 
 // ------------------------------------------------------------ launchers
-void small_layout(const SmallWork &w, int qe, double *theta, int final_level, SmallItem *it, SmallLds *lds) {
+void small_layout(const SmallWork &w, int qe, double *theta, SmallItem *it, SmallLds *lds) {
     const size_t ld = w.ld, dn = w.dn;
     const size_t pbase = ld <= 32 ? 10 * ld * ld + kRedSmall + dn + 1 : 3 * ld * ld + 64 + dn + 1;
     const int fg_in_lds = (pbase + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
@@ -1263,7 +1263,6 @@ void small_layout(const SmallWork &w, int qe, double *theta, int final_level, Sm
     it->w = w;
     it->theta = theta;
     it->qe = qe;
-    it->final_level = final_level;
     it->fg_in_lds = fg_in_lds;
     it->ct_in_lds = ct_in_lds;
     it->use_lds = use_lds;
@@ -1275,14 +1274,14 @@ void small_layout(const SmallWork &w, int qe, double *theta, int final_level, Sm
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
     SmallItem it;
     SmallLds lds;
-    small_layout(w, 1, nullptr, 0, &it, &lds);
+    small_layout(w, 1, nullptr, &it, &lds);
     hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds.pencil, s, w, rank_tol, it.fg_in_lds);
 }
 
 void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level) {
     SmallItem it;
     SmallLds lds;
-    small_layout(w, qe, theta, final_level, &it, &lds);
+    small_layout(w, qe, theta, &it, &lds);
     hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(kB), lds.bisect, s, w, theta, it.ct_in_lds);
     hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), lds.rr, s, w, qe, it.use_lds, theta, final_level);
 }

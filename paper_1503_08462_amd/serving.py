@@ -22,6 +22,11 @@ import numpy as np
 from . import INIT_NESTED, Context, correct_batch_joint, defaults
 
 
+def _default_init(contexts):
+    for c in contexts:
+        c.init(INIT_NESTED)
+
+
 class Request:
     __slots__ = ("id", "ctx", "q", "tol", "max_steps", "footprint", "arrival", "admitted", "done", "stream",
                  "result")
@@ -49,10 +54,15 @@ class Server:
     batch_fn:         (contexts, steps) -> None; the default is
                       correct_batch_joint (each context on its own stream, the
                       small eigenproblems of all of them in shared launches)
+    init_fn:          (contexts) -> None, the nested start of the requests
+                      admitted in one round; the default is each context's own
+                      init on its stream (init_batch_joint, which solves the
+                      small problems of the starts together, holds the new
+                      requests in step with each other and measured slower)
     """
 
     def __init__(self, budget_bytes, n_streams=4, steps_per_round=2, opts=None, context_factory=None,
-                 batch_fn=None, stream_factory=None, clock=time.perf_counter, max_active=None):
+                 batch_fn=None, stream_factory=None, clock=time.perf_counter, max_active=None, init_fn=None):
         if budget_bytes <= 0 or n_streams < 1 or steps_per_round < 1 or (max_active is not None and max_active < 1):
             raise ValueError("budget, stream count, steps per round and active limit must be positive")
         self.max_active = max_active
@@ -62,6 +72,7 @@ class Server:
         self.clock = clock
         self._make = context_factory or (lambda p, o: Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], o))
         self._batch = batch_fn or (lambda cs, steps: correct_batch_joint(cs, steps))
+        self._init = init_fn or _default_init
         if stream_factory is None:
             def stream_factory():
                 import torch
@@ -96,17 +107,22 @@ class Server:
         return rid
 
     def _admit(self):
+        new = []
         while (self.queue and self.in_use + self.queue[0].footprint <= self.budget
-               and (self.max_active is None or len(self.active) < self.max_active)):
+               and (self.max_active is None or len(self.active) + len(new) < self.max_active)):
             req = self.queue.pop(0)
             req.stream = self.streams[self._next_stream % len(self.streams)]
             self._next_stream += 1
             req.ctx.bind(stream=req.stream)
-            req.ctx.init(INIT_NESTED)
-            req.admitted = self.clock()
             self.in_use += req.footprint
             self.peak_in_use = max(self.peak_in_use, self.in_use)
-            self.active.append(req)
+            new.append(req)
+        if new:
+            self._init([r.ctx for r in new])
+            now = self.clock()
+            for req in new:
+                req.admitted = now
+            self.active.extend(new)
 
     def _retire(self):
         still = []

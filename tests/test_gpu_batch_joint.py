@@ -153,3 +153,35 @@ def test_joint_graph_parts_equal_eager_joint():
     for e_round, g_round in zip(res[0], res[1]):
         for (te, Ue), (tg, Ug) in zip(e_round, g_round):
             assert np.array_equal(te, tg) and np.array_equal(Ue, Ug)
+
+
+def test_joint_nested_start_equals_separate_starts():
+    """Members with different numbers of levels started together (the small
+    eigenproblems of each level in shared launches) hold bitwise the block and
+    Ritz values of separate nested starts, before and after joint steps."""
+    torch = _torch()
+    probs = [(make(), kw) for make, kw in MEMBERS]
+    _say("joint nested start of %d members, 2 streams" % len(probs))
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    joint = []
+    for i, (p, kw) in enumerate(probs):
+        ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(use_graph=0, **kw))
+        ctx.bind(stream=streams[i % 2])
+        joint.append(ctx)
+    assert len({len(c.info()["dims"]) for c in joint}) > 1  # uneven hierarchies
+    ae.init_batch_joint(joint)
+    solo = [_ctx(p, torch.cuda.Stream(), **kw) for p, kw in probs]
+    for a, b in zip(joint, solo):
+        ta, Ua = _state(a)
+        tb, Ub = _state(b)
+        assert np.array_equal(ta, tb) and np.array_equal(Ua, Ub)
+        assert a.progress()["steps"] == 0
+    ae.correct_batch_joint(joint, 2)
+    for c in solo:
+        c.correct(2)
+    for a, b in zip(joint, solo):
+        ta, Ua = _state(a)
+        tb, Ub = _state(b)
+        assert np.array_equal(ta, tb) and np.array_equal(Ua, Ub)
+    for c in joint + solo:
+        c.close()

@@ -111,3 +111,20 @@ def test_active_limit_caps_concurrency_and_keeps_order():
     binds = [n for k, n in FakeCtx.log if k == "bind"]
     assert binds == ["a", "b", "c", "d"]
     assert all(r["converged"] for r in res.values())
+
+
+def test_requests_admitted_in_one_round_start_together():
+    """A custom start hook receives, once per round, the requests admitted in
+    that round (already bound), before their first corrections."""
+    starts = []
+
+    def init_fn(cs):
+        assert all(c.bound for c in cs)
+        starts.append([c.name for c in cs])
+    srv, batches = make_server(60, steps_per_round=1, init_fn=init_fn)
+    for name, fp, need in (("a", 20, 3), ("b", 20, 1), ("c", 20, 1), ("d", 30, 1)):
+        srv.submit(prob(name, fp, need))
+    srv.run()
+    assert starts[0] == ["a", "b", "c"]  # d does not fit until b and c leave
+    assert starts[1] == ["d"]
+    assert batches[0] == ["a", "b", "c"]
