@@ -665,9 +665,13 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
 }
 
 // Wide blocks: U = P Y + V X_v on the correction level.  One wavefront per
-// 16 consecutive rows: V X_v as 16 x 16 tiles on the FP64 matrix cores (X_v
-// staged in LDS), then each lane adds the prolongation P Y for its four
-// (row, column) entries of the tile and writes them.
+// 16 consecutive rows, striding over the row tiles so that each workgroup
+// stages X_v in LDS once: V X_v as 16 x 16 tiles on the FP64 matrix cores,
+// then each lane adds the prolongation P Y for its four
+// (row, column) entries of the tile and writes them.  The first kPRow entries
+// of the lane's four rows of P are held in registers across the column tiles,
+// so that a tile's gathers of Y are independent loads issued together.
+constexpr int kPRow = 4;
 __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
                                                const int32_t *__restrict__ col, const double *__restrict__ val,
                                                const double *__restrict__ Y, const double *__restrict__ V,
@@ -678,28 +682,55 @@ __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t 
     for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) xv[e] = Xv[e];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int64_t r0 = (xcd_block() * (blockDim.x / kWave) + wv) * 16;
-    if (r0 >= n) return;  // the whole wavefront
+    const int c = lane & 15, kk = lane >> 4;
     const int tj = (ld + 15) / 16;
-    for (int tb = 0; tb < tj; ++tb) {
-        const dbl4 acc = mfma_tn16(
-            [&](int k, int c) -> double {
-                const int64_t row = r0 + c;
-                return row < n ? V[row * ld + k] : 0.0;
-            },
-            [&](int k, int c) -> double {
-                const int j = 16 * tb + c;
-                return j < ld ? xv[k * ld + j] : 0.0;
-            },
-            ld);
-        const int j = 16 * tb + (lane & 15);
+    const int64_t tiles = (n + 15) / 16, stride = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t tile = xcd_block() * (blockDim.x / kWave) + wv; tile < tiles; tile += stride) {
+        const int64_t r0 = tile * 16;
+        int32_t pb[4], pe[4], pc[4][kPRow];
+        double pv[4][kPRow];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int64_t row = r0 + (lane >> 4) + 4 * u;
-            if (row < n && j < ld) {
-                double v = acc[u];
-                for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) v += val[p] * Y[(int64_t)col[p] * ld + j];
-                U[row * ld + j] = v;
+            const int64_t row = r0 + kk + 4 * u;
+            pb[u] = row < n ? ptr[row] : 0;
+            pe[u] = row < n ? ptr[row + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < kPRow; ++t) {
+                const bool ok = pb[u] + t < pe[u];
+                pc[u][t] = ok ? col[pb[u] + t] : 0;  // padding reads row 0 of Y with weight 0
+                pv[u][t] = ok ? val[pb[u] + t] : 0.0;
+            }
+        for (int tb = 0; tb < tj; ++tb) {
+            const int j = 16 * tb + c;
+            const int jc = j < ld ? j : ld - 1;  // clamped column for the gathers
+            double yv[4][kPRow];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < kPRow; ++t) yv[u][t] = Y[(int64_t)pc[u][t] * ld + jc];
+            const dbl4 acc = mfma_tn16([&](int k, int cc) -> double {
+                                           const int64_t row = r0 + cc;
+                                           return row < n ? V[row * ld + k] : 0.0;
+                                       },
+                                       [&](int k, int cc) -> double {
+                                           const int jj = 16 * tb + cc;
+                                           return jj < ld ? xv[k * ld + jj] : 0.0;
+                                       },
+                                       ld);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t row = r0 + kk + 4 * u;
+                if (row < n && j < ld) {
+                    double v = acc[u];
+#pragma unroll
+                    for (int t = 0; t < kPRow; ++t)
+                        if (pb[u] + t < pe[u]) v += pv[u][t] * yv[u][t];
+                    for (int32_t p = pb[u] + kPRow; p < pe[u]; ++p) v += val[p] * Y[(int64_t)col[p] * ld + j];
+                    U[row * ld + j] = v;
+                }
             }
         }
     }
@@ -905,7 +936,10 @@ void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const in
                                             Y, V, Xv, U, status));
         return;
     }
-    const int64_t tiles = (n + 15) / 16, nb = (tiles + (kBlock / kWave) - 1) / (kBlock / kWave);
+    // workgroups: enough to fill the chip (four per CU by LDS), each striding
+    // over the row tiles
+    const int64_t tiles = (n + 15) / 16, need = (tiles + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const int64_t nb = need < 2048 ? need : 2048;
     hipLaunchKernelGGL(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr,
                        col, val, Y, V, Xv, U, status);
 }
