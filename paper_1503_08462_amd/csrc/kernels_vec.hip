@@ -562,12 +562,12 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int ld, const double *_
     }
 }
 
-// Phase 1 for wide blocks (more than 8 tiles): the workgroup stages 16 rows
-// of V and W at a time in LDS (coalesced loads by all threads); the tiles of
+// Phase 1 for wide blocks (more than 8 tiles): the workgroup stages kGramRows
+// rows of V and W at a time in LDS (coalesced loads by all threads); the tiles of
 // the ld x 2ld result are dealt round-robin to its four wavefronts, which
 // accumulate them from LDS and finally write them to part[b] directly.
 constexpr int kGramTilesPerWave = 12;  // covers ld <= 68 (5 x 9 tiles)
-constexpr int kGramRows = 16;
+constexpr int kGramRows = 32;
 
 __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const double *__restrict__ V,
                                                    const double *__restrict__ W, double *__restrict__ part,
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
     dbl4 acc[kGramTilesPerWave];
 #pragma unroll
     for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) acc[s2] = dbl4{0.0, 0.0, 0.0, 0.0};
-    double *sv = stage, *sw = stage + kGramRows * ld;  // 16 rows of V, then 16 rows of W
+    double *sv = stage, *sw = stage + kGramRows * ld;  // rows of V, then the same rows of W
     for (int64_t base = r0; base < r1; base += kGramRows) {
         const int rows = r1 - base < kGramRows ? (int)(r1 - base) : kGramRows;
         __syncthreads();  // the previous chunk is consumed
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
             if (t < ntiles) {  // wave-uniform
                 const int ta = t / tj, tb = t - ta * tj;
                 const int ca = 16 * ta + c, cb = 16 * tb + c;
-#pragma unroll
+#pragma unroll 4
                 for (int k0 = 0; k0 < kGramRows; k0 += 4) {
                     const int rr = k0 + kk;
                     double x = (ca < ld && rr < rows) ? sv[rr * ld + ca] : 0.0;
