@@ -214,8 +214,11 @@ int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld);
 /* Enable (1) or stop (0) HIP-event timing of the finest-level kernel sites
  * for eagerly launched steps (steps replayed from a captured graph are not
  * timed; with use_graph and timing on, the second step of every enqueued
- * chunk of three or more steps runs eagerly and is timed).  Enabling resets
- * the counters. */
+ * chunk of three or more steps runs eagerly and is timed).  A site of one
+ * kernel (all but GRAM and SMALL) passes its events to that kernel's launch,
+ * which records them at the kernel's own start and end; GRAM and SMALL are
+ * bracketed by events recorded on the stream.  Enabling resets the
+ * counters. */
 int amg_eig_timing(amg_eig_ctx *c, int enable);
 
 /* Waits for the bound stream, then reports for one site: the algorithmic

@@ -319,27 +319,57 @@ int upload_levels(amg_eig_ctx *c) {
 }
 
 // ---------------------------------------------------------- site timing
+// Sites that wrap one kernel launch (exact) hand a start/stop pair to that
+// launch, which records them at the kernel's own start and end; the others
+// record stream events around their launches.
 struct SiteScope {
     amg_eig_ctx *c;
     int site;
     bool on;
-    SiteScope(amg_eig_ctx *ctx, int s, int level) : c(ctx), site(s), on(ctx->timing && level == 0) {
-        if (on) record();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SiteScope(amg_eig_ctx *ctx, int s, int level, bool exact = false)
+        : c(ctx), site(s), on(ctx->timing && level == 0) {
+        if (!on) return;
+        if (!exact) {
+            record();
+            return;
+        }
+        e0 = next();
+        e1 = e0 ? next() : nullptr;
+        if (!e1) {  // no events left: the site is not timed
+            on = false;
+            if (e0) c->sites[site].used -= 1;
+            e0 = nullptr;
+            return;
+        }
+        set_launch_events(e0, e1);
     }
     ~SiteScope() {
-        if (on) record();
+        if (!on) return;
+        if (!e0) {
+            record();
+        } else if (launch_events_pending()) {  // the launch did not take them
+            clear_launch_events();
+            (void)hipEventRecord(e0, c->stream);
+            (void)hipEventRecord(e1, c->stream);
+        }
     }
-    void record() {
+    hipEvent_t next() {
         auto &st = c->sites[site];
         if (st.used == st.ev.size()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) {
-                on = false;
-                return;
-            }
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
             st.ev.push_back(e);
         }
-        (void)hipEventRecord(st.ev[st.used++], c->stream);
+        return st.ev[st.used++];
+    }
+    void record() {
+        hipEvent_t e = next();
+        if (!e) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(e, c->stream);
     }
 };
 
@@ -400,14 +430,14 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
         DevLevel &d = c->dl[l];
         if (cheb) {
             {
-                SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
+                SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l, true);
                 launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                    (const T *)d.b, (T *)d.x, lo, st, d.cpt[0]);
             }
             launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
                                      (const T *)d.x, (T *)d.r, st, d.cpt[0]);
         } else {
-            SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
+            SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l, true);
             launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                  (const T *)d.b, (T *)d.r, st, d.cpt[0]);
         }
@@ -430,14 +460,14 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
                                 (T *)d.r, st, d.cpt[0]);
             launch_cheb_post1<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv, (const T *)d.b,
                                  (const T *)d.r, (T *)d.t, lo, st, d.cpt[0]);
-            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
+            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l, true);
             launch_cheb_post2<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val,
                                  (const T *)d.dinv, (const T *)d.r, (const T *)d.t, (T *)d.x, c->U, c->V, lo, st,
                                  d.cpt[0]);
         } else {
             launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
                                   (const T *)d.dinv, (const T *)d.b, (T *)d.r, st, d.cpt[0]);
-            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
+            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l, true);
             launch_smooth_post<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                   (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st, d.cpt[0]);
         }
@@ -471,7 +501,7 @@ void rr_front(amg_eig_ctx *c, int k) {
     const int *st = c->status;
     DevLevel &d = c->dl[k];
     {
-        SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k);
+        SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k, true);
         launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, d.cpt[1]);
     }
     {
@@ -485,7 +515,7 @@ void rr_front(amg_eig_ctx *c, int k) {
     for (int l = k; l < bottom; ++l) {
         DevLevel &a = c->dl[l];
         DevLevel &b = c->dl[l + 1];
-        SiteScope sc(c, AMG_EIG_SITE_RESTRICT, l);
+        SiteScope sc(c, AMG_EIG_SITE_RESTRICT, l, true);
         launch_spmm<double>(s, b.n, 2 * ld, a.pt_ptr, a.pt_col, a.pt64, src, b.cw, st, b.cpt[2]);
         src = b.cw;
     }
@@ -531,7 +561,7 @@ void rr_back(amg_eig_ctx *c, int k) {
         y = a.cw;
     }
     {
-        SiteScope sc(c, AMG_EIG_SITE_FINAL, k);
+        SiteScope sc(c, AMG_EIG_SITE_FINAL, k, true);
         launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, y, c->V, c->sw.Xv, c->U, st, d.cpt[1]);
     }
 }
@@ -546,7 +576,7 @@ template <typename T>
 void residual(amg_eig_ctx *c, int k, int check) {
     DevLevel &d = c->dl[k];
     {
-        SiteScope sc(c, AMG_EIG_SITE_RESIDUAL, k);
+        SiteScope sc(c, AMG_EIG_SITE_RESIDUAL, k, true);
         launch_residual<T>(c->stream, d.n, c->ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (T *)d.b,
                            c->part_res, c->status, d.cpt[1]);
     }

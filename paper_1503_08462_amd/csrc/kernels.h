@@ -115,6 +115,13 @@ struct SmallWork {
     int *status = nullptr;
     int *diag = nullptr;          // 4 * kMaxWidth + 8 counters (solver statistics)
 };
+// Start/stop events for the next launch of a single-kernel launcher (the
+// residual, smoothing, SpMM, dual SpMM and final-update launchers): recorded
+// by the dispatch at the kernel's own start and end, then cleared.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
+void clear_launch_events();
+
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);
 // one request's small-eigensolver launch parameters, kept in device memory for
 // the batched launches

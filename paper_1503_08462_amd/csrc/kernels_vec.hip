@@ -17,6 +17,8 @@
 //   k_final         U = P Y + V X_v on the correction level (recombination)
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -817,6 +819,30 @@ bool cpt_valid(int width, int cpt) {
 // `hint` when it is a valid choice for the width (a tuned value), else cpt_for.
 int pick_cpt(int width, int hint) { return cpt_valid(width, hint) ? hint : cpt_for(width); }
 
+// Events handed to the next launch of a single-kernel timing site: recorded by
+// the dispatch itself at the kernel's start and end (hipExtLaunchKernelGGL),
+// so their elapsed time is the kernel's own duration.
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+}
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+bool launch_events_pending() { return t_ev_start != nullptr; }
+void clear_launch_events() { t_ev_start = t_ev_stop = nullptr; }
+
+#define KLAUNCH(K, G, B, SH, S, ...)                                                  \
+    do {                                                                              \
+        if (t_ev_start) {                                                             \
+            hipEvent_t e0_ = t_ev_start, e1_ = t_ev_stop;                             \
+            t_ev_start = t_ev_stop = nullptr;                                         \
+            hipExtLaunchKernelGGL(K, G, B, (std::uint32_t)(SH), S, e0_, e1_, 0, __VA_ARGS__); \
+        } else {                                                                      \
+            hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                          \
+        }                                                                             \
+    } while (0)
+
 #define DISPATCH_CPT(width, hint, ...)             \
     do {                                           \
         const int cpt_sel = pick_cpt(width, hint); \
@@ -851,7 +877,7 @@ void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const
     // part: 2 ld final sums, then nb x 2 ld per-block partials
     const int64_t nb = residual_blocks(n, ld, cpt);
     double *blocks = part + 2 * ld;
-    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld,
+    DISPATCH_CPT(ld, cpt, KLAUNCH((k_residual<TO, CPT>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld,
                                              ptr, col, a, m, U, theta, R, blocks, status));
 }
 
@@ -865,14 +891,14 @@ void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsi
 template <typename T>
 void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
                        const T *dinv, const T *b, T *r, const int *status, int cpt) {
-    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_smooth_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+    DISPATCH_CPT(ld, cpt, KLAUNCH((k_smooth_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
                                         0, s, n, ld, ptr, col, val, dinv, b, r, status));
 }
 
 template <typename T>
 void launch_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
                  const T *x, T *y, const int *status, int cpt) {
-    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_spmm<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0, s,
+    DISPATCH_CPT(ld, cpt, KLAUNCH((k_spmm<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0, s,
                                         n, ld, ptr, col, val, x, y, status));
 }
 
@@ -888,10 +914,10 @@ void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int3
                         const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
                         const int *status, int cpt) {
     if (final)
-        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_smooth_post<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_smooth_post<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
     else
-        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_smooth_post<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_smooth_post<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
 }
 
@@ -904,7 +930,7 @@ void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t
 
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                       const double *m, const double *V, double *W, const int *status, int cpt) {
-    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
+    DISPATCH_CPT(ld, cpt, KLAUNCH((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
                                         s, n, ld, ptr, col, a, m, V, W, status));
 }
 
@@ -931,7 +957,7 @@ void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
                   const double *Y, const double *V, const double *Xv, double *U, const int *status, int cpt) {
     if (ld <= 32) {
-        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_final_rows<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_final_rows<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr, col, val,
                                             Y, V, Xv, U, status));
         return;
@@ -940,7 +966,7 @@ void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const in
     // over the row tiles
     const int64_t tiles = (n + 15) / 16, need = (tiles + (kBlock / kWave) - 1) / (kBlock / kWave);
     const int64_t nb = need < 2048 ? need : 2048;
-    hipLaunchKernelGGL(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr,
+    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr,
                        col, val, Y, V, Xv, U, status);
 }
 
@@ -974,7 +1000,7 @@ template <typename T>
 void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
                      const T *dinv, const T *b, T *x, double lo, const int *status, int cpt) {
     const ChebCoef kc = cheb_coefficients(lo);
-    DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+    DISPATCH_CPT(ld, cpt, KLAUNCH((k_cheb_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
                                         0, s, n, ld, ptr, col, val, dinv, b, x, kc, status));
 }
 
@@ -1006,11 +1032,11 @@ void launch_cheb_post2(hipStream_t s, bool final, int64_t n, int ld, const int32
                        double lo, const int *status, int cpt) {
     const ChebCoef kc = cheb_coefficients(lo);
     if (final)
-        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_post2<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_cheb_post2<T, CPT, true>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
                                             status));
     else
-        DISPATCH_CPT(ld, cpt, hipLaunchKernelGGL((k_cheb_post2<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_cheb_post2<T, CPT, false>), dim3((unsigned)row_blocks(n, ld, CPT)),
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, y, d0, x, U, V, kc,
                                             status));
 }
