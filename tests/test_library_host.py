@@ -117,3 +117,18 @@ def test_calls_out_of_order_are_rejected_on_the_host():
         ctx.init()
     assert ei.value.code == ae.ESTATE
     ctx.close()
+
+
+def test_joint_batch_calls_reject_unbound_members_on_the_host():
+    """The joint batch entry points check their members before any device
+    call: unbound (or uninitialised) members are state errors, and an empty
+    list is a no-op."""
+    p = configs.square(8, q=2)
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], 2, ae.defaults(coarse_max=20, coarse_min=8))
+    for call in (lambda: ae.init_batch_joint([ctx]), lambda: ae.correct_batch_joint([ctx], 1)):
+        with pytest.raises(ae.AmgEigError) as ei:
+            call()
+        assert ei.value.code == ae.ESTATE
+    ae.init_batch_joint([])
+    ae.correct_batch_joint([], 1)
+    ctx.close()
