@@ -667,8 +667,8 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
 }
 
 // Wide blocks: U = P Y + V X_v on the correction level.  One wavefront per
-// 16 consecutive rows, striding over the row tiles so that each workgroup
-// stages X_v in LDS once: V X_v as 16 x 16 tiles on the FP64 matrix cores,
+// 16 consecutive rows, looping over the row tiles of its workgroup so that each
+// workgroup stages X_v in LDS once: V X_v as 16 x 16 tiles on the FP64 matrix cores,
 // then each lane adds the prolongation P Y for its four
 // (row, column) entries of the tile and writes them.  The first kPRow entries
 // of the lane's four rows of P are held in registers across the column tiles,
@@ -686,8 +686,12 @@ __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t 
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int c = lane & 15, kk = lane >> 4;
     const int tj = (ld + 15) / 16;
-    const int64_t tiles = (n + 15) / 16, stride = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t tile = xcd_block() * (blockDim.x / kWave) + wv; tile < tiles; tile += stride) {
+    // workgroup b owns a contiguous range of row tiles, which its wavefronts
+    // take in turn: neighbouring fine rows, whose prolongation reads the same
+    // coarse rows of Y, run on the same CU close together in time
+    const int64_t tiles = (n + 15) / 16, nbk = gridDim.x, lb = xcd_block();
+    const int64_t t0 = tiles * lb / nbk, t1 = tiles * (lb + 1) / nbk;
+    for (int64_t tile = t0 + wv; tile < t1; tile += blockDim.x / kWave) {
         const int64_t r0 = tile * 16;
         int32_t pb[4], pe[4], pc[4][kPRow];
         double pv[4][kPRow];
