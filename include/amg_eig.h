@@ -159,13 +159,14 @@ int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_st
 /* Batching form of the correction (Algorithm 3.1, steps of eq (3.3)): enqueue
  * `steps` correction steps for each of n initialised contexts, with the small
  * eigenproblem of every member solved jointly.  Per step, each member's
- * residual, V-cycle and projection products run on its own stream; the lead
- * stream (that of cs[0]) then waits for all of them and solves the n small
- * pencils in three launches over a device-side table of per-request
- * descriptors (one workgroup per member for the pencil and the Ritz polish, qe
- * workgroups per member for the eigenvalues, members of different d_n and qe
- * side by side, up to 64 per launch); the members' streams wait for that and
- * recombine.  Results are bitwise those of amg_eig_correct on each member.
+ * residual, V-cycle, dual SpMM, Gram product and restriction chain run on its
+ * own stream; the lead stream (that of cs[0]) then waits for all of them and,
+ * over a device-side table of per-request descriptors (members of different
+ * N, d_n and qe side by side, up to 64 per launch), forms the coarse products
+ * Z^T B (a work list of 16 x 16 tiles over all members), solves the n small
+ * pencils in three launches (one workgroup per member for the pencil and the
+ * Ritz polish, qe workgroups per member for the eigenvalues) and forms
+ * Y = Z X_c; the members' streams wait for that and recombine.  Results are bitwise those of amg_eig_correct on each member.
  * A member whose options ask for graphs (and whose site timing is off)
  * replays its two own parts from graphs captured on its first joint step; the
  * joint launches are eager.  Members may share streams.  A context may appear

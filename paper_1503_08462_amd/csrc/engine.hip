@@ -495,8 +495,34 @@ void build_tail(amg_eig_ctx *c) {
 
 // Rayleigh-Ritz on level k in three parts: the products that form the small
 // pencil (up to Z^T B), the small eigensolver, and the recombination
-void rr_front(amg_eig_ctx *c, int k) {
+// The two coarse-space products of a Rayleigh-Ritz step on level k: FG =
+// Z^T B (B the block W restricted to the coarsest level, or Z_t^T B on the
+// tail level) and Y = Z X_c (Z_t X_c on the tail level).
+void coarse_gemms(const amg_eig_ctx *c, int k, GemmDesc *fg, GemmDesc *yg) {
     const int L = (int)c->dl.size(), ld = c->ld, dn = c->H.dn;
+    const bool tail = c->tail >= 0 && k < c->tail;
+    const int bottom = tail ? c->tail : L - 1;
+    const double *src = bottom > k ? c->dl[bottom].cw : c->W;
+    if (tail) {
+        const int nt = (int)c->dl[bottom].n;
+        *fg = GemmDesc{c->Zk, src, c->sw.FG, dn, 2 * ld, nt, dn, 2 * ld, 2 * ld, 1};
+        *yg = GemmDesc{c->Zkt, c->sw.Xc, c->dl[bottom].cw, nt, ld, dn, nt, ld, ld, 1};
+    } else {
+        *fg = GemmDesc{c->Z, src, c->sw.FG, dn, 2 * ld, dn, dn, 2 * ld, 2 * ld, 0};
+        *yg = GemmDesc{c->Zt, c->sw.Xc, c->Yn, dn, ld, dn, dn, ld, ld, 0};
+    }
+}
+
+void launch_desc(hipStream_t s, const GemmDesc &g, const int *st) {
+    if (g.long_k)
+        launch_gemm_tn_long<double>(s, g.m, g.n, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, st);
+    else
+        launch_gemm_tn<double>(s, g.m, g.n, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, st);
+}
+
+// with_gemm = false leaves Z^T B to the caller (the joint batch launches it)
+void rr_front(amg_eig_ctx *c, int k, bool with_gemm = true) {
+    const int L = (int)c->dl.size(), ld = c->ld;
     hipStream_t s = c->stream;
     const int *st = c->status;
     DevLevel &d = c->dl[k];
@@ -520,11 +546,10 @@ void rr_front(amg_eig_ctx *c, int k) {
         src = b.cw;
     }
     site_mark(c, AMG_EIG_SITE_SMALL, k);  // the small site spans Z^T B .. Z X_c
-    if (tail) {
-        const int nt = (int)c->dl[bottom].n;
-        launch_gemm_tn_long<double>(s, dn, 2 * ld, nt, c->Zk, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
-    } else {
-        launch_gemm_tn<double>(s, dn, 2 * ld, dn, c->Z, dn, src, 2 * ld, c->sw.FG, 2 * ld, st);
+    if (with_gemm) {
+        GemmDesc fg, yg;
+        coarse_gemms(c, k, &fg, &yg);
+        launch_desc(s, fg, st);
     }
 }
 
@@ -535,26 +560,19 @@ void rr_small(amg_eig_ctx *c, int k) {
     launch_arrow_eig(c->stream, c->sw, c->qe, c->theta, k == 0 ? 1 : 0);
 }
 
-void rr_back(amg_eig_ctx *c, int k) {
-    const int L = (int)c->dl.size(), ld = c->ld, dn = c->H.dn;
+// with_gemm = false: Y = Z X_c was launched by the caller (the joint batch)
+void rr_back(amg_eig_ctx *c, int k, bool with_gemm = true) {
+    const int L = (int)c->dl.size(), ld = c->ld;
     hipStream_t s = c->stream;
     const int *st = c->status;
     DevLevel &d = c->dl[k];
     const bool tail = c->tail >= 0 && k < c->tail;
     const int bottom = tail ? c->tail : L - 1;
-    const double *y;
-    {
-        if (tail) {  // Y on the tail level = Zk X_c
-            double *yt = c->dl[bottom].cw;
-            launch_gemm_tn_long<double>(s, (int)c->dl[bottom].n, ld, dn, c->Zkt, (int)c->dl[bottom].n, c->sw.Xc,
-                                        ld, yt, ld, st);
-            y = yt;
-        } else {
-            launch_gemm_tn<double>(s, dn, ld, dn, c->Zt, dn, c->sw.Xc, ld, c->Yn, ld, st);
-            y = c->Yn;
-        }
-        site_mark(c, AMG_EIG_SITE_SMALL, k);
-    }
+    GemmDesc fg, yg;
+    coarse_gemms(c, k, &fg, &yg);
+    if (with_gemm) launch_desc(s, yg, st);
+    const double *y = yg.C;  // Y on the tail level (Z_t X_c) or on the coarsest level
+    site_mark(c, AMG_EIG_SITE_SMALL, k);
     for (int l = bottom - 1; l > k; --l) {
         DevLevel &a = c->dl[l];
         launch_spmm<double>(s, a.n, ld, a.p_ptr, a.p_col, a.p64, y, a.cw, st, a.cpt[1]);
@@ -584,7 +602,7 @@ void residual(amg_eig_ctx *c, int k, int check) {
                            c->status, check, d.cpt[1]);
 }
 
-void correction_front(amg_eig_ctx *c, int k) {
+void correction_front(amg_eig_ctx *c, int k, bool with_gemm = true) {
     if (c->mixed) {
         residual<float>(c, k, k == 0);
         vcycle<float>(c, k);
@@ -592,7 +610,7 @@ void correction_front(amg_eig_ctx *c, int k) {
         residual<double>(c, k, k == 0);
         vcycle<double>(c, k);
     }
-    rr_front(c, k);
+    rr_front(c, k, with_gemm);
 }
 
 void correction(amg_eig_ctx *c, int k) {
@@ -639,25 +657,25 @@ void nested_prolong(amg_eig_ctx *c, int k) {
 // warm-bracket flag and the rank survive)
 void reset_step_count(amg_eig_ctx *c) { launch_fill_i32(c->stream, 2, 0, c->status); }
 
-// part 0: residual, V-cycle and the products up to Z^T B; part 1: the
-// recombination.  Replayed from a captured graph when the context asks for
+// part 0: residual, V-cycle and the products before Z^T B; part 1: the
+// recombination after Y = Z X_c (the joint batch launches both products).  Replayed from a captured graph when the context asks for
 // graphs and no site timing is on.
 int enqueue_part(amg_eig_ctx *c, int part) {
     if (c->o.use_graph && c->stream && !c->timing) {
         if (!c->part_exec[part]) {
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             if (part == 0)
-                correction_front(c, 0);
+                correction_front(c, 0, false);
             else
-                rr_back(c, 0);
+                rr_back(c, 0, false);
             HIPCHK(c, hipStreamEndCapture(c->stream, &c->part_graph[part]));
             HIPCHK(c, hipGraphInstantiate(&c->part_exec[part], c->part_graph[part], nullptr, nullptr, 0));
         }
         HIPCHK(c, hipGraphLaunch(c->part_exec[part], c->stream));
     } else if (part == 0) {
-        correction_front(c, 0);
+        correction_front(c, 0, false);
     } else {
-        rr_back(c, 0);
+        rr_back(c, 0, false);
     }
     return AMG_EIG_OK;
 }
@@ -703,10 +721,29 @@ int check_joint(amg_eig_ctx *const *cs, int n, bool initialised) {
     return AMG_EIG_OK;
 }
 
+// The fg (which = 0) or yg (1) products of up to kMaxBatch members at the
+// finest level, one launch per tile code.
+void launch_gemms(hipStream_t s, amg_eig_ctx *const *cs, int m, int which) {
+    for (int lk = 0; lk < 2; ++lk) {
+        GemmTable t{};
+        t.which = which;
+        t.n = 0;
+        t.first[0] = 0;
+        for (int j = 0; j < m; ++j) {
+            const GemmDesc &g = which ? cs[j]->item_host.yg : cs[j]->item_host.fg;
+            if (g.long_k != lk) continue;
+            t.item[t.n] = cs[j]->item_dev;
+            t.first[t.n + 1] = t.first[t.n] + ((g.m + 15) / 16) * ((g.n + 15) / 16);
+            ++t.n;
+        }
+        launch_gemm_batch(s, t, lk == 1);
+    }
+}
+
 // The small eigenproblems of n members whose front parts are enqueued: the
 // stream of cs[0] waits for the others (one event per distinct stream), runs
 // the three batched kernels over their descriptors, and the others wait for it.
-int joint_small(amg_eig_ctx *const *cs, int n, int final_level) {
+int joint_small(amg_eig_ctx *const *cs, int n, int final_level, bool gemms) {
     if (n <= 0) return AMG_EIG_OK;
     amg_eig_ctx *lead = cs[0];
     hipStream_t ls = lead->stream;
@@ -735,7 +772,9 @@ int joint_small(amg_eig_ctx *const *cs, int n, int final_level) {
             lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
             lds.rr = std::max(lds.rr, c->small_lds.rr);
         }
+        if (gemms) launch_gemms(ls, cs + i0, m, 0);
         launch_small_batch(ls, t, lds, kRankTol);
+        if (gemms) launch_gemms(ls, cs + i0, m, 1);
     }
     HIPCHK(lead, hipEventRecord(lead->join_ev, ls));
     for (amg_eig_ctx *o : others) HIPCHK(o, hipStreamWaitEvent(o->stream, lead->join_ev, 0));
@@ -823,6 +862,7 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     launch_fill_i32(c->stream, ST_COUNT, 0, c->status);
     launch_fill_i32(c->stream, 5 * kMaxWidth + 8, 0, c->sw.diag);
     small_layout(c->sw, c->qe, c->theta, &c->item_host, &c->small_lds);
+    coarse_gemms(c, 0, &c->item_host.fg, &c->item_host.yg);
     rc = put(c, c->item_dev, &c->item_host, sizeof(SmallItem));
     if (rc) return rc;
     std::vector<unsigned> zero(16, 0u);
@@ -969,7 +1009,7 @@ int amg_eig_correct_batch_joint(amg_eig_ctx *const *cs, int n, int steps) {
     for (int step = 0; step < steps && n > 0; ++step) {
         for (int i = 0; i < n; ++i)
             if ((rc = enqueue_part(cs[i], 0))) return rc;
-        if ((rc = joint_small(cs, n, 1))) return rc;
+        if ((rc = joint_small(cs, n, 1, true))) return rc;
         for (int i = 0; i < n; ++i)
             if ((rc = enqueue_part(cs[i], 1))) return rc;
     }
@@ -999,7 +1039,7 @@ int amg_eig_init_batch_joint(amg_eig_ctx *const *cs, int n) {
             if (k >= 1) correction_front(c, k);
         }
         if (k == 0) break;
-        if ((rc = joint_small(act.data(), (int)act.size(), 0))) return rc;
+        if ((rc = joint_small(act.data(), (int)act.size(), 0, false))) return rc;
         for (amg_eig_ctx *c : act) rr_back(c, k);
     }
     for (int i = 0; i < n; ++i) {

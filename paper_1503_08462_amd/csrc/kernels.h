@@ -125,11 +125,19 @@ void clear_launch_events();
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol);
 // one request's small-eigensolver launch parameters, kept in device memory for
 // the batched launches
+// C (m x n, row stride ldc) = A^T B, A K x m and B K x n row-major (FP64);
+// long_k selects the sixteen-wavefront tile code
+struct GemmDesc {
+    const double *A = nullptr, *B = nullptr;
+    double *C = nullptr;
+    int m = 0, n = 0, K = 0, lda = 0, ldb = 0, ldc = 0, long_k = 0;
+};
 struct SmallItem {
     SmallWork w;
     double *theta = nullptr;  // Ritz values: previous on entry, new on exit
     int qe = 0;
     int fg_in_lds = 0, ct_in_lds = 0, use_lds = 0;
+    GemmDesc fg, yg;  // finest-level steps: Z^T B into FG, and Y = Z X_c
 };
 struct SmallLds {
     size_t pencil = 0, bisect = 0, rr = 0;  // dynamic LDS bytes per kernel
@@ -145,6 +153,14 @@ struct SmallTable {
 // pencil, eigenpairs and Ritz polish of every member of the table, three
 // launches in all; lds holds the largest size over the members
 void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol);
+struct GemmTable {
+    const SmallItem *item[kMaxBatch];  // device addresses
+    int first[kMaxBatch + 1];          // tiles of member m: first[m] .. first[m+1]-1
+    int n;
+    int which;                         // 0: the fg product, 1: the yg product
+};
+// the fg or yg products of the members of the table (all with the same long_k)
+void launch_gemm_batch(hipStream_t s, const GemmTable &t, bool long_k);
 // eigenpairs of H, Ritz polish and recombination coefficients; theta holds the
 // previous Ritz values on entry and the new ones on exit
 void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level);

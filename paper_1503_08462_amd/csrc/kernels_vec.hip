@@ -411,12 +411,10 @@ __global__ __launch_bounds__(256) void k_dense_rows(int64_t m, int64_t K, const 
 // 16 x 16 tile of C; its four wavefronts take a quarter of K each and the
 // partial tiles are summed in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_tn(int m, int n, int K, const T *__restrict__ A, int lda,
-                                                 const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
-                                                 const int *status) {
+__device__ __forceinline__ void gemm_tn_tile(int m, int n, int K, const T *__restrict__ A, int lda,
+                                             const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc, int ta,
+                                             int tb) {
     __shared__ double part[4 * 256];
-    if (status[ST_CONVERGED]) return;
-    const int ta = blockIdx.x, tb = blockIdx.y;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int chunk = ((K + 3) / 4 + 3) & ~3;
     const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
@@ -442,16 +440,22 @@ __global__ __launch_bounds__(256) void k_gemm_tn(int m, int n, int K, const T *_
     if (i < m && j < n) C[(int64_t)i * ldc + j] = (T)v;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_tn(int m, int n, int K, const T *__restrict__ A, int lda,
+                                                 const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
+                                                 const int *status) {
+    if (status[ST_CONVERGED]) return;
+    gemm_tn_tile<T>(m, n, K, A, lda, B, ldb, C, ldc, blockIdx.x, blockIdx.y);
+}
+
 // C (m x n) = A^T B as k_gemm_tn for long K: one workgroup of 16 wavefronts
 // per 16 x 16 tile of C, each wavefront a sixteenth of K, the partial tiles
 // summed in a fixed order in LDS.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_gemm_tn_long(int m, int n, int K, const T *__restrict__ A, int lda,
-                                                       const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
-                                                       const int *status) {
+__device__ __forceinline__ void gemm_tn_long_tile(int m, int n, int K, const T *__restrict__ A, int lda,
+                                                  const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
+                                                  int ta, int tb) {
     __shared__ double red[16 * 256];
-    if (status[ST_CONVERGED]) return;
-    const int ta = blockIdx.x, tb = blockIdx.y;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int chunk = ((K + nw - 1) / nw + 3) & ~3;
     const int k0 = wv * chunk, k1 = K < k0 + chunk ? K : k0 + chunk;
@@ -478,6 +482,34 @@ __global__ __launch_bounds__(1024) void k_gemm_tn_long(int m, int n, int K, cons
         if (i < m && j < n) C[(int64_t)i * ldc + j] = (T)v;
     }
 }
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gemm_tn_long(int m, int n, int K, const T *__restrict__ A, int lda,
+                                                       const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
+                                                       const int *status) {
+    if (status[ST_CONVERGED]) return;
+    gemm_tn_long_tile<T>(m, n, K, A, lda, B, ldb, C, ldc, blockIdx.x, blockIdx.y);
+}
+
+// The coarse-space products of several requests in one launch: workgroup b
+// computes tile b - first[r] of request r's product (the descriptors live in
+// the requests' device memory), with the same tile code as the single launch.
+template <bool LONG>
+__device__ __forceinline__ void gemm_batch_body(const GemmTable &t) {
+    int r = 0;
+    while (r + 1 < t.n && t.first[r + 1] <= (int)blockIdx.x) ++r;
+    const SmallItem *it = t.item[r];
+    if (it->w.status[ST_CONVERGED]) return;
+    const GemmDesc g = t.which ? it->yg : it->fg;
+    const int local = (int)blockIdx.x - t.first[r], tm = (g.m + 15) / 16;
+    const int ta = local % tm, tb = local / tm;
+    if constexpr (LONG)
+        gemm_tn_long_tile<double>(g.m, g.n, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, ta, tb);
+    else
+        gemm_tn_tile<double>(g.m, g.n, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, ta, tb);
+}
+__global__ __launch_bounds__(256) void k_gemm_tn_batch(GemmTable t) { gemm_batch_body<false>(t); }
+__global__ __launch_bounds__(1024) void k_gemm_tn_long_batch(GemmTable t) { gemm_batch_body<true>(t); }
 
 // b (n x ld) = columns j0 .. j0 + ld - 1 of the identity
 template <typename T>
@@ -1053,6 +1085,14 @@ void launch_gemm_tn_long(hipStream_t s, int m, int n, int K, const T *A, int lda
 }
 template void launch_gemm_tn_long<float>(hipStream_t, int, int, int, const float *, int, const float *, int, float *,
                                          int, const int *);
+
+void launch_gemm_batch(hipStream_t s, const GemmTable &t, bool long_k) {
+    if (t.n <= 0 || t.first[t.n] <= 0) return;
+    if (long_k)
+        hipLaunchKernelGGL(k_gemm_tn_long_batch, dim3((unsigned)t.first[t.n]), dim3(1024), 0, s, t);
+    else
+        hipLaunchKernelGGL(k_gemm_tn_batch, dim3((unsigned)t.first[t.n]), dim3(256), 0, s, t);
+}
 template void launch_gemm_tn_long<double>(hipStream_t, int, int, int, const double *, int, const double *, int,
                                           double *, int, const int *);
 
