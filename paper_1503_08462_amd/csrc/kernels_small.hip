@@ -1248,18 +1248,23 @@ __global__ __launch_bounds__(256) void k_arrow_rr_batch(SmallTable t) {
 }
 
 // ------------------------------------------------------------ launchers
+// Dynamic LDS a small kernel may take for its optional copies: the 160 KB of a
+// gfx950 workgroup less 4 KB for the kernels' static shared arrays (at most
+// 2.9 KB).
+constexpr size_t kLdsBudget = 160 * 1024 - 4096;
+
 void small_layout(const SmallWork &w, int qe, double *theta, SmallItem *it, SmallLds *lds) {
     const size_t ld = w.ld, dn = w.dn;
     const size_t pbase = ld <= 32 ? 10 * ld * ld + kRedSmall + dn + 1 : 3 * ld * ld + 64 + dn + 1;
-    const int fg_in_lds = (pbase + dn * 2 * ld) * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    const int fg_in_lds = (pbase + dn * 2 * ld) * sizeof(double) <= kLdsBudget ? 1 : 0;
     // the rank r <= ld is only known on the device: size for r = ld
     const size_t ldp = (ld + 15) & ~(size_t)15, dtl = ld <= 32 ? ldp * ldp : 0;  // the kernel's layout
     const size_t bbase = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64 + dn + ldp;
-    const int ct_in_lds = (bbase + dn * ldp) * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    const int ct_in_lds = (bbase + dn * ldp) * sizeof(double) <= kLdsBudget ? 1 : 0;
     const size_t rsmall = ld <= 32;
     const size_t rbase = 3 * ld * ld + (rsmall ? kRed : 64) + dn + 1 + (rsmall ? ld * ld : 0);
     const size_t full = rbase + 2 * (dn + ld) * ld + dn * ld;
-    const int use_lds = full * sizeof(double) <= 150 * 1024 ? 1 : 0;
+    const int use_lds = full * sizeof(double) <= kLdsBudget ? 1 : 0;
     it->w = w;
     it->theta = theta;
     it->qe = qe;
