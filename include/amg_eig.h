@@ -43,6 +43,8 @@ extern "C" {
 /* ----------------------------------------------------------------- codes */
 #define AMG_EIG_OK 0
 #define AMG_EIG_NOT_CONVERGED 1   /* warning: best-so-far results returned */
+#define AMG_EIG_WIDENED 2         /* warning: automatic block width raised (see
+                                     amg_eig_progress); the iterate is discarded */
 #define AMG_EIG_EINVAL (-1)       /* malformed input or option */
 #define AMG_EIG_ENOTSPD (-2)      /* a_ii <= 0 or m_ii < 0 */
 #define AMG_EIG_EBREAKDOWN (-3)   /* projected problem lost definiteness */
@@ -70,7 +72,10 @@ typedef struct {
     int coarse_max;     /* stop coarsening once d_k <= coarse_max */
     int coarse_min;     /* never create a level smaller than this (0: auto) */
     int max_levels;     /* hierarchy depth limit */
-    int qe;             /* block width (wanted + extra pairs); 0: guard rule */
+    int qe;             /* block width (wanted + extra pairs); 0: guard rule
+                           on the coarsest eigenvalues, rounded up to a
+                           multiple of 4, then the width control of
+                           amg_eig_progress() */
     double guard_gap;   /* guard rule: block may not end inside a cluster of
                            relative width < guard_gap */
     int smoother;       /* AMG_EIG_SMOOTH_* */
@@ -81,6 +86,8 @@ typedef struct {
     double tol;         /* convergence: max_{j<=q} rho_j <= tol */
     int max_steps;      /* finest-level corrections in amg_eig_solve */
     int use_graph;      /* capture one correction step as a hipGraph */
+    int qe_max;         /* widest block the automatic width control may choose
+                           (0: min(80, d_n, N - d_n)) */
 } amg_eig_opts;
 
 /* Paper defaults (Section 4.1: theta = 0.25, one V-cycle with one pre- and
@@ -140,20 +147,44 @@ int amg_eig_correct(amg_eig_ctx *c, int steps);
 /* Wait for the bound stream and report the current Ritz values theta[qe],
  * relative residuals rho[qe] (of the iterate before the last step's update),
  * the number of corrections done and whether the test holds.  Any output
- * pointer may be NULL.  rho_j = ||A u_j - theta_j M u_j||_2 / (theta_j ||M u_j||_2). */
+ * pointer may be NULL.  rho_j = ||A u_j - theta_j M u_j||_2 / (theta_j ||M u_j||_2),
+ * the stopping test of the driver (Algorithm 3.2 with the residual of (3.1)).
+ *
+ * Block width control (contexts set up with opts.qe = 0, whose width comes
+ * from the guard rule on the coarsest eigenvalues): the coarsest level may
+ * not resolve a cluster of eigenvalues, and a block that ends inside one
+ * stalls.  When, after at least 12 corrections since the start,
+ * max_{j<=q} rho_j has fallen by less than a factor 2 over the last 8 or more
+ * corrections while the Ritz values past the q-th show no relative gap >=
+ * guard_gap inside the block, the width is doubled (at most qe_max) - the
+ * paper's remedy of computing extra eigenpairs (Section 4.5) - and WIDENED is
+ * returned: the iterate is discarded, and amg_eig_init() must follow, after a
+ * bind of a workspace of amg_eig_footprint() bytes if the new width does not
+ * fit the bound one (the context is then unbound).  Once a widened block has
+ * converged, the next start takes the narrowest multiple of 4 whose Ritz
+ * values end at such a gap.  amg_eig_info() reports the width in effect.
+ * Errors: ESTATE (not bound), EBREAKDOWN, EHIP. */
 int amg_eig_progress(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged);
 
-/* init(NESTED) unless already initialised, then correct until
- * max_{j<=q} rho_j <= tol or max_steps corrections; copies the q wanted
- * eigenvalues to lambda_host[q] and eigenvectors to U_dev (device, N x ldu
- * row-major, ldu >= q) when non-NULL.  Returns NOT_CONVERGED (with the
- * best-so-far pairs) if the step limit is reached. */
+/* Driver of Algorithm 3.2: init(NESTED) unless already initialised, then
+ * correction steps (Algorithm 3.1) until max_{j<=q} rho_j <= tol or max_steps
+ * corrections; copies the q wanted eigenvalues to lambda_host[q] and
+ * eigenvectors to U_dev (device, N x ldu row-major, ldu >= q) when non-NULL.
+ * A solve of an iterate that an earlier call left converged re-tests it
+ * against this tol.  When the block width control widens the block inside the
+ * bound workspace, the solve restarts with the wider block by itself; when
+ * the wider block needs a larger workspace it returns WIDENED (bind, then call
+ * again).  Returns NOT_CONVERGED (with the best-so-far pairs) if the step
+ * limit is reached. */
 int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host, double *U_dev,
                   int64_t ldu);
 
-/* Enqueue `steps` correction steps for each of n bound contexts on one stream
- * (requests of uneven N batched on the device; each context keeps its own
- * hierarchy and block).  Errors: ESTATE, EHIP. */
+/* Batching form of the correction step (Algorithm 3.1): enqueue `steps`
+ * correction steps for each of n initialised contexts (requests of uneven N;
+ * each context keeps its own hierarchy and block), step by step across the
+ * members.  hip_stream NULL: each member on its own bound stream, so the
+ * kernels of different members overlap; else every member must be bound to
+ * that stream.  Errors: EINVAL, ESTATE, EHIP. */
 int amg_eig_correct_batch(amg_eig_ctx *const *cs, int n, int steps, void *hip_stream);
 
 /* Batching form of the correction (Algorithm 3.1, steps of eq (3.3)): enqueue

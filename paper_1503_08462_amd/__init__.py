@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, WIDENED = 0, 1, 2
 EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EWORKSPACE, EHIP, ECANCELLED, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
 SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
@@ -50,6 +50,7 @@ class Opts(ctypes.Structure):
         ("smoother", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("cheb_lo", ctypes.c_double),
         ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("precision", ctypes.c_int),
         ("tol", ctypes.c_double), ("max_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
+        ("qe_max", ctypes.c_int),
     ]
 
 
@@ -190,6 +191,7 @@ class Context:
     # --------------------------------------------------------- device side
     def bind(self, device="cuda", stream=None):
         import torch
+        self.workspace = None  # a rebind releases the old workspace first
         self.workspace = torch.empty(self.footprint(), dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         self._check(_lib.amg_eig_bind(self._c, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
@@ -206,19 +208,30 @@ class Context:
         self._check(_lib.amg_eig_correct(self._c, steps))
 
     def progress(self):
+        """Ritz values, residuals, corrections done, convergence; "widened" is
+        True when the block width control raised the width (the iterate is then
+        discarded: bind again if `bound` is False, then init)."""
         qe = self.info()["qe"]
         th, rh = np.zeros(qe), np.zeros(qe)
         st, cv = ctypes.c_int(), ctypes.c_int()
-        self._check(_lib.amg_eig_progress(self._c, _p(th), _p(rh), ctypes.byref(st), ctypes.byref(cv)))
-        return {"theta": th, "rho": rh, "steps": st.value, "converged": bool(cv.value)}
+        rc = self._check(_lib.amg_eig_progress(self._c, _p(th), _p(rh), ctypes.byref(st), ctypes.byref(cv)))
+        widened = rc == WIDENED
+        return {"theta": th, "rho": rh, "steps": st.value, "converged": bool(cv.value) and not widened,
+                "widened": widened, "bound": not widened or self.footprint() <= self.workspace.numel()}
 
     def solve(self, tol=1e-8, max_steps=100, U_out=None):
+        """Algorithm 3.2 to max_{j<=q} rho_j <= tol; a widened block that needs a
+        larger workspace is bound to a new one (same device and stream) and the
+        solve starts again."""
         lam = np.zeros(self.q)
         ptr, ldu = None, 0
         if U_out is not None:
             ptr, ldu = ctypes.c_void_p(U_out.data_ptr()), U_out.stride(0)
-        rc = self._check(_lib.amg_eig_solve(self._c, tol, max_steps, _p(lam), ptr, ldu))
-        return lam, rc == OK
+        while True:
+            rc = self._check(_lib.amg_eig_solve(self._c, tol, max_steps, _p(lam), ptr, ldu))
+            if rc != WIDENED:
+                return lam, rc == OK
+            self.bind(device=self.workspace.device, stream=self.stream)
 
     def iterate(self):
         """The device iterate as a torch view (N x ld FP64, first qe columns used)."""

@@ -81,6 +81,17 @@ struct amg_eig_ctx {
     SmallItem item_host;
     SmallLds small_lds;
     hipEvent_t join_ev = nullptr;
+    // the bound workspace, kept for changes of the block width inside it
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    // block width control of the solve driver (automatic width, opts.qe = 0):
+    // the width may be raised when the iteration stalls with the block ending
+    // inside a cluster, and lowered for later starts once a widened block
+    // has converged and its Ritz values show a gap earlier
+    bool width_auto = false, width_decided = true, widened = false;
+    int qe_cap = 0;   // widest block the control may choose
+    int qe_next = 0;  // > 0: block width to take at the next start
+    std::vector<std::pair<int, double>> hist;  // (finest corrections, max_{j<q} rho_j) per progress call
     // host staging kept alive until the upload completes
     std::vector<std::vector<char>> staging;
     hipGraph_t graph = nullptr;
@@ -149,6 +160,11 @@ void choose_tail(amg_eig_ctx *c) {
 }
 
 // ------------------------------------------------------------ memory plan
+// Everything whose size does not depend on the block width (matrices, the
+// coarse basis, the dense tail operator, Ritz values and residuals sized for
+// the widest block, flags) comes first; the blocks follow.  A change of the
+// block width inside the same workspace (width control of the solve driver)
+// therefore keeps every uploaded array where it is.
 void plan(amg_eig_ctx *c, char *base) {
     Carver cv(base);
     const Hierarchy &H = c->H;
@@ -181,6 +197,29 @@ void plan(amg_eig_ctx *c, char *base) {
             d.pt_val = cv.take<char>(lv.Pt.col.size() * sT);
             d.pt64 = cv.take<double>(lv.Pt.col.size());
         }
+    }
+    c->Z = cv.take<double>((size_t)dn * dn);
+    c->Zt = cv.take<double>((size_t)dn * dn);
+    c->lam = cv.take<double>(dn);
+    c->Ainv = cv.take<char>((size_t)dn * dn * sT);
+    c->theta = cv.take<double>(kMaxWidth);
+    c->rho = cv.take<double>(kMaxWidth);
+    c->counters = cv.take<unsigned>(16);
+    if (c->tail >= 0) {
+        const int nt = (int)H.lv[c->tail].n;
+        c->Bt = cv.take<char>((size_t)nt * nt * sT);
+        c->Zk = cv.take<double>((size_t)nt * dn);
+        c->Zkt = cv.take<double>((size_t)nt * dn);
+    }
+    c->status = cv.take<int>(ST_COUNT);
+    c->item_dev = cv.take<SmallItem>(1);
+#if AMG_EIG_SMALL_STATS
+    int *diag = cv.take<int>(5 * kMaxWidth + 8);
+#endif
+    // ---- blocks (width ld)
+    for (int l = 0; l < L; ++l) {
+        const Level &lv = H.lv[l];
+        DevLevel &d = c->dl[l];
         d.b = cv.take<char>((size_t)lv.n * ld * sT);
         d.r = cv.take<char>((size_t)lv.n * ld * sT);
         d.x = cv.take<char>((size_t)lv.n * ld * sT);
@@ -190,25 +229,11 @@ void plan(amg_eig_ctx *c, char *base) {
     c->U = cv.take<double>((size_t)N * ld);
     c->V = cv.take<double>((size_t)N * ld);
     c->W = cv.take<double>((size_t)N * 2 * ld);
-    c->Z = cv.take<double>((size_t)dn * dn);
-    c->Zt = cv.take<double>((size_t)dn * dn);
-    c->lam = cv.take<double>(dn);
-    c->Ainv = cv.take<char>((size_t)dn * dn * sT);
     c->Yn = cv.take<double>((size_t)dn * ld);
-    c->theta = cv.take<double>(ld);
-    c->rho = cv.take<double>(ld);
     int64_t maxn = 0;
     for (const Level &lv : H.lv) maxn = std::max(maxn, lv.n);
     c->part_res = cv.take<double>(((size_t)residual_blocks_max(maxn, ld) + 1) * 2 * ld);
     c->part_gram = cv.take<double>((size_t)gram_blocks(maxn, ld) * 2 * ld * ld);
-    c->counters = cv.take<unsigned>(16);
-    if (c->tail >= 0) {
-        const int nt = (int)H.lv[c->tail].n;
-        c->Bt = cv.take<char>((size_t)nt * nt * sT);
-        c->Zk = cv.take<double>((size_t)nt * dn);
-        c->Zkt = cv.take<double>((size_t)nt * dn);
-    }
-    c->status = cv.take<int>(ST_COUNT);
     SmallWork &w = c->sw;
     w.dn = dn;
     w.ld = ld;
@@ -228,8 +253,11 @@ void plan(amg_eig_ctx *c, char *base) {
     w.Xc = cv.take<double>((size_t)dn * ld);
     w.Xv = cv.take<double>((size_t)ld * ld);
     w.status = c->status;
-    w.diag = cv.take<int>(5 * kMaxWidth + 8);
-    c->item_dev = cv.take<SmallItem>(1);
+#if AMG_EIG_SMALL_STATS
+    w.diag = diag;
+#else
+    w.diag = nullptr;
+#endif
     c->need = cv.off + 256;
 }
 
@@ -632,6 +660,80 @@ void drop_graph(amg_eig_ctx *c) {
     }
 }
 
+// ------------------------------------------------------ block width control
+// The guard rule of the paper's "compute extra eigenpairs" strategy (Section
+// 4.5) on Ritz values th[0..n): the smallest m in [q, n-1] with a relative
+// gap th[m] / th[m-1] - 1 >= gap after the m-th value, or 0 when the values
+// past the q-th show no such gap inside the block.
+int closed_width(const double *th, int n, int q, double gap) {
+    for (int m = q; m < n; ++m)
+        if (th[m - 1] > 0.0 && th[m] / th[m - 1] - 1.0 >= gap) return m;
+    return 0;
+}
+
+int round4(int w) { return (w + 3) / 4 * 4; }
+
+// Give the context block width w.  When it is bound and the workspace holds
+// the new plan, the blocks are re-carved in place (the uploaded matrices,
+// coarse basis and dense tail keep their addresses) and true is returned;
+// otherwise the context is left unbound with amg_eig_footprint() bytes needed.
+// Either way the iterate is discarded: a start must follow.
+bool set_width(amg_eig_ctx *c, int w) {
+    drop_graph(c);
+    c->qe = c->ld = w;
+    c->initialised = false;
+    c->hist.clear();
+    plan(c, nullptr);
+    if (c->bound && c->ws && c->need <= c->ws_bytes) {
+        plan(c, c->ws);
+        small_layout(c->sw, c->qe, c->theta, &c->item_host, &c->small_lds);
+        coarse_gemms(c, 0, &c->item_host.fg, &c->item_host.yg);
+        if (hipMemcpyAsync(c->item_dev, &c->item_host, sizeof(SmallItem), hipMemcpyHostToDevice, c->stream) ==
+            hipSuccess)
+            return true;
+    }
+    c->bound = false;
+    return false;
+}
+
+// Called with the host copies of the Ritz values and residuals after every
+// progress report.  A block that stalls (after at least 12 corrections,
+// max_{j<q} rho_j reduced by less than a factor 2 over the last 8 or more;
+// a block that holds its cluster may rise and fall during its first dozen
+// corrections, one cut inside a cluster stays flat) while no gap of the guard rule lies
+// inside it past the q-th value ends inside a cluster: its width is doubled
+// (up to qe_cap) and true is returned.  After a widened block converges, the
+// next start takes the narrowest multiple of 4 that ends at such a gap.
+bool width_check(amg_eig_ctx *c, const double *th, const double *rho, int steps, int conv) {
+    if (!c->width_auto || c->width_decided) return false;
+    const int q = c->q, qe = c->qe;
+    if (conv) {
+        c->width_decided = true;
+        if (c->widened) {
+            const int m = closed_width(th, qe, q, c->o.guard_gap);
+            if (m > 0 && round4(m) < qe) c->qe_next = round4(m);
+        }
+        return false;
+    }
+    double r = 0.0;
+    for (int j = 0; j < q; ++j) r = std::max(r, rho[j]);
+    c->hist.emplace_back(steps, r);
+    if (steps < 12 || !(r > c->o.tol)) return false;
+    double r0 = -1.0;
+    for (const auto &h : c->hist)
+        if (h.first <= steps - 8) r0 = h.second;
+    if (r0 <= 0.0 || !(r > 0.5 * r0)) return false;
+    if (closed_width(th, qe, q, c->o.guard_gap) > 0) return false;
+    const int w = std::min(c->qe_cap, round4(2 * qe));
+    if (w <= qe) {
+        c->width_decided = true;
+        return false;
+    }
+    c->widened = true;
+    set_width(c, w);
+    return true;
+}
+
 // Algorithm 3.2: the coarsest eigenpairs start the block; the prolongated
 // coarsest eigenvectors already approximate the wanted ones, so the first
 // Rayleigh-Ritz step may start from them (the inertia counts still certify
@@ -803,6 +905,7 @@ void amg_eig_opts_default(amg_eig_opts *o) {
     o->tol = 1e-8;
     o->max_steps = 100;
     o->use_graph = 0;
+    o->qe_max = 0;
 }
 
 int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o, amg_eig_ctx **out) {
@@ -837,6 +940,14 @@ int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_e
     c->q = q;
     c->ld = c->qe;
     c->mixed = c->o.precision == AMG_EIG_PREC_MIXED;
+    c->width_auto = c->o.qe <= 0;
+    c->width_decided = !c->width_auto;
+    {
+        const int64_t n0 = c->H.lv[0].n, dn = c->H.dn;
+        int cap = (int)std::min<int64_t>({(int64_t)kMaxWidth, dn, n0 - dn});
+        if (c->o.qe_max > 0) cap = std::min(cap, c->o.qe_max);
+        c->qe_cap = std::max(c->qe, cap / 4 * 4);
+    }
     choose_tail(c);
     plan(c, nullptr);
     *out = c;
@@ -855,12 +966,14 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
         return fail(c, AMG_EIG_EWORKSPACE, "workspace missing, unaligned or smaller than the footprint");
     drop_graph(c);
     c->stream = (hipStream_t)hip_stream;
+    c->ws = (char *)ws;
+    c->ws_bytes = bytes;
     plan(c, (char *)ws);
     c->staging.clear();
     int rc = c->mixed ? upload_levels<float>(c) : upload_levels<double>(c);
     if (rc) return rc;
     launch_fill_i32(c->stream, ST_COUNT, 0, c->status);
-    launch_fill_i32(c->stream, 5 * kMaxWidth + 8, 0, c->sw.diag);
+    if (c->sw.diag) launch_fill_i32(c->stream, 5 * kMaxWidth + 8, 0, c->sw.diag);
     small_layout(c->sw, c->qe, c->theta, &c->item_host, &c->small_lds);
     coarse_gemms(c, 0, &c->item_host.fg, &c->item_host.yg);
     rc = put(c, c->item_dev, &c->item_host, sizeof(SmallItem));
@@ -884,6 +997,12 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
 int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, int64_t ldu) {
     if (!c) return AMG_EIG_EINVAL;
     if (!c->bound) return fail(c, AMG_EIG_ESTATE, "init before bind");
+    if (c->qe_next > 0) {  // a converged widened block showed a narrower one suffices
+        const int w = c->qe_next;
+        c->qe_next = 0;
+        if (!set_width(c, w)) return fail(c, AMG_EIG_EHIP, "block width change inside the workspace failed");
+    }
+    c->hist.clear();
     const int L = (int)c->dl.size(), ld = c->ld, qe = c->qe;
     hipStream_t s = c->stream;
     const int64_t N = c->dl[0].n;
@@ -918,30 +1037,53 @@ int amg_eig_correct(amg_eig_ctx *c, int steps) {
     return enqueue_steps(c, steps);
 }
 
+namespace {
+// progress report; `control` lets the block width control act on it
+int progress_report(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged, bool control);
+}  // namespace
+
 int amg_eig_progress(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged) {
+    return progress_report(c, theta, rho, steps, converged, true);
+}
+
+namespace {
+int progress_report(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged, bool control) {
     if (!c) return AMG_EIG_EINVAL;
     if (!c->bound) return fail(c, AMG_EIG_ESTATE, "progress before bind");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     int st[ST_COUNT];
+    double th[kMaxWidth], rh[kMaxWidth];
     HIPCHK(c, hipMemcpy(st, c->status, sizeof(st), hipMemcpyDeviceToHost));
-    if (theta) HIPCHK(c, hipMemcpy(theta, c->theta, c->qe * sizeof(double), hipMemcpyDeviceToHost));
-    if (rho) HIPCHK(c, hipMemcpy(rho, c->rho, c->qe * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(th, c->theta, c->qe * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(rh, c->rho, c->qe * sizeof(double), hipMemcpyDeviceToHost));
+    if (theta) std::memcpy(theta, th, c->qe * sizeof(double));
+    if (rho) std::memcpy(rho, rh, c->qe * sizeof(double));
     if (steps) *steps = st[ST_STEPS];
     if (converged) *converged = st[ST_CONVERGED];
     if (st[ST_BREAKDOWN]) return fail(c, AMG_EIG_EBREAKDOWN, "projected problem lost definiteness");
+    if (control && c->initialised && width_check(c, th, rh, st[ST_STEPS], st[ST_CONVERGED])) {
+        fail(c, AMG_EIG_WIDENED, "block width raised to " + std::to_string(c->qe));
+        return AMG_EIG_WIDENED;
+    }
     return AMG_EIG_OK;
 }
+}  // namespace
 
 int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host, double *U_dev, int64_t ldu) {
     if (!c) return AMG_EIG_EINVAL;
     if (!c->bound) return fail(c, AMG_EIG_ESTATE, "solve before bind");
     if (tol > 0 && tol != c->o.tol) {
         c->o.tol = tol;
-        drop_graph(c);
+        drop_graph(c);  // the captured step holds the old tolerance
     }
     if (!c->initialised) {
         int rc = amg_eig_init(c, AMG_EIG_INIT_NESTED, 0, nullptr, 0);
         if (rc) return rc;
+    } else {
+        // the converged flag may stem from an earlier test with a looser
+        // tolerance: clear it, so that the first step re-evaluates the residual
+        // of the current iterate against this tolerance
+        launch_fill_i32(c->stream, 1, 0, c->status + ST_CONVERGED);
     }
     int done = 0, conv = 0, steps = 0, rc;
     // Steps go out in chunks between synchronisations.  Convergence of the
@@ -958,6 +1100,17 @@ int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host
         if (rc) return rc;
         done += chunk;
         rc = amg_eig_progress(c, nullptr, rho.data(), &steps, &conv);
+        if (rc == AMG_EIG_WIDENED) {
+            // the block ended inside a cluster: start again with the wider block
+            // (a larger workspace is the caller's to bind)
+            if (!c->bound) return rc;
+            rho.assign(c->qe, 0.0);
+            if ((rc = amg_eig_init(c, AMG_EIG_INIT_NESTED, 0, nullptr, 0))) return rc;
+            rho_prev = -1.0;
+            steps_prev = 0;
+            chunk = 4;
+            continue;
+        }
         if (rc) return rc;
         const double r = *std::max_element(rho.begin(), rho.begin() + c->q);
         chunk = 4;
@@ -974,7 +1127,7 @@ int amg_eig_solve(amg_eig_ctx *c, double tol, int max_steps, double *lambda_host
             residual<float>(c, 0, 1);
         else
             residual<double>(c, 0, 1);
-        rc = amg_eig_progress(c, nullptr, nullptr, &steps, &conv);
+        rc = progress_report(c, nullptr, nullptr, &steps, &conv, false);
         if (rc) return rc;
     }
     if (lambda_host) HIPCHK(c, hipMemcpy(lambda_host, c->theta, c->q * sizeof(double), hipMemcpyDeviceToHost));
@@ -1258,14 +1411,17 @@ const char *amg_eig_strerror(int code) {
 
 const char *amg_eig_last_error(const amg_eig_ctx *c) { return c ? c->err.c_str() : ""; }
 
-// Solver statistics of the small eigensolver since bind (not part of the
-// public header): per eigenvalue index the inertia counts, warm brackets
-// used and calls, then the Jacobi sweeps and phase times.  out has 5 * 80 + 8 ints.
+#if AMG_EIG_SMALL_STATS
+// Solver statistics of the small eigensolver since bind, in builds with
+// AMG_EIG_SMALL_STATS only (not part of the public header): per eigenvalue
+// index the inertia counts, warm brackets used and calls, then the Jacobi
+// sweeps and phase clocks.  out has 5 * kMaxWidth + 8 ints.
 int amg_eig_internal_diag(amg_eig_ctx *c, int *out) {
     if (!c || !out || !c->bound) return AMG_EIG_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->sw.diag, (5 * kMaxWidth + 8) * sizeof(int), hipMemcpyDeviceToHost));
     return AMG_EIG_OK;
 }
+#endif
 
 }  // extern "C"

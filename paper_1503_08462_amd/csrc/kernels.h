@@ -61,9 +61,6 @@ template <typename T>
 void launch_cheb_post2(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
                        const T *val, const T *dinv, const T *y, const T *d0, T *x, const double *U, double *V,
                        double lo, const int *status, int cpt = 0);
-template <typename T, typename TA>
-void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
-                       const int *status);
 // C (m x n) = A^T B, A K x m, B K x n (row-major), FP64 matrix-core accumulation
 template <typename T>
 void launch_gemm_tn(hipStream_t s, int m, int n, int K, const T *A, int lda, const T *B, int ldb, T *C, int ldc,
@@ -113,7 +110,8 @@ struct SmallWork {
     double *Xc = nullptr;         // dn x ld: coarse coefficients
     double *Xv = nullptr;         // ld x ld: coefficients of V
     int *status = nullptr;
-    int *diag = nullptr;          // 4 * kMaxWidth + 8 counters (solver statistics)
+    int *diag = nullptr;          // 5 * kMaxWidth + 8 counters (solver statistics; null unless
+                                  // built with AMG_EIG_SMALL_STATS)
 };
 // Start/stop events for the next launch of a single-kernel launcher (the
 // residual, smoothing, SpMM, dual SpMM and final-update launchers): recorded

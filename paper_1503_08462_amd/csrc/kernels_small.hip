@@ -27,6 +27,21 @@ namespace amgeig {
 namespace {
 
 constexpr int kB = 256;  // threads per block of the small kernels
+
+// Solver statistics (inertia counts per eigenvalue, fallbacks, Jacobi sweeps
+// and phase clocks, added into w.diag) are compiled in only with
+// -DAMG_EIG_SMALL_STATS=1.  Otherwise no clock is read and w.diag is null, so
+// every statistics branch is skipped.
+#ifndef AMG_EIG_SMALL_STATS
+#define AMG_EIG_SMALL_STATS 0
+#endif
+__device__ __forceinline__ uint64_t stat_clock() {
+#if AMG_EIG_SMALL_STATS
+    return wall_clock64();
+#else
+    return 0;
+#endif
+}
 // Rayleigh-quotient iteration stops at ||H x - rho x|| <= kRqiTol |rho|.  The
 // Rayleigh-Ritz polish over the span of all accepted vectors then leaves the
 // Ritz values with errors of the order of the squared residual over the gap.
@@ -318,7 +333,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
     const int rcap = small ? kRedSmall : 64;
     __shared__ int perm[kMaxWidth];
     uint64_t tk[8];  // solver statistics: phase clocks (thread 0)
-    tk[0] = wall_clock64();
+    tk[0] = stat_clock();
     for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
     if (fg_in_lds) block_copy(fg, w.FG, dn * 2 * ld);
     if (small) block_copy(gagl, w.GAGM, 2 * ld * ld);
@@ -326,7 +341,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
     __syncthreads();
     const int l2 = 2 * ld;
     auto fgv = [&](int i, int a) -> double { return fg_in_lds ? fg[i * l2 + a] : w.FG[(int64_t)i * l2 + a]; };
-    tk[1] = wall_clock64();
+    tk[1] = stat_clock();
     // P3 = G^T [F | G | Lambda G]   (G = FG(:, ld:2ld), F = FG(:, 0:ld))
     block_xty([&](int i, int a) -> double { return a < ld ? fgv(i, ld + a) : 0.0; },
               [&](int i, int b) -> double {
@@ -352,7 +367,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
         Li[e] = 0.0;
     }
     __syncthreads();
-    tk[2] = wall_clock64();
+    tk[2] = stat_clock();
     // pivoted Cholesky of D_M, the same symmetric permutation applied to D_A
     int r = 0;
     for (int p = 0; p < ld; ++p) {
@@ -414,7 +429,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
         r = p + 1;
         __syncthreads();
     }
-    tk[3] = wall_clock64();
+    tk[3] = stat_clock();
     // L^-1 (column c by thread c)
     if (tid < r) {
         const int c = tid;
@@ -447,7 +462,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
     }
     if (tid < ld) w.perm[tid] = perm[tid];
     if (tid == 0) w.status[ST_RANK] = r;
-    tk[4] = wall_clock64();
+    tk[4] = stat_clock();
     // C~ = (F - Lambda G)(:, perm_r) L^-T on the matrix cores
     block_tiles(
         [&](int k, int i) -> double {
@@ -458,7 +473,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
         [&](int k, int a) -> double { return a < r ? Li[a * ld + k] : 0.0; }, r, dn, ld,
         [&](int i, int a, double v) { w.Ct[(int64_t)i * ld + a] = v; }, red, rcap);
     if (tid == 0 && w.diag) {
-        tk[5] = wall_clock64();
+        tk[5] = stat_clock();
         for (int j = 0; j < 5; ++j) atomicAdd(&w.diag[330 + j], (int)(tk[j + 1] - tk[j]));
     }
 }
@@ -507,7 +522,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
     __shared__ int ipiv[kMaxWidth];
     __shared__ unsigned long long tim[8];  // solver statistics: phase clocks
     if (tid < 8) tim[tid] = 0;
-    const uint64_t t_begin = wall_clock64();
+    const uint64_t t_begin = stat_clock();
     if (ct_in_lds) {  // rows of ld doubles (ld a multiple of 4) as double2 pairs
         const int hp = ldp / 2, hl = ld / 2;
         for (int e = tid; e < dn * hp; e += nthr) {
@@ -526,7 +541,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
             dtl[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
         }
     __syncthreads();
-    if (tid == 0) tim[0] += wall_clock64() - t_begin;
+    if (tid == 0) tim[0] += stat_clock() - t_begin;
     auto ct = [&](int i, int a) -> double {
         if (ct_in_lds) return ctl[i * ldp + a];
         return a < ld ? w.Ct[(int64_t)i * ld + a] : 0.0;  // columns r..ld-1 hold zeros
@@ -546,7 +561,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
     // ---- factorisation of H - sigma through S(sigma); returns nu(sigma)
     auto factor = [&](double sigma) -> int {
         ++ncount;
-        const uint64_t f0 = wall_clock64();
+        const uint64_t f0 = stat_clock();
         int lo_i = 0, hi_i = dn;  // #{lambda_i < sigma}, lam ascending
         while (lo_i < hi_i) {
             const int mid = (lo_i + hi_i) / 2;
@@ -606,11 +621,11 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
             }
         }
         __syncthreads();
-        const uint64_t f1 = wall_clock64();
+        const uint64_t f1 = stat_clock();
         const int neg = bk_factor(S, Lm, r, ls, ipiv);
         if (tid == 0) {
             tim[1] += f1 - f0;
-            tim[2] += wall_clock64() - f1;
+            tim[2] += stat_clock() - f1;
         }
         return nlow + neg;
     };
@@ -644,7 +659,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
 
     // ---- x <- (H - sigma)^-1 x for the factorisation in S, ipiv, wdn
     auto solve = [&](double *x) {
-        const uint64_t s0 = wall_clock64();
+        const uint64_t s0 = stat_clock();
         for (int i = tid; i < dn; i += nthr) x[i] *= wdn[i];  // t = (Lambda - sigma)^-1 x_y
         __syncthreads();
         ct_t_times(x, fz);
@@ -658,7 +673,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         }
         for (int a = tid; a < r; a += nthr) x[dn + a] = fz[a];
         __syncthreads();
-        if (tid == 0) tim[3] += wall_clock64() - s0;
+        if (tid == 0) tim[3] += stat_clock() - s0;
     };
     auto normalise = [&](double *x) {
         double s2 = 0.0;
@@ -671,7 +686,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
     };
     // rho = x^T H x (x normalised) and ||H x - rho x||
     auto rayleigh = [&](const double *x, double &rho, double &res) {
-        const uint64_t q0 = wall_clock64();
+        const uint64_t q0 = stat_clock();
         ct_t_times(x, fz);  // C~^T y
         for (int i = tid; i < dn; i += nthr) {
             double s2 = lam[i] * x[i];
@@ -693,7 +708,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
             e2 += d * d;
         }
         res = sqrt(bsum(e2));
-        if (tid == 0) tim[4] += wall_clock64() - q0;
+        if (tid == 0) tim[4] += stat_clock() - q0;
     };
 
     // ---- warm start.  The corrected vector V e_k has the coordinates
@@ -898,7 +913,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi))) break;
     }
     if (tid == 0 && w.diag && (k == 0 || k == nk - 1)) {
-        tim[5] = wall_clock64() - t_begin;
+        tim[5] = stat_clock() - t_begin;
         int *slot = w.diag + (k == 0 ? 5 * kMaxWidth - 8 : 3 * kMaxWidth);
         for (int j = 0; j < 6; ++j) atomicAdd(&slot[j], (int)tim[j]);
     }
@@ -927,7 +942,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
     uint64_t tk[9];  // solver statistics: phase clocks (thread 0)
-    tk[0] = wall_clock64();
+    tk[0] = stat_clock();
     double *T = sm;                 // ld x ld
     double *Q = T + ldp * ldp;      // ld x ld
     double *G = Q + ldp * ldp;      // ld x ld
@@ -964,7 +979,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     __shared__ double s_off;
     __shared__ int order[kMaxWidth];
     __shared__ double s_theta[kMaxWidth];
-    tk[1] = wall_clock64();
+    tk[1] = stat_clock();
     // ---- Cholesky-QR on X (nh x m); a second pass unless every pivot of the
     // first was within 10% of 1 (then X was already orthonormal to a few
     // units of rounding and one pass leaves it so).  A column whose pivot
@@ -1059,7 +1074,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
         ++passes;
         if (near_identity) break;
     }
-    tk[2] = wall_clock64();
+    tk[2] = stat_clock();
     // ---- HX (nh x m): rows i < dn: lam_i x_i + C~_i z ; rows dn+a: C~^T y + D~ z
     block_tiles([&](int a, int i) -> double { return (i < dn && a < r) ? Ctp[(int64_t)i * ld + a] : 0.0; },
                 [&](int a, int c) -> double { return c < m ? Xp[(int64_t)(dn + a) * ld + c] : 0.0; }, r, dn, m,
@@ -1069,7 +1084,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     block_tiles([&](int b, int a) -> double { return (a < r && b < r) ? dtv[b * ldp + a] : 0.0; },  // D~ symmetric
                 [&](int b, int c) -> double { return c < m ? Xp[(int64_t)(dn + b) * ld + c] : 0.0; }, r, r, m,
                 [&](int a, int c, double v) { HXp[(int64_t)(dn + a) * ld + c] += v; }, red, rcap);
-    tk[3] = wall_clock64();
+    tk[3] = stat_clock();
     // ---- T = X^T HX, symmetrised
     block_xty(xa, hxa, nh, m, m, Q, ldp, red, rcap);
     for (int e = tid; e < m * m; e += nthr) {
@@ -1082,7 +1097,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
         Q[a * ldp + b] = a == b ? 1.0 : 0.0;
     }
     __syncthreads();
-    tk[4] = wall_clock64();
+    tk[4] = stat_clock();
     // ---- cyclic Jacobi with the round-robin ordering (m even)
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int round = 0; round < m - 1; ++round) {
@@ -1147,7 +1162,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
         __syncthreads();
         if (s_off < 1e-15) break;
     }
-    tk[5] = wall_clock64();
+    tk[5] = stat_clock();
     // ---- sort Ritz values ascending and write Xr = X Q(:, order), theta
     if (tid == 0) {
         for (int a = 0; a < m; ++a) {
@@ -1170,13 +1185,13 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
         w.theta[c] = th;
         theta_out[c] = th;
     }
-    tk[6] = wall_clock64();
+    tk[6] = stat_clock();
     // ---- Ritz vectors of H: Xr = X Q(:, order)   (H X is no longer needed)
     double *Xr = use_lds ? HXp : w.Xr;
     block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
                 [&](int a, int c) -> double { return c < m ? Q[a * ldp + order[c]] : 0.0; }, m, nh, ld,
                 [&](int i, int c, double v) { Xr[(int64_t)i * ld + c] = v; }, red, rcap);
-    tk[7] = wall_clock64();
+    tk[7] = stat_clock();
     // ---- recombination coefficients X_v = Pi_r L^-T z, X_c = y - G X_v
     double *Li = G;   // r x r, stride ldp (only the lower triangle is read)
     double *Xv = T;   // ld x ld, stride ldp
@@ -1204,7 +1219,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
         w.status[ST_WARM] = 1;
         if (final_level) w.status[ST_STEPS] += 1;
         if (w.diag) {
-            tk[8] = wall_clock64();
+            tk[8] = stat_clock();
             for (int j = 0; j < 8; ++j) atomicAdd(&w.diag[321 + j], (int)(tk[j + 1] - tk[j]));
         }
     }

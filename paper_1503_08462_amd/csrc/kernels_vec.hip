@@ -11,7 +11,6 @@
 //   k_prolong_add   y = D^-1 b + P x_c (coarse-grid correction of x1)
 //   k_smooth_post   x = y + D^-1 (b - A y); on the correction level it writes
 //                   the FP64 block V = U + x
-//   k_dense_rows    C = A B for a small dense A (coarse solve, Z products)
 //   k_dual_spmm     W = [A V | M V] (FP64, shared pattern)
 //   k_gram          [V^T A V | V^T M V] by a two-phase deterministic reduction
 //   k_final         U = P Y + V X_v on the correction level (recombination)
@@ -388,21 +387,6 @@ __global__ __launch_bounds__(256) void k_cheb_post2(int64_t n, int ld, const int
     } else {
         stv<T, CPT>(x + rm.row * ld + c0, o);
     }
-}
-
-// ------------------------------------------------------------ dense rows
-template <typename T, typename TA, int CPT>
-__global__ __launch_bounds__(256) void k_dense_rows(int64_t m, int64_t K, const TA *__restrict__ A, int64_t lda,
-                                                    int ld, const T *__restrict__ B, T *__restrict__ C,
-                                                    const int *status) {
-    if (status[ST_CONVERGED]) return;
-    RowMap rm(ld, CPT, m);
-    if (!rm.active) return;
-    const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = zero_v<T, CPT>();
-    const TA *arow = A + rm.row * lda;
-    for (int64_t l = 0; l < K; ++l) fma_v(acc, (T)arow[l], ldv<T, CPT>(B + l * ld + c0));
-    stv<T, CPT>(C + rm.row * ld + c0, acc);
 }
 
 // ------------------------------------------------------------ small GEMM
@@ -957,13 +941,6 @@ void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int3
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
 }
 
-template <typename T, typename TA>
-void launch_dense_rows(hipStream_t s, int64_t m, int64_t K, const TA *A, int64_t lda, int ld, const T *B, T *C,
-                       const int *status) {
-    DISPATCH_CPT(ld, 0, hipLaunchKernelGGL((k_dense_rows<T, TA, CPT>), dim3((unsigned)row_blocks(m, ld, CPT)),
-                                        dim3(kBlock), 0, s, m, K, A, lda, ld, B, C, status));
-}
-
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                       const double *m, const double *V, double *W, const int *status, int cpt) {
     DISPATCH_CPT(ld, cpt, KLAUNCH((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
@@ -1161,9 +1138,5 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
 INST(float)
 INST(double)
 #undef INST
-template void launch_dense_rows<float, float>(hipStream_t, int64_t, int64_t, const float *, int64_t, int,
-                                              const float *, float *, const int *);
-template void launch_dense_rows<double, double>(hipStream_t, int64_t, int64_t, const double *, int64_t, int,
-                                                const double *, double *, const int *);
 
 }  // namespace amgeig

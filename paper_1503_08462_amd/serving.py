@@ -9,7 +9,9 @@ of different requests overlap on the device, and by default solves the small
 eigenproblems (3.3) of all of them in shared launches.  Requests join at a
 round boundary (after their Algorithm 3.2 start) and leave as soon as their
 convergence test holds or their step limit is reached, which frees their
-memory for the next arrivals (continuous batching).  Latency is measured from
+memory for the next arrivals (continuous batching).  A request whose block
+the library widens (its block ended inside a cluster of eigenvalues) goes back
+to the head of the queue with its larger footprint.  Latency is measured from
 submission (or the given arrival time) to completion.
 
 The scheduler only orders host calls into the library; every step of a solve
@@ -29,7 +31,7 @@ def _default_init(contexts):
 
 class Request:
     __slots__ = ("id", "ctx", "q", "tol", "max_steps", "footprint", "arrival", "admitted", "done", "stream",
-                 "result")
+                 "result", "widened")
 
     def __init__(self, rid, ctx, q, tol, max_steps, arrival):
         self.id, self.ctx, self.q, self.tol, self.max_steps = rid, ctx, q, tol, max_steps
@@ -38,6 +40,7 @@ class Request:
         self.admitted = self.done = None
         self.stream = None
         self.result = None
+        self.widened = 0
 
 
 class Server:
@@ -125,14 +128,39 @@ class Server:
             self.active.extend(new)
 
     def _retire(self):
-        still = []
+        still, again = [], []
         for req in self.active:
             pr = req.ctx.progress()
+            if pr.get("widened"):
+                # the library raised the block width (the block ended inside a
+                # cluster): the iterate is gone; start again in place, or wait
+                # for memory at the head of the queue with the larger footprint
+                if pr.get("bound"):
+                    self._init([req.ctx])
+                    still.append(req)
+                else:
+                    self.in_use -= req.footprint
+                    if hasattr(req.ctx, "workspace"):
+                        req.ctx.workspace = None
+                    req.footprint = req.ctx.footprint()
+                    req.widened += 1
+                    if req.footprint <= self.budget:
+                        again.append(req)
+                        continue
+                    # the wider block can never be admitted: finish unconverged
+                    req.done = self.clock()
+                    req.result = {"lam": np.asarray(pr["theta"][:req.q]).copy(),
+                                  "rho": np.asarray(pr["rho"][:req.q]).copy(), "steps": pr["steps"],
+                                  "converged": False, "latency_s": req.done - req.arrival,
+                                  "widened": req.widened}
+                    req.ctx.close()
+                    self.finished[req.id] = req
+                continue
             if pr["converged"] or pr["steps"] >= req.max_steps:
                 req.done = self.clock()
                 req.result = {"lam": np.asarray(pr["theta"][:req.q]).copy(), "rho": np.asarray(pr["rho"][:req.q]).copy(),
                               "steps": pr["steps"], "converged": bool(pr["converged"]),
-                              "latency_s": req.done - req.arrival}
+                              "latency_s": req.done - req.arrival, "widened": req.widened}
                 req.ctx.close()
                 if hasattr(req.ctx, "workspace"):
                     req.ctx.workspace = None  # back to the allocator for the next admissions
@@ -141,6 +169,7 @@ class Server:
             else:
                 still.append(req)
         self.active = still
+        self.queue[:0] = again
 
     def round(self):
         """One scheduling round; returns the number of requests still pending."""

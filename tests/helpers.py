@@ -1,7 +1,9 @@
-"""Shared test helpers: dense brute force, cluster-aware subspace comparison."""
+"""Shared test helpers: dense brute force, an independent reference spectrum,
+cluster-aware subspace comparison."""
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 def mats(p):
@@ -18,12 +20,26 @@ def brute_force(p, count):
     return sla.eigh(A.toarray(), M.toarray(), subset_by_index=[0, count - 1])
 
 
-def gap_prefixes(lam, q, gap=1e-2):
-    """Prefix sizes m <= q after which the spectrum has a relative gap >= gap."""
-    out = []
-    for m in range(1, min(q, len(lam) - 1) + 1):
-        if lam[m] / lam[m - 1] - 1.0 >= gap:
-            out.append(m)
+def reference_eigenvalues(p, count):
+    """The `count` smallest eigenvalues of (A, M), ascending: dense LAPACK for
+    N <= 2500, else shift-invert Lanczos about 0 (ARPACK through SciPy).  Both
+    are library solvers independent of the oracle and of the HIP path; used to
+    place the cluster gaps that decide which subspaces are comparable."""
+    A, M = mats(p)
+    if p["n"] <= 2500:
+        return sla.eigh(A.toarray(), M.toarray(), eigvals_only=True, subset_by_index=[0, count - 1])
+    lam = spla.eigsh(A.tocsc(), k=count, M=M.tocsc(), sigma=0.0, which="LM", return_eigenvectors=False,
+                     ncv=max(2 * count + 1, count + 20))
+    return np.sort(lam)
+
+
+def gap_prefixes(lam, q, qe=None, gap=1e-2):
+    """Prefix sizes m after which the reference spectrum lam has a relative gap
+    lam[m] / lam[m-1] - 1 >= gap: every such m <= q, and m = qe (the whole
+    block) when lam holds at least qe + 1 values."""
+    out = [m for m in range(1, min(q, len(lam) - 1) + 1) if lam[m] / lam[m - 1] - 1.0 >= gap]
+    if qe is not None and qe > q and len(lam) > qe and lam[qe] / lam[qe - 1] - 1.0 >= gap:
+        out.append(qe)
     return out
 
 
@@ -40,9 +56,14 @@ def sin_angle_M(Uref, U, M):
     return float(np.sqrt(max(0.0, np.linalg.eigvalsh(0.5 * (S + S.T)).max())))
 
 
-def compare_subspaces(lam_ref, Uref, U, M, q, gap=1e-2):
-    """Max over gap-delimited prefixes m <= q of sin angle between the m-dim subspaces."""
+def compare_subspaces(lam_ref, Uref, U, M, q, qe=None, gap=1e-2, min_prefixes=1):
+    """Largest sine of the angle between the m-dimensional leading subspaces of
+    Uref and U over the gap-delimited prefixes of lam_ref (gap_prefixes), and
+    the list of prefix sizes compared.  Fails when fewer than `min_prefixes`
+    prefixes qualify, so that a check never passes by comparing nothing."""
+    ms = gap_prefixes(lam_ref, q, qe, gap)
+    assert len(ms) >= min_prefixes, "no gap-delimited prefix to compare (q=%d, qe=%s)" % (q, qe)
     worst = 0.0
-    for m in gap_prefixes(lam_ref, q, gap):
+    for m in ms:
         worst = max(worst, sin_angle_M(Uref[:, :m], U[:, :m], M))
-    return worst
+    return worst, ms

@@ -58,7 +58,9 @@ def test_semidefinite_mass_matches_brute_force(prec):
     tol = 1e-10 if prec == ae.PREC_FP64 else 1e-6
     assert np.abs(lam / lam_ref[:q] - 1).max() < tol, (lam, lam_ref[:q])
     # subspaces in the A inner product (M2 is only a seminorm)
-    for m in gap_prefixes(lam_ref, q):
+    ms = gap_prefixes(lam_ref, q)
+    assert ms, "no gap-delimited prefix to compare"
+    for m in ms:
         assert sin_angle_M(XA[:, :m], U[:, :m], A) < 1e-6
     Uq = U[:, :q]
     assert np.abs(Uq.T @ (M2 @ Uq) - np.eye(q)).max() < 1e-10
@@ -76,4 +78,6 @@ def test_smallest_admissible_problems(m, q, cm):
     assert ok, pr
     assert np.abs(lam / lam_ref[:q] - 1).max() < 1e-10
     _, M = mats(p)
-    assert compare_subspaces(lam_ref, Uref, U, M, q) < 1e-6
+    worst, ms = compare_subspaces(lam_ref, Uref, U, M, q, qe=U.shape[1])
+    print("compared prefixes", ms, "sin", worst)
+    assert worst < 1e-6

@@ -29,7 +29,8 @@ def test_converges_to_dense_brute_force(name, make, smoother):
     assert info["rho"][:q].max() <= 1e-11
     ref, Uref = brute_force(p, o.qe + 1)
     assert np.abs(lam[:q] / ref[:q] - 1).max() < 1e-10
-    assert compare_subspaces(ref, Uref, U, M, q) < 1e-6
+    worst, ms = compare_subspaces(ref, Uref, U, M, q, qe=o.qe)
+    assert worst < 1e-6, (worst, ms)
     assert np.abs(U.T @ (M @ U) - np.eye(o.qe)).max() < 1e-12
 
 
@@ -81,7 +82,7 @@ def test_exact_eigenpairs_are_a_fixed_point():
     ref, Uref = brute_force(p, 5)
     lam, U = o.correction(0, ref[:4].copy(), Uref[:, :4].copy())
     assert np.abs(lam / ref[:4] - 1).max() < 1e-13
-    assert compare_subspaces(ref, Uref, U, M, 4) < 1e-10
+    assert compare_subspaces(ref, Uref, U, M, 4, qe=4)[0] < 1e-10
 
 
 @pytest.mark.parametrize("smoother,bound", [("gs", 0.25), ("l1jacobi", 0.45), ("chebyshev", 0.15)])
@@ -181,3 +182,34 @@ def test_chebyshev_smoother_is_the_scaled_chebyshev_polynomial(degree, lo):
     # the scaled polynomial is bounded by 1 / T_s(theta / delta) on [lo, 1]
     on = (lam >= lo)
     assert np.abs(pl[on]).max() <= 1.0 / cheb_t(degree, np.array([theta / delta]))[0] + 1e-14
+
+
+def test_eig_pencil_range_restriction_on_dependent_basis():
+    """Rayleigh-Ritz (Algorithm 3.1 step 2) on a basis with dependent columns:
+    B = [B1, B1 C] makes the projected mass matrix M^ = B^T M B singular, and
+    the oracle's small solver then restricts the pencil to the range of M^.
+    With A, M positive definite the projected pencil's finite eigenpairs are
+    those of (B1^T A B1, B1^T M B1) on the independent basis B1, so dense brute
+    force there fixes both the values and the spanned subspace."""
+    import scipy.linalg as sla
+    from tests.helpers import sin_angle_M
+    p = configs.square(12, q=4)
+    A, M = mats(p)
+    rng = np.random.default_rng(3)
+    B1 = rng.standard_normal((p["n"], 9))
+    B = np.hstack([B1, B1 @ rng.standard_normal((9, 3))])
+    Ah = B.T @ (A @ B)
+    Mh = B.T @ (M @ B)
+    # precondition: M^ is singular to rounding, so the Cholesky branch is not taken
+    try:
+        c = np.linalg.cholesky(0.5 * (Mh + Mh.T))
+        assert (np.diag(c) ** 2).min() <= 1e-13 * np.diag(Mh).max()
+    except np.linalg.LinAlgError:
+        pass
+    mu, X = Oracle.eig_pencil(Ah, Mh, 5)
+    ref, Y = sla.eigh(B1.T @ (A @ B1), B1.T @ (M @ B1), subset_by_index=[0, 5])
+    assert np.abs(mu / ref[:5] - 1).max() < 1e-9
+    V = B @ X
+    assert np.abs(V.T @ (M @ V) - np.eye(5)).max() < 1e-9
+    assert ref[5] / ref[4] - 1 > 1e-2  # the 5-dimensional subspace is isolated
+    assert sin_angle_M(B1 @ Y[:, :5], V, M) < 1e-7

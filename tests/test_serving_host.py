@@ -128,3 +128,55 @@ def test_requests_admitted_in_one_round_start_together():
     assert starts[0] == ["a", "b", "c"]  # d does not fit until b and c leave
     assert starts[1] == ["d"]
     assert batches[0] == ["a", "b", "c"]
+
+
+class WideningCtx(FakeCtx):
+    """Stalls until its block is widened once: the first progress report after
+    `stall` corrections says the width was raised and the footprint doubled
+    (the context unbound, its iterate gone); after the next bind and start it
+    converges after `need` corrections."""
+
+    def __init__(self, p, opts):
+        super().__init__(p, opts)
+        self.stall, self.wide, self.inits = p.get("stall", 10 ** 9), False, 0
+
+    def init(self, mode):
+        assert self.bound
+        self.inits += 1
+        self.steps = 0
+
+    def correct(self, steps):
+        self.steps += steps
+
+    def progress(self):
+        pr = super().progress()
+        if not self.wide and self.stall < 10 ** 9:
+            pr["converged"] = False
+            if self.steps >= self.stall:
+                self.wide, self.bound, self.fp = True, False, 2 * self.fp
+                pr["widened"], pr["bound"] = True, False
+        return pr
+
+
+def test_widened_request_goes_back_to_the_head_of_the_queue():
+    tick = iter(range(10 ** 6))
+    srv = Server(100, context_factory=WideningCtx, batch_fn=lambda cs, n: [c.correct(n) for c in cs],
+                 stream_factory=lambda: object(), clock=lambda: float(next(tick)), steps_per_round=2)
+    a = srv.submit(dict(prob("a", 30, need=4), stall=4))
+    b = srv.submit(prob("b", 60, need=20), max_steps=100)
+    srv.round()  # both admitted (90 of 100)
+    assert srv.in_use == 90 and len(srv.active) == 2
+    srv.round()  # a widens: releases 30 and waits at the head of the queue with 60
+    assert [r.id for r in srv.queue] == [a] and srv.queue[0].footprint == 60 and srv.in_use == 60
+    res = srv.run()
+    assert res[a]["converged"] and res[a]["widened"] == 1 and res[b]["converged"]
+    assert srv.finished[a].ctx.inits == 2 and srv.peak_in_use <= 100
+
+
+def test_widened_request_beyond_the_budget_finishes_unconverged():
+    tick = iter(range(10 ** 6))
+    srv = Server(100, context_factory=WideningCtx, batch_fn=lambda cs, n: [c.correct(n) for c in cs],
+                 stream_factory=lambda: object(), clock=lambda: float(next(tick)), steps_per_round=2)
+    a = srv.submit(dict(prob("a", 70, need=4), stall=2))
+    res = srv.run()
+    assert not res[a]["converged"] and res[a]["widened"] == 1 and srv.in_use == 0
