@@ -153,9 +153,9 @@ int amg_eig_correct(amg_eig_ctx *c, int steps);
  * Block width control (contexts set up with opts.qe = 0, whose width comes
  * from the guard rule on the coarsest eigenvalues): the coarsest level may
  * not resolve a cluster of eigenvalues, and a block that ends inside one
- * stalls.  When, after at least 12 corrections since the start,
- * max_{j<=q} rho_j has fallen by less than a factor 2 over the last 8 or more
- * corrections while the Ritz values past the q-th show no relative gap >=
+ * stalls.  When, after at least 16 corrections since the start, the smallest
+ * max_{j<=q} rho_j reported over the last 10 corrections is not below half
+ * the smallest reported before them, while the Ritz values past the q-th show no relative gap >=
  * guard_gap inside the block, the width is doubled (at most qe_max) - the
  * paper's remedy of computing extra eigenpairs (Section 4.5) - and WIDENED is
  * returned: the iterate is discarded, and amg_eig_init() must follow, after a

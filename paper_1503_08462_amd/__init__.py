@@ -137,6 +137,7 @@ class Context:
         self.q = int(q)
         self.workspace = None
         self.stream = None
+        self._ws_bytes = 0
 
     # ----------------------------------------------------------- host side
     def _check(self, rc):
@@ -196,6 +197,7 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         self._check(_lib.amg_eig_bind(self._c, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                       ctypes.c_void_p(self.stream.cuda_stream)))
+        self._ws_bytes = self.workspace.numel()
         return self
 
     def init(self, mode=INIT_NESTED, seed=0, U=None):
@@ -217,7 +219,7 @@ class Context:
         rc = self._check(_lib.amg_eig_progress(self._c, _p(th), _p(rh), ctypes.byref(st), ctypes.byref(cv)))
         widened = rc == WIDENED
         return {"theta": th, "rho": rh, "steps": st.value, "converged": bool(cv.value) and not widened,
-                "widened": widened, "bound": not widened or self.footprint() <= self.workspace.numel()}
+                "widened": widened, "bound": not widened or self.footprint() <= self._ws_bytes}
 
     def solve(self, tol=1e-8, max_steps=100, U_out=None):
         """Algorithm 3.2 to max_{j<=q} rho_j <= tol; a widened block that needs a

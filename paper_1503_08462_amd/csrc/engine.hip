@@ -697,13 +697,15 @@ bool set_width(amg_eig_ctx *c, int w) {
 }
 
 // Called with the host copies of the Ritz values and residuals after every
-// progress report.  A block that stalls (after at least 12 corrections,
-// max_{j<q} rho_j reduced by less than a factor 2 over the last 8 or more;
-// a block that holds its cluster may rise and fall during its first dozen
-// corrections, one cut inside a cluster stays flat) while no gap of the guard rule lies
-// inside it past the q-th value ends inside a cluster: its width is doubled
-// (up to qe_cap) and true is returned.  After a widened block converges, the
-// next start takes the narrowest multiple of 4 that ends at such a gap.
+// progress report.  A block stalls when, after at least 16 corrections, the
+// smallest max_{j<q} rho_j reported in the last 10 corrections is not below
+// half the smallest reported before them (a block that holds its cluster may
+// rise and fall during its first dozen corrections but keeps making new lows;
+// one cut inside a cluster stays flat).  A stalled block with no gap of the
+// guard rule inside it past the q-th Ritz value ends inside a cluster: its
+// width is doubled (up to qe_cap) and true is returned.  After a widened
+// block converges, the next start takes the narrowest multiple of 4 that ends
+// at such a gap.
 bool width_check(amg_eig_ctx *c, const double *th, const double *rho, int steps, int conv) {
     if (!c->width_auto || c->width_decided) return false;
     const int q = c->q, qe = c->qe;
@@ -718,11 +720,13 @@ bool width_check(amg_eig_ctx *c, const double *th, const double *rho, int steps,
     double r = 0.0;
     for (int j = 0; j < q; ++j) r = std::max(r, rho[j]);
     c->hist.emplace_back(steps, r);
-    if (steps < 12 || !(r > c->o.tol)) return false;
-    double r0 = -1.0;
-    for (const auto &h : c->hist)
-        if (h.first <= steps - 8) r0 = h.second;
-    if (r0 <= 0.0 || !(r > 0.5 * r0)) return false;
+    if (steps < 16 || !(r > c->o.tol)) return false;
+    double recent = -1.0, before = -1.0;
+    for (const auto &h : c->hist) {
+        double &m = h.first > steps - 10 ? recent : before;
+        if (h.second > 0.0 && (m < 0.0 || h.second < m)) m = h.second;
+    }
+    if (before <= 0.0 || recent <= 0.0 || !(recent > 0.5 * before)) return false;
     if (closed_width(th, qe, q, c->o.guard_gap) > 0) return false;
     const int w = std::min(c->qe_cap, round4(2 * qe));
     if (w <= qe) {

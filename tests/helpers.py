@@ -35,11 +35,16 @@ def reference_eigenvalues(p, count):
 
 def gap_prefixes(lam, q, qe=None, gap=1e-2):
     """Prefix sizes m after which the reference spectrum lam has a relative gap
-    lam[m] / lam[m-1] - 1 >= gap: every such m <= q, and m = qe (the whole
-    block) when lam holds at least qe + 1 values."""
-    out = [m for m in range(1, min(q, len(lam) - 1) + 1) if lam[m] / lam[m - 1] - 1.0 >= gap]
-    if qe is not None and qe > q and len(lam) > qe and lam[qe] / lam[qe - 1] - 1.0 >= gap:
-        out.append(qe)
+    lam[m] / lam[m-1] - 1 >= gap: every such m <= q, and, when the q-th value
+    lies inside a cluster that the block of qe columns holds entirely, the end
+    of that cluster (the first such m in (q, qe])."""
+    ok = lambda m: len(lam) > m and lam[m] / lam[m - 1] - 1.0 >= gap
+    out = [m for m in range(1, min(q, len(lam) - 1) + 1) if ok(m)]
+    if qe is not None and not ok(q):
+        for m in range(q + 1, qe + 1):
+            if ok(m):
+                out.append(m)
+                break
     return out
 
 

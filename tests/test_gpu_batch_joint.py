@@ -27,11 +27,13 @@ def _torch():
 
 MEMBERS = [
     # (problem, options): uneven N, q_e, d_n and precision in one batch
-    (lambda: configs.square(16, q=4), dict(coarse_max=100, precision=ae.PREC_FP64)),
-    (lambda: configs.lshape(24, q=6, jitter_seed=4), dict(coarse_max=200, precision=ae.PREC_MIXED)),
-    (lambda: configs.oscillator(40, q=6), dict(coarse_max=150, precision=ae.PREC_FP64)),
+    # (explicit widths: the width control acts on progress reports, whose
+    # cadence differs between joint and separate runs)
+    (lambda: configs.square(16, q=4), dict(coarse_max=100, qe=8, precision=ae.PREC_FP64)),
+    (lambda: configs.lshape(24, q=6, jitter_seed=4), dict(coarse_max=200, qe=8, precision=ae.PREC_MIXED)),
+    (lambda: configs.oscillator(40, q=6), dict(coarse_max=150, qe=8, precision=ae.PREC_FP64)),
     (lambda: configs.cube(12, q=20), dict(coarse_max=300, qe=36, precision=ae.PREC_FP64)),
-    (lambda: configs.lshape(40, q=10, jitter_seed=3), dict(precision=ae.PREC_MIXED)),
+    (lambda: configs.lshape(40, q=10, jitter_seed=3), dict(qe=12, precision=ae.PREC_MIXED)),
 ]
 
 
