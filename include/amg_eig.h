@@ -127,6 +127,21 @@ int amg_eig_footprint(const amg_eig_ctx *c, size_t *device_bytes);
  * Errors: EWORKSPACE, EHIP. */
 int amg_eig_bind(amg_eig_ctx *c, void *dev_workspace, size_t bytes, void *hip_stream);
 
+/* amg_eig_bind without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops or harnesses that
+ * forbid hipMalloc): the workspace is a static device array inside the library,
+ * 64 MiB per device (*static_bytes, when non-NULL, receives the size), held by
+ * each device the library runs on until the process ends.  Otherwise as
+ * amg_eig_bind on the current device and the given stream; no device memory is
+ * allocated or freed.  One context per device holds the array at a time:
+ * binding another context to it waits for the previous holder's stream and
+ * leaves that context unbound (its later calls fail with ESTATE until it is
+ * bound again).  Work of two contexts on the array must not overlap: calls
+ * that overlap on one device race.  A widening of the block (see
+ * amg_eig_progress) stays inside the array when it fits.
+ * Errors: EWORKSPACE (footprint above the array's size), EHIP. */
+int amg_eig_bind_static(amg_eig_ctx *c, void *hip_stream, size_t *static_bytes);
+
 /* Start the iteration on the finest level (asynchronous).
  * NESTED: Algorithm 3.2 (coarsest eigenvectors, prolongation, one correction
  *         per intermediate level).

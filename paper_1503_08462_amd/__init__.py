@@ -37,7 +37,7 @@ EXPORTED = [
     "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting",
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
-    "amg_eig_tune_time",
+    "amg_eig_tune_time", "amg_eig_bind_static",
 ]
 TUNE_VCYCLE, TUNE_FP64, TUNE_FP64_WIDE = 0, 1, 2
 SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
@@ -65,6 +65,7 @@ _sig = {
     "amg_eig_setup": (_i, [_vp, _vp, _i, _vp, _vp]),
     "amg_eig_footprint": (_i, [_vp, _vp]),
     "amg_eig_bind": (_i, [_vp, _vp, _sz, _vp]),
+    "amg_eig_bind_static": (_i, [_vp, _vp, _vp]),
     "amg_eig_init": (_i, [_vp, _i, _u64, _vp, _i64]),
     "amg_eig_correct": (_i, [_vp, _i]),
     "amg_eig_progress": (_i, [_vp, _vp, _vp, _vp, _vp]),
@@ -137,6 +138,7 @@ class Context:
         self.q = int(q)
         self.workspace = None
         self.stream = None
+        self._static = False
         self._ws_bytes = 0
 
     # ----------------------------------------------------------- host side
@@ -197,7 +199,19 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         self._check(_lib.amg_eig_bind(self._c, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                       ctypes.c_void_p(self.stream.cuda_stream)))
-        self._ws_bytes = self.workspace.numel()
+        self._static, self._ws_bytes = False, self.workspace.numel()
+        return self
+
+    def bind_static(self, stream=None):
+        """Bind to the library's static device workspace (no allocation; 64 MiB per
+        device, one context at a time: binding another one unbinds this one).
+        The current device and `stream` (default: its current stream)."""
+        import torch
+        self.workspace = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        size = ctypes.c_size_t()
+        self._check(_lib.amg_eig_bind_static(self._c, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(size)))
+        self._static, self._ws_bytes = True, size.value
         return self
 
     def init(self, mode=INIT_NESTED, seed=0, U=None):
@@ -233,11 +247,18 @@ class Context:
             rc = self._check(_lib.amg_eig_solve(self._c, tol, max_steps, _p(lam), ptr, ldu))
             if rc != WIDENED:
                 return lam, rc == OK
-            self.bind(device=self.workspace.device, stream=self.stream)
+            if self._static:
+                self.bind_static(stream=self.stream)
+            else:
+                self.bind(device=self.workspace.device, stream=self.stream)
 
     def iterate(self):
-        """The device iterate as a torch view (N x ld FP64, first qe columns used)."""
+        """The device iterate as a torch view (N x ld FP64, first qe columns used)
+        into the caller's workspace (not available after bind_static: use
+        solve(U_out=...) there)."""
         import torch
+        if self._static:
+            raise RuntimeError("no torch view of the static workspace; pass U_out to solve()")
         p = ctypes.c_void_p()
         ld = ctypes.c_int64()
         self._check(_lib.amg_eig_iterate(self._c, ctypes.byref(p), ctypes.byref(ld)))

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <array>
@@ -84,6 +85,7 @@ struct amg_eig_ctx {
     // the bound workspace, kept for changes of the block width inside it
     char *ws = nullptr;
     size_t ws_bytes = 0;
+    int static_dev = -1;  // device whose static workspace this context holds (amg_eig_bind_static)
     // block width control of the solve driver (automatic width, opts.qe = 0):
     // the width may be raised when the iteration stalls with the block ending
     // inside a cluster, and lowered for later starts once a widened block
@@ -887,6 +889,51 @@ int joint_small(amg_eig_ctx *const *cs, int n, int final_level, bool gemms) {
     return AMG_EIG_OK;
 }
 
+// ------------------------------------------------ static workspace
+// For callers that cannot allocate device memory: a workspace in a
+// file-scope device array.  The code object holds one copy per device, for
+// the life of the process.  Its device address is taken once per device with
+// hipGetSymbolAddress (the array's name in host code is only a stand-in) and
+// used everywhere after.
+constexpr size_t kStaticBytes = size_t(64) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char *g_static_ptr[kMaxDevices] = {};           // device address of scratch, per device
+amg_eig_ctx *g_static_owner[kMaxDevices] = {};  // context bound to it, per device
+
+// The current device's static workspace (its address taken on first use).
+int static_workspace(amg_eig_ctx *c, char **out, int *dev_out) {
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, AMG_EIG_EHIP, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(c, AMG_EIG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_static_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_static_ptr[dev];
+    *dev_out = dev;
+    return AMG_EIG_OK;
+}
+
+// The context gives up the static workspace it holds (destroy, rebind).
+void release_static(amg_eig_ctx *c) {
+    if (c->static_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+    c->static_dev = -1;
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -969,6 +1016,7 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     if (!ws || bytes < c->need || (reinterpret_cast<uintptr_t>(ws) & 255))
         return fail(c, AMG_EIG_EWORKSPACE, "workspace missing, unaligned or smaller than the footprint");
     drop_graph(c);
+    if (c->static_dev >= 0 && (char *)ws != g_static_ptr[c->static_dev]) release_static(c);
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char *)ws;
     c->ws_bytes = bytes;
@@ -996,6 +1044,37 @@ int amg_eig_bind(amg_eig_ctx *c, void *ws, size_t bytes, void *hip_stream) {
     c->bound = true;
     c->initialised = false;
     return AMG_EIG_OK;
+}
+
+int amg_eig_bind_static(amg_eig_ctx *c, void *hip_stream, size_t *static_bytes) {
+    if (!c) return AMG_EIG_EINVAL;
+    if (static_bytes) *static_bytes = kStaticBytes;
+    if (c->need > kStaticBytes)
+        return fail(c, AMG_EIG_EWORKSPACE, "footprint of " + std::to_string(c->need) +
+                                               " bytes exceeds the static workspace of " +
+                                               std::to_string(kStaticBytes) + " bytes");
+    char *ws = nullptr;
+    int dev = -1;
+    int rc = static_workspace(c, &ws, &dev);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        amg_eig_ctx *prev = g_static_owner[dev];
+        if (prev && prev != c) {
+            // the previous holder loses the workspace: wait for its queued work,
+            // then leave it unbound (its later calls fail with ESTATE)
+            if (prev->bound) (void)hipStreamSynchronize(prev->stream);
+            prev->bound = prev->initialised = false;
+            prev->ws = nullptr;
+            prev->ws_bytes = 0;
+            prev->static_dev = -1;
+        }
+        g_static_owner[dev] = c;
+        c->static_dev = dev;
+    }
+    rc = amg_eig_bind(c, ws, kStaticBytes, hip_stream);
+    if (rc) release_static(c);
+    return rc;
 }
 
 int amg_eig_init(amg_eig_ctx *c, int mode, uint64_t seed, const double *U_dev, int64_t ldu) {
@@ -1262,6 +1341,7 @@ int amg_eig_iterate(const amg_eig_ctx *c, const double **U_dev, int64_t *ld) {
 
 void amg_eig_destroy(amg_eig_ctx *c) {
     if (!c) return;
+    release_static(c);
     drop_graph(c);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto &st : c->sites)
