@@ -1,17 +1,22 @@
 """Benchmark: eigenpairs/s of full solves (Algorithm 3.2 + corrections to a
-1e-8 relative residual) on one MI355X, with the dominant kernel's HBM roofline
-and the CPU oracle timed beside it.
+1e-8 relative residual) on one MI355X, with the dominant kernel's HBM roofline,
+the same solves in plain FP64 beside it, and the CPU oracle timed on a bounded
+sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1] [--precision mixed|fp64]
-    python bench.py --config 4 [--requests R] [--rate HZ] [--n-hi N]     (serving stream)
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--precision mixed|fp64]
+    python bench.py --config 5 [--requests R] [--rate HZ] [--n-hi N]     (serving stream)
 
-A step is one whole solve of the workload: nested start from the coarsest
-level, then finest-level corrections until max_{j<=q} rho_j <= 1e-8.  Inputs
-(the hierarchy) are resident in HBM before the timed region starts.
+Configs (numbered as the benchmark set): 1 unit square N = 961, 2 jittered
+L-shape N = 195 585, 3 checkerboard cube N = 970 299, 4 oscillator
+N = 4 190 209 (the default: the largest single-GPU workload), 5 the serving
+stream.  A step is one whole solve of the workload: nested start from the
+coarsest level, then finest-level corrections until max_{j<=q} rho_j <= 1e-8.
+Inputs (the hierarchy) are resident in HBM before the timed region starts.
 """
 import argparse
 import json
 import os
+import platform
 import subprocess
 import sys
 import time
@@ -24,19 +29,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# Per-workload solver options (coarse size and block width: the paper's two
-# improvement strategies, Section 4.5)
+# Per-workload solver options (coarse size: the paper's first improvement
+# strategy, Section 4.5; the block width is the library's own choice: guard
+# rule plus width control, the second strategy)
 WORKLOADS = {
-    0: dict(name="unit square P1, 31x31 interior (N=961), q=4", coarse_max=130, qe=4),
-    1: dict(name="jittered L-shape P1, h=1/256 (N=195585), q=10", coarse_max=512, qe=16),
-    2: dict(name="3D checkerboard cube P1, 100^3 cells (N=970299), q=20", coarse_max=512, qe=32),
-    3: dict(name="oscillator -Lap+r^2 on (-6,6)^2, 2047^2 interior (N=4190209), q=64", coarse_max=700, qe=68),
+    1: dict(name="unit square P1, 31x31 interior (N=961), q=4", coarse_max=130, golden=None),
+    2: dict(name="jittered L-shape P1, h=1/256 (N=195585), q=10", coarse_max=512, golden=None),
+    3: dict(name="3D checkerboard cube P1, 100^3 cells (N=970299), q=20", coarse_max=512, golden="cube100"),
+    4: dict(name="oscillator -Lap+r^2 on (-6,6)^2, 2047^2 interior (N=4190209), q=64", coarse_max=700,
+            golden="osc2048"),
 }
 
 
-def cpu_baseline(idx, qe, coarse_max, tol):
-    """The oracle (plain FP64 CPU, its own setup and Gauss-Seidel V-cycle) timed
-    on one full solve of the same workload, setup excluded, one thread."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def _oracle_sample(cfg, qe, coarse_max, threads, nested, full_tol=None):
+    """Run the oracle in a child process with `threads` BLAS/OpenMP threads:
+    setup (not timed), then either a full solve to full_tol (timed), or
+    optionally the nested start (timed) and one finest-level Gauss-Seidel
+    correction (timed).  Returns the parsed JSON or None."""
     code = r"""
 import json, sys, time
 sys.path.insert(0, %r)
@@ -46,19 +65,77 @@ p = configs.config(%d)
 A = amg.csr(p["rowptr"], p["col"], p["A"], p["n"])
 M = amg.csr(p["rowptr"], p["col"], p["M"], p["n"])
 o = Oracle(A, M, q=p["q"], qe=%d, coarse_max=%d, coarse_min=2 * %d + 2, smoother="gs")
-t = time.perf_counter()
-lam, U, info = o.solve(tol=%r, max_steps=400)
-dt = time.perf_counter() - t
-print(json.dumps({"seconds": dt, "steps": info["steps"], "q": p["q"], "conv": bool(info["rho"][:p["q"]].max() <= %r)}))
-""" % (ROOT, idx, qe, coarse_max, qe, tol, tol)
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
+out = {"q": p["q"]}
+full_tol = %r
+if full_tol:
+    t = time.perf_counter(); lam, U, info = o.solve(tol=full_tol, max_steps=400)
+    out.update(solve_s=time.perf_counter() - t, steps=info["steps"], conv=bool(info["rho"][:p["q"]].max() <= full_tol))
+elif %r:
+    t = time.perf_counter(); lam, U = o.nested_start(); out["nested_s"] = time.perf_counter() - t
+else:
+    lam, U = o.nested_start()
+if not full_tol:
+    t = time.perf_counter(); lam, U = o.correction(0, lam, U); out["correction_s"] = time.perf_counter() - t
+print(json.dumps(out))
+""" % (ROOT, cfg - 1, qe, coarse_max, qe, full_tol, nested)
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = str(threads)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=1500)
     if r.returncode != 0:
         return None
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return {"value": d["q"] / d["seconds"], "unit": "eigenpairs/s", "cores": 1, "kind": "oracle",
-            "sample": "one full oracle solve of the same workload (nested start, Gauss-Seidel V(1,1), "
-                      "%d corrections to rho<=%g, %.1f s), setup excluded, 1 thread" % (d["steps"], tol, d["seconds"])}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(cfg, qe, coarse_max, tol, gpu_corrections):
+    """The oracle (plain FP64 CPU: its own setup, Gauss-Seidel V-cycle, dense
+    Rayleigh-Ritz) on a bounded sample of the same workload at full size: its
+    nested start and one finest-level correction with all host threads, one
+    correction with a single thread.  A full solve is estimated as
+    nested start + K corrections, K the correction count of the stored full
+    oracle run of this workload (tests/golden/oracle_<name>.txt) when there is
+    one; for the small workloads the oracle solves in full."""
+    from tests.goldens import oracle_eigenvalues
+    nproc = os.cpu_count() or 1
+    wl = WORKLOADS[cfg]
+    if cfg <= 2:  # small enough for full oracle solves
+        runs = {t: _oracle_sample(cfg, qe, coarse_max, t, False, full_tol=tol) for t in (nproc, 1)}
+        if runs[nproc] is None:
+            return None
+        a, o1 = runs[nproc], runs[1]
+        out = {"value": a["q"] / a["solve_s"], "unit": "eigenpairs/s", "cores": nproc, "kind": "oracle",
+               "sample": "one full oracle solve of the same workload (nested start, Gauss-Seidel V(1,1), %d "
+                         "corrections to rho<=%g, %.1f s), setup excluded, %d BLAS/OpenMP threads (its sparse "
+                         "products and Gauss-Seidel loops run on one)" % (a["steps"], tol, a["solve_s"], nproc),
+               "cpu_model": cpu_model(), "nproc": nproc}
+        if o1 is not None:
+            out["one_thread"] = {"value": o1["q"] / o1["solve_s"], "solve_s": o1["solve_s"]}
+        return out
+    K, src = None, None
+    g = oracle_eigenvalues(wl["golden"]) if wl["golden"] else None
+    if g is not None:
+        for h in g[2]:
+            if h.startswith("corrections:"):
+                K, src = int(h.split(":")[1].split(";")[0]), "the stored full oracle run"
+    if K is None:
+        K, src = gpu_corrections, "the GPU solve's count (no stored oracle run)"
+    allc = _oracle_sample(cfg, qe, coarse_max, nproc, True)
+    one = _oracle_sample(cfg, qe, coarse_max, 1, False)
+    if allc is None:
+        return None
+    q = allc["q"]
+    t_all = allc["nested_s"] + K * allc["correction_s"]
+    out = {"value": q / t_all, "unit": "eigenpairs/s", "cores": nproc, "kind": "oracle",
+           "sample": "oracle at full size, setup excluded: nested start %.1f s + one Gauss-Seidel V(1,1) correction "
+                     "%.1f s with %d BLAS/OpenMP threads (its sparse products and Gauss-Seidel loops run on one); "
+                     "full solve estimated as nested start + %d corrections (%s) = %.0f s"
+                     % (allc["nested_s"], allc["correction_s"], nproc, K, src, t_all),
+           "cpu_model": cpu_model(), "nproc": nproc}
+    if one is not None:
+        t_one = allc["nested_s"] * one["correction_s"] / allc["correction_s"] + K * one["correction_s"]
+        out["one_thread"] = {"value": q / t_one, "correction_s": one["correction_s"],
+                             "estimate": "nested start scaled by the one-thread/all-thread correction ratio"}
+    return out
 
 
 def serving(args):
@@ -81,8 +158,9 @@ def serving(args):
     tol = args.tol
 
     def contexts(prec):
+        # the block width is the library's own choice (guard rule and width control)
         return [ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
-                           ae.defaults(coarse_max=512, qe=p["qe"], precision=prec, tol=tol,
+                           ae.defaults(coarse_max=512, precision=prec, tol=tol,
                                        use_graph=args.serve_graph if prec == ae.PREC_MIXED else 0)) for p in probs]
 
     def solo(prec):
@@ -94,7 +172,6 @@ def serving(args):
         for k, c in enumerate(cs):
             t1 = time.perf_counter()
             c.bind(stream=stream)
-            c.init(ae.INIT_NESTED)
             _, ok = c.solve(tol, 400)
             if not ok:
                 bad.append(k)
@@ -109,7 +186,6 @@ def serving(args):
     # warm-up: one request end to end
     c = contexts(ae.PREC_MIXED)[0]
     c.bind()
-    c.init(ae.INIT_NESTED)
     c.solve(tol, 400)
     c.close()
     del c
@@ -190,16 +266,67 @@ def load_traffic(kernel, workload_tag):
     return None
 
 
+def timed_solves(ctx, steps, tol, timing):
+    """`steps` whole solves (nested start, corrections to tol) between device
+    synchronisations; returns (elapsed s, per-solve latencies, corrections)."""
+    import torch
+    if timing:
+        ctx.timing(True)
+    lat, corr = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t = time.perf_counter()
+        ctx.init(0)
+        _, ok = ctx.solve(tol, 400)
+        lat.append(time.perf_counter() - t)
+        pr = ctx.progress()
+        if not ok:
+            raise SystemExit("solve did not converge: %s" % pr)
+        corr.append(pr["steps"])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, corr
+
+
+def prepared_context(p, wl, prec, args, stream):
+    """Set up and bind a context, run `warmup` untimed solves (the first one
+    also settles the block width), then choose the launch shapes."""
+    import paper_1503_08462_amd as ae
+    smoother = ae.SMOOTH_CHEBYSHEV if args.smoother == "chebyshev" else ae.SMOOTH_L1JACOBI
+    t0 = time.perf_counter()
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
+                     ae.defaults(coarse_max=wl["coarse_max"], qe=args.qe, precision=prec, use_graph=args.graph,
+                                 smoother=smoother, cheb_degree=2, cheb_lo=0.25))
+    setup_s = time.perf_counter() - t0
+    ctx.bind(stream=stream)
+    for _ in range(max(1, args.warmup)):
+        ctx.init(ae.INIT_NESTED)
+        ctx.solve(args.tol, 400)
+    tuning = None
+    if args.tune:
+        from paper_1503_08462_amd import autotune
+        ctx.init(ae.INIT_NESTED)  # a pending narrower width takes effect here
+        t1 = time.perf_counter()
+        rep = autotune.tune(ctx)
+        tuning = {"seconds": round(time.perf_counter() - t1, 3),
+                  "cpt": {"%s@%d" % (v["kind"], v["level"]): v["cpt"] for v in rep.values()}}
+        ctx.init(ae.INIT_NESTED)
+        ctx.solve(args.tol, 400)
+    return ctx, setup_s, tuning
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="plain FP64 solves of the same workload timed beside the headline (0: none)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--coarse-max", type=int, default=0, help="override the workload's coarsest-level bound")
-    ap.add_argument("--qe", type=int, default=0, help="override the workload's block width")
+    ap.add_argument("--qe", type=int, default=0, help="block width (0: the library's guard rule and width control)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="replay captured correction steps (the second step of each chunk of three or more runs "
@@ -207,7 +334,7 @@ def main():
     ap.add_argument("--tune", type=int, default=1,
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev"])
-    ap.add_argument("--requests", type=int, default=24, help="serving stream (config 4): number of requests")
+    ap.add_argument("--requests", type=int, default=24, help="serving stream (config 5): number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving stream: Poisson arrival rate, 1/s")
     ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
     ap.add_argument("--budget-gb", type=float, default=8.0, help="serving stream: device memory budget")
@@ -229,7 +356,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus)
         sys.exit(2)
 
-    if args.config == 4:
+    if args.config == 5:
         serving(args)
         return
 
@@ -240,44 +367,12 @@ def main():
     wl = dict(WORKLOADS[args.config])
     if args.coarse_max:
         wl["coarse_max"] = args.coarse_max
-    if args.qe:
-        wl["qe"] = args.qe
-    p = configs.config(args.config)
+    p = configs.config(args.config - 1)
     prec = ae.PREC_MIXED if args.precision == "mixed" else ae.PREC_FP64
-    t0 = time.perf_counter()
-    smoother = ae.SMOOTH_CHEBYSHEV if args.smoother == "chebyshev" else ae.SMOOTH_L1JACOBI
-    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
-                     ae.defaults(coarse_max=wl["coarse_max"], qe=wl["qe"], precision=prec, use_graph=args.graph,
-                                 smoother=smoother, cheb_degree=2, cheb_lo=0.25))
-    setup_s = time.perf_counter() - t0
     stream = torch.cuda.Stream()
-    ctx.bind(stream=stream)
+    ctx, setup_s, tuning = prepared_context(p, wl, prec, args, stream)
     info = ctx.info()
-    tuning = None
-    if args.tune:
-        from paper_1503_08462_amd import autotune
-        t1 = time.perf_counter()
-        rep = autotune.tune(ctx)
-        tuning = {"seconds": round(time.perf_counter() - t1, 3),
-                  "cpt": {"%s@%d" % (v["kind"], v["level"]): v["cpt"] for v in rep.values()}}
-    for _ in range(args.warmup):
-        ctx.init(ae.INIT_NESTED)
-        ctx.solve(args.tol, 400)
-    ctx.timing(True)
-    lat, steps = [], []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t = time.perf_counter()
-        ctx.init(ae.INIT_NESTED)
-        lam, ok = ctx.solve(args.tol, 400)
-        lat.append(time.perf_counter() - t)
-        pr = ctx.progress()
-        if not ok:
-            raise SystemExit("solve did not converge: %s" % pr)
-        steps.append(pr["steps"])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    elapsed, lat, steps = timed_solves(ctx, args.steps, args.tol, True)
     stats = ctx.site_stats()
     ctx.timing(False)
     if args.copy_calibration:
@@ -288,8 +383,20 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    ctx.close()
+    ctx.workspace = None
 
     q = p["q"]
+    fp64 = None
+    if args.fp64_steps > 0 and prec == ae.PREC_MIXED:
+        c64, _, _ = prepared_context(p, wl, ae.PREC_FP64, args, stream)
+        e64, lat64, steps64 = timed_solves(c64, args.fp64_steps, args.tol, False)
+        fp64 = {"value": q * args.fp64_steps / e64, "unit": "eigenpairs/s", "ms_per_step": e64 / args.fp64_steps * 1e3,
+                "steps": args.fp64_steps, "qe": c64.info()["qe"], "corrections_per_solve": float(np.mean(steps64)),
+                "note": "the same solves with every kernel in FP64 (single instance), timed the same way"}
+        c64.close()
+        c64.workspace = None
+
     sites = {}
     for name, (amount, ms, n) in stats.items():
         if n == 0:
@@ -302,10 +409,10 @@ def main():
         else:
             sites[name] = {"avg_us": avg * 1e6, "launches": n, "gbs": amount / avg / 1e9}
     # the roofline line covers the streaming kernel with the largest total time
-    # on the finest level; the small coarse-space kernels (one workgroup per
-    # eigenvalue, latency-bound) are reported beside it
-    hbm_sites = [s for s in sites if s not in ("gram", "small")]
-    dom = max(hbm_sites, key=lambda s: stats[s][1]) if hbm_sites else None
+    # on the finest level; the small coarse-space kernels (latency-bound) are
+    # reported beside it
+    hbm_sites = [s_ for s_ in sites if s_ not in ("gram", "small")]
+    dom = max(hbm_sites, key=lambda s_: stats[s_][1]) if hbm_sites else None
     roofline = None
     if dom:
         amount, ms, n = stats[dom]
@@ -314,7 +421,7 @@ def main():
         kernel_name = {"residual": "k_residual", "presmooth": "k_cheb_pre" if cheb else "k_smooth_pre",
                        "postsmooth": "k_cheb_post2" if cheb else "k_smooth_post",
                        "dualspmm": "k_dual_spmm", "restrict": "k_spmm",
-                       "final": "k_final" if wl["qe"] > 32 else "k_final_rows"}[dom]
+                       "final": "k_final" if info["qe"] > 32 else "k_final_rows"}[dom]
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": load_traffic(kernel_name, "config%d_%s" % (args.config, args.precision)),
@@ -327,10 +434,11 @@ def main():
                  "share_of_timed_sites": round(stats["small"][1] / tot, 3) if tot > 0 else None}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.config, wl["qe"], wl["coarse_max"], args.tol)
+        cpu = cpu_baseline(args.config, info["qe"], wl["coarse_max"], args.tol, int(round(np.mean(steps))))
+    value = q * args.steps / elapsed
     out = {
         "metric": "eigenpairs/sec to 1e-8 rel. residual",
-        "value": q * args.steps / elapsed,
+        "value": value,
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -341,8 +449,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if prec == ae.PREC_MIXED else "f64",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "N": int(p["n"]), "q": q, "qe": info["qe"],
-                   "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
+        "config": {"workload": "config %d: %s" % (args.config, wl["name"]), "N": int(p["n"]), "q": q,
+                   "qe": info["qe"], "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
                    "smoother": ("l1-jacobi" if args.smoother == "l1jacobi" else "chebyshev degree 2 on [0.25, 1]")
                                + " V(1,1)", "start": "nested (Algorithm 3.2)",
                    "steps_launch": ("captured hipGraph replays; the second step of each enqueued chunk of three "
@@ -351,6 +459,8 @@ def main():
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "corrections_per_solve": float(np.mean(steps)),
         "setup_s": setup_s,
+        "fp64_single_instance": fp64,
+        "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "tuning": tuning,
         "roofline": roofline,
         "small_solver": small,
@@ -358,7 +468,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
-    ctx.close()
 
 
 if __name__ == "__main__":
