@@ -580,11 +580,15 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int ld, const double *_
     }
 }
 
-// Phase 1 for wide blocks (more than 8 tiles): the workgroup stages kGramRows
-// rows of V and W at a time in LDS (coalesced loads by all threads); the tiles of
-// the ld x 2ld result are dealt round-robin to its four wavefronts, which
-// accumulate them from LDS and finally write them to part[b] directly.
-constexpr int kGramTilesPerWave = 12;  // covers ld <= 68 (5 x 9 tiles)
+// Phase 1 for wide blocks (more than 8 tiles of the ld x 2ld result): the
+// workgroup stages kGramRows rows of V and W at a time in LDS (coalesced loads
+// by all threads).  V^T A V and V^T M V are symmetric, so only the 16 x 16
+// tiles on and above the diagonal of each (two grids of ti (ti + 1) / 2 tiles,
+// ti = ceil(ld / 16)) are accumulated; they are dealt round-robin to the four
+// wavefronts, which accumulate them from LDS and finally write them to
+// part[b].  The reduction fills the entries below the diagonals from their
+// mirror images.
+constexpr int kGramTilesPerWave = 8;  // covers ld <= 80 (2 x 15 tiles)
 constexpr int kGramRows = 32;
 
 __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const double *__restrict__ V,
@@ -595,9 +599,23 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int64_t nb = gridDim.x, lb = xcd_block();
     const int64_t r0 = n * lb / nb, r1 = n * (lb + 1) / nb;
-    const int l2 = 2 * ld, ti = (ld + 15) / 16, tj = (l2 + 15) / 16, ntiles = ti * tj;
+    const int l2 = 2 * ld, ti = (ld + 15) / 16, tu = ti * (ti + 1) / 2, ntiles = 2 * tu;
     const int outsz = ld * l2;
     const int kk = lane >> 4, c = lane & 15;
+    // tile s2 of this wavefront: grid half (A or M part), row tile, column tile >= row tile
+    int t_off[kGramTilesPerWave], t_a[kGramTilesPerWave], t_b[kGramTilesPerWave];
+#pragma unroll
+    for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
+        const int t = wv + s2 * nw, h = t < tu ? 0 : 1;
+        int u = t - h * tu, ta = 0;
+        while (ta < ti && u >= ti - ta) {
+            u -= ti - ta;
+            ++ta;
+        }
+        t_off[s2] = h * ld;
+        t_a[s2] = ta;
+        t_b[s2] = ta + u;
+    }
     dbl4 acc[kGramTilesPerWave];
 #pragma unroll
     for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) acc[s2] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -610,15 +628,13 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
         __syncthreads();
 #pragma unroll
         for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
-            const int t = wv + s2 * nw;
-            if (t < ntiles) {  // wave-uniform
-                const int ta = t / tj, tb = t - ta * tj;
-                const int ca = 16 * ta + c, cb = 16 * tb + c;
+            if (wv + s2 * nw < ntiles) {  // wave-uniform
+                const int ca = 16 * t_a[s2] + c, cb = 16 * t_b[s2] + c, off = t_off[s2];
 #pragma unroll 4
                 for (int k0 = 0; k0 < kGramRows; k0 += 4) {
                     const int rr = k0 + kk;
                     double x = (ca < ld && rr < rows) ? sv[rr * ld + ca] : 0.0;
-                    double y = (cb < l2 && rr < rows) ? sw[rr * l2 + cb] : 0.0;
+                    double y = (cb < ld && rr < rows) ? sw[rr * l2 + off + cb] : 0.0;
                     acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[s2], 0, 0, 0);
                 }
             }
@@ -626,13 +642,11 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
     }
 #pragma unroll
     for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
-        const int t = wv + s2 * nw;
-        if (t < ntiles) {
-            const int ta = t / tj, tb = t - ta * tj;
+        if (wv + s2 * nw < ntiles) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
-                if (i < ld && j < l2) part[lb * outsz + i * l2 + j] = acc[s2][u];
+                const int i = 16 * t_a[s2] + (lane >> 4) + 4 * u, j = 16 * t_b[s2] + (lane & 15);
+                if (i < ld && j < ld) part[lb * outsz + i * l2 + t_off[s2] + j] = acc[s2][u];
             }
         }
     }
@@ -640,14 +654,20 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
 
 // Phase 2: G[e] = sum over blocks of part[b][e]; one wavefront per element,
 // lane l sums blocks l, l+64, ..., then a fixed butterfly over the lanes.
-__global__ __launch_bounds__(256) void k_gram_reduce(int64_t nb, int outsz, const double *__restrict__ part,
-                                                     double *__restrict__ G, const int *status) {
+__global__ __launch_bounds__(256) void k_gram_reduce(int64_t nb, int outsz, int ld, int sym,
+                                                     const double *__restrict__ part, double *__restrict__ G,
+                                                     const int *status) {
     if (status[ST_CONVERGED]) return;
     const int e = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (e >= outsz) return;
+    int src = e;  // with sym, an entry below the diagonal of V^T A V or V^T M V is its mirror's sum
+    if (sym) {
+        const int l2 = 2 * ld, i = e / l2, j = e - i * l2, h = j < ld ? 0 : ld, jl = j - h;
+        if (jl < i) src = jl * l2 + h + i;
+    }
     double sum = 0.0;
-    for (int64_t b = lane; b < nb; b += kWave) sum += part[b * outsz + e];
+    for (int64_t b = lane; b < nb; b += kWave) sum += part[b * outsz + src];
     for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
     if (lane == 0) G[e] = sum;
 }
@@ -682,33 +702,45 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
     stv<double, CPT>(U + rm.row * ld + c0, acc);
 }
 
-// Wide blocks: U = P Y + V X_v on the correction level.  One wavefront per
-// 16 consecutive rows, looping over the row tiles of its workgroup so that each
-// workgroup stages X_v in LDS once: V X_v as 16 x 16 tiles on the FP64 matrix cores,
-// then each lane adds the prolongation P Y for its four
-// (row, column) entries of the tile and writes them.  The first kPRow entries
-// of the lane's four rows of P are held in registers across the column tiles,
-// so that a tile's gathers of Y are independent loads issued together.
+// Wide blocks: U = P Y + V X_v on the correction level.  A workgroup stages
+// X_v in LDS once, then walks its blocks of kFinalRows consecutive rows: all
+// its threads copy the block's rows of V (contiguous in memory) into LDS with
+// coalesced 16-byte loads, and each wavefront takes 16 of the rows: V X_v as
+// 16 x 16 tiles on the FP64 matrix cores with both operands from LDS (each
+// row of V is read from memory once, whatever the number of column tiles),
+// then each lane adds the prolongation P Y for its four (row, column) entries
+// of the tile and writes them.  The first kPRow entries of the lane's four
+// rows of P are held in registers across the column tiles, so that a tile's
+// gathers of Y are independent loads issued together.
 constexpr int kPRow = 4;
+constexpr int kFinalRows = 64;
 __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
                                                const int32_t *__restrict__ col, const double *__restrict__ val,
                                                const double *__restrict__ Y, const double *__restrict__ V,
                                                const double *__restrict__ Xv, double *__restrict__ U,
                                                const int *status) {
-    extern __shared__ double xv[];
+    extern __shared__ double sm[];
+    double *xv = sm;            // ld x ld
+    double *vt = sm + ld * ld;  // kFinalRows x ld: the rows of V of the current block
     if (status[ST_CONVERGED]) return;
     for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) xv[e] = Xv[e];
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int c = lane & 15, kk = lane >> 4;
     const int tj = (ld + 15) / 16;
-    // workgroup b owns a contiguous range of row tiles, which its wavefronts
-    // take in turn: neighbouring fine rows, whose prolongation reads the same
-    // coarse rows of Y, run on the same CU close together in time
-    const int64_t tiles = (n + 15) / 16, nbk = gridDim.x, lb = xcd_block();
-    const int64_t t0 = tiles * lb / nbk, t1 = tiles * (lb + 1) / nbk;
-    for (int64_t tile = t0 + wv; tile < t1; tile += blockDim.x / kWave) {
-        const int64_t r0 = tile * 16;
+    // workgroup b owns a contiguous range of row blocks: neighbouring fine
+    // rows, whose prolongation reads the same coarse rows of Y, run on the
+    // same CU close together in time
+    const int64_t blocks = (n + kFinalRows - 1) / kFinalRows, nbk = gridDim.x, lb = xcd_block();
+    const int64_t b0 = blocks * lb / nbk, b1 = blocks * (lb + 1) / nbk;
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        const int64_t base = blk * kFinalRows;
+        const int rows = n - base < kFinalRows ? (int)(n - base) : kFinalRows;
+        __syncthreads();                             // the previous block is consumed (X_v staged)
+        block_copy(vt, V + base * ld, rows * ld);  // contiguous rows: coalesced 16-byte loads
+        __syncthreads();
+        const int w0 = 16 * wv;  // this wavefront's first row in the block
+        if (w0 >= rows) continue;  // wave-uniform; no barrier follows before the next block's
+        const int64_t r0 = base + w0;
         int32_t pb[4], pe[4], pc[4][kPRow];
         double pv[4][kPRow];
 #pragma unroll
@@ -734,8 +766,7 @@ __global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t 
 #pragma unroll
                 for (int t = 0; t < kPRow; ++t) yv[u][t] = Y[(int64_t)pc[u][t] * ld + jc];
             const dbl4 acc = mfma_tn16([&](int k, int cc) -> double {
-                                           const int64_t row = r0 + cc;
-                                           return row < n ? V[row * ld + k] : 0.0;
+                                           return w0 + cc < rows ? vt[(w0 + cc) * ld + k] : 0.0;
                                        },
                                        [&](int k, int cc) -> double {
                                            const int jj = 16 * tb + cc;
@@ -957,14 +988,15 @@ void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double
                  const int *status) {
     const int64_t nb = gram_blocks(n, ld);
     const int outsz = 2 * ld * ld;
-    const int ntiles = ((ld + 15) / 16) * ((2 * ld + 15) / 16);
-    if (ntiles > 8 && ntiles <= 4 * kGramTilesPerWave)
+    const int ti = (ld + 15) / 16;
+    const bool wide = ti * ((2 * ld + 15) / 16) > 8;  // ld > 32; 2 ti (ti + 1) / 2 <= 30 tiles for ld <= 80
+    if (wide)
         hipLaunchKernelGGL(k_gram_wide, dim3((unsigned)nb), dim3(kBlock),
                            (size_t)kGramRows * 3 * ld * sizeof(double), s, n, ld, V, W, part, status);
     else
         hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, part, G,
-                       status);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, ld,
+                       wide ? 1 : 0, part, G, status);
 }
 
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
@@ -975,12 +1007,12 @@ void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const in
                                             Y, V, Xv, U, status));
         return;
     }
-    // workgroups: enough to fill the chip (four per CU by LDS), each striding
-    // over the row tiles
-    const int64_t tiles = (n + 15) / 16, need = (tiles + (kBlock / kWave) - 1) / (kBlock / kWave);
-    const int64_t nb = need < 2048 ? need : 2048;
-    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)ld * ld * sizeof(double), s, n, ld, ptr,
-                       col, val, Y, V, Xv, U, status);
+    // workgroups: each owns a contiguous range of 64-row blocks; LDS holds X_v
+    // and one block of V rows (two workgroups per CU at ld = 68)
+    const int64_t blocks = (n + kFinalRows - 1) / kFinalRows;
+    const int64_t nb = blocks < 2048 ? blocks : 2048;
+    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)(ld * ld + kFinalRows * ld) * sizeof(double), s,
+            n, ld, ptr, col, val, Y, V, Xv, U, status);
 }
 
 template <typename T>

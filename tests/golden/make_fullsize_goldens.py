@@ -8,8 +8,8 @@ minutes to about an hour of one CPU core and tens of GB of host memory (the
     python tests/golden/make_fullsize_goldens.py NAME [NAME ...]
 
 NAME is one of the keys of WORKLOADS.  The output file oracle_<NAME>.txt holds
-the workload recipe, the oracle's settings, the number of corrections, and one
-line per block column: index j (1-based), Ritz value theta_j, relative residual
+the workload recipe, the oracle's settings, the number of corrections, the
+residual history max_{j<=q} rho_j after each correction, and one line per block column: index j (1-based), Ritz value theta_j, relative residual
 rho_j = ||A u_j - theta_j M u_j|| / (theta_j ||M u_j||).
 """
 import os
@@ -66,6 +66,8 @@ def run(name):
         f.write("# levels: %s\n" % " ".join(str(L.n) for L in o.levels))
         f.write("# corrections: %d; stop rule max_{j<=q} rho_j <= %g or %d corrections; "
                 "final max_{j<=q} rho_j = %.3e\n" % (info["steps"], tol, max_steps, rho[:q].max()))
+        f.write("# history (corrections: max_{j<=q} rho_j): %s\n"
+                % " ".join("%d:%.3e" % (k, h[1][:q].max()) for k, h in enumerate(info["history"])))
         f.write("# j theta_j rho_j\n")
         for j in range(qe):
             f.write("%d %.17e %.3e\n" % (j + 1, lam[j], rho[j]))
