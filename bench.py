@@ -115,8 +115,16 @@ def cpu_baseline(cfg, qe, coarse_max, tol, gpu_corrections):
     g = oracle_eigenvalues(wl["golden"]) if wl["golden"] else None
     if g is not None:
         for h in g[2]:
-            if h.startswith("corrections:"):
-                K, src = int(h.split(":")[1].split(";")[0]), "the stored full oracle run"
+            if h.startswith("history"):  # corrections until max_{j<=q} rho_j <= tol
+                hist = [(int(a), float(b)) for a, b in (x.split(":") for x in h.split("): ", 1)[1].split())]
+                hits = [k for k, r in hist if r <= tol]
+                if hits:
+                    K, src = hits[0], "the stored full oracle run, corrections to rho<=%g" % tol
+        if K is None:
+            for h in g[2]:
+                if h.startswith("corrections:"):
+                    K = int(h.split(":")[1].split(";")[0])
+                    src = "the stored full oracle run (to its own, tighter stop rule)"
     if K is None:
         K, src = gpu_corrections, "the GPU solve's count (no stored oracle run)"
     allc = _oracle_sample(cfg, qe, coarse_max, nproc, True)

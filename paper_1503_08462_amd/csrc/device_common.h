@@ -24,19 +24,23 @@ __device__ __forceinline__ int64_t xcd_block() {
     return x * per + (x < rem ? x : rem) + slot;
 }
 
+// Lane -> (row, columns) map of the row kernels: the rows of a block of
+// width ld are served by ld / cpt consecutive threads each (cpt consecutive
+// columns per thread), numbered across the whole grid, so that every lane of
+// every wavefront has work (a row may span two wavefronts: the row kernels
+// exchange nothing between lanes).  Blocks are taken in XCD-aware order
+// (xcd_block), so neighbouring rows run on the same XCD.
 struct RowMap {
-    int tpr, rpw, sub, grp;
+    int tpr, sub;
     int64_t row;
     bool active;
     __device__ __forceinline__ RowMap(int ld, int cpt, int64_t nrows) {
         tpr = ld / cpt;
-        rpw = kWave / tpr;
-        const int lane = threadIdx.x & (kWave - 1);
-        grp = lane / tpr;
-        sub = lane - grp * tpr;
-        const int64_t wave = xcd_block() * (blockDim.x / kWave) + threadIdx.x / kWave;
-        row = wave * rpw + grp;
-        active = grp < rpw && row < nrows;
+        const uint32_t t = (uint32_t)xcd_block() * blockDim.x + threadIdx.x;  // < nrows * tpr + blockDim.x < 2^31
+        const uint32_t r = t / (uint32_t)tpr;
+        row = r;
+        sub = (int)(t - r * (uint32_t)tpr);
+        active = row < nrows;
     }
 };
 

@@ -837,16 +837,19 @@ __global__ void k_fill_i32(int count, int value, int *dst) {
 namespace {
 constexpr int kBlock = 256;
 
+// workgroups of the row kernels (RowMap): n rows of ld / cpt threads each
 inline int64_t row_blocks(int64_t n, int ld, int cpt) {
-    const int tpr = ld / cpt, rpw = kWave / tpr;
-    const int64_t waves = (n + rpw - 1) / rpw;
-    return (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const int64_t threads = n * (ld / cpt);
+    return (threads + kBlock - 1) / kBlock;
 }
 }  // namespace
 
-// Columns per lane for a row-major block of the given width: the choice among
-// 2, 4 and 8 that leaves the fewest idle lanes in a wavefront (rows of
-// width / CPT lanes each; ties to fewer columns per lane).
+// Columns per lane for a row-major block of the given width when no tuned
+// value is set: among 2, 4 and 8, the one whose rows of width / CPT threads
+// pack a wavefront best (ties to fewer columns per lane).  With RowMap's flat
+// numbering every lane has work whatever the choice; this rule picks the
+// vector width (4 columns for widths of 17 x 4 and the like, 2 for widths a
+// power of two up to 16), and the autotuner times the others.
 int cpt_for(int width) {
     int best = 0;
     double bu = -1.0;
