@@ -871,11 +871,13 @@ int joint_small(amg_eig_ctx *const *cs, int n, int final_level, bool gemms) {
         SmallLds lds;
         t.n = m;
         t.final_level = final_level;
-        t.first[0] = 0;
+        t.first[0] = t.p3first[0] = t.ctfirst[0] = 0;
         for (int j = 0; j < m; ++j) {
             const amg_eig_ctx *c = cs[i0 + j];
             t.item[j] = c->item_dev;
             t.first[j + 1] = t.first[j] + c->qe;
+            t.p3first[j + 1] = t.p3first[j] + pencil_p3_blocks(c->ld);
+            t.ctfirst[j + 1] = t.ctfirst[j] + pencil_ct_waves(c->ld, c->H.dn);
             lds.pencil = std::max(lds.pencil, c->small_lds.pencil);
             lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
             lds.rr = std::max(lds.rr, c->small_lds.rr);

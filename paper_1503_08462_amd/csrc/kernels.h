@@ -145,9 +145,15 @@ constexpr int kMaxBatch = 64;
 struct SmallTable {
     const SmallItem *item[kMaxBatch];  // device addresses
     int first[kMaxBatch + 1];          // eigenvalue workgroups of member m: first[m] .. first[m+1]-1
+    int p3first[kMaxBatch + 1];        // wide pencil products: P3 workgroups of member m
+    int ctfirst[kMaxBatch + 1];        // and its C~ wavefronts (prefix sums; 0 for ld <= 32)
     int n;
     int final_level;                   // finest-level step (counted) or a step of the nested start
 };
+// P3 workgroups and C~ wavefronts of the wide pencil products of one member
+// (zero for ld <= 32, where the pencil kernel forms both in LDS)
+int pencil_p3_blocks(int ld);
+int pencil_ct_waves(int ld, int dn);
 // pencil, eigenpairs and Ritz polish of every member of the table, three
 // launches in all; lds holds the largest size over the members
 void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol);

@@ -342,13 +342,15 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
     const int l2 = 2 * ld;
     auto fgv = [&](int i, int a) -> double { return fg_in_lds ? fg[i * l2 + a] : w.FG[(int64_t)i * l2 + a]; };
     tk[1] = stat_clock();
-    // P3 = G^T [F | G | Lambda G]   (G = FG(:, ld:2ld), F = FG(:, 0:ld))
-    block_xty([&](int i, int a) -> double { return a < ld ? fgv(i, ld + a) : 0.0; },
-              [&](int i, int b) -> double {
-                  if (b < l2) return fgv(i, b);
-                  return b < 3 * ld ? lam[i] * fgv(i, b - ld) : 0.0;
-              },
-              dn, ld, 3 * ld, P3, 3 * ld, red, rcap);
+    // P3 = G^T [F | G | Lambda G]   (G = FG(:, ld:2ld), F = FG(:, 0:ld)); for
+    // wide blocks k_pencil_p3 has formed it over many workgroups
+    if (small)
+        block_xty([&](int i, int a) -> double { return a < ld ? fgv(i, ld + a) : 0.0; },
+                  [&](int i, int b) -> double {
+                      if (b < l2) return fgv(i, b);
+                      return b < 3 * ld ? lam[i] * fgv(i, b - ld) : 0.0;
+                  },
+                  dn, ld, 3 * ld, P3, 3 * ld, red, rcap);
     for (int e = tid; e < ld * ld; e += nthr) {
         const int a = e / ld, b = e - a * ld;
         const double gm_ab = gag[a * l2 + ld + b], gm_ba = gag[b * l2 + ld + a];
@@ -463,7 +465,9 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
     if (tid < ld) w.perm[tid] = perm[tid];
     if (tid == 0) w.status[ST_RANK] = r;
     tk[4] = stat_clock();
-    // C~ = (F - Lambda G)(:, perm_r) L^-T on the matrix cores
+    // C~ = (F - Lambda G)(:, perm_r) L^-T on the matrix cores (for wide blocks
+    // k_pencil_ct forms it over many workgroups after this kernel)
+    if (small)
     block_tiles(
         [&](int k, int i) -> double {
             if (i >= dn || k >= r) return 0.0;
@@ -585,9 +589,14 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
             const int tb = t - ta * (ta + 1) / 2;
             const int k0 = kc * chunk, k1 = dn < k0 + chunk ? dn : k0 + chunk;
             dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-            if (k1 > k0)
-                acc = mfma_tn16([&](int i, int c) { return wdn[k0 + i] * ct(k0 + i, 16 * ta + c); },
-                                [&](int i, int c) { return ct(k0 + i, 16 * tb + c); }, k1 - k0);
+            if (k1 > k0) {
+                if (ct_in_lds)
+                    acc = mfma_tn16([&](int i, int c) { return wdn[k0 + i] * ct(k0 + i, 16 * ta + c); },
+                                    [&](int i, int c) { return ct(k0 + i, 16 * tb + c); }, k1 - k0);
+                else  // C~ from global memory (L2): eight steps of operands in flight
+                    acc = mfma_tn16_deep([&](int i, int c) { return wdn[k0 + i] * ct(k0 + i, 16 * ta + c); },
+                                         [&](int i, int c) { return ct(k0 + i, 16 * tb + c); }, k1 - k0);
+            }
             if (ksplit == 1) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -1225,6 +1234,88 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     }
 }
 
+// ------------------------------------------- wide pencil products (a9)
+// For wide blocks (ld > 32) the two plain products of the pencil step run
+// over many workgroups, before and after the single-workgroup part:
+//   P3 = G^T [F | G | Lambda G]          (ld x 3 ld, sum over the d_n coarse rows)
+//   C~ = (F - Lambda G)(:, perm_r) L^-T   (d_n x ld, sum over the r kept columns)
+// P3: one 16 x 16 tile per workgroup, whose four wavefronts take a quarter of
+// the rows each (partial tiles summed in a fixed order); C~: one tile per
+// wavefront.  The same device functions serve the single and the batched
+// launches, so a joint step computes what a separate one does.
+__device__ __forceinline__ int p3_tiles(int ld) { return ((ld + 15) / 16) * ((3 * ld + 15) / 16); }
+__device__ __forceinline__ int ct_tiles(int ld, int dn) { return ((dn + 15) / 16) * ((ld + 15) / 16); }
+
+__device__ void pencil_p3_tile(const SmallWork &w, int tile) {
+    __shared__ double part[4 * 4 * kWave];
+    const int ld = w.ld, dn = w.dn, l2 = 2 * ld, l3 = 3 * ld, tj = (l3 + 15) / 16;
+    const int ta = tile / tj, tb = tile - ta * tj;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int chunk = ((dn + nw - 1) / nw + 3) & ~3;
+    const int k0 = wv * chunk, k1 = dn < k0 + chunk ? dn : k0 + chunk;
+    const double *FG = w.FG;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (k1 > k0)
+        acc = mfma_tn16_deep(
+            [&](int i, int c) -> double {
+                const int a = 16 * ta + c;
+                return a < ld ? FG[(int64_t)(k0 + i) * l2 + ld + a] : 0.0;
+            },
+            [&](int i, int c) -> double {
+                const int b = 16 * tb + c;
+                const int64_t row = (int64_t)(k0 + i) * l2;
+                if (b < l2) return FG[row + b];
+                return b < l3 ? w.lam[k0 + i] * FG[row + b - ld] : 0.0;
+            },
+            k1 - k0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) part[(wv * 4 + u) * kWave + lane] = acc[u];
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double v = 0.0;
+            for (int x = 0; x < nw; ++x) v += part[(x * 4 + u) * kWave + lane];
+            const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
+            if (i < ld && j < l3) w.P3[i * l3 + j] = v;
+        }
+    }
+}
+
+__device__ void pencil_ct_tile(const SmallWork &w, int tile) {  // one wavefront
+    const int ld = w.ld, dn = w.dn, l2 = 2 * ld, r = w.status[ST_RANK], tj = (ld + 15) / 16;
+    const int ti = tile / tj, tb = tile - ti * tj, lane = threadIdx.x & (kWave - 1);
+    const double *FG = w.FG;
+    const dbl4 acc = mfma_tn16(
+        [&](int k, int c) -> double {
+            const int i = 16 * ti + c;
+            if (i >= dn || k >= r) return 0.0;
+            const int pk = w.perm[k];
+            return FG[(int64_t)i * l2 + pk] - w.lam[i] * FG[(int64_t)i * l2 + ld + pk];
+        },
+        [&](int k, int c) -> double {
+            const int a = 16 * tb + c;
+            return (a < r && k < r) ? w.Li[a * ld + k] : 0.0;
+        },
+        r);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = 16 * ti + (lane >> 4) + 4 * u, a = 16 * tb + (lane & 15);
+        if (i < dn && a < ld) w.Ct[(int64_t)i * ld + a] = acc[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pencil_p3(SmallWork w) {
+    if (w.status[ST_CONVERGED]) return;
+    pencil_p3_tile(w, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_pencil_ct(SmallWork w) {
+    const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (w.status[ST_CONVERGED] || t >= ct_tiles(w.ld, w.dn)) return;  // wave-uniform
+    pencil_ct_tile(w, t);
+}
+
 // ------------------------------------------------------------ kernels
 __global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, int fg_in_lds) {
     pencil_body(w, rank_tol, fg_in_lds);
@@ -1248,6 +1339,27 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
 __global__ __launch_bounds__(256) void k_pencil_batch(SmallTable t, double rank_tol) {
     const SmallItem *it = t.item[blockIdx.x];
     pencil_body(it->w, rank_tol, it->fg_in_lds);
+}
+
+// the wide pencil products of the members with ld > 32: P3 tiles (workgroups)
+// of member m are p3first[m] .. p3first[m + 1] - 1, C~ tiles (wavefronts)
+// ctfirst[m] .. ctfirst[m + 1] - 1
+__global__ __launch_bounds__(256) void k_pencil_p3_batch(SmallTable t) {
+    int m = 0;
+    while (m + 1 < t.n && t.p3first[m + 1] <= (int)blockIdx.x) ++m;
+    const SmallItem *it = t.item[m];
+    if (it->w.status[ST_CONVERGED]) return;
+    pencil_p3_tile(it->w, (int)blockIdx.x - t.p3first[m]);
+}
+
+__global__ __launch_bounds__(256) void k_pencil_ct_batch(SmallTable t) {
+    const int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (g >= t.ctfirst[t.n]) return;
+    int m = 0;
+    while (m + 1 < t.n && t.ctfirst[m + 1] <= g) ++m;
+    const SmallItem *it = t.item[m];
+    if (it->w.status[ST_CONVERGED]) return;
+    pencil_ct_tile(it->w, g - t.ctfirst[m]);
 }
 
 __global__ __launch_bounds__(256) void k_arrow_bisect_batch(SmallTable t) {
@@ -1291,11 +1403,17 @@ void small_layout(const SmallWork &w, int qe, double *theta, SmallItem *it, Smal
     lds->rr = (use_lds ? full : rbase) * sizeof(double);
 }
 
+int pencil_p3_blocks(int ld) { return ld > 32 ? ((ld + 15) / 16) * ((3 * ld + 15) / 16) : 0; }
+int pencil_ct_waves(int ld, int dn) { return ld > 32 ? ((dn + 15) / 16) * ((ld + 15) / 16) : 0; }
+
 void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
     SmallItem it;
     SmallLds lds;
     small_layout(w, 1, nullptr, &it, &lds);
+    const int np3 = pencil_p3_blocks(w.ld), nct = pencil_ct_waves(w.ld, w.dn);
+    if (np3) hipLaunchKernelGGL(k_pencil_p3, dim3(np3), dim3(kB), 0, s, w);
     hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds.pencil, s, w, rank_tol, it.fg_in_lds);
+    if (nct) hipLaunchKernelGGL(k_pencil_ct, dim3((nct + kB / kWave - 1) / (kB / kWave)), dim3(kB), 0, s, w);
 }
 
 void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, int final_level) {
@@ -1308,7 +1426,11 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, 
 
 void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol) {
     if (t.n <= 0) return;
+    if (t.p3first[t.n] > 0) hipLaunchKernelGGL(k_pencil_p3_batch, dim3(t.p3first[t.n]), dim3(kB), 0, s, t);
     hipLaunchKernelGGL(k_pencil_batch, dim3(t.n), dim3(kB), lds.pencil, s, t, rank_tol);
+    if (t.ctfirst[t.n] > 0)
+        hipLaunchKernelGGL(k_pencil_ct_batch, dim3((t.ctfirst[t.n] + kB / kWave - 1) / (kB / kWave)), dim3(kB), 0, s,
+                           t);
     hipLaunchKernelGGL(k_arrow_bisect_batch, dim3(t.first[t.n]), dim3(kB), lds.bisect, s, t);
     hipLaunchKernelGGL(k_arrow_rr_batch, dim3(t.n), dim3(kB), lds.rr, s, t);
 }
