@@ -865,26 +865,35 @@ int joint_small(amg_eig_ctx *const *cs, int n, int final_level, bool gemms) {
         HIPCHK(o, hipEventRecord(o->join_ev, o->stream));
         HIPCHK(lead, hipStreamWaitEvent(ls, o->join_ev, 0));
     }
-    for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
-        const int m = std::min(n - i0, kMaxBatch);
-        SmallTable t{};
-        SmallLds lds;
-        t.n = m;
-        t.final_level = final_level;
-        t.first[0] = t.p3first[0] = t.ctfirst[0] = 0;
-        for (int j = 0; j < m; ++j) {
-            const amg_eig_ctx *c = cs[i0 + j];
-            t.item[j] = c->item_dev;
-            t.first[j + 1] = t.first[j] + c->qe;
-            t.p3first[j + 1] = t.p3first[j] + pencil_p3_blocks(c->ld);
-            t.ctfirst[j + 1] = t.ctfirst[j] + pencil_ct_waves(c->ld, c->H.dn);
-            lds.pencil = std::max(lds.pencil, c->small_lds.pencil);
-            lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
-            lds.rr = std::max(lds.rr, c->small_lds.rr);
+    // narrow (ld <= 32) and wide members in separate launches: the pencil and
+    // Rayleigh-Ritz kernels of wide blocks run more wavefronts, as in a
+    // member's separate launch
+    std::vector<amg_eig_ctx *> group[2];
+    for (int i = 0; i < n; ++i) group[cs[i]->ld > 32 ? 1 : 0].push_back(cs[i]);
+    for (int wide = 0; wide < 2; ++wide) {
+        const std::vector<amg_eig_ctx *> &g = group[wide];
+        const int ng = (int)g.size();
+        for (int i0 = 0; i0 < ng; i0 += kMaxBatch) {
+            const int m = std::min(ng - i0, kMaxBatch);
+            SmallTable t{};
+            SmallLds lds;
+            t.n = m;
+            t.final_level = final_level;
+            t.first[0] = t.p3first[0] = t.ctfirst[0] = 0;
+            for (int j = 0; j < m; ++j) {
+                const amg_eig_ctx *c = g[i0 + j];
+                t.item[j] = c->item_dev;
+                t.first[j + 1] = t.first[j] + c->qe;
+                t.p3first[j + 1] = t.p3first[j] + pencil_p3_blocks(c->ld);
+                t.ctfirst[j + 1] = t.ctfirst[j] + pencil_ct_waves(c->ld, c->H.dn);
+                lds.pencil = std::max(lds.pencil, c->small_lds.pencil);
+                lds.bisect = std::max(lds.bisect, c->small_lds.bisect);
+                lds.rr = std::max(lds.rr, c->small_lds.rr);
+            }
+            if (gemms) launch_gemms(ls, g.data() + i0, m, 0);
+            launch_small_batch(ls, t, lds, kRankTol, wide == 1);
+            if (gemms) launch_gemms(ls, g.data() + i0, m, 1);
         }
-        if (gemms) launch_gemms(ls, cs + i0, m, 0);
-        launch_small_batch(ls, t, lds, kRankTol);
-        if (gemms) launch_gemms(ls, cs + i0, m, 1);
     }
     HIPCHK(lead, hipEventRecord(lead->join_ev, ls));
     for (amg_eig_ctx *o : others) HIPCHK(o, hipStreamWaitEvent(o->stream, lead->join_ev, 0));

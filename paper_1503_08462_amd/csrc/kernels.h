@@ -156,7 +156,9 @@ int pencil_p3_blocks(int ld);
 int pencil_ct_waves(int ld, int dn);
 // pencil, eigenpairs and Ritz polish of every member of the table, three
 // launches in all; lds holds the largest size over the members
-void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol);
+// wide: every member has ld > 32 (the pencil and Rayleigh-Ritz kernels then
+// run sixteen wavefronts, as in a member's separate launch), else none has
+void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol, bool wide);
 struct GemmTable {
     const SmallItem *item[kMaxBatch];  // device addresses
     int first[kMaxBatch + 1];          // tiles of member m: first[m] .. first[m+1]-1

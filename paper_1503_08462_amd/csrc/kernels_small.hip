@@ -27,6 +27,13 @@ namespace amgeig {
 namespace {
 
 constexpr int kB = 256;  // threads per block of the small kernels
+// The single-workgroup pencil and Rayleigh-Ritz kernels of wide blocks
+// (ld > 32, operands beyond LDS in global memory) run sixteen wavefronts:
+// their products deal 16 x 16 tiles to the wavefronts, each tile summed by one
+// wavefront in a fixed order, so more wavefronts hide more load latency and
+// leave the results unchanged.
+constexpr int kBWide = 1024;
+inline int small_threads(int ld) { return ld > 32 ? kBWide : kB; }
 
 // Solver statistics (inertia counts per eigenvalue, fallbacks, Jacobi sweeps
 // and phase clocks, added into w.diag) are compiled in only with
@@ -1317,7 +1324,7 @@ __global__ __launch_bounds__(256) void k_pencil_ct(SmallWork w) {
 }
 
 // ------------------------------------------------------------ kernels
-__global__ __launch_bounds__(256) void k_pencil(SmallWork w, double rank_tol, int fg_in_lds) {
+__global__ __launch_bounds__(1024) void k_pencil(SmallWork w, double rank_tol, int fg_in_lds) {
     pencil_body(w, rank_tol, fg_in_lds);
 }
 
@@ -1326,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double 
     arrow_bisect_body(w, theta_prev, ct_in_lds, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_lds, double *theta_out, int final_level) {
+__global__ __launch_bounds__(1024) void k_arrow_rr(SmallWork w, int qe, int use_lds, double *theta_out, int final_level) {
     arrow_rr_body(w, qe, use_lds, theta_out, final_level);
 }
 
@@ -1336,7 +1343,7 @@ __global__ __launch_bounds__(256) void k_arrow_rr(SmallWork w, int qe, int use_l
 // Every member's descriptor (pointers into its own workspace, widths, LDS
 // layout flags) lives in device memory; the launch takes the largest LDS size
 // any member needs.
-__global__ __launch_bounds__(256) void k_pencil_batch(SmallTable t, double rank_tol) {
+__global__ __launch_bounds__(1024) void k_pencil_batch(SmallTable t, double rank_tol) {
     const SmallItem *it = t.item[blockIdx.x];
     pencil_body(it->w, rank_tol, it->fg_in_lds);
 }
@@ -1369,7 +1376,7 @@ __global__ __launch_bounds__(256) void k_arrow_bisect_batch(SmallTable t) {
     arrow_bisect_body(it->w, it->theta, it->ct_in_lds, (int)blockIdx.x - t.first[m], it->qe);
 }
 
-__global__ __launch_bounds__(256) void k_arrow_rr_batch(SmallTable t) {
+__global__ __launch_bounds__(1024) void k_arrow_rr_batch(SmallTable t) {
     const SmallItem *it = t.item[blockIdx.x];
     arrow_rr_body(it->w, it->qe, it->use_lds, it->theta, t.final_level);
 }
@@ -1412,7 +1419,7 @@ void launch_pencil(hipStream_t s, const SmallWork &w, double rank_tol) {
     small_layout(w, 1, nullptr, &it, &lds);
     const int np3 = pencil_p3_blocks(w.ld), nct = pencil_ct_waves(w.ld, w.dn);
     if (np3) hipLaunchKernelGGL(k_pencil_p3, dim3(np3), dim3(kB), 0, s, w);
-    hipLaunchKernelGGL(k_pencil, dim3(1), dim3(kB), lds.pencil, s, w, rank_tol, it.fg_in_lds);
+    hipLaunchKernelGGL(k_pencil, dim3(1), dim3(small_threads(w.ld)), lds.pencil, s, w, rank_tol, it.fg_in_lds);
     if (nct) hipLaunchKernelGGL(k_pencil_ct, dim3((nct + kB / kWave - 1) / (kB / kWave)), dim3(kB), 0, s, w);
 }
 
@@ -1421,18 +1428,19 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, 
     SmallLds lds;
     small_layout(w, qe, theta, &it, &lds);
     hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(kB), lds.bisect, s, w, theta, it.ct_in_lds);
-    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(kB), lds.rr, s, w, qe, it.use_lds, theta, final_level);
+    hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(small_threads(w.ld)), lds.rr, s, w, qe, it.use_lds, theta, final_level);
 }
 
-void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol) {
+void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds, double rank_tol, bool wide) {
+    const int nt = wide ? kBWide : kB;
     if (t.n <= 0) return;
     if (t.p3first[t.n] > 0) hipLaunchKernelGGL(k_pencil_p3_batch, dim3(t.p3first[t.n]), dim3(kB), 0, s, t);
-    hipLaunchKernelGGL(k_pencil_batch, dim3(t.n), dim3(kB), lds.pencil, s, t, rank_tol);
+    hipLaunchKernelGGL(k_pencil_batch, dim3(t.n), dim3(nt), lds.pencil, s, t, rank_tol);
     if (t.ctfirst[t.n] > 0)
         hipLaunchKernelGGL(k_pencil_ct_batch, dim3((t.ctfirst[t.n] + kB / kWave - 1) / (kB / kWave)), dim3(kB), 0, s,
                            t);
     hipLaunchKernelGGL(k_arrow_bisect_batch, dim3(t.first[t.n]), dim3(kB), lds.bisect, s, t);
-    hipLaunchKernelGGL(k_arrow_rr_batch, dim3(t.n), dim3(kB), lds.rr, s, t);
+    hipLaunchKernelGGL(k_arrow_rr_batch, dim3(t.n), dim3(nt), lds.rr, s, t);
 }
 
 }  // namespace amgeig
