@@ -41,7 +41,10 @@ __device__ __forceinline__ Vec<T, C> zero_v() {
 
 // Gathers x[col[p]] (CPT values from column c0) for p in [p0, p1) and hands
 // each to consume(p, j, x_j) in ascending p; the loads of four neighbours are
-// issued before the first of them is consumed.
+// issued before the first of them is consumed, and the last one to three
+// neighbours of a row are loaded together too (a masked entry reloads the
+// first of them and is not consumed), so a row of 5, 7 or 15 neighbours costs
+// two or four dependent round trips, not one per leftover neighbour.
 template <typename T, int CPT, class F>
 __device__ __forceinline__ void gather4(int32_t p0, int32_t p1, const int32_t *__restrict__ col,
                                         const T *__restrict__ x, int ld, int c0, const F &consume) {
@@ -57,9 +60,15 @@ __device__ __forceinline__ void gather4(int32_t p0, int32_t p1, const int32_t *_
         consume(p + 2, j2, x2);
         consume(p + 3, j3, x3);
     }
-    for (; p < p1; ++p) {
-        const int64_t j = col[p];
-        consume(p, j, ldv<T, CPT>(x + j * ld + c0));
+    const int rem = p1 - p;  // 0 .. 3
+    if (rem > 0) {
+        const int64_t j0 = col[p], j1 = rem > 1 ? col[p + 1] : j0, j2 = rem > 2 ? col[p + 2] : j0;
+        const Vec<T, CPT> x0 = ldv<T, CPT>(x + j0 * ld + c0);
+        const Vec<T, CPT> x1 = ldv<T, CPT>(x + j1 * ld + c0);
+        const Vec<T, CPT> x2 = ldv<T, CPT>(x + j2 * ld + c0);
+        consume(p, j0, x0);
+        if (rem > 1) consume(p + 1, j1, x1);
+        if (rem > 2) consume(p + 2, j2, x2);
     }
 }
 
@@ -845,25 +854,13 @@ inline int64_t row_blocks(int64_t n, int ld, int cpt) {
 }  // namespace
 
 // Columns per lane for a row-major block of the given width when no tuned
-// value is set: among 2, 4 and 8, the one whose rows of width / CPT threads
-// pack a wavefront best (ties to fewer columns per lane).  With RowMap's flat
-// numbering every lane has work whatever the choice; this rule picks the
-// vector width (4 columns for widths of 17 x 4 and the like, 2 for widths a
-// power of two up to 16), and the autotuner times the others.
+// value is set: 4 (16-byte FP32 and 32-byte FP64 accesses per lane) when the
+// width allows it, else 2, else 8.  With RowMap's flat numbering every lane
+// has work whatever the choice; the autotuner times the others.
 int cpt_for(int width) {
-    int best = 0;
-    double bu = -1.0;
-    for (int c = 2; c <= 8; c *= 2) {
-        if (width % c) continue;
-        const int tpr = width / c;
-        if (tpr > kWave) continue;
-        const double u = (double)((kWave / tpr) * tpr) / kWave;
-        if (u > bu + 0.02) {
-            bu = u;
-            best = c;
-        }
-    }
-    return best ? best : 8;
+    for (int c : {4, 2, 8})
+        if (width % c == 0 && width / c <= kWave) return c;
+    return 8;
 }
 
 bool cpt_valid(int width, int cpt) {

@@ -35,7 +35,7 @@ class FakeCtx:
 
     def get_cpt(self, kind, level):
         c = self.set.get((kind, level), 0)
-        return c if c else 2  # the built-in rule picks 2 for width 16 and 32
+        return c if c else 2  # a stand-in built-in choice
 
     def tune_time(self, kind, level, cpt, reps):
         self.calls.append((kind, level, cpt))
@@ -77,11 +77,11 @@ def test_candidates_respect_width():
 def test_library_validates_launch_shape():
     p = configs.config(0)
     ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(coarse_max=130))
-    assert ctx.get_cpt(ae.TUNE_VCYCLE, 0) == 2  # width 4: two lanes of two columns
-    ctx.set_cpt(ae.TUNE_VCYCLE, 0, 4)
-    assert ctx.get_cpt(ae.TUNE_VCYCLE, 0) == 4
-    ctx.set_cpt(ae.TUNE_VCYCLE, 0, 0)
+    assert ctx.get_cpt(ae.TUNE_VCYCLE, 0) == 4  # width 4: the built-in rule takes 4 columns per lane
+    ctx.set_cpt(ae.TUNE_VCYCLE, 0, 2)
     assert ctx.get_cpt(ae.TUNE_VCYCLE, 0) == 2
+    ctx.set_cpt(ae.TUNE_VCYCLE, 0, 0)
+    assert ctx.get_cpt(ae.TUNE_VCYCLE, 0) == 4
     for bad in (1, 3, 8, 16):  # 8 does not divide width 4
         with pytest.raises(ae.AmgEigError) as e:
             ctx.set_cpt(ae.TUNE_VCYCLE, 0, bad)
