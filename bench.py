@@ -147,116 +147,156 @@ def cpu_baseline(cfg, qe, coarse_max, tol, gpu_corrections):
 
 
 def serving(args):
-    """Serving stream: seeded requests from the three mesh families with uneven N
-    and q, Poisson arrivals at a fixed rate, admission by device footprint and
-    continuous batching over a stream pool (mixed precision).  Beside it, the
-    same requests solved one after another as plain single-instance solves, in
-    FP64 and in mixed precision.  Host setup (the AMG hierarchy) is done before
-    each timed pass; binding (device workspace) and the solve are inside."""
+    """Serving stream (config 5): seeded requests from the three mesh families
+    with uneven N and q, admission by device footprint and continuous batching
+    over a stream pool, mixed precision, the block width the library's own.
+
+    Meshes and host setup (the AMG hierarchies) of all requests are built
+    before any timed pass, in a thread pool.  Passes over the same requests:
+    a warm-up burst (every request arrives at once; the width control
+    settles each block), a burst whose throughput is the capacity, then
+    Poisson arrivals at the given fractions of that capacity, each reporting
+    throughput and p50/p99 latency (arrival to result).  Beside them, plain
+    FP64 single-instance solves one after another on every `solo_every`-th
+    request (each solved once untimed, then timed)."""
+    import concurrent.futures as cf
     import torch
     import paper_1503_08462_amd as ae
     from paper_1503_08462_amd.serving import Server
     from workloads import configs
 
-    reqs = configs.request_stream(args.requests, seed=5, n_lo=10_000, n_hi=args.n_hi)
-    probs = [configs.build_request(r) for r in reqs]
-    qs = np.array([p["q"] for p in probs])
-    gaps = -np.log1p(-np.array([r["u_arrival"] for r in reqs])) / args.rate
-    arrivals = np.cumsum(gaps) - gaps[0]
     tol = args.tol
+    reqs = configs.request_stream(args.requests, seed=5, n_lo=10_000, n_hi=args.n_hi)
+    opts = lambda prec: ae.defaults(coarse_max=512, precision=prec, tol=tol,
+                                    use_graph=args.serve_graph if prec == ae.PREC_MIXED else 0)
 
-    def contexts(prec):
-        # the block width is the library's own choice (guard rule and width control)
-        return [ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
-                           ae.defaults(coarse_max=512, precision=prec, tol=tol,
-                                       use_graph=args.serve_graph if prec == ae.PREC_MIXED else 0)) for p in probs]
+    def build(r):
+        p = configs.build_request(r)
+        c = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], opts(ae.PREC_MIXED))
+        solo = None
+        if r["id"] % args.solo_every == 0:
+            solo = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], opts(ae.PREC_FP64))
+        return {"n": int(p["n"]), "q": int(p["q"]), "family": r["family"], "ctx": c, "solo": solo}
 
-    def solo(prec):
-        cs = contexts(prec)
-        stream = torch.cuda.Stream()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        lat, bad = [], []
-        for k, c in enumerate(cs):
-            t1 = time.perf_counter()
-            c.bind(stream=stream)
-            _, ok = c.solve(tol, 400)
-            if not ok:
-                bad.append(k)
-            c.close()
-            c.workspace = None
-            lat.append(time.perf_counter() - t1)
-        torch.cuda.synchronize()
-        if bad:
-            raise SystemExit("solo solves of requests %s did not converge" % bad)
-        return qs.sum() / (time.perf_counter() - t), lat
-
-    # warm-up: one request end to end
-    c = contexts(ae.PREC_MIXED)[0]
-    c.bind()
-    c.solve(tol, 400)
-    c.close()
-    del c
-    solo64, _ = solo(ae.PREC_FP64)
-    solo32, _ = solo(ae.PREC_MIXED)
-
-    cs = contexts(ae.PREC_MIXED)
-    fps = sorted(c.footprint() for c in cs)
-    budget = int(args.budget_gb * 2 ** 30)
-    srv = Server(max(budget, fps[-1]), n_streams=args.streams, steps_per_round=args.steps_per_round,
-                 max_active=args.max_active if args.max_active > 0 else None,
-                 context_factory=lambda p, o: cs[p["_k"]],
-                 batch_fn=None if args.joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)),
-                 init_fn=(lambda cs_: ae.init_batch_joint(cs_)) if args.joint_init else None)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    i = 0
-    while i < len(probs) or srv.queue or srv.active:
-        now = time.perf_counter() - t0
-        while i < len(probs) and arrivals[i] <= now:
-            srv.submit(dict(probs[i], _k=i), tol=tol, max_steps=400, arrival=t0 + arrivals[i])
-            i += 1
-        if srv.queue or srv.active:
-            srv.round()
-        elif i < len(probs):
-            time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
-    torch.cuda.synchronize()
-    makespan = time.perf_counter() - t0
-    res = srv.results()
-    bad = [k for k, r in res.items() if not r["converged"]]
-    if bad:
-        raise SystemExit("served requests %s did not converge" % bad)
-    lat = srv.latency()
-    served = qs.sum() / makespan
-    ns = [p["n"] for p in probs]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    items = [None] * len(reqs)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {ex.submit(build, r): k for k, r in enumerate(reqs)}
+        for done, f in enumerate(cf.as_completed(futs)):
+            items[futs[f]] = f.result()
+            if done % 16 == 15:
+                print("[serving] host setup %d of %d requests, %.0f s" % (done + 1, len(reqs), time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t0
+    qs = np.array([it["q"] for it in items])
+    ns = [it["n"] for it in items]
+    budget = int(args.budget_gb * 2 ** 30)
+    if budget <= 0:  # 0: 80% of the device memory free now
+        budget = int(0.8 * torch.cuda.mem_get_info()[0])
+
+    # plain FP64 single-instance solves on the sample, one after another
+    stream = torch.cuda.Stream()
+    sample = [it for it in items if it["solo"] is not None]
+    solo_s = 0.0
+    for it in sample:
+        c = it["solo"]
+        c.bind(stream=stream)
+        c.solve(tol, 400)  # settles the block width
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c.init(ae.INIT_NESTED)
+        _, ok = c.solve(tol, 400)
+        torch.cuda.synchronize()
+        solo_s += time.perf_counter() - t1
+        if not ok:
+            raise SystemExit("solo FP64 solve of request %d did not converge" % items.index(it))
+        c.close()
+        c.workspace = None
+    solo64 = float(sum(it["q"] for it in sample) / solo_s) if solo_s > 0 else None
+
+    def one_pass(arrivals):
+        srv = Server(budget, n_streams=args.streams, steps_per_round=args.steps_per_round,
+                     max_active=args.max_active if args.max_active > 0 else None,
+                     context_factory=lambda p_, o_: items[p_["_k"]]["ctx"], keep_contexts=True,
+                     batch_fn=None if args.joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)),
+                     init_fn=(lambda cs_: ae.init_batch_joint(cs_)) if args.joint_init else None)
+        order = np.argsort(arrivals, kind="stable")
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        i = 0
+        while i < len(order) or srv.queue or srv.active:
+            now = time.perf_counter() - t_start
+            while i < len(order) and arrivals[order[i]] <= now:
+                k = int(order[i])
+                srv.submit({"q": items[k]["q"], "_k": k}, tol=tol, max_steps=400, arrival=t_start + arrivals[k])
+                i += 1
+            if srv.queue or srv.active:
+                srv.round()
+            elif i < len(order):
+                time.sleep(max(0.0, arrivals[order[i]] - (time.perf_counter() - t_start)))
+        torch.cuda.synchronize()
+        span = time.perf_counter() - t_start
+        res = srv.results()
+        bad = [k for k, r in res.items() if not r["converged"]]
+        if bad:
+            raise SystemExit("served requests %s did not converge" % bad)
+        lat = srv.latency()
+        return {"eigenpairs_per_s": float(qs.sum() / span), "requests_per_s": len(items) / span, "seconds": span,
+                "p50_ms": lat["p50_s"] * 1e3, "p99_ms": lat["p99_s"] * 1e3,
+                "peak_resident_gb": srv.peak_in_use / 2 ** 30, "rounds": srv.rounds,
+                "widened_requests": int(sum(1 for r in res.values() if r.get("widened")))}
+
+    print("[serving] solo FP64 sample done, %.0f s" % solo_s, file=sys.stderr, flush=True)
+    burst = np.zeros(len(items))
+    warm = one_pass(burst)
+    print("[serving] warm-up burst pass %.1f s" % warm["seconds"], file=sys.stderr, flush=True)
+    cap = one_pass(burst)
+    print("[serving] capacity pass %.1f s" % cap["seconds"], file=sys.stderr, flush=True)
+    u = np.array([r["u_arrival"] for r in reqs])
+    passes = []
+    for f in [float(x) for x in args.rates.split(",") if x.strip()]:
+        rate = f * cap["requests_per_s"]
+        gaps = -np.log1p(-u) / rate
+        arr = np.cumsum(gaps) - gaps[0]
+        r_ = one_pass(arr)
+        r_.update(fraction_of_capacity=f, arrival_rate_per_s=rate)
+        passes.append(r_)
+        print("[serving] pass at %.1f of capacity %.1f s" % (f, r_["seconds"]), file=sys.stderr, flush=True)
+    head = passes[len(passes) // 2] if passes else cap
     out = {
         "metric": "eigenpairs/sec to 1e-8 rel. residual (served stream)",
-        "value": served,
+        "value": cap["eigenpairs_per_s"],
         "unit": "eigenpairs/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 1,
-        "ms_per_step": makespan * 1e3,
+        "ms_per_step": cap["seconds"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "serving stream: %d seeded requests (L-shape, checkerboard cube, oscillator), "
-                               "N in [%d, %d], q in {4, 8, 16, 32}, Poisson arrivals at %g/s"
-                               % (len(probs), min(ns), max(ns), args.rate),
-                   "requests": len(probs), "eigenpairs": int(qs.sum()), "budget_gb": args.budget_gb,
-                   "streams": args.streams, "steps_per_round": args.steps_per_round, "tol": tol,
-                   "max_active": args.max_active or None,
-                   "graph_steps": bool(args.serve_graph), "joint_small_solves": bool(args.joint),
-                   "joint_starts": bool(args.joint_init)},
-        "p50_ms": lat["p50_s"] * 1e3,
-        "p99_ms": lat["p99_s"] * 1e3,
-        "peak_resident_gb": srv.peak_in_use / 2 ** 30,
-        "rounds": srv.rounds,
+        "config": {"workload": "config 5: serving stream of %d seeded requests (L-shape, checkerboard cube, oscillator), "
+                               "N in [%d, %d], q in {4, 8, 16, 32}" % (len(items), min(ns), max(ns)),
+                   "requests": len(items), "eigenpairs": int(qs.sum()),
+                   "families": {f: sum(1 for it in items if it["family"] == f) for f in ("lshape", "cube", "oscillator")},
+                   "budget_gb": budget / 2 ** 30, "streams": args.streams, "steps_per_round": args.steps_per_round,
+                   "tol": tol, "max_active": args.max_active or None, "graph_steps": bool(args.serve_graph),
+                   "joint_small_solves": bool(args.joint), "joint_starts": bool(args.joint_init),
+                   "block_width": "library (guard rule and width control)"},
+        "value_is": "capacity: throughput of a burst pass (every request arriving at once) after a warm-up pass",
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "latency_at": "the middle Poisson pass (%s of capacity)" % (head.get("fraction_of_capacity", "burst")),
+        "host_setup_s": setup_s,
+        "warmup_pass": warm,
+        "capacity_pass": cap,
+        "poisson_passes": passes,
         "solo_fp64_eigenpairs_per_s": solo64,
-        "solo_mixed_eigenpairs_per_s": solo32,
-        "served_vs_solo_fp64": served / solo64,
+        "solo_fp64_sample": "%d of %d requests (every %d-th), each solved once untimed then timed" % (
+            len(sample), len(items), args.solo_every),
+        "served_vs_solo_fp64": (cap["eigenpairs_per_s"] / solo64) if solo64 else None,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -343,9 +383,13 @@ def main():
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev"])
     ap.add_argument("--requests", type=int, default=24, help="serving stream (config 5): number of requests")
-    ap.add_argument("--rate", type=float, default=200.0, help="serving stream: Poisson arrival rate, 1/s")
     ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
-    ap.add_argument("--budget-gb", type=float, default=8.0, help="serving stream: device memory budget")
+    ap.add_argument("--budget-gb", type=float, default=8.0,
+                    help="serving stream: device memory budget (0: 80%% of the free device memory)")
+    ap.add_argument("--rates", default="0.5,0.7,0.9",
+                    help="serving stream: Poisson arrival rates as fractions of the measured capacity")
+    ap.add_argument("--solo-every", type=int, default=4,
+                    help="serving stream: plain FP64 solves on every n-th request (the solo baseline)")
     ap.add_argument("--streams", type=int, default=8, help="serving stream: stream pool size")
     ap.add_argument("--steps-per-round", type=int, default=2, help="serving stream: corrections per round")
     ap.add_argument("--serve-graph", type=int, default=1, help="serving stream: replay captured steps (or, with "

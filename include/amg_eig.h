@@ -176,8 +176,11 @@ int amg_eig_correct(amg_eig_ctx *c, int steps);
  * returned: the iterate is discarded, and amg_eig_init() must follow, after a
  * bind of a workspace of amg_eig_footprint() bytes if the new width does not
  * fit the bound one (the context is then unbound).  Once a widened block has
- * converged, the next start takes the narrowest multiple of 4 whose Ritz
- * values end at such a gap.  amg_eig_info() reports the width in effect.
+ * converged, the next start takes the narrowest multiple of 4, w >= q, with
+ * theta_{w+1} >= 1.25 theta_q (so the wanted pairs keep contracting by about
+ * (theta_q / theta_{w+1})^2 <= 0.64 per correction), if the wide block holds
+ * one; otherwise the wide width stays.  amg_eig_info() reports the width in
+ * effect.
  * Errors: ESTATE (not bound), EBREAKDOWN, EHIP. */
 int amg_eig_progress(amg_eig_ctx *c, double *theta, double *rho, int *steps, int *converged);
 

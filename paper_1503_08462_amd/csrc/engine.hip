@@ -675,6 +675,10 @@ int closed_width(const double *th, int n, int q, double gap) {
 
 int round4(int w) { return (w + 3) / 4 * 4; }
 
+// separation the width control keeps between the q-th Ritz value and the
+// first one past a narrowed block
+constexpr double kNarrowSep = 1.25;
+
 // Give the context block width w.  When it is bound and the workspace holds
 // the new plan, the blocks are re-carved in place (the uploaded matrices,
 // coarse basis and dense tail keep their addresses) and true is returned;
@@ -706,16 +710,24 @@ bool set_width(amg_eig_ctx *c, int w) {
 // one cut inside a cluster stays flat).  A stalled block with no gap of the
 // guard rule inside it past the q-th Ritz value ends inside a cluster: its
 // width is doubled (up to qe_cap) and true is returned.  After a widened
-// block converges, the next start takes the narrowest multiple of 4 that ends
-// at such a gap.
+// block converges, the next start takes the narrowest multiple of 4 that
+// keeps the first Ritz value past it kNarrowSep above the q-th, if the wide
+// block holds one.
 bool width_check(amg_eig_ctx *c, const double *th, const double *rho, int steps, int conv) {
     if (!c->width_auto || c->width_decided) return false;
     const int q = c->q, qe = c->qe;
     if (conv) {
         c->width_decided = true;
         if (c->widened) {
-            const int m = closed_width(th, qe, q, c->o.guard_gap);
-            if (m > 0 && round4(m) < qe) c->qe_next = round4(m);
+            // the narrowest multiple of 4 whose next Ritz value lies well above the
+            // q-th (theta_{w+1} >= kNarrowSep theta_q: a block of width w
+            // contracts the wanted pairs by about (theta_q / theta_{w+1})^2 per
+            // correction); without one inside the block, the wide width stays
+            for (int w = round4(q); w < qe; w += 4)
+                if (th[w] >= kNarrowSep * th[q - 1]) {
+                    c->qe_next = w;
+                    break;
+                }
         }
         return false;
     }

@@ -711,8 +711,9 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
     stv<double, CPT>(U + rm.row * ld + c0, acc);
 }
 
-// Wide blocks: U = P Y + V X_v on the correction level.  A workgroup stages
-// X_v in LDS once, then walks its blocks of kFinalRows consecutive rows: all
+// Wide blocks: U = P Y + V X_v on the correction level.  A workgroup (eight
+// wavefronts) stages X_v in LDS once, then walks its blocks of kFinalRows
+// consecutive rows: all
 // its threads copy the block's rows of V (contiguous in memory) into LDS with
 // coalesced 16-byte loads, and each wavefront takes 16 of the rows: V X_v as
 // 16 x 16 tiles on the FP64 matrix cores with both operands from LDS (each
@@ -722,8 +723,9 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
 // rows of P are held in registers across the column tiles, so that a tile's
 // gathers of Y are independent loads issued together.
 constexpr int kPRow = 4;
-constexpr int kFinalRows = 64;
-__global__ __launch_bounds__(256) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
+constexpr int kFinalRows = 128;  // 16 rows per wavefront, eight wavefronts per workgroup
+constexpr int kFinalThreads = 512;
+__global__ __launch_bounds__(kFinalThreads) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
                                                const int32_t *__restrict__ col, const double *__restrict__ val,
                                                const double *__restrict__ Y, const double *__restrict__ V,
                                                const double *__restrict__ Xv, double *__restrict__ U,
@@ -1007,11 +1009,12 @@ void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const in
                                             Y, V, Xv, U, status));
         return;
     }
-    // workgroups: each owns a contiguous range of 64-row blocks; LDS holds X_v
-    // and one block of V rows (two workgroups per CU at ld = 68)
+    // workgroups: each owns a contiguous range of 128-row blocks; LDS holds X_v
+    // and one block of V rows (107 KB at ld = 68, 133 KB at ld = 80: one
+    // workgroup of eight wavefronts per CU)
     const int64_t blocks = (n + kFinalRows - 1) / kFinalRows;
-    const int64_t nb = blocks < 2048 ? blocks : 2048;
-    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kBlock), (size_t)(ld * ld + kFinalRows * ld) * sizeof(double), s,
+    const int64_t nb = blocks < 1024 ? blocks : 1024;
+    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kFinalThreads), (size_t)(ld * ld + kFinalRows * ld) * sizeof(double), s,
             n, ld, ptr, col, val, Y, V, Xv, U, status);
 }
 

@@ -62,13 +62,18 @@ class Server:
                       init on its stream (init_batch_joint, which solves the
                       small problems of the starts together, holds the new
                       requests in step with each other and measured slower)
+    keep_contexts:    a finished request gives back its device workspace but
+                      its context stays open (the caller may submit it again,
+                      e.g. for another measured pass over the same requests)
     """
 
     def __init__(self, budget_bytes, n_streams=4, steps_per_round=2, opts=None, context_factory=None,
-                 batch_fn=None, stream_factory=None, clock=time.perf_counter, max_active=None, init_fn=None):
+                 batch_fn=None, stream_factory=None, clock=time.perf_counter, max_active=None, init_fn=None,
+                 keep_contexts=False):
         if budget_bytes <= 0 or n_streams < 1 or steps_per_round < 1 or (max_active is not None and max_active < 1):
             raise ValueError("budget, stream count, steps per round and active limit must be positive")
         self.max_active = max_active
+        self.keep_contexts = keep_contexts
         self.budget = int(budget_bytes)
         self.steps_per_round = int(steps_per_round)
         self.opts = opts
@@ -161,7 +166,8 @@ class Server:
                 req.result = {"lam": np.asarray(pr["theta"][:req.q]).copy(), "rho": np.asarray(pr["rho"][:req.q]).copy(),
                               "steps": pr["steps"], "converged": bool(pr["converged"]),
                               "latency_s": req.done - req.arrival, "widened": req.widened}
-                req.ctx.close()
+                if not self.keep_contexts:
+                    req.ctx.close()
                 if hasattr(req.ctx, "workspace"):
                     req.ctx.workspace = None  # back to the allocator for the next admissions
                 self.in_use -= req.footprint

@@ -146,3 +146,31 @@ def test_tighter_tolerance_after_a_converged_solve():
     rho = np.linalg.norm(R, axis=0) / (pr["theta"][:6] * np.linalg.norm(MU, axis=0))
     assert rho.max() <= 1e-10 * 1.01, rho
     ctx.close()
+
+
+def test_narrowed_width_keeps_a_convergence_margin():
+    """A jittered L-shape (N = 339 360, q = 32) whose coarse rule gives q_e = q:
+    the block stalls (lambda_33 is only 1.8% above lambda_32), is widened, and
+    converges.  The next start must not narrow back to a width whose first
+    Ritz value past the block lies close to lambda_q (that block would
+    contract by about (1 / 1.018)^2 per correction): both solves converge and
+    the second keeps theta_{q_e+1} >= 1.25 theta_q inside the first's block."""
+    _torch()
+    r = configs.request_stream(32, seed=5, n_lo=10_000, n_hi=1_000_000)[24]
+    p = configs.build_request(r)
+    _say("L-shape N=%d q=%d, two solves with the default width control" % (p["n"], p["q"]))
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(coarse_max=512, tol=1e-8))
+    ctx.bind()
+    lam1, ok = ctx.solve(tol=1e-8, max_steps=400)
+    assert ok
+    wide = ctx.info()["qe"]
+    th = ctx.progress()["theta"]
+    ctx.init(ae.INIT_NESTED)
+    lam2, ok = ctx.solve(tol=1e-8, max_steps=400)
+    w = ctx.info()["qe"]
+    print("widths %d then %d, %d corrections" % (wide, w, ctx.progress()["steps"]))
+    assert ok and w <= wide
+    if w < wide:
+        assert th[w] >= 1.25 * th[p["q"] - 1]
+    assert np.abs(lam2 / lam1 - 1).max() < 1e-9
+    ctx.close()
