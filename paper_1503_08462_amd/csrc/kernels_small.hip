@@ -34,6 +34,10 @@ constexpr int kB = 256;  // threads per block of the small kernels
 // leave the results unchanged.
 constexpr int kBWide = 1024;
 inline int small_threads(int ld) { return ld > 32 ? kBWide : kB; }
+// The eigenvalue workgroups of wide blocks run eight wavefronts: the register
+// budget of sixteen would not hold the deep product pipeline.
+constexpr int kBisectWide = 512;
+inline int bisect_threads(int ld) { return ld > 32 ? kBisectWide : kB; }
 
 // Solver statistics (inertia counts per eigenvalue, fallbacks, Jacobi sweeps
 // and phase clocks, added into w.diag) are compiled in only with
@@ -70,37 +74,90 @@ __device__ __forceinline__ double wave_allsum(double v) {
     return v;
 }
 
+// Largest v over the wavefront and the lowest index holding it; every lane
+// ends with the same pair.  Applied to per-lane scans that keep the first of
+// equal values (strict >), it selects what one scan in index order selects.
+__device__ __forceinline__ void wave_argmax(double &v, int &idx) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, kWave);
+        const int oi = __shfl_xor(idx, off, kWave);
+        const bool take = ov > v || (ov == v && oi < idx);
+        v = take ? ov : v;
+        idx = take ? oi : idx;
+    }
+}
+
+__device__ __forceinline__ double wave_allmax(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// X = L^-1 for the lower triangular r x r matrix whose entries L(i, k), i >= k,
+// the accessor returns, into X (row stride xs, zero above the diagonal).  Right-looking: step k subtracts L_ik times row
+// k of the inverse from the rows i > k, where row k is X(k, :) / L_kk, the
+// division of a forward substitution; the stored row k receives that quotient
+// one step later, once nobody reads it.  Every entry thus sees the subtractions
+// in increasing k and one division, as in a column-by-column substitution, with
+// one barrier per step.
+template <class LF>
+__device__ void tri_inverse(LF L, double *X, int xs, int r) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int e = tid; e < r * r; e += nthr) {
+        const int a = e / r, b = e - a * r;
+        X[a * xs + b] = a == b ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < r; ++k) {
+        const double lkk = L(k, k);
+        const int rows = r - 1 - k, cols = k + 1;
+        for (int e = tid; e < rows * cols; e += nthr) {
+            const int i = k + 1 + e / cols, c = e - (i - k - 1) * cols;
+            X[i * xs + c] -= L(i, k) * (X[k * xs + c] / lkk);
+        }
+        if (k > 0) {  // row k - 1 is no longer read: store its quotient
+            const double lpp = L(k - 1, k - 1);
+            for (int c = tid; c < k; c += nthr) X[(k - 1) * xs + c] /= lpp;
+        }
+        __syncthreads();
+    }
+    if (r > 0)
+        for (int c = tid; c < r; c += nthr) X[(r - 1) * xs + c] /= L(r - 1, r - 1);
+    __syncthreads();
+}
+
 // Bunch-Kaufman symmetric indefinite LDL^T of S (r x r, LDS, row stride ls).
 // D (1x1 and 2x2 diagonal blocks) stays on the diagonal of S, the multipliers
 // go to the strict lower part of Lm (same stride).
 // ipiv[p] = kp >= 0: 1x1 pivot, rows p and kp interchanged;
 // ipiv[p] = ipiv[p+1] = -(kp+1): 2x2 pivot, rows p+1 and kp interchanged.
 // Returns the number of negative eigenvalues of S (Sylvester's law).  Every
-// thread evaluates the pivot choice itself from the shared column (broadcast
-// reads), so a pivot step costs one barrier, two with an interchange.  The
-// trailing update evaluates the same product for (i, j) and (j, i): the
-// active part stays exactly symmetric.
+// wavefront evaluates the pivot choice itself from the shared column (a scan
+// split over its lanes and a butterfly reduction), so a pivot step costs one
+// barrier, two with an interchange.  The trailing update evaluates the same
+// product for (i, j) and (j, i): the active part stays exactly symmetric.
 __device__ int bk_factor(double *S, double *Lm, int r, int ls, int *ipiv) {
     const double alpha = 0.6403882032022076;  // (1 + sqrt(17)) / 8
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & (kWave - 1);
     const int tx = tid & 15, ty = tid >> 4, nty = nthr >> 4;
     int neg = 0;
     int p = 0;
     while (p < r) {
         double colmax = 0.0;  // largest |S[i][p]|, i > p, lowest index on ties
         int imax = p;
-        for (int i = p + 1; i < r; ++i) {
+        for (int i = p + 1 + lane; i < r; i += kWave) {
             const double v = fabs(S[i * ls + p]);
             imax = v > colmax ? i : imax;
             colmax = v > colmax ? v : colmax;
         }
+        wave_argmax(colmax, imax);
         const double absakk = fabs(S[p * ls + p]);
         int kp = p, size = 1;
         const bool read_row = colmax > 0.0 && absakk < alpha * colmax;  // the same in every thread
         if (read_row) {
             double rowmax = 0.0;
-            for (int j = p; j < r; ++j)
+            for (int j = p + lane; j < r; j += kWave)
                 if (j != imax) rowmax = fmax(rowmax, fabs(S[imax * ls + j]));
+            rowmax = wave_allmax(rowmax);
             if (absakk * rowmax >= alpha * colmax * colmax) {
                 kp = p;
             } else if (fabs(S[imax * ls + imax]) >= alpha * rowmax) {
@@ -319,31 +376,32 @@ constexpr int kRedSmall = 3 * 4 * 256;
 __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg_in_lds) {
     extern __shared__ double sm[];
     if (w.status[ST_CONVERGED]) return;
-    const int ld = w.ld, dn = w.dn, tid = threadIdx.x, nthr = blockDim.x;
+    const int ld = w.ld, dn = w.dn, tid = threadIdx.x, nthr = blockDim.x, lane = tid & (kWave - 1);
     const int tx = tid & 15, ty = tid >> 4, nty = nthr >> 4;
-    // ld <= 32: everything in LDS; wider: D_M, D_A, L^-1 in LDS, L and the
-    // scratch product in the (then consumed) P3 buffer, P3 and [V^T A V | V^T M V]
-    // in global memory
+    // ld <= 32: everything in LDS; wider: D_M, D_A, L^-1 in LDS, P3 and
+    // [V^T A V | V^T M V] in global memory.  The ld x ld matrices in LDS have
+    // row stride ls = ld + 1, so that a column walk spreads over the banks.
     const bool small = ld <= 32;
-    double *DM = sm;               // ld x ld
-    double *DA = DM + ld * ld;     // ld x ld
-    double *Li = DA + ld * ld;     // ld x ld: L^-1
-    double *ext = Li + ld * ld;    // small: L, Yb, P3, gag
-    double *Lc = small ? ext : w.P3;                          // ld x ld: L
-    double *Yb = small ? ext + ld * ld : w.P3 + ld * ld;      // ld x ld
-    double *P3 = small ? ext + 2 * ld * ld : w.P3;            // ld x 3 ld
-    double *gagl = ext + 5 * ld * ld;                          // ld x 2 ld when small
-    double *red = small ? ext + 7 * ld * ld : ext;             // kRedSmall or 64
-    double *lam = red + (small ? kRedSmall : 64);              // dn
-    double *fg = lam + ((dn + 1) & ~1);  // dn x 2 ld when fg_in_lds (16-byte aligned)
+    const int ls = ld + 1, msz = ld * ls;  // msz is even (ld is a multiple of 4)
+    double *DM = sm;               // ld x ls: D_M, then L^T in its strict upper triangle, then L^-1 D_A
+    double *DA = DM + msz;         // ld x ls
+    double *Li = DA + msz;         // ld x ls: L^-1
+    double *ext = Li + msz;        // small: P3, gag, partial tiles, lambda, FG
+    double *P3 = small ? ext : w.P3;                           // ld x 3 ld
+    double *gagl = ext + 3 * ld * ld;                          // ld x 2 ld when small
+    double *red = small ? ext + 5 * ld * ld : ext;             // kRedSmall (small only)
+    double *lam = red + kRedSmall;                             // dn (small only)
+    double *fg = lam + ((dn + 1) & ~1);  // dn x 2 ld when fg_in_lds (small only; 16-byte aligned)
     const double *gag = small ? gagl : w.GAGM;
-    const int rcap = small ? kRedSmall : 64;
     __shared__ int perm[kMaxWidth];
+    __shared__ double ldg[kMaxWidth];  // diagonal of L
     uint64_t tk[8];  // solver statistics: phase clocks (thread 0)
     tk[0] = stat_clock();
-    for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
-    if (fg_in_lds) block_copy(fg, w.FG, dn * 2 * ld);
-    if (small) block_copy(gagl, w.GAGM, 2 * ld * ld);
+    if (small) {
+        for (int i = tid; i < dn; i += nthr) lam[i] = w.lam[i];
+        if (fg_in_lds) block_copy(fg, w.FG, dn * 2 * ld);
+        block_copy(gagl, w.GAGM, 2 * ld * ld);
+    }
     if (tid < ld) perm[tid] = tid;
     __syncthreads();
     const int l2 = 2 * ld;
@@ -357,7 +415,7 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
                       if (b < l2) return fgv(i, b);
                       return b < 3 * ld ? lam[i] * fgv(i, b - ld) : 0.0;
                   },
-                  dn, ld, 3 * ld, P3, 3 * ld, red, rcap);
+                  dn, ld, 3 * ld, P3, 3 * ld, red, kRedSmall);
     for (int e = tid; e < ld * ld; e += nthr) {
         const int a = e / ld, b = e - a * ld;
         const double gm_ab = gag[a * l2 + ld + b], gm_ba = gag[b * l2 + ld + a];
@@ -365,95 +423,90 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
         const double gg = 0.5 * (P3[a * 3 * ld + ld + b] + P3[b * 3 * ld + ld + a]);
         const double gf = P3[a * 3 * ld + b], fgt = P3[b * 3 * ld + a];
         const double glg = 0.5 * (P3[a * 3 * ld + 2 * ld + b] + P3[b * 3 * ld + 2 * ld + a]);
-        DM[e] = 0.5 * (gm_ab + gm_ba) - gg;
-        DA[e] = 0.5 * (ga_ab + ga_ba) - gf - fgt + glg;
+        DM[a * ls + b] = 0.5 * (gm_ab + gm_ba) - gg;
+        DA[a * ls + b] = 0.5 * (ga_ab + ga_ba) - gf - fgt + glg;
     }
     double scale = 0.0;
-    for (int a = 0; a < ld; ++a) scale = fmax(scale, gag[a * l2 + ld + a]);
-    __syncthreads();  // P3 consumed: its buffer may now hold L
-    for (int e = tid; e < ld * ld; e += nthr) {
-        Lc[e] = 0.0;
-        Li[e] = 0.0;
-    }
+    for (int a = lane; a < ld; a += kWave) scale = fmax(scale, gag[a * l2 + ld + a]);
+    scale = wave_allmax(scale);
+    for (int e = tid; e < msz; e += nthr) Li[e] = 0.0;
     __syncthreads();
     tk[2] = stat_clock();
-    // pivoted Cholesky of D_M, the same symmetric permutation applied to D_A
+    // pivoted Cholesky of D_M, the same symmetric permutation applied to D_A.
+    // Step p writes column p of L, transposed, into row p of D_M right of the
+    // diagonal (no thread reads that row during the step) and L_pp into ldg.
+    // The symmetric interchange of a later step then swaps these stored
+    // columns exactly as it swaps rows of L.
     int r = 0;
     for (int p = 0; p < ld; ++p) {
-        int best = p;
-        double bv = DM[p * ld + p];
-        for (int a = p + 1; a < ld; ++a) {
-            const double v = DM[a * ld + a];
+        int best = p;  // largest remaining diagonal entry, lowest index on ties
+        double bv = DM[p * ls + p];
+        for (int a = p + 1 + lane; a < ld; a += kWave) {
+            const double v = DM[a * ls + a];
             best = v > bv ? a : best;
             bv = v > bv ? v : bv;
         }
+        wave_argmax(bv, best);
         if (!(bv > rank_tol * scale)) break;  // the same decision in every thread
         __syncthreads();  // every thread has read the diagonal before the update below rewrites it
         if (best != p) {
             for (int j = tid; j < ld; j += nthr) {
                 if (j == p || j == best) continue;
-                double t = DM[p * ld + j];
-                DM[p * ld + j] = DM[best * ld + j];
-                DM[best * ld + j] = t;
-                t = DM[j * ld + p];
-                DM[j * ld + p] = DM[j * ld + best];
-                DM[j * ld + best] = t;
-                t = DA[p * ld + j];
-                DA[p * ld + j] = DA[best * ld + j];
-                DA[best * ld + j] = t;
-                t = DA[j * ld + p];
-                DA[j * ld + p] = DA[j * ld + best];
-                DA[j * ld + best] = t;
-                if (j < p) {
-                    t = Lc[p * ld + j];
-                    Lc[p * ld + j] = Lc[best * ld + j];
-                    Lc[best * ld + j] = t;
-                }
+                double t = DM[p * ls + j];
+                DM[p * ls + j] = DM[best * ls + j];
+                DM[best * ls + j] = t;
+                t = DM[j * ls + p];
+                DM[j * ls + p] = DM[j * ls + best];
+                DM[j * ls + best] = t;
+                t = DA[p * ls + j];
+                DA[p * ls + j] = DA[best * ls + j];
+                DA[best * ls + j] = t;
+                t = DA[j * ls + p];
+                DA[j * ls + p] = DA[j * ls + best];
+                DA[j * ls + best] = t;
             }
             if (tid == 0) {
-                double t = DM[p * ld + p];
-                DM[p * ld + p] = DM[best * ld + best];
-                DM[best * ld + best] = t;
-                t = DA[p * ld + p];
-                DA[p * ld + p] = DA[best * ld + best];
-                DA[best * ld + best] = t;
+                double t = DM[p * ls + p];
+                DM[p * ls + p] = DM[best * ls + best];
+                DM[best * ls + best] = t;
+                t = DA[p * ls + p];
+                DA[p * ls + p] = DA[best * ls + best];
+                DA[best * ls + best] = t;
                 const int ti = perm[p];
                 perm[p] = perm[best];
                 perm[best] = ti;
             }
             __syncthreads();
         }
-        const double dpp = DM[p * ld + p], lpp = sqrt(dpp), ipp = 1.0 / lpp;
+        const double dpp = DM[p * ls + p], lpp = sqrt(dpp), ipp = 1.0 / lpp;
         // trailing update with the scaled column computed on the fly; column p itself is not written
         for (int i = p + 1 + ty; i < ld; i += nty) {
-            const double li = DM[i * ld + p] * ipp;
+            const double li = DM[i * ls + p] * ipp;
             for (int j = p + 1 + tx; j <= i; j += 16) {
-                const double t = li * (DM[j * ld + p] * ipp);
-                DM[i * ld + j] -= t;
-                DM[j * ld + i] = DM[i * ld + j];
+                const double t = li * (DM[j * ls + p] * ipp);
+                DM[i * ls + j] -= t;
+                DM[j * ls + i] = DM[i * ls + j];
             }
-            if (tx == 0) Lc[i * ld + p] = li;
+            if (tx == 0) DM[p * ls + i] = li;
         }
-        if (tid == 0) Lc[p * ld + p] = lpp;
+        if (tid == 0) ldg[p] = lpp;
         r = p + 1;
         __syncthreads();
     }
     tk[3] = stat_clock();
-    // L^-1 (column c by thread c)
-    if (tid < r) {
-        const int c = tid;
-        for (int i = c; i < r; ++i) {
-            double v = i == c ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) v -= Lc[i * ld + k] * Li[k * ld + c];
-            Li[i * ld + c] = v / Lc[i * ld + i];
-        }
+    auto lval = [&](int i, int k) -> double { return i == k ? ldg[k] : DM[k * ls + i]; };  // L_ik, i >= k
+    tri_inverse(lval, Li, ls, r);
+    for (int e = tid; e < ld * ld; e += nthr) {
+        const int a = e / ld, b = e - a * ld;
+        w.L1[e] = (a < r && b <= a) ? lval(a, b) : 0.0;
     }
-    __syncthreads();
+    __syncthreads();  // L is read: D_M's buffer takes L^-1 D_A
+    double *Yb = DM;
     for (int e = tid; e < r * r; e += nthr) {  // Yb = L^-1 D_A
         const int a = e / r, b = e - a * r;
         double v = 0.0;
-        for (int k = 0; k <= a; ++k) v += Li[a * ld + k] * DA[k * ld + b];
-        Yb[a * ld + b] = v;
+        for (int k = 0; k <= a; ++k) v += Li[a * ls + k] * DA[k * ls + b];
+        Yb[a * ls + b] = v;
     }
     __syncthreads();
     for (int e = tid; e < ld * ld; e += nthr) {
@@ -461,13 +514,12 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
         double v = 0.0;
         if (a < r && b < r) {  // D~ = Yb L^-T, symmetrised
             double s1 = 0.0, s2 = 0.0;
-            for (int k = 0; k <= b; ++k) s1 += Yb[a * ld + k] * Li[b * ld + k];
-            for (int k = 0; k <= a; ++k) s2 += Yb[b * ld + k] * Li[a * ld + k];
+            for (int k = 0; k <= b; ++k) s1 += Yb[a * ls + k] * Li[b * ls + k];
+            for (int k = 0; k <= a; ++k) s2 += Yb[b * ls + k] * Li[a * ls + k];
             v = 0.5 * (s1 + s2);
         }
         w.Dt[e] = v;
-        w.L1[e] = (a < r && b <= a) ? Lc[e] : 0.0;
-        w.Li[e] = Li[e];
+        w.Li[e] = Li[a * ls + b];
     }
     if (tid < ld) w.perm[tid] = perm[tid];
     if (tid == 0) w.status[ST_RANK] = r;
@@ -481,8 +533,8 @@ __device__ __forceinline__ void pencil_body(SmallWork w, double rank_tol, int fg
             const int pk = perm[k];
             return fgv(i, pk) - lam[i] * fgv(i, ld + pk);
         },
-        [&](int k, int a) -> double { return a < r ? Li[a * ld + k] : 0.0; }, r, dn, ld,
-        [&](int i, int a, double v) { w.Ct[(int64_t)i * ld + a] = v; }, red, rcap);
+        [&](int k, int a) -> double { return a < r ? Li[a * ls + k] : 0.0; }, r, dn, ld,
+        [&](int i, int a, double v) { w.Ct[(int64_t)i * ld + a] = v; }, red, kRedSmall);
     if (tid == 0 && w.diag) {
         tk[5] = stat_clock();
         for (int j = 0; j < 5; ++j) atomicAdd(&w.diag[330 + j], (int)(tk[j + 1] - tk[j]));
@@ -587,7 +639,9 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         }
         __syncthreads();
         const int nt = (r + 15) >> 4, ntiles = nt * (nt + 1) / 2;
-        const int ksplit = ntiles >= nw ? 1 : nw / ntiles;  // row chunks per tile
+        // row chunks per tile; their partial tiles (ntiles * ksplit * 256) fit in red
+        const int kcap = 4 / ntiles > 1 ? 4 / ntiles : 1;
+        const int ksplit = ntiles >= nw ? 1 : (nw / ntiles < kcap ? nw / ntiles : kcap);
         const int chunk = ((dn + ksplit - 1) / ksplit + 3) & ~3;
         for (int item = wv; item < ntiles * ksplit; item += nw) {  // lower tiles of C~^T W C~
             const int t = item % ntiles, kc = item / ntiles;
@@ -953,30 +1007,35 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     if (w.status[ST_CONVERGED]) return;
     const int ld = w.ld, dn = w.dn, r = w.status[ST_RANK];
     const int nh = dn + r, m = qe;
-    const int ldp = ld;                   // row stride of the m x m matrices below
-    const bool small = ld <= 32;          // wider: D~ from global memory, no split-K partials
+    // row stride of the ld x ld matrices below, odd so that a column walk
+    // spreads over the LDS banks
+    const int ldp = ld + 1, msz = ld * ldp;  // msz is even (ld is a multiple of 4)
+    const bool small = ld <= 32;          // wider: D~ and lambda from global memory, no split-K partials
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = nthr / kWave;
     uint64_t tk[9];  // solver statistics: phase clocks (thread 0)
     tk[0] = stat_clock();
-    double *T = sm;                 // ld x ld
-    double *Q = T + ldp * ldp;      // ld x ld
-    double *G = Q + ldp * ldp;      // ld x ld
-    double *red = G + ldp * ldp;    // kRed (small) or 64
-    double *lamv = red + (small ? kRed : 64);  // dn
-    double *dtl = lamv + ((dn + 1) & ~1);      // ld x ld when small (keeps the copies below 16-byte aligned)
-    for (int i = tid; i < dn; i += nthr) lamv[i] = w.lam[i];
-    if (small)
-        for (int e = tid; e < ldp * ldp; e += nthr) {
+    double *T = sm;                 // ld x ldp
+    double *Q = T + msz;            // ld x ldp
+    double *G = Q + msz;            // ld x ldp
+    double *red = G + msz;          // kRed (small) or 64
+    double *lamv = red + (small ? kRed : 64);              // dn when small
+    double *dtl = lamv + (small ? ((dn + 1) & ~1) : 0);    // ld x ldp when small (keeps the copies below 16-byte aligned)
+    if (small) {
+        for (int i = tid; i < dn; i += nthr) lamv[i] = w.lam[i];
+        for (int e = tid; e < msz; e += nthr) {
             const int a = e / ldp, b = e - a * ldp;
             dtl[e] = (a < r && b < r) ? w.Dt[a * ld + b] : 0.0;
         }
+    }
+    const double *lamp = small ? lamv : w.lam;
     const double *dtv = small ? dtl : w.Dt;
+    const int dts = small ? ldp : ld;  // row stride of D~: the LDS copy's or the global array's
     const int rcap = small ? kRed : 64;
     double *Xp = w.X, *HXp = w.HX;
     const double *Ctp = w.Ct;
     if (use_lds) {
-        double *Xl = dtl + (small ? ldp * ldp : 0);
+        double *Xl = dtl + (small ? msz : 0);
         double *HXl = Xl + (dn + ld) * ld;
         double *Ctl = HXl + (dn + ld) * ld;
         block_copy(Xl, w.X, nh * ld);
@@ -1067,19 +1126,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
             __syncthreads();
             continue;
         }
-        if (tid < m) {  // L^-1 into Q, column c by thread c (zero above the diagonal)
-            const int c = tid;
-            for (int i = 0; i < m; ++i) {
-                double v = 0.0;
-                if (i >= c) {
-                    v = i == c ? 1.0 : 0.0;
-                    for (int k = c; k < i; ++k) v -= G[i * ldp + k] * Q[k * ldp + c];
-                    v /= G[i * ldp + i];
-                }
-                Q[i * ldp + c] = v;
-            }
-        }
-        __syncthreads();
+        tri_inverse([&](int i, int k) -> double { return G[i * ldp + k]; }, Q, ldp, m);  // L^-1 into Q
         // X L^-T on the matrix cores into the other buffer, then swap
         block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
                     [&](int a, int c) -> double { return c < m ? Q[c * ldp + a] : 0.0; }, m, nh, m,
@@ -1094,10 +1141,10 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     // ---- HX (nh x m): rows i < dn: lam_i x_i + C~_i z ; rows dn+a: C~^T y + D~ z
     block_tiles([&](int a, int i) -> double { return (i < dn && a < r) ? Ctp[(int64_t)i * ld + a] : 0.0; },
                 [&](int a, int c) -> double { return c < m ? Xp[(int64_t)(dn + a) * ld + c] : 0.0; }, r, dn, m,
-                [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = lamv[i] * Xp[(int64_t)i * ld + c] + v; },
+                [&](int i, int c, double v) { HXp[(int64_t)i * ld + c] = lamp[i] * Xp[(int64_t)i * ld + c] + v; },
                 red, rcap);
     block_xty(cta, xa, dn, r, m, HXp + (int64_t)dn * ld, ld, red, rcap);
-    block_tiles([&](int b, int a) -> double { return (a < r && b < r) ? dtv[b * ldp + a] : 0.0; },  // D~ symmetric
+    block_tiles([&](int b, int a) -> double { return (a < r && b < r) ? dtv[b * dts + a] : 0.0; },  // D~ symmetric
                 [&](int b, int c) -> double { return c < m ? Xp[(int64_t)(dn + b) * ld + c] : 0.0; }, r, r, m,
                 [&](int a, int c, double v) { HXp[(int64_t)(dn + a) * ld + c] += v; }, red, rcap);
     tk[3] = stat_clock();
@@ -1215,7 +1262,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
         const int a = e / r, b = e - a * r;
         Li[a * ldp + b] = w.Li[a * ld + b];
     }
-    for (int e = tid; e < ldp * ldp; e += nthr) Xv[e] = 0.0;
+    for (int e = tid; e < msz; e += nthr) Xv[e] = 0.0;
     __syncthreads();
     for (int e = tid; e < r * ld; e += nthr) {
         const int a = e / ld, c = e - a * ld;
@@ -1328,7 +1375,7 @@ __global__ __launch_bounds__(1024) void k_pencil(SmallWork w, double rank_tol, i
     pencil_body(w, rank_tol, fg_in_lds);
 }
 
-__global__ __launch_bounds__(256) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
+__global__ __launch_bounds__(kBisectWide) void k_arrow_bisect(SmallWork w, const double *__restrict__ theta_prev,
                                                       int ct_in_lds) {
     arrow_bisect_body(w, theta_prev, ct_in_lds, blockIdx.x, gridDim.x);
 }
@@ -1369,7 +1416,7 @@ __global__ __launch_bounds__(256) void k_pencil_ct_batch(SmallTable t) {
     pencil_ct_tile(it->w, g - t.ctfirst[m]);
 }
 
-__global__ __launch_bounds__(256) void k_arrow_bisect_batch(SmallTable t) {
+__global__ __launch_bounds__(kBisectWide) void k_arrow_bisect_batch(SmallTable t) {
     int m = 0;
     while (m + 1 < t.n && t.first[m + 1] <= (int)blockIdx.x) ++m;
     const SmallItem *it = t.item[m];
@@ -1388,15 +1435,15 @@ __global__ __launch_bounds__(1024) void k_arrow_rr_batch(SmallTable t) {
 constexpr size_t kLdsBudget = 160 * 1024 - 4096;
 
 void small_layout(const SmallWork &w, int qe, double *theta, SmallItem *it, SmallLds *lds) {
-    const size_t ld = w.ld, dn = w.dn;
-    const size_t pbase = ld <= 32 ? 10 * ld * ld + kRedSmall + dn + 1 : 3 * ld * ld + 64 + dn + 1;
-    const int fg_in_lds = (pbase + dn * 2 * ld) * sizeof(double) <= kLdsBudget ? 1 : 0;
+    const size_t ld = w.ld, dn = w.dn, msz = ld * (ld + 1);  // the ld x (ld + 1) matrices of the pencil and Rayleigh-Ritz kernels
+    const size_t pbase = ld <= 32 ? 3 * msz + 5 * ld * ld + kRedSmall + dn + 1 : 3 * msz + 64;
+    const int fg_in_lds = ld <= 32 && (pbase + dn * 2 * ld) * sizeof(double) <= kLdsBudget ? 1 : 0;
     // the rank r <= ld is only known on the device: size for r = ld
     const size_t ldp = (ld + 15) & ~(size_t)15, dtl = ld <= 32 ? ldp * ldp : 0;  // the kernel's layout
     const size_t bbase = 2 * ld * (ld + 1) + dn + 2 * (dn + ldp) + ldp + dn + dtl + 1024 + 64 + dn + ldp;
     const int ct_in_lds = (bbase + dn * ldp) * sizeof(double) <= kLdsBudget ? 1 : 0;
     const size_t rsmall = ld <= 32;
-    const size_t rbase = 3 * ld * ld + (rsmall ? kRed : 64) + dn + 1 + (rsmall ? ld * ld : 0);
+    const size_t rbase = 3 * msz + (rsmall ? kRed + dn + 1 + msz : 64);
     const size_t full = rbase + 2 * (dn + ld) * ld + dn * ld;
     const int use_lds = full * sizeof(double) <= kLdsBudget ? 1 : 0;
     it->w = w;
@@ -1427,7 +1474,7 @@ void launch_arrow_eig(hipStream_t s, const SmallWork &w, int qe, double *theta, 
     SmallItem it;
     SmallLds lds;
     small_layout(w, qe, theta, &it, &lds);
-    hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(kB), lds.bisect, s, w, theta, it.ct_in_lds);
+    hipLaunchKernelGGL(k_arrow_bisect, dim3(qe), dim3(bisect_threads(w.ld)), lds.bisect, s, w, theta, it.ct_in_lds);
     hipLaunchKernelGGL(k_arrow_rr, dim3(1), dim3(small_threads(w.ld)), lds.rr, s, w, qe, it.use_lds, theta, final_level);
 }
 
@@ -1439,7 +1486,7 @@ void launch_small_batch(hipStream_t s, const SmallTable &t, const SmallLds &lds,
     if (t.ctfirst[t.n] > 0)
         hipLaunchKernelGGL(k_pencil_ct_batch, dim3((t.ctfirst[t.n] + kB / kWave - 1) / (kB / kWave)), dim3(kB), 0, s,
                            t);
-    hipLaunchKernelGGL(k_arrow_bisect_batch, dim3(t.first[t.n]), dim3(kB), lds.bisect, s, t);
+    hipLaunchKernelGGL(k_arrow_bisect_batch, dim3(t.first[t.n]), dim3(wide ? kBisectWide : kB), lds.bisect, s, t);
     hipLaunchKernelGGL(k_arrow_rr_batch, dim3(t.n), dim3(nt), lds.rr, s, t);
 }
 
