@@ -1063,13 +1063,19 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
     // replaced by the coordinates of the corrected vector V e_p (then, if
     // that fails too, by a pseudo-random vector) and the pass restarts.
     __shared__ int tries[kMaxWidth];
+    __shared__ double ldq[kMaxWidth];  // diagonal of the Cholesky factor
+    const int tx = tid & 15, ty = tid >> 4, nty = nthr >> 4;
     if (tid < m) tries[tid] = 0;
     int passes = 0;
     for (int it = 0; it < 2 + 2 * m && passes < 2; ++it) {
         bool near_identity = true;  // the same in every thread
         int bad = -1;
         block_xty(xa, xa, nh, m, m, G, ldp, red, rcap);
-        for (int p = 0; p < m; ++p) {  // G = L L^T in place (lower)
+        // G = L L^T, one barrier per step: the update of the lower triangle
+        // right of column p scales column p on the fly, and the scaled column
+        // goes to row p right of the diagonal (no thread reads it during the
+        // step), L_pp to ldq
+        for (int p = 0; p < m; ++p) {
             const double d = G[p * ldp + p];
             near_identity = near_identity && d > 0.9 && d < 1.1;
             if (!(d > 1e-10)) {
@@ -1077,15 +1083,12 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
                 break;
             }
             const double lpp = sqrt(d);
-            __syncthreads();
-            for (int i = p + 1 + tid; i < m; i += nthr) G[i * ldp + p] /= lpp;
-            if (tid == 0) G[p * ldp + p] = lpp;
-            __syncthreads();
-            const int mm = m - p - 1;
-            for (int e = tid; e < mm * mm; e += nthr) {
-                const int i = p + 1 + e / mm, j = p + 1 + e % mm;
-                if (j <= i) G[i * ldp + j] -= G[i * ldp + p] * G[j * ldp + p];
+            for (int i = p + 1 + ty; i < m; i += nty) {
+                const double li = G[i * ldp + p] / lpp;
+                for (int j = p + 1 + tx; j <= i; j += 16) G[i * ldp + j] -= li * (G[j * ldp + p] / lpp);
+                if (tx == 0) G[p * ldp + i] = li;
             }
+            if (tid == 0) ldq[p] = lpp;
             __syncthreads();
         }
         if (bad >= 0) {
@@ -1126,7 +1129,7 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
             __syncthreads();
             continue;
         }
-        tri_inverse([&](int i, int k) -> double { return G[i * ldp + k]; }, Q, ldp, m);  // L^-1 into Q
+        tri_inverse([&](int i, int k) -> double { return i == k ? ldq[k] : G[k * ldp + i]; }, Q, ldp, m);  // L^-1 into Q
         // X L^-T on the matrix cores into the other buffer, then swap
         block_tiles([&](int a, int i) -> double { return (i < nh && a < m) ? Xp[(int64_t)i * ld + a] : 0.0; },
                     [&](int a, int c) -> double { return c < m ? Q[c * ldp + a] : 0.0; }, m, nh, m,
@@ -1187,23 +1190,32 @@ __device__ __forceinline__ void arrow_rr_body(SmallWork w, int qe, int use_lds, 
                 sn[k2] = sv;
             }
             __syncthreads();
-            for (int e = tid; e < (m / 2) * m; e += nthr) {  // rows: J^T T
-                const int k2 = e / m, j = e - k2 * m, p = pairs[2 * k2], q = pairs[2 * k2 + 1];
-                const double c = cs[k2], sv = sn[k2];
-                const double tp = T[p * ldp + j], tq = T[q * ldp + j];
-                T[p * ldp + j] = c * tp - sv * tq;
-                T[q * ldp + j] = sv * tp + c * tq;
-            }
-            __syncthreads();
-            for (int e = tid; e < (m / 2) * m; e += nthr) {  // columns: T J, Q J
-                const int k2 = e / m, i = e - k2 * m, p = pairs[2 * k2], q = pairs[2 * k2 + 1];
-                const double c = cs[k2], sv = sn[k2];
-                const double tp = T[i * ldp + p], tq = T[i * ldp + q];
-                T[i * ldp + p] = c * tp - sv * tq;
-                T[i * ldp + q] = sv * tp + c * tq;
-                const double qp = Q[i * ldp + p], qq = Q[i * ldp + q];
-                Q[i * ldp + p] = c * qp - sv * qq;
-                Q[i * ldp + q] = sv * qp + c * qq;
+            // J^T T J and Q J in one phase: the pairs split the indices, so the
+            // 2 x 2 block of T at rows (p, q) of pair k2 and columns (p3, q3) of
+            // pair k3 is one thread's: rotated by k2 over its rows, then by k3
+            // over its columns; a row of Q's column pair k3 likewise
+            const int h = m / 2;
+            for (int e = tid; e < h * h + h * m; e += nthr) {
+                if (e < h * h) {
+                    const int k2 = e / h, k3 = e - k2 * h;
+                    const int p = pairs[2 * k2], q = pairs[2 * k2 + 1], p3 = pairs[2 * k3], q3 = pairs[2 * k3 + 1];
+                    const double c = cs[k2], sv = sn[k2], c3 = cs[k3], s3 = sn[k3];
+                    const double tpp = T[p * ldp + p3], tqp = T[q * ldp + p3];
+                    const double tpq = T[p * ldp + q3], tqq = T[q * ldp + q3];
+                    const double rpp = c * tpp - sv * tqp, rqp = sv * tpp + c * tqp;  // rows of column p3
+                    const double rpq = c * tpq - sv * tqq, rqq = sv * tpq + c * tqq;  // rows of column q3
+                    T[p * ldp + p3] = c3 * rpp - s3 * rpq;
+                    T[p * ldp + q3] = s3 * rpp + c3 * rpq;
+                    T[q * ldp + p3] = c3 * rqp - s3 * rqq;
+                    T[q * ldp + q3] = s3 * rqp + c3 * rqq;
+                } else {
+                    const int e2 = e - h * h, k3 = e2 / m, i = e2 - k3 * m;
+                    const int p = pairs[2 * k3], q = pairs[2 * k3 + 1];
+                    const double c = cs[k3], sv = sn[k3];
+                    const double qp = Q[i * ldp + p], qq = Q[i * ldp + q];
+                    Q[i * ldp + p] = c * qp - sv * qq;
+                    Q[i * ldp + q] = sv * qp + c * qq;
+                }
             }
             __syncthreads();
         }
