@@ -167,27 +167,74 @@ def serving(args):
 
     tol = args.tol
     reqs = configs.request_stream(args.requests, seed=5, n_lo=10_000, n_hi=args.n_hi)
+    # no captured steps with the asynchronous admission: the admission workers
+    # allocate and free device memory, and a device-wide synchronisation in
+    # another thread invalidates a stream capture in progress
+    graphs = args.serve_graph and not args.async_admit
     opts = lambda prec: ae.defaults(coarse_max=512, precision=prec, tol=tol,
-                                    use_graph=args.serve_graph if prec == ae.PREC_MIXED else 0)
+                                    use_graph=graphs if prec == ae.PREC_MIXED else 0)
 
-    def build(r):
-        p = configs.build_request(r)
-        c = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], opts(ae.PREC_MIXED))
+    def rss_gb():
+        try:
+            return int(open("/proc/self/statm").read().split()[1]) * os.sysconf("SC_PAGE_SIZE") / 2 ** 30
+        except (OSError, ValueError):
+            return 0.0
+
+    # Meshes in a pool of spawned processes (their assembly is numpy work that
+    # threads would serialise), one per distinct mesh: cube and oscillator
+    # meshes depend only on the mesh parameter, the L-shape also on the
+    # request's jitter seed.  The hierarchies (library setup, which releases
+    # the interpreter lock) in a thread pool as the meshes arrive.
+    def key_of(r):
+        return (r["family"], r["m"], r["seed"] if r["family"] == "lshape" else 0)
+
+    by_key = {}
+    for k, r in enumerate(reqs):
+        by_key.setdefault(key_of(r), []).append(k)
+
+    def build(k, p):
+        r = reqs[k]
+        c = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], r["q"], opts(ae.PREC_MIXED))
         solo = None
         if r["id"] % args.solo_every == 0:
-            solo = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], opts(ae.PREC_FP64))
-        return {"n": int(p["n"]), "q": int(p["q"]), "family": r["family"], "ctx": c, "solo": solo}
+            solo = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], r["q"], opts(ae.PREC_FP64))
+        return k, {"n": int(p["n"]), "q": int(r["q"]), "family": r["family"], "ctx": c, "solo": solo}
 
     t0 = time.perf_counter()
     workers = max(1, min(16, os.cpu_count() or 1))
     items = [None] * len(reqs)
-    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        futs = {ex.submit(build, r): k for k, r in enumerate(reqs)}
-        for done, f in enumerate(cf.as_completed(futs)):
-            items[futs[f]] = f.result()
-            if done % 16 == 15:
-                print("[serving] host setup %d of %d requests, %.0f s" % (done + 1, len(reqs), time.perf_counter() - t0),
-                      file=sys.stderr, flush=True)
+    done = 0
+    peak_rss = 0.0
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as px, \
+            cf.ThreadPoolExecutor(max_workers=workers) as tx:
+        meshes = {px.submit(configs.build_request, reqs[ks[0]]): key for key, ks in by_key.items()}
+        builds = set()
+        for f in cf.as_completed(meshes):
+            p = f.result()
+            builds |= {tx.submit(build, k, p) for k in by_key[meshes[f]]}
+            del p
+            finished = [b for b in builds if b.done()]
+            for b in finished:
+                k, it = b.result()
+                items[k] = it
+                builds.discard(b)
+                done += 1
+                if done % 16 == 0:
+                    print("[serving] host setup %d of %d requests, %.0f s, host memory %.0f GB"
+                          % (done, len(reqs), time.perf_counter() - t0, rss_gb()), file=sys.stderr, flush=True)
+            peak_rss = max(peak_rss, rss_gb())
+            if peak_rss > args.host_cap_gb:
+                raise SystemExit("serving: host setup needs more than %.0f GB of host memory; use fewer requests "
+                                 "or a smaller --n-hi" % args.host_cap_gb)
+        for b in cf.as_completed(list(builds)):
+            k, it = b.result()
+            items[k] = it
+            done += 1
+            if done % 16 == 0:
+                print("[serving] host setup %d of %d requests, %.0f s, host memory %.0f GB"
+                      % (done, len(reqs), time.perf_counter() - t0, rss_gb()), file=sys.stderr, flush=True)
+    peak_rss = max(peak_rss, rss_gb())
     setup_s = time.perf_counter() - t0
     qs = np.array([it["q"] for it in items])
     ns = [it["n"] for it in items]
@@ -215,28 +262,35 @@ def serving(args):
         c.workspace = None
     solo64 = float(sum(it["q"] for it in sample) / solo_s) if solo_s > 0 else None
 
-    def one_pass(arrivals):
-        srv = Server(budget, n_streams=args.streams, steps_per_round=args.steps_per_round,
+    def one_pass(arrivals, streams=None, steps_per_round=None, joint=None, budget_=None, async_admit=None,
+                 admit_workers=None):
+        streams = args.streams if streams is None else streams
+        steps_per_round = args.steps_per_round if steps_per_round is None else steps_per_round
+        joint = args.joint if joint is None else joint
+        srv = Server(budget if budget_ is None else budget_, n_streams=streams, steps_per_round=steps_per_round,
                      max_active=args.max_active if args.max_active > 0 else None,
                      context_factory=lambda p_, o_: items[p_["_k"]]["ctx"], keep_contexts=True,
-                     batch_fn=None if args.joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)),
-                     init_fn=(lambda cs_: ae.init_batch_joint(cs_)) if args.joint_init else None)
+                     batch_fn=None if joint else (lambda cs_, steps: ae.correct_batch(cs_, steps)),
+                     init_fn=(lambda cs_: ae.init_batch_joint(cs_)) if args.joint_init else None,
+                     async_admit=bool(args.async_admit) if async_admit is None else bool(async_admit),
+                     admit_workers=args.admit_workers if admit_workers is None else admit_workers)
         order = np.argsort(arrivals, kind="stable")
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         i = 0
-        while i < len(order) or srv.queue or srv.active:
+        while i < len(order) or srv.queue or srv.active or srv.binding:
             now = time.perf_counter() - t_start
             while i < len(order) and arrivals[order[i]] <= now:
                 k = int(order[i])
                 srv.submit({"q": items[k]["q"], "_k": k}, tol=tol, max_steps=400, arrival=t_start + arrivals[k])
                 i += 1
-            if srv.queue or srv.active:
+            if srv.queue or srv.active or srv.binding:
                 srv.round()
             elif i < len(order):
                 time.sleep(max(0.0, arrivals[order[i]] - (time.perf_counter() - t_start)))
         torch.cuda.synchronize()
         span = time.perf_counter() - t_start
+        srv.close()
         res = srv.results()
         bad = [k for k, r in res.items() if not r["converged"]]
         if bad:
@@ -245,6 +299,7 @@ def serving(args):
         return {"eigenpairs_per_s": float(qs.sum() / span), "requests_per_s": len(items) / span, "seconds": span,
                 "p50_ms": lat["p50_s"] * 1e3, "p99_ms": lat["p99_s"] * 1e3,
                 "peak_resident_gb": srv.peak_in_use / 2 ** 30, "rounds": srv.rounds,
+                "host_s": {k: round(v, 2) for k, v in srv.host_s.items()},
                 "widened_requests": int(sum(1 for r in res.values() if r.get("widened")))}
 
     print("[serving] solo FP64 sample done, %.0f s" % solo_s, file=sys.stderr, flush=True)
@@ -253,6 +308,18 @@ def serving(args):
     print("[serving] warm-up burst pass %.1f s" % warm["seconds"], file=sys.stderr, flush=True)
     cap = one_pass(burst)
     print("[serving] capacity pass %.1f s" % cap["seconds"], file=sys.stderr, flush=True)
+    variants = []
+    for spec in [v for v in args.variants.split(";") if v.strip()]:
+        kw = {}
+        for item in spec.split(","):
+            name, val = item.split("=")
+            kw[{"streams": "streams", "spr": "steps_per_round", "joint": "joint", "budget": "budget_",
+                "async": "async_admit", "workers": "admit_workers"}[name.strip()]] = \
+                int(float(val) * 2 ** 30) if name.strip() == "budget" else int(val)
+        v_ = one_pass(burst, **kw)
+        v_["settings"] = spec
+        variants.append(v_)
+        print("[serving] burst pass with %s %.1f s" % (spec, v_["seconds"]), file=sys.stderr, flush=True)
     u = np.array([r["u_arrival"] for r in reqs])
     passes = []
     for f in [float(x) for x in args.rates.split(",") if x.strip()]:
@@ -282,16 +349,19 @@ def serving(args):
                    "requests": len(items), "eigenpairs": int(qs.sum()),
                    "families": {f: sum(1 for it in items if it["family"] == f) for f in ("lshape", "cube", "oscillator")},
                    "budget_gb": budget / 2 ** 30, "streams": args.streams, "steps_per_round": args.steps_per_round,
-                   "tol": tol, "max_active": args.max_active or None, "graph_steps": bool(args.serve_graph),
+                   "tol": tol, "max_active": args.max_active or None, "graph_steps": bool(graphs),
                    "joint_small_solves": bool(args.joint), "joint_starts": bool(args.joint_init),
+                   "async_admission": bool(args.async_admit), "admission_workers": args.admit_workers,
                    "block_width": "library (guard rule and width control)"},
         "value_is": "capacity: throughput of a burst pass (every request arriving at once) after a warm-up pass",
         "p50_ms": head["p50_ms"],
         "p99_ms": head["p99_ms"],
         "latency_at": "the middle Poisson pass (%s of capacity)" % (head.get("fraction_of_capacity", "burst")),
         "host_setup_s": setup_s,
+        "host_memory_peak_gb": round(peak_rss, 1),
         "warmup_pass": warm,
         "capacity_pass": cap,
+        "variant_passes": variants,
         "poisson_passes": passes,
         "solo_fp64_eigenpairs_per_s": solo64,
         "solo_fp64_sample": "%d of %d requests (every %d-th), each solved once untimed then timed" % (
@@ -388,6 +458,15 @@ def main():
                     help="serving stream: device memory budget (0: 80%% of the free device memory)")
     ap.add_argument("--rates", default="0.5,0.7,0.9",
                     help="serving stream: Poisson arrival rates as fractions of the measured capacity")
+    ap.add_argument("--async-admit", type=int, default=1,
+                    help="serving stream: bind and start admitted requests on a worker thread while the rounds run")
+    ap.add_argument("--admit-workers", type=int, default=8,
+                    help="serving stream: worker threads of the asynchronous admission")
+    ap.add_argument("--variants", default="",
+                    help="serving stream: extra burst passes after the capacity pass, ';'-separated settings such "
+                         "as 'spr=6' or 'streams=16,joint=0' (spr: corrections per round, budget in GB)")
+    ap.add_argument("--host-cap-gb", type=float, default=240.0,
+                    help="serving stream: stop with a message if host setup needs more host memory than this")
     ap.add_argument("--solo-every", type=int, default=4,
                     help="serving stream: plain FP64 solves on every n-th request (the solo baseline)")
     ap.add_argument("--streams", type=int, default=8, help="serving stream: stream pool size")

@@ -85,7 +85,10 @@ typedef struct {
     int precision;      /* AMG_EIG_PREC_* */
     double tol;         /* convergence: max_{j<=q} rho_j <= tol */
     int max_steps;      /* finest-level corrections in amg_eig_solve */
-    int use_graph;      /* capture one correction step as a hipGraph */
+    int use_graph;      /* capture one correction step as a hipGraph (captured on the bound
+                           stream at the first step after a bind, thread-local capture mode;
+                           another thread that synchronises the device meanwhile, e.g. through
+                           hipFree, invalidates the capture and the step returns AMG_EIG_EHIP) */
     int qe_max;         /* widest block the automatic width control may choose
                            (0: min(80, d_n, N - d_n)) */
 } amg_eig_opts;

@@ -318,13 +318,22 @@ def correct_batch(contexts, steps=1, stream=None):
         raise AmgEigError(rc)
 
 
+def _batch_error(rc, contexts):
+    msgs = []
+    for c in contexts:
+        m = _lib.amg_eig_last_error(c._c)
+        if m:
+            msgs.append(m.decode())
+    return AmgEigError(rc, "; ".join(dict.fromkeys(msgs)))
+
+
 def correct_batch_joint(contexts, steps=1):
     """Correction steps for several requests with their small eigenproblems
     solved in shared launches (each member on its own bound stream)."""
     arr = (ctypes.c_void_p * max(1, len(contexts)))(*[c._c.value for c in contexts])
     rc = _lib.amg_eig_correct_batch_joint(arr, len(contexts), steps)
     if rc < 0:
-        raise AmgEigError(rc)
+        raise _batch_error(rc, contexts)
 
 
 def init_batch_joint(contexts):
@@ -333,7 +342,7 @@ def init_batch_joint(contexts):
     arr = (ctypes.c_void_p * max(1, len(contexts)))(*[c._c.value for c in contexts])
     rc = _lib.amg_eig_init_batch_joint(arr, len(contexts))
     if rc < 0:
-        raise AmgEigError(rc)
+        raise _batch_error(rc, contexts)
 
 
 def from_problem(p, **opts):

@@ -17,6 +17,7 @@ submission (or the given arrival time) to completion.
 The scheduler only orders host calls into the library; every step of a solve
 runs in the library's kernels.
 """
+import concurrent.futures as _cf
 import time
 
 import numpy as np
@@ -65,11 +66,18 @@ class Server:
     keep_contexts:    a finished request gives back its device workspace but
                       its context stays open (the caller may submit it again,
                       e.g. for another measured pass over the same requests)
+    async_admit:      bind and start admitted requests on worker threads
+                      (workspace, upload of the hierarchy, Algorithm 3.2 start)
+                      while this thread keeps enqueueing the active requests'
+                      rounds; each admitted request then gets a stream of its
+                      own (a bind waits for its stream).  A request joins the
+                      rounds once its start is enqueued.
+    admit_workers:    worker threads of the asynchronous admission
     """
 
     def __init__(self, budget_bytes, n_streams=4, steps_per_round=2, opts=None, context_factory=None,
                  batch_fn=None, stream_factory=None, clock=time.perf_counter, max_active=None, init_fn=None,
-                 keep_contexts=False):
+                 keep_contexts=False, async_admit=False, admit_workers=8):
         if budget_bytes <= 0 or n_streams < 1 or steps_per_round < 1 or (max_active is not None and max_active < 1):
             raise ValueError("budget, stream count, steps per round and active limit must be positive")
         self.max_active = max_active
@@ -85,13 +93,21 @@ class Server:
             def stream_factory():
                 import torch
                 return torch.cuda.Stream()  # default priority
+        self._stream_factory = stream_factory
         self.streams = [stream_factory() for _ in range(n_streams)]
+        self.async_admit = bool(async_admit) and init_fn is None
+        self._binder = _cf.ThreadPoolExecutor(max_workers=max(1, int(admit_workers))) if self.async_admit else None
+        self._free_streams = []  # per-request streams of the asynchronous admission, for reuse
+        self.binding = []        # (request, future) being bound and started
         self.queue = []       # submitted, waiting for memory, in arrival order
         self.active = []      # on the device
         self.finished = {}    # id -> Request
         self.in_use = 0       # bytes held by active requests
         self.peak_in_use = 0
         self.rounds = 0
+        # host seconds spent admitting (bind, upload, start), enqueueing the
+        # rounds' steps, and waiting for and reading the progress reports
+        self.host_s = {"admit": 0.0, "enqueue": 0.0, "retire": 0.0}
         self._next_id = 0
         self._next_stream = 0
 
@@ -114,7 +130,36 @@ class Server:
         self.queue.append(req)
         return rid
 
+    def _bind_start(self, req):
+        req.ctx.bind(stream=req.stream)
+        self._init([req.ctx])
+
+    def _admit_async(self):
+        ready = [b for b in self.binding if b[1].done()]
+        if not self.active and self.binding and not ready:
+            ready = [self.binding[0]]  # nothing to run meanwhile: wait for the oldest
+        for req, fut in ready:
+            fut.result()
+            req.admitted = self.clock()
+            self.active.append(req)
+        self.binding = [b for b in self.binding if b not in ready]
+        while (self.queue and self.in_use + self.queue[0].footprint <= self.budget
+               and (self.max_active is None or len(self.active) + len(self.binding) < self.max_active)):
+            req = self.queue.pop(0)
+            req.stream = self._free_streams.pop() if self._free_streams else self._stream_factory()
+            self.in_use += req.footprint
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.binding.append((req, self._binder.submit(self._bind_start, req)))
+
+    def _release_stream(self, req):
+        if self.async_admit and req.stream is not None:
+            self._free_streams.append(req.stream)
+        req.stream = None
+
     def _admit(self):
+        if self.async_admit:
+            self._admit_async()
+            return
         new = []
         while (self.queue and self.in_use + self.queue[0].footprint <= self.budget
                and (self.max_active is None or len(self.active) + len(new) < self.max_active)):
@@ -147,6 +192,7 @@ class Server:
                     self.in_use -= req.footprint
                     if hasattr(req.ctx, "workspace"):
                         req.ctx.workspace = None
+                    self._release_stream(req)
                     req.footprint = req.ctx.footprint()
                     req.widened += 1
                     if req.footprint <= self.budget:
@@ -170,6 +216,7 @@ class Server:
                     req.ctx.close()
                 if hasattr(req.ctx, "workspace"):
                     req.ctx.workspace = None  # back to the allocator for the next admissions
+                self._release_stream(req)
                 self.in_use -= req.footprint
                 self.finished[req.id] = req
             else:
@@ -179,19 +226,31 @@ class Server:
 
     def round(self):
         """One scheduling round; returns the number of requests still pending."""
+        t0 = self.clock()
         self._admit()
-        if not self.active and self.queue:  # cannot happen while every request fits the budget
+        t1 = self.clock()
+        self.host_s["admit"] += t1 - t0
+        if not self.active and self.queue and not self.binding:  # cannot happen while every request fits the budget
             raise RuntimeError("no request can be admitted")
         if self.active:
             self._batch([r.ctx for r in self.active], self.steps_per_round)
             self.rounds += 1
+            t2 = self.clock()
+            self.host_s["enqueue"] += t2 - t1
             self._retire()
-        return len(self.queue) + len(self.active)
+            self.host_s["retire"] += self.clock() - t2
+        return len(self.queue) + len(self.active) + len(self.binding)
 
     def run(self):
         while self.round():
             pass
         return self.results()
+
+    def close(self):
+        """Stop the admission worker (asynchronous admission)."""
+        if self._binder is not None:
+            self._binder.shutdown(wait=True)
+            self._binder = None
 
     # -------------------------------------------------------------- reports
     def results(self):

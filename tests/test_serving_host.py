@@ -180,3 +180,25 @@ def test_widened_request_beyond_the_budget_finishes_unconverged():
     a = srv.submit(dict(prob("a", 70, need=4), stall=2))
     res = srv.run()
     assert not res[a]["converged"] and res[a]["widened"] == 1 and srv.in_use == 0
+
+
+def test_async_admission_finishes_every_request_within_budget():
+    """Binding and starting admitted requests on the worker thread: every
+    request still finishes converged, the budget holds, no request runs a
+    round before it is bound, and streams go back to a free list for reuse."""
+    FakeCtx.log = []
+    srv, batches = make_server(100, steps_per_round=2, async_admit=True)
+    needs = [3, 5, 2, 7, 4, 6, 1, 8]
+    for k, need in enumerate(needs):
+        srv.submit(prob("r%d" % k, 30 + 5 * (k % 3), need))
+    while srv.round():
+        assert srv.in_use <= 100
+        for names in batches[-1:]:
+            for n in names:
+                assert ("bind", n) in FakeCtx.log
+    srv.close()
+    res = srv.results()
+    assert len(res) == len(needs) and all(r["converged"] for r in res.values())
+    assert srv.peak_in_use <= 100
+    assert not srv.binding and not srv.active and not srv.queue
+    assert len(srv._free_streams) >= 1
