@@ -27,6 +27,7 @@ struct DevLevel {
     double *u_a = nullptr, *u_m = nullptr;
     int32_t *v_ptr = nullptr, *v_col = nullptr;
     void *v_val = nullptr, *dinv = nullptr;
+    void *v_vs = nullptr;  // a_ij / d_j on the V-cycle pattern (zero-guess pre-smoothing)
     int32_t *p_ptr = nullptr, *p_col = nullptr, *pt_ptr = nullptr, *pt_col = nullptr;
     void *p_val = nullptr, *pt_val = nullptr;
     double *p64 = nullptr, *pt64 = nullptr;
@@ -189,6 +190,7 @@ void plan(amg_eig_ctx *c, char *base) {
             d.v_ptr = cv.take<int32_t>(lv.n + 1);
             d.v_col = cv.take<int32_t>(lv.av.col.size());
             d.v_val = cv.take<char>(lv.av.col.size() * sT);
+            d.v_vs = cv.take<char>(lv.av.col.size() * sT);
             d.dinv = cv.take<char>(lv.n * sT);
             d.p_ptr = cv.take<int32_t>(lv.n + 1);
             d.p_col = cv.take<int32_t>(lv.P.col.size());
@@ -321,7 +323,12 @@ int upload_levels(amg_eig_ctx *c) {
             rc |= upload_vec(c, d.v_val, convert<T>(lv.av.val));
             std::vector<double> dinv(lv.n);
             for (int64_t i = 0; i < lv.n; ++i) dinv[i] = 1.0 / lv.l1[i];
-            rc |= upload_vec(c, d.dinv, convert<T>(dinv));
+            const std::vector<T> dinv_t = convert<T>(dinv), val_t = convert<T>(lv.av.val);
+            // the product the pre-smoother would form per neighbour, in the working precision
+            std::vector<T> vs(val_t.size());
+            for (size_t p = 0; p < vs.size(); ++p) vs[p] = val_t[p] * dinv_t[lv.av.col[p]];
+            rc |= upload_vec(c, d.v_vs, vs);
+            rc |= upload_vec(c, d.dinv, dinv_t);
             rc |= upload_vec(c, d.p_ptr, narrow_ptr<int32_t>(lv.P.ptr));
             rc |= upload_vec(c, d.p_col, lv.P.col);
             rc |= upload_vec(c, d.p_val, convert<T>(lv.P.val));
@@ -461,14 +468,14 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
         if (cheb) {
             {
                 SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l, true);
-                launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_vs, (const T *)d.dinv,
                                    (const T *)d.b, (T *)d.x, lo, st, d.cpt[0]);
             }
             launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
                                      (const T *)d.x, (T *)d.r, st, d.cpt[0]);
         } else {
             SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l, true);
-            launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+            launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_vs, (const T *)d.dinv,
                                  (const T *)d.b, (T *)d.r, st, d.cpt[0]);
         }
         DevLevel &e = c->dl[l + 1];
@@ -1440,7 +1447,7 @@ int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, do
                 launch_spmm<T>(s, d.n, ld, f.pt_ptr, f.pt_col, (const T *)f.pt_val, (const T *)f.r, (T *)d.b, st, cpt);
             }
             if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV) {
-                launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_vs, (const T *)d.dinv,
                                    (const T *)d.b, (T *)d.x, lo, st, cpt);
                 launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
                                          (const T *)d.x, (T *)d.r, st, cpt);
@@ -1451,7 +1458,7 @@ int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, do
                 launch_cheb_post2<T>(s, false, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
                                      (const T *)d.r, (const T *)d.t, (T *)d.x, c->U, c->V, lo, st, cpt);
             } else {
-                launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
+                launch_smooth_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_vs, (const T *)d.dinv,
                                      (const T *)d.b, (T *)d.r, st, cpt);
                 launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
                                       (const T *)d.dinv, (const T *)d.b, (T *)d.r, st, cpt);

@@ -29,7 +29,7 @@ void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const
 void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
                             double *rho, int q, double tol, int *status, int check, int cpt = 0);
 template <typename T>
-void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *vs,
                        const T *dinv, const T *b, T *r, const int *status, int cpt = 0);
 template <typename T>
 void launch_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
@@ -46,7 +46,7 @@ void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int3
 // prolongation y = x + P xc, and post-smoothing of y (scratch d0; x, or on
 // the correction level V = U + x in FP64).
 template <typename T>
-void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *vs,
                      const T *dinv, const T *b, T *x, double lo, const int *status, int cpt = 0);
 template <typename T>
 void launch_level_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,

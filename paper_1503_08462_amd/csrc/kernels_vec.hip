@@ -172,9 +172,11 @@ __global__ __launch_bounds__(256) void k_residual_finish(int64_t nb, int ld, con
 }
 
 // ------------------------------------------------------------------- a2
+// vs = a_ij / d_j on the pattern of the V-cycle operator (column-scaled
+// values, formed once at bind in the working precision)
 template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_smooth_pre(int64_t n, int ld, const int32_t *__restrict__ ptr,
-                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ vs,
                                                     const T *__restrict__ dinv, const T *__restrict__ b,
                                                     T *__restrict__ r, const int *status) {
     if (status[ST_CONVERGED]) return;
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(256) void k_smooth_pre(int64_t n, int ld, const int
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
     gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, b, ld, c0,
-                    [&](int32_t p, int64_t j, const Vec<T, CPT> &xj) { fma_v(acc, -val[p] * dinv[j], xj); });
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -vs[p], xj); });
     stv<T, CPT>(r + rm.row * ld + c0, acc);
 }
 
@@ -277,10 +279,11 @@ __device__ __forceinline__ void cheb_coef(const ChebCoef &k, T &itheta, T &theta
     }
 }
 
-// Pre-smoothing from x0 = 0: r0 = D^-1 b, so one product A (D^-1 b) gives x.
+// Pre-smoothing from x0 = 0: r0 = D^-1 b, so one product A (D^-1 b) gives x;
+// vs = a_ij / d_j, the column-scaled values (no gather of d_j per neighbour).
 template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_cheb_pre(int64_t n, int ld, const int32_t *__restrict__ ptr,
-                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                  const int32_t *__restrict__ col, const T *__restrict__ vs,
                                                   const T *__restrict__ dinv, const T *__restrict__ b,
                                                   T *__restrict__ x, ChebCoef kc, const int *status) {
     if (status[ST_CONVERGED]) return;
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(256) void k_cheb_pre(int64_t n, int ld, const int32
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> az = zero_v<T, CPT>();  // A D^-1 b
     gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, b, ld, c0,
-                    [&](int32_t p, int64_t j, const Vec<T, CPT> &bj) { fma_v(az, val[p] * dinv[j], bj); });
+                    [&](int32_t p, int64_t, const Vec<T, CPT> &bj) { fma_v(az, vs[p], bj); });
     const Vec<T, CPT> bi = ldv<T, CPT>(b + rm.row * ld + c0);
     const T di = dinv[rm.row];
     Vec<T, CPT> o;
@@ -942,10 +945,10 @@ void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsi
 }
 
 template <typename T>
-void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+void launch_smooth_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *vs,
                        const T *dinv, const T *b, T *r, const int *status, int cpt) {
     DISPATCH_CPT(ld, cpt, KLAUNCH((k_smooth_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
-                                        0, s, n, ld, ptr, col, val, dinv, b, r, status));
+                                        0, s, n, ld, ptr, col, vs, dinv, b, r, status));
 }
 
 template <typename T>
@@ -1045,11 +1048,11 @@ ChebCoef cheb_coefficients(double lo) {
 }
 
 template <typename T>
-void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *val,
+void launch_cheb_pre(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const T *vs,
                      const T *dinv, const T *b, T *x, double lo, const int *status, int cpt) {
     const ChebCoef kc = cheb_coefficients(lo);
     DISPATCH_CPT(ld, cpt, KLAUNCH((k_cheb_pre<T, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
-                                        0, s, n, ld, ptr, col, val, dinv, b, x, kc, status));
+                                        0, s, n, ld, ptr, col, vs, dinv, b, x, kc, status));
 }
 
 template <typename T>
