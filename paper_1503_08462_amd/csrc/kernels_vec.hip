@@ -72,6 +72,84 @@ __device__ __forceinline__ void gather4(int32_t p0, int32_t p1, const int32_t *_
     }
 }
 
+// Gathers like gather4, with the CSR entries loaded once per wavefront: the
+// rows a wavefront serves (row groups may straddle wavefronts) have their
+// entries in [wp0, wp1); when these are at most 64, lane l loads entry wp0 + l
+// and every lane takes the column indices and values of its own row's entries
+// from the lanes holding them (cross-lane reads, no memory access), so a
+// neighbour costs one vector-memory load (its row of x) instead of one per
+// column index and value.  Wavefronts with more entries (the denser Galerkin
+// rows of coarse levels) load them per lane as gather4 does.  load_vals(p)
+// returns the values of entry p (a struct of doubles or floats, moved lane to
+// lane as 32-bit words); consume(vals, j, x_j) sees the row's entries in
+// ascending p either way.  Every lane of the wavefront must call it (lanes
+// past the last row with active = false); the loop that moves values between
+// lanes is uniform across the wavefront.
+template <typename V>
+__device__ __forceinline__ V lane_take(const V &v, int src) {
+    static_assert(sizeof(V) % 4 == 0, "values move as 32-bit words");
+    V r;
+    const int *pv = reinterpret_cast<const int *>(&v);
+    int *pr = reinterpret_cast<int *>(&r);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(V) / 4); ++w) pr[w] = __shfl(pv[w], src, kWave);
+    return r;
+}
+
+template <typename T, int CPT, class LV, class F>
+__device__ __forceinline__ void gather_wave(int64_t row, int sub, int tpr, bool active, int64_t nrows,
+                                            const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                            const T *__restrict__ x, int ld, int c0, const LV &load_vals,
+                                            const F &consume) {
+    const int lane = threadIdx.x & (kWave - 1);
+    // flat index of lane 0 of this wavefront, and the rows its lanes serve
+    const int64_t t0 = (int64_t)__builtin_amdgcn_readfirstlane((int)(row * tpr + sub - lane));
+    const int64_t r_lo = t0 / tpr;
+    int64_t r_hi = (t0 + kWave - 1) / tpr;
+    r_hi = r_hi < nrows - 1 ? r_hi : nrows - 1;
+    if (r_lo > r_hi) return;  // the whole wavefront is past the last row
+    const int32_t wp0 = ptr[r_lo], wp1 = ptr[r_hi + 1];
+    const int32_t p0 = active ? ptr[row] : 0, p1 = active ? ptr[row + 1] : 0;
+    if (wp1 - wp0 > kWave) {  // uniform: per-lane loads
+        if (active)
+            gather4<T, CPT>(p0, p1, col, x, ld, c0,
+                            [&](int32_t p, int64_t j, const Vec<T, CPT> &xj) { consume(load_vals(p), j, xj); });
+        return;
+    }
+    {
+        const int32_t base = wp0;
+        const int32_t pe = base + lane < wp1 ? base + lane : base;
+        const int32_t cl = col[pe];
+        const auto vl = load_vals(pe);
+        const int cnt = p1 - p0;
+        int cmax = cnt;
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const int o = __shfl_xor(cmax, off, kWave);
+            cmax = o > cmax ? o : cmax;
+        }
+        const int q0 = cnt > 0 ? p0 - base : 0;  // lane holding this lane's first entry
+        for (int t = 0; t < cmax; t += 4) {
+            int q[4];
+            int64_t j[4];
+            Vec<T, CPT> xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                q[u] = t + u < cnt ? q0 + t + u : q0;
+                j[u] = __shfl(cl, q[u], kWave);
+            }
+            // only the entries a lane consumes are loaded (rows of a wavefront
+            // differ in length, and x rows are wide)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = t + u < cnt ? ldv<T, CPT>(x + j[u] * ld + c0) : zero_v<T, CPT>();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const auto vu = lane_take(vl, q[u]);
+                if (t + u < cnt) consume(vu, j[u], xv[u]);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- a1
@@ -95,15 +173,17 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32
         th[c] = grp < rpw ? theta[c0 + c] : 0.0;
         rr[c] = mm[c] = 0.0;
     }
-    for (int64_t w = w0 + wib; w < w1; w += wpb) {
+    for (int64_t w = w0 + wib; w < w1; w += wpb) {  // the same trip count for every lane of a wavefront
         const int64_t row = w * rpw + grp;
-        if (grp >= rpw || row >= n) continue;
+        const bool active = grp < rpw && row < n;
         Vec<double, CPT> au = zero_v<double, CPT>(), mu = zero_v<double, CPT>();
-        gather4<double, CPT>(ptr[row], ptr[row + 1], col, U, ld, c0,
-                             [&](int32_t p, int64_t, const Vec<double, CPT> &u) {
-                                 fma_v(au, a[p], u);
-                                 fma_v(mu, m[p], u);
-                             });
+        gather_wave<double, CPT>(row, sub, tpr, active, n, ptr, col, U, ld, c0,
+                                 [&](int32_t p) { return double2{a[p], m[p]}; },
+                                 [&](const double2 &am, int64_t, const Vec<double, CPT> &u) {
+                                     fma_v(au, am.x, u);
+                                     fma_v(mu, am.y, u);
+                                 });
+        if (!active) continue;
         Vec<TO, CPT> out;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -181,11 +261,12 @@ __global__ __launch_bounds__(256) void k_smooth_pre(int64_t n, int ld, const int
                                                     T *__restrict__ r, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, b, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -vs[p], xj); });
+    Vec<T, CPT> acc = ldv<T, CPT>(b + row * ld + c0);
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, b, ld, c0, [&](int32_t p) { return vs[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -v, xj); });
+    if (!rm.active) return;
     stv<T, CPT>(r + rm.row * ld + c0, acc);
 }
 
@@ -196,11 +277,11 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, int ld, const int32_t *
                                               const T *__restrict__ x, T *__restrict__ y, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> acc = zero_v<T, CPT>();
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, x, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, val[p], xj); });
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, x, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, v, xj); });
+    if (!rm.active) return;
     stv<T, CPT>(y + rm.row * ld + c0, acc);
 }
 
@@ -212,14 +293,15 @@ __global__ __launch_bounds__(256) void k_prolong_add(int64_t n, int ld, const in
                                                      const T *__restrict__ b, T *__restrict__ y, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    const T di = dinv[rm.row];
+    Vec<T, CPT> acc = ldv<T, CPT>(b + row * ld + c0);
+    const T di = dinv[row];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) acc.v[c] *= di;
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, xc, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, val[p], xj); });
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, xc, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, v, xj); });
+    if (!rm.active) return;
     stv<T, CPT>(y + rm.row * ld + c0, acc);
 }
 
@@ -233,11 +315,12 @@ __global__ __launch_bounds__(256) void k_smooth_post(int64_t n, int ld, const in
                                                      const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, y, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -val[p], xj); });
+    Vec<T, CPT> acc = ldv<T, CPT>(b + row * ld + c0);
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, y, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -v, xj); });
+    if (!rm.active) return;
     const Vec<T, CPT> yi = ldv<T, CPT>(y + rm.row * ld + c0);
     const T di = dinv[rm.row];
     if constexpr (FINAL) {
@@ -288,13 +371,14 @@ __global__ __launch_bounds__(256) void k_cheb_pre(int64_t n, int ld, const int32
                                                   T *__restrict__ x, ChebCoef kc, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     T itheta, theta, c1, c2;
     cheb_coef(kc, itheta, theta, c1, c2);
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> az = zero_v<T, CPT>();  // A D^-1 b
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, b, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &bj) { fma_v(az, vs[p], bj); });
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, b, ld, c0, [&](int32_t p) { return vs[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &bj) { fma_v(az, v, bj); });
+    if (!rm.active) return;
     const Vec<T, CPT> bi = ldv<T, CPT>(b + rm.row * ld + c0);
     const T di = dinv[rm.row];
     Vec<T, CPT> o;
@@ -317,11 +401,12 @@ __global__ __launch_bounds__(256) void k_level_residual(int64_t n, int ld, const
                                                         T *__restrict__ r, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, x, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -val[p], xj); });
+    Vec<T, CPT> acc = ldv<T, CPT>(b + row * ld + c0);
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, x, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -v, xj); });
+    if (!rm.active) return;
     stv<T, CPT>(r + rm.row * ld + c0, acc);
 }
 
@@ -333,11 +418,12 @@ __global__ __launch_bounds__(256) void k_prolong_x(int64_t n, int ld, const int3
                                                    T *__restrict__ y, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = ldv<T, CPT>(x + rm.row * ld + c0);
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, xc, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, val[p], xj); });
+    Vec<T, CPT> acc = ldv<T, CPT>(x + row * ld + c0);
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, xc, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, v, xj); });
+    if (!rm.active) return;
     stv<T, CPT>(y + rm.row * ld + c0, acc);
 }
 
@@ -350,13 +436,14 @@ __global__ __launch_bounds__(256) void k_cheb_post1(int64_t n, int ld, const int
                                                     const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     T itheta, theta, c1, c2;
     cheb_coef(kc, itheta, theta, c1, c2);
     const int c0 = rm.sub * CPT;
-    Vec<T, CPT> acc = ldv<T, CPT>(b + rm.row * ld + c0);
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, y, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &yj) { fma_v(acc, -val[p], yj); });
+    Vec<T, CPT> acc = ldv<T, CPT>(b + row * ld + c0);
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, y, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &yj) { fma_v(acc, -v, yj); });
+    if (!rm.active) return;
     const T di = dinv[rm.row];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) acc.v[c] = (di * acc.v[c]) * itheta;
@@ -374,13 +461,14 @@ __global__ __launch_bounds__(256) void k_cheb_post2(int64_t n, int ld, const int
                                                     ChebCoef kc, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
+    const int64_t row = rm.active ? rm.row : n - 1;  // lanes past the last row read it and store nothing
     T itheta, theta, c1, c2;
     cheb_coef(kc, itheta, theta, c1, c2);
     const int c0 = rm.sub * CPT;
     Vec<T, CPT> ad = zero_v<T, CPT>();
-    gather4<T, CPT>(ptr[rm.row], ptr[rm.row + 1], col, d0, ld, c0,
-                    [&](int32_t p, int64_t, const Vec<T, CPT> &dj) { fma_v(ad, val[p], dj); });
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, d0, ld, c0, [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &dj) { fma_v(ad, v, dj); });
+    if (!rm.active) return;
     const Vec<T, CPT> di0 = ldv<T, CPT>(d0 + rm.row * ld + c0);
     const Vec<T, CPT> yi = ldv<T, CPT>(y + rm.row * ld + c0);
     const T di = dinv[rm.row];
@@ -533,14 +621,15 @@ __global__ __launch_bounds__(256) void k_dual_spmm(int64_t n, int ld, const int3
                                                    double *__restrict__ W, const int *status) {
     if (status[ST_CONVERGED]) return;
     RowMap rm(ld, CPT, n);
-    if (!rm.active) return;
     const int c0 = rm.sub * CPT;
     Vec<double, CPT> wa = zero_v<double, CPT>(), wm = zero_v<double, CPT>();
-    gather4<double, CPT>(ptr[rm.row], ptr[rm.row + 1], col, V, ld, c0,
-                         [&](int32_t p, int64_t, const Vec<double, CPT> &v) {
-                             fma_v(wa, a[p], v);
-                             fma_v(wm, m[p], v);
-                         });
+    gather_wave<double, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, V, ld, c0,
+                             [&](int32_t p) { return double2{a[p], m[p]}; },
+                             [&](const double2 &am, int64_t, const Vec<double, CPT> &v) {
+                                 fma_v(wa, am.x, v);
+                                 fma_v(wm, am.y, v);
+                             });
+    if (!rm.active) return;
     stv<double, CPT>(W + rm.row * 2 * ld + c0, wa);
     stv<double, CPT>(W + rm.row * 2 * ld + ld + c0, wm);
 }
