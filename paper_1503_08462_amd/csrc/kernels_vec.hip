@@ -42,9 +42,9 @@ __device__ __forceinline__ Vec<T, C> zero_v() {
 // Gathers x[col[p]] (CPT values from column c0) for p in [p0, p1) and hands
 // each to consume(p, j, x_j) in ascending p; the loads of four neighbours are
 // issued before the first of them is consumed, and the last one to three
-// neighbours of a row are loaded together too (a masked entry reloads the
-// first of them and is not consumed), so a row of 5, 7 or 15 neighbours costs
-// two or four dependent round trips, not one per leftover neighbour.
+// neighbours of a row are loaded together too, so a row of 5, 7 or 15
+// neighbours costs two or four dependent round trips, not one per leftover
+// neighbour.
 template <typename T, int CPT, class F>
 __device__ __forceinline__ void gather4(int32_t p0, int32_t p1, const int32_t *__restrict__ col,
                                         const T *__restrict__ x, int ld, int c0, const F &consume) {
@@ -64,8 +64,8 @@ __device__ __forceinline__ void gather4(int32_t p0, int32_t p1, const int32_t *_
     if (rem > 0) {
         const int64_t j0 = col[p], j1 = rem > 1 ? col[p + 1] : j0, j2 = rem > 2 ? col[p + 2] : j0;
         const Vec<T, CPT> x0 = ldv<T, CPT>(x + j0 * ld + c0);
-        const Vec<T, CPT> x1 = ldv<T, CPT>(x + j1 * ld + c0);
-        const Vec<T, CPT> x2 = ldv<T, CPT>(x + j2 * ld + c0);
+        const Vec<T, CPT> x1 = rem > 1 ? ldv<T, CPT>(x + j1 * ld + c0) : zero_v<T, CPT>();
+        const Vec<T, CPT> x2 = rem > 2 ? ldv<T, CPT>(x + j2 * ld + c0) : zero_v<T, CPT>();
         consume(p, j0, x0);
         if (rem > 1) consume(p + 1, j1, x1);
         if (rem > 2) consume(p + 2, j2, x2);
@@ -805,9 +805,10 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
 
 // Wide blocks: U = P Y + V X_v on the correction level.  A workgroup (eight
 // wavefronts) stages X_v in LDS once, then walks its blocks of kFinalRows
-// consecutive rows: all
-// its threads copy the block's rows of V (contiguous in memory) into LDS with
-// coalesced 16-byte loads, and each wavefront takes 16 of the rows: V X_v as
+// consecutive rows: all its threads load the next block's rows of V
+// (contiguous in memory, coalesced 16-byte loads) into registers while the
+// current block's products run, and store them to LDS after it; each
+// wavefront takes 16 of the rows: V X_v as
 // 16 x 16 tiles on the FP64 matrix cores with both operands from LDS (each
 // row of V is read from memory once, whatever the number of column tiles),
 // then each lane adds the prolongation P Y for its four (row, column) entries
@@ -835,14 +836,45 @@ __global__ __launch_bounds__(kFinalThreads) void k_final(int64_t n, int ld, cons
     // same CU close together in time
     const int64_t blocks = (n + kFinalRows - 1) / kFinalRows, nbk = gridDim.x, lb = xcd_block();
     const int64_t b0 = blocks * lb / nbk, b1 = blocks * (lb + 1) / nbk;
-    for (int64_t blk = b0; blk < b1; ++blk) {
+    // the next block's rows of V are loaded into registers while this block's
+    // products run, and stored to LDS once every wavefront is done with it
+    // (ld <= kMaxWidth, ld even: kPre double2 per thread hold a block)
+    constexpr int kPre = kFinalRows * kMaxWidth / 2 / kFinalThreads;
+    const double2 *V2 = reinterpret_cast<const double2 *>(V);
+    double2 *vt2 = reinterpret_cast<double2 *>(vt);
+    double2 pre[kPre];
+    auto block_rows = [&](int64_t blk) -> int {
         const int64_t base = blk * kFinalRows;
-        const int rows = n - base < kFinalRows ? (int)(n - base) : kFinalRows;
-        __syncthreads();                             // the previous block is consumed (X_v staged)
-        block_copy(vt, V + base * ld, rows * ld);  // contiguous rows: coalesced 16-byte loads
-        __syncthreads();
+        return n - base < kFinalRows ? (int)(n - base) : kFinalRows;
+    };
+    auto fetch = [&](int64_t blk) {
+        const int n2 = block_rows(blk) * ld / 2;
+        const double2 *src = V2 + blk * kFinalRows * ld / 2;
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int e = threadIdx.x + i * kFinalThreads;
+            pre[i] = e < n2 ? src[e] : make_double2(0.0, 0.0);
+        }
+    };
+    auto put = [&](int64_t blk) {
+        const int n2 = block_rows(blk) * ld / 2;
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int e = threadIdx.x + i * kFinalThreads;
+            if (e < n2) vt2[e] = pre[i];
+        }
+    };
+    if (b0 < b1) {
+        fetch(b0);
+        put(b0);
+    }
+    __syncthreads();  // X_v and the first block staged
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        if (blk + 1 < b1) fetch(blk + 1);
+        const int64_t base = blk * kFinalRows;
+        const int rows = block_rows(blk);
         const int w0 = 16 * wv;  // this wavefront's first row in the block
-        if (w0 >= rows) continue;  // wave-uniform; no barrier follows before the next block's
+        if (w0 < rows) {         // wave-uniform; every wavefront reaches the barriers below
         const int64_t r0 = base + w0;
         int32_t pb[4], pe[4], pc[4][kPRow];
         double pv[4][kPRow];
@@ -889,6 +921,10 @@ __global__ __launch_bounds__(kFinalThreads) void k_final(int64_t n, int ld, cons
                 }
             }
         }
+        }
+        __syncthreads();  // every wavefront is done with this block's rows of V
+        if (blk + 1 < b1) put(blk + 1);
+        __syncthreads();
     }
 }
 
