@@ -721,11 +721,40 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
 #pragma unroll
     for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) acc[s2] = dbl4{0.0, 0.0, 0.0, 0.0};
     double *sv = stage, *sw = stage + kGramRows * ld;  // rows of V, then the same rows of W
+    // a chunk's rows of V and W (contiguous) are staged with all of a thread's
+    // double2 loads issued before its first store, so the whole chunk is in
+    // flight at once (ld <= kMaxWidth, ld even)
+    constexpr int kPre = kGramRows * 3 * kMaxWidth / 2 / 256;
+    auto chunk_rows = [&](int64_t base) -> int { return r1 - base < kGramRows ? (int)(r1 - base) : kGramRows; };
+    double2 pre[kPre];
+    auto fetch = [&](int64_t base) {
+        const int rows = chunk_rows(base), nv = rows * ld / 2, nt = nv + rows * l2 / 2;
+        const double2 *v2 = reinterpret_cast<const double2 *>(V + base * ld);
+        const double2 *w2 = reinterpret_cast<const double2 *>(W + base * l2);
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int e = threadIdx.x + i * 256;
+            pre[i] = e < nv ? v2[e] : (e < nt ? w2[e - nv] : make_double2(0.0, 0.0));
+        }
+    };
+    auto put = [&](int64_t base) {
+        const int rows = chunk_rows(base), nv = rows * ld / 2, nt = nv + rows * l2 / 2;
+        double2 *v2 = reinterpret_cast<double2 *>(sv);
+        double2 *w2 = reinterpret_cast<double2 *>(sw);
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+            const int e = threadIdx.x + i * 256;
+            if (e < nv)
+                v2[e] = pre[i];
+            else if (e < nt)
+                w2[e - nv] = pre[i];
+        }
+    };
     for (int64_t base = r0; base < r1; base += kGramRows) {
-        const int rows = r1 - base < kGramRows ? (int)(r1 - base) : kGramRows;
+        const int rows = chunk_rows(base);
+        fetch(base);
         __syncthreads();  // the previous chunk is consumed
-        block_copy(sv, V + base * ld, rows * ld);  // contiguous rows, double2 loads, four in flight
-        block_copy(sw, W + base * l2, rows * l2);
+        put(base);
         __syncthreads();
 #pragma unroll
         for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
