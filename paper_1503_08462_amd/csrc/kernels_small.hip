@@ -908,6 +908,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         for (int i = tid; i < dn + r; i += nthr) vec[i] = start_entry(k, i);
         __syncthreads();
     }
+    const int c_warm = ncount;  // solver statistics: counts per phase
     // ---- the previous Ritz value theta_prev[k] is close to eigenvalue k once
     // the iteration has settled: counts at widening windows around it give a
     // narrow bracket in a few factorisations (any count is a valid bracket
@@ -921,6 +922,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
             if (have_lo && have_hi && hi - lo <= 2.0 * d) break;
         }
     }
+    const int c_win = ncount;
     if (!(have_lo && have_hi)) {
         // Gershgorin lower bound of H; the upper end is the interlacing bound
         double g = 1e300;
@@ -961,6 +963,7 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         const double mid = 0.5 * (lo + hi);
         force(mid, factor(mid));
     }
+    const int c_bis = ncount;
     // ---- Rayleigh-quotient iteration inside the bracket, from the corrected
     // vector when there is one (the warm attempts may have left a neighbour's
     // eigenvector in vec)
@@ -988,6 +991,12 @@ __device__ __forceinline__ void arrow_bisect_body(SmallWork w, const double *__r
         for (int j = 0; j < 6; ++j) atomicAdd(&slot[j], (int)tim[j]);
     }
     if (tid == 0 && w.diag) {
+        atomicAdd(&w.diag[340], c_warm);
+        atomicAdd(&w.diag[341], c_win - c_warm);
+        atomicAdd(&w.diag[342], c_bis - c_win);
+        atomicAdd(&w.diag[343], ncount - c_bis);
+        atomicAdd(&w.diag[344], c_bis > c_win ? 1 : 0);
+        atomicMax(&w.diag[345], ncount);
         atomicAdd(&w.diag[k], ncount);
         atomicAdd(&w.diag[kMaxWidth + k], done ? 1 : 0);
         atomicAdd(&w.diag[2 * kMaxWidth + k], 1);

@@ -35,6 +35,14 @@ WORKLOADS = {
     # the stop rule is rho <= 2e-9.
     "ex1_square2048": (lambda: configs.square(2048, q=14), "unit square, P1, h = 1/2048 (N = 2047^2)",
                        14, 20, 512, 2e-9, 30),
+    # Example 2 of the paper at its finest size (Table 2): L-shape
+    # (-1,1)^2 minus (0,1)x(-1,0), h = 1/1024, no jitter, interior unknowns only
+    # (N = 2047^2 - 1024^2); q = 31 so that every ratio printed up to
+    # lambda_30 / lambda_31 is covered.  lambda_31 and lambda_32 are 0.1% apart,
+    # so the block holds 40 vectors: it ends at a 3% gap, with lambda_41 about
+    # 1.26 lambda_31.
+    "ex2_lshape1024": (lambda: configs.lshape(1024, q=31), "L-shape (-1,1)^2 minus (0,1)x(-1,0), P1, h = 1/1024, "
+                       "no jitter (N = 2047^2 - 1024^2)", 31, 40, 512, 2e-9, 40),
     # checkerboard cube, 100^3 cells (N = 970 299), q = 20 inside the 32-member low cluster
     "cube100": (lambda: configs.cube(100, q=20), "unit cube, Kuhn P1, 100^3 cells, 4x4x4 checkerboard kappa 1 / 1e3",
                 20, 32, 512, 1e-10, 80),

@@ -6,6 +6,9 @@ which runs only the oracle) and against the paper's Table 1:
   - Example 1 of the paper (unit square, h = 1/2048, N = 4 190 209, q = 14):
     FP64 eigenvalues equal the oracle's to 1e-10 and reproduce Table 1's ratio
     column lambda_q / lambda_{q+1} to 1e-11;
+  - Example 2 of the paper (L-shape, h = 1/1024, N = 3 141 633, q = 31):
+    FP64 eigenvalues equal the oracle's to 1e-10 and reproduce Table 2's ratio
+    column to 1e-11 and its eigenvalues up to one uniform scale factor;
   - the checkerboard cube (N = 970 299, q = 20, a block of 32 holding the low
     cluster), FP64 and mixed precision;
   - the oscillator (N = 4 190 209, q = 64), mixed precision and FP64.
@@ -21,6 +24,7 @@ import scipy.sparse as sp
 import paper_1503_08462_amd as ae
 from workloads import configs
 from tests.goldens import oracle_eigenvalues, paper_table1_ratios
+from tests.test_paper_tables import TABLE2_RATIO_TOL, TABLE2_SCALE_SPREAD_TOL, TABLE2_SCALE_TOL, table2_differences
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +86,22 @@ def test_paper_example1_full_size_table1():
     diff = max(abs(lam[q - 1] / lam[q] - r) for q, r in paper_table1_ratios().items())
     _say("largest difference from Table 1's ratio column %.2e" % diff)
     assert diff < 1e-11
+
+
+def test_paper_example2_full_size_table2():
+    p = configs.lshape(1024, q=31)
+    _say("Example 2 full size, N = %d, FP64, q = 31, q_e = 40" % p["n"])
+    lam, ok, pr, U = _solve(p, ae.PREC_FP64, 512, 40, 2e-9)
+    assert ok, pr
+    _check_pairs(p, lam, U, 2e-9)
+    ref = _golden("ex2_lshape1024", 31)
+    err = np.abs(lam / ref - 1).max()
+    _say("max relative difference from the oracle %.2e" % err)
+    assert err < 1e-10
+    spread, scale, ratio_err = table2_differences(lam)
+    _say("Table 2: eigenvalue scale 1 %+.2e (spread %.1e), largest ratio difference %.2e" % (scale, spread, ratio_err))
+    assert spread < TABLE2_SCALE_SPREAD_TOL and abs(scale) < TABLE2_SCALE_TOL
+    assert ratio_err < TABLE2_RATIO_TOL
 
 
 @pytest.mark.parametrize("prec", [ae.PREC_MIXED, ae.PREC_FP64], ids=["mixed", "fp64"])
