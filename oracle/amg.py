@@ -10,6 +10,10 @@ Test infrastructure only: the eigensolver library never imports this.
   galerkin            eq. (2.5): A_{k+1} = P^T A_k P, M_{k+1} = P^T M_k P
   build_hierarchy     the level loop of Section 2.3
   coarse_eigen        the small generalized eigenproblem on the coarsest level
+  colouring           first-fit colouring of a level's matrix graph and the
+                      colour-ordered row sequence of the multicolour
+                      Gauss-Seidel smoother (a reordering of the paper's
+                      Gauss-Seidel smoothing, Section 4.1)
 """
 import numpy as np
 import scipy.linalg as sla
@@ -143,3 +147,21 @@ def coarse_eigen(levels):
     Mn = levels[-1].M.toarray()
     lam, Z = sla.eigh(0.5 * (An + An.T), 0.5 * (Mn + Mn.T))
     return lam, Z
+
+
+def colouring(A):
+    """Colours of a level for multicolour Gauss-Seidel: i and j are neighbours
+    when a_ij != 0 or a_ji != 0 (i != j); rows 0..n-1 in turn take the smallest
+    colour no coloured neighbour holds.  Returns (colour, order) where order
+    lists the rows colour by colour, ascending within a colour, so that a
+    Gauss-Seidel sweep in that order updates each colour's rows from values of
+    other colours only."""
+    S = sp.csr_matrix(A, copy=True)
+    S.setdiag(0.0)
+    S.eliminate_zeros()
+    S.data[:] = 1.0
+    G = (S + S.T).tocsr()
+    G.sort_indices()
+    colour, _ = native.greedy_colour(G)
+    order = np.argsort(colour, kind="stable").astype(np.int64)
+    return colour, order

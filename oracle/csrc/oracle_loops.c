@@ -7,7 +7,10 @@
  *  rs_second_pass classical second pass: strongly coupled F points must share
  *                 a strong C point (the coarsening the paper refers to).
  *  gs_sweep       one Gauss-Seidel sweep on a block of right-hand sides
- *                 (the smoother of the paper's default settings, Section 4.1).
+ *                 (the smoother of the paper's default settings, Section 4.1),
+ *                 in the natural row order or in a given one.
+ *  greedy_colour  first-fit colouring of a graph in the natural vertex order
+ *                 (the ordering of the multicolour Gauss-Seidel smoother).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -138,13 +141,16 @@ int64_t rs_second_pass(int64_t n, const int64_t *s_ptr, const int32_t *s_col, in
 
 /*
  * One Gauss-Seidel sweep for A x = b, q right-hand sides stored row-major
- * (x[i*q + c]).  backward != 0 runs the rows in decreasing order.
+ * (x[i*q + c]).  Rows are visited in the order order[0], order[1], ...
+ * (natural order when order is NULL); backward != 0 runs that sequence from
+ * its end.
  */
 void gs_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-              int q, const double *b, double *x, int backward) {
+              int q, const double *b, double *x, int backward, const int64_t *order) {
     double *acc = (double *)malloc(sizeof(double) * (size_t)q);
     for (int64_t t = 0; t < n; ++t) {
-        int64_t i = backward ? n - 1 - t : t;
+        int64_t s = backward ? n - 1 - t : t;
+        int64_t i = order ? order[s] : s;
         double diag = 0.0;
         for (int c = 0; c < q; ++c) acc[c] = b[i * q + c];
         for (int64_t a = rowptr[i]; a < rowptr[i + 1]; ++a) {
@@ -155,4 +161,30 @@ void gs_sweep(int64_t n, const int64_t *rowptr, const int32_t *col, const double
         for (int c = 0; c < q; ++c) x[i * q + c] = acc[c] / diag;
     }
     free(acc);
+}
+
+/*
+ * First-fit colouring: vertices 0, 1, ..., n-1 in turn take the smallest
+ * colour that no already coloured neighbour holds.  adj is a symmetric
+ * adjacency list in CSR form without self loops.  Returns the number of
+ * colours, or -1 if memory runs out.
+ */
+int64_t greedy_colour(int64_t n, const int64_t *rowptr, const int32_t *adj, int32_t *colour) {
+    int64_t ncol = 0;
+    int64_t *seen = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!seen) return -1;
+    for (int64_t c = 0; c <= n; ++c) seen[c] = -1;
+    for (int64_t i = 0; i < n; ++i) colour[i] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t a = rowptr[i]; a < rowptr[i + 1]; ++a) {
+            int32_t c = colour[adj[a]];
+            if (c >= 0) seen[c] = i;  /* colour c is taken next to vertex i */
+        }
+        int32_t c = 0;
+        while (seen[c] == i) ++c;
+        colour[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(seen);
+    return ncol;
 }

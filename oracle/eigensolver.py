@@ -13,7 +13,8 @@ never touches a GPU.  It follows the paper's formulation directly:
                 until the relative residual criterion holds
 
 Smoothers: "gs" (the paper's Gauss-Seidel: forward before, backward after the
-coarse correction), "l1jacobi" (x += D^-1 (b - A x), d_i = sum_j |a_ij|) and
+coarse correction), "mcgs" (the same sweeps with the rows of each level taken
+colour by colour, amg.colouring), "l1jacobi" (x += D^-1 (b - A x), d_i = sum_j |a_ij|) and
 "chebyshev" (degree-s Chebyshev polynomial in D^-1 A for the l1 diagonal D,
 on the interval [lo, 1]; 1 bounds the spectrum of D^-1 A by Gershgorin since
 d_i = a_ii + sum_{j != i} |a_ij|).
@@ -59,6 +60,8 @@ class Oracle:
             np.add.at(d, amg._rows(L.A), np.abs(L.A.data))
             L.l1 = d
             L.diag = L.A.diagonal()
+            if smoother == "mcgs":
+                L.colour, L.order = amg.colouring(L.A)
         self.history = []
 
     # ------------------------------------------------------------------ smoothing
@@ -66,6 +69,9 @@ class Oracle:
         if self.smoother == "gs":
             x = np.ascontiguousarray(x, dtype=np.float64).copy()
             return native.gs_sweep(L.A, b, x, backward=backward)
+        if self.smoother == "mcgs":
+            x = np.ascontiguousarray(x, dtype=np.float64).copy()
+            return native.gs_sweep(L.A, b, x, backward=backward, order=L.order)
         if self.smoother == "l1jacobi":
             return x + (b - L.A @ x) / L.l1[:, None]
         if self.smoother == "chebyshev":

@@ -31,7 +31,9 @@ def lib():
         L.rs_second_pass.restype = ctypes.c_int64
         L.rs_second_pass.argtypes = [ctypes.c_int64, p, p, p]
         L.gs_sweep.restype = None
-        L.gs_sweep.argtypes = [ctypes.c_int64, p, p, p, ctypes.c_int, p, p, ctypes.c_int]
+        L.gs_sweep.argtypes = [ctypes.c_int64, p, p, p, ctypes.c_int, p, p, ctypes.c_int, p]
+        L.greedy_colour.restype = ctypes.c_int64
+        L.greedy_colour.argtypes = [ctypes.c_int64, p, p, p]
         _lib = L
     return _lib
 
@@ -61,8 +63,10 @@ def rs_second_pass(S, cf):
     return cf
 
 
-def gs_sweep(A, b, x, backward=False):
-    """In-place Gauss-Seidel sweep on x (n x q, C-contiguous float64)."""
+def gs_sweep(A, b, x, backward=False, order=None):
+    """In-place Gauss-Seidel sweep on x (n x q, C-contiguous float64), rows in
+    natural order or in ``order`` (a permutation of 0..n-1); backward runs the
+    sequence from its end."""
     n = A.shape[0]
     q = x.shape[1]
     assert x.flags.c_contiguous and x.dtype == np.float64
@@ -70,5 +74,23 @@ def gs_sweep(A, b, x, backward=False):
     rp = np.ascontiguousarray(A.indptr, np.int64)
     ci = np.ascontiguousarray(A.indices, np.int32)
     va = np.ascontiguousarray(A.data, np.float64)
-    lib().gs_sweep(n, _ptr(rp), _ptr(ci), _ptr(va), q, _ptr(bb), _ptr(x), 1 if backward else 0)
+    od = None
+    if order is not None:
+        od = np.ascontiguousarray(order, np.int64)
+        assert od.shape == (n,)
+    lib().gs_sweep(n, _ptr(rp), _ptr(ci), _ptr(va), q, _ptr(bb), _ptr(x), 1 if backward else 0,
+                   _ptr(od) if od is not None else None)
     return x
+
+
+def greedy_colour(G):
+    """First-fit colouring of the symmetric graph G (scipy CSR pattern, no
+    diagonal) in the natural vertex order: (colour[n] int32, number of colours)."""
+    n = G.shape[0]
+    rp = np.ascontiguousarray(G.indptr, np.int64)
+    ci = np.ascontiguousarray(G.indices, np.int32)
+    colour = np.empty(n, dtype=np.int32)
+    nc = lib().greedy_colour(n, _ptr(rp), _ptr(ci), _ptr(colour))
+    if nc < 0:
+        raise MemoryError("greedy_colour")
+    return colour, int(nc)

@@ -17,7 +17,7 @@ SMALL = [
 
 
 @pytest.mark.parametrize("name,make", SMALL)
-@pytest.mark.parametrize("smoother", ["gs", "l1jacobi", "chebyshev"])
+@pytest.mark.parametrize("smoother", ["gs", "mcgs", "l1jacobi", "chebyshev"])
 def test_converges_to_dense_brute_force(name, make, smoother):
     p = make()
     A, M = mats(p)
@@ -85,7 +85,7 @@ def test_exact_eigenpairs_are_a_fixed_point():
     assert compare_subspaces(ref, Uref, U, M, 4, qe=4)[0] < 1e-10
 
 
-@pytest.mark.parametrize("smoother,bound", [("gs", 0.25), ("l1jacobi", 0.45), ("chebyshev", 0.15)])
+@pytest.mark.parametrize("smoother,bound", [("gs", 0.25), ("mcgs", 0.25), ("l1jacobi", 0.45), ("chebyshev", 0.15)])
 def test_vcycle_is_symmetric_a_norm_contraction(smoother, bound):
     """The V-cycle as an affine iteration x -> x + B (b - A x): B symmetric and
     ||I - B A||_A < 1 (with textbook-sized factors for the 5-point Laplacian)."""
