@@ -410,7 +410,8 @@ def prepared_context(p, wl, prec, args, stream):
     """Set up and bind a context, run `warmup` untimed solves (the first one
     also settles the block width), then choose the launch shapes."""
     import paper_1503_08462_amd as ae
-    smoother = ae.SMOOTH_CHEBYSHEV if args.smoother == "chebyshev" else ae.SMOOTH_L1JACOBI
+    smoother = {"chebyshev": ae.SMOOTH_CHEBYSHEV, "l1jacobi": ae.SMOOTH_L1JACOBI,
+                "gs": ae.SMOOTH_GAUSS_SEIDEL}[args.smoother]
     t0 = time.perf_counter()
     ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
                      ae.defaults(coarse_max=wl["coarse_max"], qe=args.qe, precision=prec, use_graph=args.graph,
@@ -451,7 +452,8 @@ def main():
                          "eagerly and carries the per-kernel event timing)")
     ap.add_argument("--tune", type=int, default=1,
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
-    ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev"])
+    ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev", "gs"],
+                    help="gs: multicolour Gauss-Seidel, forward before and backward after the coarse correction")
     ap.add_argument("--requests", type=int, default=24, help="serving stream (config 5): number of requests")
     ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
     ap.add_argument("--budget-gb", type=float, default=8.0,
@@ -549,8 +551,10 @@ def main():
         amount, ms, n = stats[dom]
         achieved = amount / (ms / n * 1e-3) / 1e9
         cheb = args.smoother == "chebyshev"
-        kernel_name = {"residual": "k_residual", "presmooth": "k_cheb_pre" if cheb else "k_smooth_pre",
-                       "postsmooth": "k_cheb_post2" if cheb else "k_smooth_post",
+        gs = args.smoother == "gs"
+        kernel_name = {"residual": "k_residual",
+                       "presmooth": "k_gs_colour" if gs else "k_cheb_pre" if cheb else "k_smooth_pre",
+                       "postsmooth": "k_gs_colour" if gs else "k_cheb_post2" if cheb else "k_smooth_post",
                        "dualspmm": "k_dual_spmm", "restrict": "k_spmm",
                        "final": "k_final" if info["qe"] > 32 else "k_final_rows"}[dom]
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -582,8 +586,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "config %d: %s" % (args.config, wl["name"]), "N": int(p["n"]), "q": q,
                    "qe": info["qe"], "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
-                   "smoother": ("l1-jacobi" if args.smoother == "l1jacobi" else "chebyshev degree 2 on [0.25, 1]")
-                               + " V(1,1)", "start": "nested (Algorithm 3.2)",
+                   "smoother": {"l1jacobi": "l1-jacobi", "chebyshev": "chebyshev degree 2 on [0.25, 1]",
+                                "gs": "multicolour gauss-seidel"}[args.smoother] + " V(1,1)", "start": "nested (Algorithm 3.2)",
                    "steps_launch": ("captured hipGraph replays; the second step of each enqueued chunk of three "
                                     "or more eager and event-timed" if args.graph else "eager")},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),

@@ -57,6 +57,10 @@ extern "C" {
 /* --------------------------------------------------------------- options */
 #define AMG_EIG_SMOOTH_L1JACOBI 0  /* x += D^-1 (b - A x), d_i = sum_j |a_ij| */
 #define AMG_EIG_SMOOTH_CHEBYSHEV 1 /* degree-2 Chebyshev polynomial in D^-1 A on [cheb_lo, 1] (cheb_degree must be 2) */
+#define AMG_EIG_SMOOTH_GAUSS_SEIDEL 2 /* multicolour Gauss-Seidel, the smoother of the paper's Section 4.1
+                                        settings with each level's rows visited colour by colour (first-fit
+                                        colouring of the graph of A_k in natural row order): a forward sweep
+                                        before the coarse correction, a backward sweep after it */
 
 #define AMG_EIG_PREC_FP64 0  /* everything in FP64 */
 #define AMG_EIG_PREC_MIXED 1 /* V-cycle (smoothing, transfers) in FP32 with FP32
@@ -248,6 +252,10 @@ int amg_eig_level_matrix(const amg_eig_ctx *c, int level, int64_t *nnz, int64_t 
 int amg_eig_level_prolongation(const amg_eig_ctx *c, int level, int64_t *nnz, int64_t *rowptr,
                                int32_t *col, double *p);
 int amg_eig_level_splitting(const amg_eig_ctx *c, int level, int32_t *cf);
+/* Multicolour Gauss-Seidel only: the colour of each row of level k < nlevels-1
+ * (colour[d_k], may be NULL) and the number of colours.  EINVAL for another
+ * smoother or the coarsest level. */
+int amg_eig_level_colouring(const amg_eig_ctx *c, int level, int32_t *colour, int *ncolours);
 int amg_eig_coarse_eigenvalues(const amg_eig_ctx *c, double *lam);
 
 /* Device pointer to the current FP64 iterate (N x ld row-major) and its ld. */

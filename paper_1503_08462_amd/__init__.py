@@ -26,7 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, NOT_CONVERGED, WIDENED = 0, 1, 2
 EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EWORKSPACE, EHIP, ECANCELLED, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
-SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
+SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV, SMOOTH_GAUSS_SEIDEL = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 INIT_NESTED, INIT_RANDOM, INIT_USER = 0, 1, 2
 
@@ -34,7 +34,7 @@ EXPORTED = [
     "amg_eig_opts_default", "amg_eig_setup", "amg_eig_footprint", "amg_eig_bind", "amg_eig_init",
     "amg_eig_correct", "amg_eig_progress", "amg_eig_solve", "amg_eig_correct_batch", "amg_eig_correct_batch_joint",
     "amg_eig_init_batch_joint", "amg_eig_info",
-    "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting",
+    "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting", "amg_eig_level_colouring",
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
     "amg_eig_tune_time", "amg_eig_bind_static",
@@ -77,6 +77,7 @@ _sig = {
     "amg_eig_level_matrix": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "amg_eig_level_prolongation": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "amg_eig_level_splitting": (_i, [_vp, _i, _vp]),
+    "amg_eig_level_colouring": (_i, [_vp, _i, _vp, _vp]),
     "amg_eig_coarse_eigenvalues": (_i, [_vp, _vp]),
     "amg_eig_iterate": (_i, [_vp, _vp, _vp]),
     "amg_eig_destroy": (None, [_vp]),
@@ -185,6 +186,14 @@ class Context:
         cf = np.zeros(n, np.int32)
         self._check(_lib.amg_eig_level_splitting(self._c, level, _p(cf)))
         return cf
+
+    def colouring(self, level):
+        """Colours of level ``level``'s rows (multicolour Gauss-Seidel only)."""
+        n = int(self.info()["dims"][level])
+        colour = np.zeros(n, np.int32)
+        nc = ctypes.c_int(0)
+        self._check(_lib.amg_eig_level_colouring(self._c, level, _p(colour), ctypes.byref(nc)))
+        return colour, nc.value
 
     def coarse_eigenvalues(self):
         lam = np.zeros(int(self.info()["dims"][-1]))

@@ -33,6 +33,10 @@ struct DevLevel {
     double *p64 = nullptr, *pt64 = nullptr;
     void *b = nullptr, *r = nullptr, *x = nullptr, *t = nullptr;  // t: Chebyshev scratch
     double *cw = nullptr;
+    // multicolour Gauss-Seidel: rows in colour order, av's rows in that order
+    // without the diagonal (all entries; entries of smaller colours), a_ii
+    int32_t *gs_rows = nullptr, *gs_ptr = nullptr, *gs_col = nullptr, *gs_lptr = nullptr, *gs_lcol = nullptr;
+    void *gs_val = nullptr, *gs_lval = nullptr, *gs_diag = nullptr;
     int cpt[3] = {0, 0, 0};  // columns per lane of the row kernels on this level's rows, by tuning kind (0: built-in)
 };
 
@@ -200,6 +204,16 @@ void plan(amg_eig_ctx *c, char *base) {
             d.pt_col = cv.take<int32_t>(lv.Pt.col.size());
             d.pt_val = cv.take<char>(lv.Pt.col.size() * sT);
             d.pt64 = cv.take<double>(lv.Pt.col.size());
+            if (c->o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL) {
+                d.gs_rows = cv.take<int32_t>(lv.n);
+                d.gs_ptr = cv.take<int32_t>(lv.n + 1);
+                d.gs_col = cv.take<int32_t>(lv.gs_all.col.size());
+                d.gs_val = cv.take<char>(lv.gs_all.col.size() * sT);
+                d.gs_lptr = cv.take<int32_t>(lv.n + 1);
+                d.gs_lcol = cv.take<int32_t>(lv.gs_lo.col.size());
+                d.gs_lval = cv.take<char>(lv.gs_lo.col.size() * sT);
+                d.gs_diag = cv.take<char>(lv.n * sT);
+            }
         }
     }
     c->Z = cv.take<double>((size_t)dn * dn);
@@ -337,6 +351,16 @@ int upload_levels(amg_eig_ctx *c) {
             rc |= upload_vec(c, d.pt_col, lv.Pt.col);
             rc |= upload_vec(c, d.pt_val, convert<T>(lv.Pt.val));
             rc |= upload_vec(c, d.pt64, lv.Pt.val);
+            if (c->o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL) {
+                rc |= upload_vec(c, d.gs_rows, lv.corder);
+                rc |= upload_vec(c, d.gs_ptr, narrow_ptr<int32_t>(lv.gs_all.ptr));
+                rc |= upload_vec(c, d.gs_col, lv.gs_all.col);
+                rc |= upload_vec(c, d.gs_val, convert<T>(lv.gs_all.val));
+                rc |= upload_vec(c, d.gs_lptr, narrow_ptr<int32_t>(lv.gs_lo.ptr));
+                rc |= upload_vec(c, d.gs_lcol, lv.gs_lo.col);
+                rc |= upload_vec(c, d.gs_lval, convert<T>(lv.gs_lo.val));
+                rc |= upload_vec(c, d.gs_diag, convert<T>(lv.gs_diag));
+            }
         }
     }
     const int dn = H.dn;
@@ -438,8 +462,14 @@ double site_bytes(const amg_eig_ctx *c, int site) {
     const double nnz_p = (double)L0.P.col.size();
     switch (site) {
     case AMG_EIG_SITE_RESIDUAL: return ptr + nnz_u * 20.0 + 8.0 * n * ld + sT * n * ld;
-    case AMG_EIG_SITE_PRESMOOTH: return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld;
+    case AMG_EIG_SITE_PRESMOOTH:
+        if (c->o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL)  // b, x once; the smaller-colour entries; rows, a_ii
+            return ptr + (double)L0.gs_lo.col.size() * (4.0 + sT) + (4.0 + sT) * n + 2.0 * sT * n * ld;
+        return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld;
     case AMG_EIG_SITE_POSTSMOOTH:
+        if (c->o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL)  // b, y read and written; U -> V; entries; rows, a_ii
+            return ptr + (double)L0.gs_all.col.size() * (4.0 + sT) + (4.0 + sT) * n + 3.0 * sT * n * ld +
+                   16.0 * n * ld;
         // l1-Jacobi: (b, r) -> U + x; Chebyshev, second product: (y, d0) -> U + x
         return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_DUALSPMM: return ptr + nnz_u * 20.0 + 8.0 * n * ld + 16.0 * n * ld;
@@ -452,20 +482,52 @@ double site_bytes(const amg_eig_ctx *c, int site) {
 }
 
 // ---------------------------------------------------------- step pieces
+// One multicolour Gauss-Seidel sweep on level l, one launch per colour:
+// forward from a zero guess (b -> x, reading only neighbours of smaller
+// colours), or backward in place on the prolongated block in r (then V = U + r
+// row by row when final).
+template <typename T>
+void gs_sweep(amg_eig_ctx *c, int l, bool backward, bool final) {
+    DevLevel &d = c->dl[l];
+    const Level &lv = c->H.lv[l];
+    const int nc = (int)lv.coff.size() - 1;
+    for (int t = 0; t < nc; ++t) {
+        const int k = backward ? nc - 1 - t : t;
+        const int64_t r0 = lv.coff[k], nr = lv.coff[k + 1] - r0;
+        if (backward)
+            launch_gs_colour<T>(c->stream, final, nr, c->ld, d.gs_ptr + r0, d.gs_col, (const T *)d.gs_val,
+                                (const T *)d.gs_diag + r0, d.gs_rows + r0, (const T *)d.b, (T *)d.r, c->U, c->V,
+                                c->status, d.cpt[0]);
+        else
+            launch_gs_colour<T>(c->stream, false, nr, c->ld, d.gs_lptr + r0, d.gs_lcol, (const T *)d.gs_lval,
+                                (const T *)d.gs_diag + r0, d.gs_rows + r0, (const T *)d.b, (T *)d.x, nullptr,
+                                nullptr, c->status, d.cpt[0]);
+    }
+}
+
 // One V-cycle from level k (right-hand side in dl[k].b, zero initial guess)
 // down to `bottom`, where the coarse problem is solved by A_n^-1 (bottom = n)
 // or by the dense tail operator Bt.  The post-smoothing on level k writes
-// V = U + x when final_at_k, else x.
+// V = U + x when final_at_k, else x.  Returns the block that holds x on level
+// k (dl[k].x, or dl[k].r after the Gauss-Seidel post-smoothing).
 template <typename T>
-void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
+void *vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
     const int L = (int)c->dl.size(), ld = c->ld;
     hipStream_t s = c->stream;
     const int *st = c->status;
     const bool cheb = c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV;
+    const bool gs = c->o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL;
     const double lo = c->o.cheb_lo;
     for (int l = k; l < bottom; ++l) {
         DevLevel &d = c->dl[l];
-        if (cheb) {
+        if (gs) {
+            {
+                SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l);
+                gs_sweep<T>(c, l, false, false);
+            }
+            launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
+                                     (const T *)d.x, (T *)d.r, st, d.cpt[0]);
+        } else if (cheb) {
             {
                 SiteScope sc(c, AMG_EIG_SITE_PRESMOOTH, l, true);
                 launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_vs, (const T *)d.dinv,
@@ -491,7 +553,14 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
     for (int l = bottom - 1; l >= k; --l) {
         DevLevel &d = c->dl[l];
         DevLevel &e = c->dl[l + 1];
-        if (cheb) {
+        if (gs) {
+            // y = x + P x_{l+1} into r, then the backward sweep on it in place
+            const void *xc = l + 1 < bottom ? e.r : e.x;
+            launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)xc, (const T *)d.x,
+                                (T *)d.r, st, d.cpt[0]);
+            SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
+            gs_sweep<T>(c, l, true, final_at_k && l == k);
+        } else if (cheb) {
             // y = x + P x_{l+1} into r (free after the restriction), then x = smoothed y
             launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.x,
                                 (T *)d.r, st, d.cpt[0]);
@@ -509,12 +578,13 @@ void vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
                                   (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st, d.cpt[0]);
         }
     }
+    return gs && k < bottom ? c->dl[k].r : c->dl[k].x;
 }
 
 template <typename T>
 void vcycle(amg_eig_ctx *c, int k) {
     const int bottom = (c->tail >= 0 && k < c->tail) ? c->tail : (int)c->dl.size() - 1;
-    vcycle_levels<T>(c, k, bottom, true);
+    (void)vcycle_levels<T>(c, k, bottom, true);
 }
 
 // Bt (stored transposed) = the V-cycle from the tail level, one identity block
@@ -525,8 +595,8 @@ void build_tail(amg_eig_ctx *c) {
     DevLevel &d = c->dl[t];
     for (int64_t j0 = 0; j0 < d.n; j0 += ld) {
         launch_identity_block<T>(c->stream, d.n, ld, j0, (T *)d.b);
-        vcycle_levels<T>(c, t, L - 1, false);
-        launch_rows_from_block<T>(c->stream, d.n, ld, j0, (const T *)d.x, (T *)c->Bt);
+        const void *x = vcycle_levels<T>(c, t, L - 1, false);
+        launch_rows_from_block<T>(c->stream, d.n, ld, j0, (const T *)x, (T *)c->Bt);
     }
 }
 
@@ -1000,7 +1070,8 @@ int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_e
         amg_eig_opts_default(&c->o);
     const bool cheb_ok = c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV && c->o.cheb_degree == 2 && c->o.cheb_lo > 0.0 &&
                          c->o.cheb_lo < 1.0;
-    if ((c->o.smoother != AMG_EIG_SMOOTH_L1JACOBI && !cheb_ok) || c->o.nu_pre != 1 || c->o.nu_post != 1 ||
+    if ((c->o.smoother != AMG_EIG_SMOOTH_L1JACOBI && c->o.smoother != AMG_EIG_SMOOTH_GAUSS_SEIDEL && !cheb_ok) ||
+        c->o.nu_pre != 1 || c->o.nu_post != 1 ||
         (c->o.precision != AMG_EIG_PREC_FP64 && c->o.precision != AMG_EIG_PREC_MIXED)) {
         delete c;
         return AMG_EIG_EINVAL;
@@ -1355,6 +1426,15 @@ int amg_eig_level_splitting(const amg_eig_ctx *c, int level, int32_t *cf) {
     return AMG_EIG_OK;
 }
 
+int amg_eig_level_colouring(const amg_eig_ctx *c, int level, int32_t *colour, int *ncolours) {
+    if (!c || level < 0 || level + 1 >= (int)c->H.lv.size() || !ncolours) return AMG_EIG_EINVAL;
+    const Level &L = c->H.lv[level];
+    if (c->o.smoother != AMG_EIG_SMOOTH_GAUSS_SEIDEL || L.coff.empty()) return AMG_EIG_EINVAL;
+    *ncolours = (int)L.coff.size() - 1;
+    if (colour) std::memcpy(colour, L.colour.data(), L.colour.size() * sizeof(int32_t));
+    return AMG_EIG_OK;
+}
+
 int amg_eig_coarse_eigenvalues(const amg_eig_ctx *c, double *lam) {
     if (!c || !lam) return AMG_EIG_EINVAL;
     std::memcpy(lam, c->H.lam.data(), c->H.lam.size() * sizeof(double));
@@ -1446,7 +1526,18 @@ int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, do
                 DevLevel &f = c->dl[level - 1];
                 launch_spmm<T>(s, d.n, ld, f.pt_ptr, f.pt_col, (const T *)f.pt_val, (const T *)f.r, (T *)d.b, st, cpt);
             }
-            if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV) {
+            if (c->o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL) {
+                // the level's launch shape is what the sweeps take
+                const int keep = d.cpt[0];
+                d.cpt[0] = cpt;
+                gs_sweep<T>(c, level, false, false);
+                launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,
+                                         (const T *)d.x, (T *)d.r, st, cpt);
+                launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
+                                    (const T *)d.x, (T *)d.r, st, cpt);
+                gs_sweep<T>(c, level, true, false);
+                d.cpt[0] = keep;
+            } else if (c->o.smoother == AMG_EIG_SMOOTH_CHEBYSHEV) {
                 launch_cheb_pre<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_vs, (const T *)d.dinv,
                                    (const T *)d.b, (T *)d.x, lo, st, cpt);
                 launch_level_residual<T>(s, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.b,

@@ -29,6 +29,15 @@ struct Level {
     std::vector<double> l1;   // d_i = sum_j |a_ij|
     std::vector<int32_t> cf;  // C/F splitting towards level k+1 (1 = C)
     Csr P, Pt;                // prolongation n_k x n_{k+1} and its transpose
+    // Multicolour Gauss-Seidel (only with that smoother): first-fit colours of
+    // the graph of av, the rows colour by colour (ascending within a colour),
+    // the colour boundaries in that sequence, and av's rows in that sequence
+    // without their diagonal: all off-diagonal entries (gs_all) and those
+    // whose column has a smaller colour than the row (gs_lo), plus a_ii.
+    std::vector<int32_t> colour, corder;
+    std::vector<int64_t> coff;
+    Csr gs_all, gs_lo;
+    std::vector<double> gs_diag;
 };
 
 struct Hierarchy {

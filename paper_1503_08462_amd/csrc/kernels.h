@@ -41,6 +41,14 @@ template <typename T>
 void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int32_t *ptr, const int32_t *col,
                         const T *val, const T *dinv, const T *b, const T *y, T *x, const double *U, double *V,
                         const int *status, int cpt = 0);
+// One colour of a multicolour Gauss-Seidel sweep: rows[0, nrows) of a
+// colour-ordered CSR without diagonal (ptr, diag and rows offset to the
+// colour's first position), x_i = (b_i - sum a_ij x_j) / a_ii in place; with
+// final also V_i = U_i + x_i (FP64).
+template <typename T>
+void launch_gs_colour(hipStream_t s, bool final, int64_t nrows, int ld, const int32_t *ptr, const int32_t *col,
+                      const T *val, const T *diag, const int32_t *rows, const T *b, T *x, const double *U, double *V,
+                      const int *status, int cpt = 0);
 // Degree-2 Chebyshev smoothing on D^-1 A over [lo, 1] (D the l1 diagonal):
 // pre-smoothing from a zero guess (x), the level residual r = b - A x, the
 // prolongation y = x + P xc, and post-smoothing of y (scratch d0; x, or on

@@ -11,6 +11,9 @@
 //   k_prolong_add   y = D^-1 b + P x_c (coarse-grid correction of x1)
 //   k_smooth_post   x = y + D^-1 (b - A y); on the correction level it writes
 //                   the FP64 block V = U + x
+//   k_gs_colour     one colour of a multicolour Gauss-Seidel sweep (forward from
+//                   a zero guess, or backward; on the correction level it writes
+//                   the FP64 block V = U + x as rows finish)
 //   k_dual_spmm     W = [A V | M V] (FP64, shared pattern)
 //   k_gram          [V^T A V | V^T M V] by a two-phase deterministic reduction
 //   k_final         U = P Y + V X_v on the correction level (recombination)
@@ -333,6 +336,45 @@ __global__ __launch_bounds__(256) void k_smooth_post(int64_t n, int ld, const in
 #pragma unroll
         for (int c = 0; c < CPT; ++c) o.v[c] = yi.v[c] + di * acc.v[c];
         stv<T, CPT>(x + rm.row * ld + c0, o);
+    }
+}
+
+// ------------------------------------ multicolour Gauss-Seidel (a2, a6)
+// One colour of a Gauss-Seidel sweep.  The colour's rows are positions
+// [0, nrows) of a colour-ordered CSR (ptr, diag and rows start at the colour's
+// first position; rows gives the row numbers): x_i = (b_i - sum a_ij x_j) / a_ii
+// over the entries listed, which hold no diagonal (all off-diagonal entries,
+// or, from a zero guess, those of smaller colours: the others multiply zeros).
+// Rows of one colour are not neighbours, so they read rows of other colours
+// only and update in parallel; x is read and written by the same launch at
+// disjoint rows.  FINAL also writes V_i = U_i + x_i in FP64: in a sweep a row
+// changes only in its own colour's step.
+template <typename T, int CPT, bool FINAL>
+__global__ __launch_bounds__(256) void k_gs_colour(int64_t nrows, int ld, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                   const T *__restrict__ diag, const int32_t *__restrict__ rows,
+                                                   const T *__restrict__ b, T *x, const double *__restrict__ U,
+                                                   double *__restrict__ V, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, nrows);
+    const int64_t pos = rm.active ? rm.row : nrows - 1;  // lanes past the last row read it and store nothing
+    const int64_t row = rows[pos];
+    const int c0 = rm.sub * CPT;
+    Vec<T, CPT> acc = ldv<T, CPT>(b + row * ld + c0);
+    gather_wave<T, CPT>(rm.row, rm.sub, rm.tpr, rm.active, nrows, ptr, col, x, ld, c0,
+                        [&](int32_t p) { return val[p]; },
+                        [&](const T &v, int64_t, const Vec<T, CPT> &xj) { fma_v(acc, -v, xj); });
+    if (!rm.active) return;
+    const T di = diag[pos];
+    Vec<T, CPT> o;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) o.v[c] = acc.v[c] / di;
+    stv<T, CPT>(x + row * ld + c0, o);
+    if constexpr (FINAL) {
+        Vec<double, CPT> u = ldv<double, CPT>(U + row * ld + c0);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) u.v[c] += (double)o.v[c];
+        stv<double, CPT>(V + row * ld + c0, u);
     }
 }
 
@@ -1131,6 +1173,21 @@ void launch_smooth_post(hipStream_t s, bool final, int64_t n, int ld, const int3
                                             dim3(kBlock), 0, s, n, ld, ptr, col, val, dinv, b, y, x, U, V, status));
 }
 
+template <typename T>
+void launch_gs_colour(hipStream_t s, bool final, int64_t nrows, int ld, const int32_t *ptr, const int32_t *col,
+                      const T *val, const T *diag, const int32_t *rows, const T *b, T *x, const double *U, double *V,
+                      const int *status, int cpt) {
+    if (nrows <= 0) return;
+    if (final)
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_gs_colour<T, CPT, true>), dim3((unsigned)row_blocks(nrows, ld, CPT)),
+                                            dim3(kBlock), 0, s, nrows, ld, ptr, col, val, diag, rows, b, x, U, V,
+                                            status));
+    else
+        DISPATCH_CPT(ld, cpt, KLAUNCH((k_gs_colour<T, CPT, false>), dim3((unsigned)row_blocks(nrows, ld, CPT)),
+                                            dim3(kBlock), 0, s, nrows, ld, ptr, col, val, diag, rows, b, x, U, V,
+                                            status));
+}
+
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                       const double *m, const double *V, double *W, const int *status, int cpt) {
     DISPATCH_CPT(ld, cpt, KLAUNCH((k_dual_spmm<CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock), 0,
@@ -1313,6 +1370,9 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
     template void launch_smooth_post<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *,           \
                                         const T *, const T *, const T *, const T *, T *, const double *, double *,   \
                                         const int *, int);                                                                \
+    template void launch_gs_colour<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *, const T *,   \
+                                      const T *, const int32_t *, const T *, T *, const double *, double *,          \
+                                      const int *, int);                                                             \
     template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
                                      const double *, const double *, const double *, T *, double *, const int *,      \
                                      int);                                                                            \

@@ -374,6 +374,84 @@ void vcycle_operator(Level &L) {
     }
 }
 
+// Multicolour ordering of the V-cycle operator: i and j are neighbours when
+// a_ij != 0 or a_ji != 0 (i != j); rows 0, 1, ... take the smallest colour no
+// already coloured neighbour holds (first fit).  A Gauss-Seidel sweep that
+// visits the rows colour by colour updates the rows of one colour from values
+// of other colours only, so each colour is one parallel step.
+void colour_level(Level &L) {
+    const Csr &V = L.av;
+    const int64_t n = L.n;
+    // symmetric neighbour lists: row i's off-diagonal columns plus the rows
+    // that hold column i
+    std::vector<int64_t> deg(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = V.ptr[i]; p < V.ptr[i + 1]; ++p)
+            if (V.col[p] != i) {
+                ++deg[i + 1];
+                ++deg[V.col[p] + 1];
+            }
+    for (int64_t i = 0; i < n; ++i) deg[i + 1] += deg[i];
+    std::vector<int32_t> nb(deg[n]);
+    std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = V.ptr[i]; p < V.ptr[i + 1]; ++p) {
+            const int32_t j = V.col[p];
+            if (j == i) continue;
+            nb[fill[i]++] = j;
+            nb[fill[j]++] = (int32_t)i;
+        }
+    L.colour.assign(n, -1);
+    std::vector<int64_t> mark;  // mark[c] == i: colour c is held next to row i
+    int32_t ncol = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = deg[i]; p < deg[i + 1]; ++p) {
+            const int32_t c = L.colour[nb[p]];
+            if (c >= 0) mark[c] = i;
+        }
+        int32_t c = 0;
+        while (c < ncol && mark[c] == i) ++c;
+        L.colour[i] = c;
+        if (c == ncol) {
+            ++ncol;
+            mark.push_back(-1);
+        }
+    }
+    L.coff.assign(ncol + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++L.coff[L.colour[i] + 1];
+    for (int32_t c = 0; c < ncol; ++c) L.coff[c + 1] += L.coff[c];
+    L.corder.assign(n, 0);
+    {
+        std::vector<int64_t> at(L.coff.begin(), L.coff.end() - 1);
+        for (int64_t i = 0; i < n; ++i) L.corder[at[L.colour[i]]++] = (int32_t)i;
+    }
+    for (Csr *g : {&L.gs_all, &L.gs_lo}) {
+        g->nr = g->nc = n;
+        g->ptr.assign(n + 1, 0);
+        g->col.clear();
+        g->val.clear();
+    }
+    L.gs_diag.assign(n, 0.0);
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t i = L.corder[s];
+        for (int64_t p = V.ptr[i]; p < V.ptr[i + 1]; ++p) {
+            const int32_t j = V.col[p];
+            if (j == i) {
+                L.gs_diag[s] += V.val[p];
+                continue;
+            }
+            L.gs_all.col.push_back(j);
+            L.gs_all.val.push_back(V.val[p]);
+            if (L.colour[j] < L.colour[i]) {
+                L.gs_lo.col.push_back(j);
+                L.gs_lo.val.push_back(V.val[p]);
+            }
+        }
+        L.gs_all.ptr[s + 1] = (int64_t)L.gs_all.col.size();
+        L.gs_lo.ptr[s + 1] = (int64_t)L.gs_lo.col.size();
+    }
+}
+
 }  // namespace
 
 int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts &o, Hierarchy &H,
@@ -428,6 +506,8 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
         H.lv.push_back(std::move(next));
     }
     for (Level &L : H.lv) vcycle_operator(L);
+    if (o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL)
+        for (size_t l = 0; l + 1 < H.lv.size(); ++l) colour_level(H.lv[l]);
     if (H.lv.size() < 2) {
         err = "the hierarchy needs at least two levels (n <= coarse_max or coarsening stalled)";
         return AMG_EIG_EINVAL;

@@ -55,6 +55,34 @@ def test_setup_matches_oracle(make, cm):
     ctx.close()
 
 
+@pytest.mark.parametrize("make,cm", [
+    (lambda: configs.lshape(24, q=10, jitter_seed=2), 300),
+    (lambda: configs.cube(12, q=8), 100),
+    (lambda: configs.oscillator(40, q=10), 150),
+])
+def test_colouring_matches_oracle(make, cm):
+    """Multicolour Gauss-Seidel: the library's first-fit colouring of every
+    smoothed level equals the oracle's, row for row."""
+    p = make()
+    A, M = mats(p)
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
+                     ae.defaults(coarse_max=cm, qe=12, smoother=ae.SMOOTH_GAUSS_SEIDEL))
+    o = Oracle(A, M, q=p["q"], qe=12, coarse_max=cm, coarse_min=26, smoother="mcgs")
+    info = ctx.info()
+    assert info["dims"].tolist() == [L.n for L in o.levels]
+    for l in range(info["levels"] - 1):
+        colour, nc = ctx.colouring(l)
+        assert np.array_equal(colour, o.levels[l].colour), l
+        assert nc == o.levels[l].colour.max() + 1
+    with pytest.raises(ae.AmgEigError):
+        ctx.colouring(info["levels"] - 1)
+    ctx.close()
+    plain = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(coarse_max=cm, qe=12))
+    with pytest.raises(ae.AmgEigError):
+        plain.colouring(0)
+    plain.close()
+
+
 def test_guard_rule_and_width_rounding():
     """Block width = guard rule on the coarsest eigenvalues (no block ending
     inside a relative gap < 1e-2), rounded up to a multiple of 4."""
