@@ -12,6 +12,12 @@ never touches a GPU.  It follows the paper's formulation directly:
                 one correction per level, then corrections on the finest level
                 until the relative residual criterion holds
 
+Shift (Remark 3.1): with shift = sigma the linear equation of Algorithm 3.1
+becomes (A_k - sigma M_k) u~ = (lambda - sigma) M_k u, solved by the AMG
+iteration of the shifted operators A_k - sigma M_k on the same hierarchy (the
+coarsest solve with A_n - sigma M_n).  sigma must lie below the smallest
+eigenvalue for these operators to stay positive definite.
+
 Smoothers: "gs" (the paper's Gauss-Seidel: forward before, backward after the
 coarse correction), "mcgs" (the same sweeps with the rows of each level taken
 colour by colour, amg.colouring), "l1jacobi" (x += D^-1 (b - A x), d_i = sum_j |a_ij|) and
@@ -43,7 +49,7 @@ def guard_count(lam, q, gap=1e-2, cap=None):
 class Oracle:
     def __init__(self, A, M, q, qe=None, theta=0.25, coarse_max=512, coarse_min=None, max_levels=25,
                  smoother="gs", nu_pre=1, nu_post=1, cheb_degree=2, cheb_lo=0.25,
-                 guard_gap=1e-2):
+                 guard_gap=1e-2, shift=0.0):
         self.q = q
         cmin = coarse_min if coarse_min is not None else 2 * (qe if qe else q) + 2
         self.levels = amg.build_hierarchy(A, M, theta, coarse_max, cmin, max_levels)
@@ -53,38 +59,41 @@ class Oracle:
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.cheb_degree = cheb_degree
         self.cheb_lo = cheb_lo
-        An = self.levels[-1].A.toarray()
-        self._coarse_chol = sla.cho_factor(0.5 * (An + An.T))
+        self.shift = float(shift)
+        for L in self.levels:  # the operator of the linear equation on each level
+            L.As = (L.A - self.shift * L.M).tocsr() if self.shift != 0.0 else L.A
+        An = self.levels[-1].As.toarray()
+        self._coarse_chol = sla.cho_factor(0.5 * (An + An.T))  # fails unless A_n - sigma M_n is SPD
         for L in self.levels:
             d = np.zeros(L.n)
-            np.add.at(d, amg._rows(L.A), np.abs(L.A.data))
+            np.add.at(d, amg._rows(L.As), np.abs(L.As.data))
             L.l1 = d
-            L.diag = L.A.diagonal()
+            L.diag = L.As.diagonal()
             if smoother == "mcgs":
-                L.colour, L.order = amg.colouring(L.A)
+                L.colour, L.order = amg.colouring(L.As)
         self.history = []
 
     # ------------------------------------------------------------------ smoothing
     def _smooth(self, L, b, x, backward):
         if self.smoother == "gs":
             x = np.ascontiguousarray(x, dtype=np.float64).copy()
-            return native.gs_sweep(L.A, b, x, backward=backward)
+            return native.gs_sweep(L.As, b, x, backward=backward)
         if self.smoother == "mcgs":
             x = np.ascontiguousarray(x, dtype=np.float64).copy()
-            return native.gs_sweep(L.A, b, x, backward=backward, order=L.order)
+            return native.gs_sweep(L.As, b, x, backward=backward, order=L.order)
         if self.smoother == "l1jacobi":
-            return x + (b - L.A @ x) / L.l1[:, None]
+            return x + (b - L.As @ x) / L.l1[:, None]
         if self.smoother == "chebyshev":
             theta = 0.5 * (1.0 + self.cheb_lo)
             delta = 0.5 * (1.0 - self.cheb_lo)
             # Chebyshev acceleration (Saad, Iterative Methods, 2nd ed., Alg. 12.1) on D^-1 A
             sigma = theta / delta
             rho_k = 1.0 / sigma
-            r = (b - L.A @ x) / L.l1[:, None]
+            r = (b - L.As @ x) / L.l1[:, None]
             d = r / theta
             for _ in range(self.cheb_degree):
                 x = x + d
-                r = r - (L.A @ d) / L.l1[:, None]
+                r = r - (L.As @ d) / L.l1[:, None]
                 rho_n = 1.0 / (2.0 * sigma - rho_k)
                 d = rho_n * rho_k * d + (2.0 * rho_n / delta) * r
                 rho_k = rho_n
@@ -92,11 +101,12 @@ class Oracle:
         raise ValueError(self.smoother)
 
     def vcycle(self, k, b, x):
-        """One V-cycle for A_k x = b from initial guess x (the AMG iteration of (3.2))."""
+        """One V-cycle for A_k x = b (A_k - sigma M_k with a shift) from initial
+        guess x (the AMG iteration of (3.2))."""
         L = self.levels[k]
         for _ in range(self.nu_pre):
             x = self._smooth(L, b, x, backward=False)
-        r = b - L.A @ x
+        r = b - L.As @ x
         rc = L.P.T @ r
         if k + 1 == len(self.levels) - 1:
             ec = sla.cho_solve(self._coarse_chol, rc)
@@ -158,9 +168,10 @@ class Oracle:
         return mu, U
 
     def correction(self, k, lam, U):
-        """Algorithm 3.1 (m = 1): AMGCorrection(n, k, {lam, U})."""
+        """Algorithm 3.1 (m = 1): AMGCorrection(n, k, {lam, U}); with a shift
+        sigma the right-hand side is (lam - sigma) M_k u (Remark 3.1)."""
         L = self.levels[k]
-        rhs = (L.M @ U) * lam[None, :]
+        rhs = (L.M @ U) * (lam - self.shift)[None, :]
         V = self.vcycle(k, rhs, U)
         return self.rayleigh_ritz(k, V)
 
