@@ -415,7 +415,7 @@ def prepared_context(p, wl, prec, args, stream):
     t0 = time.perf_counter()
     ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
                      ae.defaults(coarse_max=wl["coarse_max"], qe=args.qe, precision=prec, use_graph=args.graph,
-                                 smoother=smoother, cheb_degree=2, cheb_lo=0.25))
+                                 smoother=smoother, cheb_degree=2, cheb_lo=0.25, shift_frac=args.shift_frac))
     setup_s = time.perf_counter() - t0
     ctx.bind(stream=stream)
     for _ in range(max(1, args.warmup)):
@@ -454,6 +454,9 @@ def main():
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev", "gs"],
                     help="gs: multicolour Gauss-Seidel, forward before and backward after the coarse correction")
+    ap.add_argument("--shift-frac", type=float, default=0.0,
+                    help="shifted correction equation: sigma = this fraction of the coarsest level's smallest "
+                         "eigenvalue (0: no shift)")
     ap.add_argument("--requests", type=int, default=24, help="serving stream (config 5): number of requests")
     ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
     ap.add_argument("--budget-gb", type=float, default=8.0,
@@ -587,7 +590,9 @@ def main():
         "config": {"workload": "config %d: %s" % (args.config, wl["name"]), "N": int(p["n"]), "q": q,
                    "qe": info["qe"], "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
                    "smoother": {"l1jacobi": "l1-jacobi", "chebyshev": "chebyshev degree 2 on [0.25, 1]",
-                                "gs": "multicolour gauss-seidel"}[args.smoother] + " V(1,1)", "start": "nested (Algorithm 3.2)",
+                                "gs": "multicolour gauss-seidel"}[args.smoother] + " V(1,1)"
+                               + (", shift %.2f lambda_1 of the coarsest level" % args.shift_frac
+                                  if args.shift_frac else ""), "start": "nested (Algorithm 3.2)",
                    "steps_launch": ("captured hipGraph replays; the second step of each enqueued chunk of three "
                                     "or more eager and event-timed" if args.graph else "eager")},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),

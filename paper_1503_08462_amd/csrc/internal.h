@@ -24,9 +24,10 @@ struct Level {
     std::vector<int64_t> ptr;
     std::vector<int32_t> col;
     std::vector<double> a, m;
-    // A_k without its explicit off-diagonal zeros: the V-cycle operator.
+    // The V-cycle operator A_k - sigma M_k without explicit off-diagonal zeros
+    // (A_k itself without a shift), and its l1 diagonal.
     Csr av;
-    std::vector<double> l1;   // d_i = sum_j |a_ij|
+    std::vector<double> l1;   // d_i = sum_j |av_ij|
     std::vector<int32_t> cf;  // C/F splitting towards level k+1 (1 = C)
     Csr P, Pt;                // prolongation n_k x n_{k+1} and its transpose
     // Multicolour Gauss-Seidel (only with that smoother): first-fit colours of
@@ -45,7 +46,8 @@ struct Hierarchy {
     int dn = 0;
     std::vector<double> lam;   // coarsest eigenvalues, ascending
     std::vector<double> Z;     // dn x dn row-major, column j = eigenvector j, Z^T M_n Z = I
-    std::vector<double> Ainv;  // dn x dn row-major, A_n^-1 = Z diag(1/lam) Z^T
+    std::vector<double> Ainv;  // dn x dn row-major, (A_n - sigma M_n)^-1 = Z diag(1/(lam - sigma)) Z^T
+    double sigma = 0.0;        // shift of the V-cycle operators A_k - sigma M_k (0: none)
 };
 
 // Status codes of amg_eig.h, returned by the setup routines.

@@ -355,23 +355,29 @@ void galerkin(const Level &L, const Csr &P, const Csr &Pt, Level &out) {
     }
 }
 
-// V-cycle operator: A_k without explicit off-diagonal zeros, and the l1 diagonal.
-void vcycle_operator(Level &L) {
+// V-cycle operator: A_k - sigma M_k (the operator of the shifted linear
+// equation of Remark 3.1; A_k when sigma = 0) without explicit off-diagonal
+// zeros, and its l1 diagonal.  Returns false if a diagonal entry is not positive.
+bool vcycle_operator(Level &L, double sigma) {
     Csr &V = L.av;
     V.nr = V.nc = L.n;
     V.ptr.assign(L.n + 1, 0);
     V.col.clear();
     V.val.clear();
     L.l1.assign(L.n, 0.0);
+    bool ok = true;
     for (int64_t i = 0; i < L.n; ++i) {
         for (int64_t p = L.ptr[i]; p < L.ptr[i + 1]; ++p) {
-            if (L.a[p] == 0.0 && L.col[p] != i) continue;
+            const double v = L.a[p] - sigma * L.m[p];
+            if (L.col[p] == i) ok = ok && v > 0.0;
+            if (v == 0.0 && L.col[p] != i) continue;
             V.col.push_back(L.col[p]);
-            V.val.push_back(L.a[p]);
-            L.l1[i] += std::fabs(L.a[p]);
+            V.val.push_back(v);
+            L.l1[i] += std::fabs(v);
         }
         V.ptr[i + 1] = (int64_t)V.col.size();
     }
+    return ok;
 }
 
 // Multicolour ordering of the V-cycle operator: i and j are neighbours when
@@ -505,9 +511,6 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
         galerkin(L, L.P, L.Pt, next);
         H.lv.push_back(std::move(next));
     }
-    for (Level &L : H.lv) vcycle_operator(L);
-    if (o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL)
-        for (size_t l = 0; l + 1 < H.lv.size(); ++l) colour_level(H.lv[l]);
     if (H.lv.size() < 2) {
         err = "the hierarchy needs at least two levels (n <= coarse_max or coarsening stalled)";
         return AMG_EIG_EINVAL;
@@ -537,10 +540,29 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
         return AMG_EIG_ENOTSPD;
     }
     H.dn = dn;
+    // shift of the linear equation (Remark 3.1): below the smallest coarsest
+    // eigenvalue, an upper bound of the smallest eigenvalue of every level
+    if (!std::isfinite(o.shift) || !(o.shift_frac >= 0.0 && o.shift_frac < 1.0) ||
+        (o.shift != 0.0 && o.shift_frac != 0.0)) {
+        err = "shift must be finite, shift_frac in [0, 1), not both set";
+        return AMG_EIG_EINVAL;
+    }
+    H.sigma = o.shift_frac > 0.0 ? o.shift_frac * H.lam[0] : o.shift;
+    if (!(H.sigma < H.lam[0])) {
+        err = "shift not below the smallest eigenvalue of the coarsest level";
+        return AMG_EIG_EINVAL;
+    }
+    for (size_t l = 0; l < H.lv.size(); ++l)
+        if (!vcycle_operator(H.lv[l], H.sigma) && H.sigma != 0.0) {
+            err = "a_ii - sigma m_ii <= 0 on level " + std::to_string(l) + ": shift too large";
+            return AMG_EIG_EINVAL;
+        }
+    if (o.smoother == AMG_EIG_SMOOTH_GAUSS_SEIDEL)
+        for (size_t l = 0; l + 1 < H.lv.size(); ++l) colour_level(H.lv[l]);
     H.Ainv.assign((size_t)dn * dn, 0.0);
     for (int i = 0; i < dn; ++i)
         for (int k = 0; k < dn; ++k) {
-            const double zik = H.Z[(size_t)i * dn + k] / H.lam[k];
+            const double zik = H.Z[(size_t)i * dn + k] / (H.lam[k] - H.sigma);
             if (zik == 0.0) continue;
             for (int j = 0; j < dn; ++j) H.Ainv[(size_t)i * dn + j] += zik * H.Z[(size_t)j * dn + k];
         }

@@ -83,6 +83,28 @@ def test_colouring_matches_oracle(make, cm):
     plain.close()
 
 
+def test_shift_options():
+    """Remark 3.1 shift: rejected unless below the coarsest level's smallest
+    eigenvalue; with multicolour Gauss-Seidel the colouring follows the
+    shifted operator's pattern, as the oracle's does."""
+    p = configs.oscillator(40, q=6)
+    A, M = mats(p)
+    o0 = Oracle(A, M, q=6, qe=8, coarse_max=150, coarse_min=26)
+    lam1 = o0.lam_n[0]
+    for kw in (dict(shift=1.001 * lam1), dict(shift_frac=1.0), dict(shift_frac=-0.1),
+               dict(shift=0.1, shift_frac=0.5), dict(shift=float("nan"))):
+        with pytest.raises(ae.AmgEigError) as e:
+            ae.Context(p["rowptr"], p["col"], p["A"], p["M"], 6, ae.defaults(coarse_max=150, qe=8, **kw))
+        assert e.value.code == ae.EINVAL, kw
+    sigma = 0.9 * lam1
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], 6,
+                     ae.defaults(coarse_max=150, qe=8, shift=sigma, smoother=ae.SMOOTH_GAUSS_SEIDEL))
+    o = Oracle(A, M, q=6, qe=8, coarse_max=150, coarse_min=26, smoother="mcgs", shift=sigma)
+    for l in range(ctx.info()["levels"] - 1):
+        assert np.array_equal(ctx.colouring(l)[0], o.levels[l].colour)
+    ctx.close()
+
+
 def test_guard_rule_and_width_rounding():
     """Block width = guard rule on the coarsest eigenvalues (no block ending
     inside a relative gap < 1e-2), rounded up to a multiple of 4."""
