@@ -454,7 +454,7 @@ def main():
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev", "gs"],
                     help="gs: multicolour Gauss-Seidel, forward before and backward after the coarse correction")
-    ap.add_argument("--shift-frac", type=float, default=0.0,
+    ap.add_argument("--shift-frac", type=float, default=0.9,
                     help="shifted correction equation: sigma = this fraction of the coarsest level's smallest "
                          "eigenvalue (0: no shift)")
     ap.add_argument("--requests", type=int, default=24, help="serving stream (config 5): number of requests")
