@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFS = 78.6  # dense FP64 matrix-core peak of the MI355X
 FP64_PEAK_TFLOPS = 78.6
 
 # Per-workload solver options (coarse size: the paper's first improvement
@@ -539,7 +540,9 @@ def main():
             continue
         avg = ms / n * 1e-3
         if name == "gram":
-            sites[name] = {"avg_us": avg * 1e6, "launches": n, "tflops": amount / avg / 1e12}
+            sites[name] = {"avg_us": avg * 1e6, "launches": n}
+            if amount > 0:  # zero when the products run inside the dual SpMM launch (reduction only)
+                sites[name]["tflops"] = amount / avg / 1e12
         elif name == "small":
             sites[name] = {"avg_us": avg * 1e6, "launches": n}
         else:
@@ -555,16 +558,28 @@ def main():
         achieved = amount / (ms / n * 1e-3) / 1e9
         cheb = args.smoother == "chebyshev"
         gs = args.smoother == "gs"
+        wide = info["qe"] > 32  # wide blocks: the Gram products run inside the dual SpMM launch
         kernel_name = {"residual": "k_residual",
                        "presmooth": "k_gs_colour" if gs else "k_cheb_pre" if cheb else "k_smooth_pre",
                        "postsmooth": "k_gs_colour" if gs else "k_cheb_post2" if cheb else "k_smooth_post",
-                       "dualspmm": "k_dual_spmm", "restrict": "k_spmm",
-                       "final": "k_final" if info["qe"] > 32 else "k_final_rows"}[dom]
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(kernel_name, "config%d_%s" % (args.config, args.precision)),
-                    "kernel": kernel_name, "site": dom, "alg_bytes_per_launch": amount,
-                    "avg_launch_us": round(ms / n * 1e3, 2)}
+                       "dualspmm": "k_dual_gram" if wide else "k_dual_spmm", "restrict": "k_spmm",
+                       "final": "k_final" if wide else "k_final_rows"}[dom]
+        traffic = load_traffic(kernel_name, "config%d_%s" % (args.config, args.precision))
+        t_launch = ms / n * 1e-3
+        flops = 4.0 * p["n"] * info["qe"] ** 2 if kernel_name == "k_dual_gram" else 0.0
+        if flops / (MFMA_F64_PEAK_TFS * 1e12) > amount / (HBM_PEAK_GBS * 1e9):
+            # its FP64 matrix-core work takes longer at peak than its bytes do
+            # at HBM peak: the matrix cores bound it
+            tf = flops / t_launch / 1e12
+            roofline = {"bound": "mfma", "achieved": round(tf, 2), "peak": MFMA_F64_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(tf / MFMA_F64_PEAK_TFS, 4), "traffic": traffic, "kernel": kernel_name,
+                        "site": dom, "alg_flops_per_launch": flops, "alg_bytes_per_launch": amount,
+                        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(ms / n * 1e3, 2)}
+        else:
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "kernel": kernel_name, "site": dom, "alg_bytes_per_launch": amount,
+                        "avg_launch_us": round(ms / n * 1e3, 2)}
     small = None
     if "small" in sites:
         tot = sum(v[1] for k, v in stats.items() if v[2] > 0)

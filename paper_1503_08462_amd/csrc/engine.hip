@@ -473,7 +473,9 @@ double site_bytes(const amg_eig_ctx *c, int site) {
         // l1-Jacobi: (b, r) -> U + x; Chebyshev, second product: (y, d0) -> U + x
         return ptr + nnz_v * (4.0 + sT) + sT * n + 2.0 * sT * n * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_DUALSPMM: return ptr + nnz_u * 20.0 + 8.0 * n * ld + 16.0 * n * ld;
-    case AMG_EIG_SITE_GRAM: return 4.0 * n * ld * ld;  // flops
+    // flops; with the Gram products fused into the dual SpMM launch (wide
+    // blocks) the site times only the reduction of the partials
+    case AMG_EIG_SITE_GRAM: return dual_gram_fused(c->ld) ? 0.0 : 4.0 * n * ld * ld;
     case AMG_EIG_SITE_RESTRICT: return 4.0 * (n1 + 1) + nnz_p * 12.0 + 16.0 * n * ld + 16.0 * n1 * ld;
     case AMG_EIG_SITE_FINAL: return ptr + nnz_p * 12.0 + 8.0 * n1 * ld + 16.0 * n * ld;
     case AMG_EIG_SITE_SMALL: return 0.0;
@@ -633,11 +635,18 @@ void rr_front(amg_eig_ctx *c, int k, bool with_gemm = true) {
     hipStream_t s = c->stream;
     const int *st = c->status;
     DevLevel &d = c->dl[k];
-    {
-        SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k, true);
-        launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, d.cpt[1]);
-    }
-    {
+    if (dual_gram_fused(ld)) {  // one pass over V and W for both products
+        {
+            SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k, true);
+            launch_dual_gram(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, c->part_gram, st, d.cpt[1]);
+        }
+        SiteScope sc(c, AMG_EIG_SITE_GRAM, k);
+        launch_gram_reduce(s, d.n, ld, c->part_gram, c->sw.GAGM, st);
+    } else {
+        {
+            SiteScope sc(c, AMG_EIG_SITE_DUALSPMM, k, true);
+            launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, d.cpt[1]);
+        }
         SiteScope sc(c, AMG_EIG_SITE_GRAM, k);
         launch_gram(s, d.n, ld, c->V, c->W, c->part_gram, c->sw.GAGM, st);
     }
@@ -1567,7 +1576,10 @@ int amg_eig_tune_time(amg_eig_ctx *c, int kind, int level, int cpt, int reps, do
             else
                 launch_residual<double>(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->theta, (double *)d.b,
                                         c->part_res, st, cpt);
-            launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, cpt);
+            if (dual_gram_fused(ld))
+                launch_dual_gram(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, c->part_gram, st, cpt);
+            else
+                launch_dual_spmm(s, d.n, ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->V, c->W, st, cpt);
             if (level >= 1) launch_spmm<double>(s, d.n, ld, d.p_ptr, d.p_col, d.p64, e.cw, d.cw, st, cpt);
             launch_final(s, d.n, ld, d.p_ptr, d.p_col, d.p64, e.cw, c->V, c->sw.Xv, c->W, st, cpt);
         } else {

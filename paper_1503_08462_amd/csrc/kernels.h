@@ -75,6 +75,12 @@ void launch_gemm_tn(hipStream_t s, int m, int n, int K, const T *A, int lda, con
                     const int *status);
 void launch_dual_spmm(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                       const double *m, const double *V, double *W, const int *status, int cpt = 0);
+// Wide blocks (ld > 32): W = [A V | M V] and the partials of the Gram products
+// in one kernel; launch_gram_reduce then forms G from the partials.
+bool dual_gram_fused(int ld);
+void launch_dual_gram(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                      const double *m, const double *V, double *W, double *part, const int *status, int cpt = 0);
+void launch_gram_reduce(hipStream_t s, int64_t n, int ld, const double *part, double *G, const int *status);
 void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
                  const int *status);
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,

@@ -824,6 +824,106 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
     }
 }
 
+// W = [A V | M V] and phase 1 of [V^T A V | V^T M V] = V^T W for wide blocks
+// in one pass over the rows, so that V and W leave memory once for both
+// products.  Workgroup b (eight wavefronts) walks the contiguous rows
+// [n b / nb, n (b+1) / nb) in passes of R = 8 rpw rows: each wavefront gathers
+// rpw rows of W as k_dual_spmm does (ld / CPT lanes per row, the lanes left
+// over idle) and writes them out; the pass's rows of W and of V are staged in
+// LDS (at most 98 KB for ld <= 80), and the 16 x 16 tiles on and above the
+// diagonals of V^T A V and V^T M V are accumulated from there on the FP64
+// matrix cores, at most four per wavefront, dealt as in k_gram_wide, whose
+// partial layout (and reduction) this shares.  Eight wavefronts per
+// workgroup keep enough rows' gathers in flight between the barriers of a pass.
+constexpr int kDualGramWaves = 8;
+constexpr int kDualGramTiles = (30 + kDualGramWaves - 1) / kDualGramWaves;  // tiles per wavefront, ld <= 80
+template <int CPT>
+__global__ __launch_bounds__(kDualGramWaves * kWave) __attribute__((amdgpu_waves_per_eu(CPT == 8 ? 2 : 4))) void k_dual_gram(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ a,
+                                                   const double *__restrict__ m, const double *__restrict__ V,
+                                                   double *__restrict__ W, double *__restrict__ part,
+                                                   const int *status) {
+    extern __shared__ double stage[];  // R rows of V (ld each), then the same rows of W (2 ld each)
+    if (status[ST_CONVERGED]) return;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int tpr = ld / CPT, rpw = kWave / tpr, R = nw * rpw;
+    const int grp = lane / tpr, sub = lane - grp * tpr, c0 = sub * CPT;
+    const int64_t nb = gridDim.x, lb = xcd_block();
+    const int64_t r0 = n * lb / nb, r1 = n * (lb + 1) / nb;
+    const int l2 = 2 * ld, ti = (ld + 15) / 16, tu = ti * (ti + 1) / 2, ntiles = 2 * tu;
+    const int outsz = ld * l2;
+    const int kk = lane >> 4, c = lane & 15;
+    // tile t of the upper triangles: grid half (A or M part), row tile, column
+    // tile >= row tile (recomputed where used: wave-uniform scalar work)
+    auto tile = [&](int t, int &off, int &ta, int &tb) {
+        const int h = t < tu ? 0 : 1;
+        int u = t - h * tu;
+        ta = 0;
+        while (ta < ti && u >= ti - ta) {
+            u -= ti - ta;
+            ++ta;
+        }
+        off = h * ld;
+        tb = ta + u;
+    };
+    dbl4 acc[kDualGramTiles];
+#pragma unroll
+    for (int s2 = 0; s2 < kDualGramTiles; ++s2) acc[s2] = dbl4{0.0, 0.0, 0.0, 0.0};
+    double *sv = stage, *sw = stage + R * ld;
+    for (int64_t base = r0; base < r1; base += R) {  // uniform across the workgroup
+        const int rows = r1 - base < R ? (int)(r1 - base) : R;
+        const int lr = wv * rpw + grp;  // this lane's row within the pass
+        const int64_t row = base + lr;
+        const bool active = grp < rpw && lr < rows;
+        Vec<double, CPT> wa = zero_v<double, CPT>(), wm = zero_v<double, CPT>();
+        gather_wave<double, CPT>(row, sub, tpr, active, n, ptr, col, V, ld, c0,
+                                 [&](int32_t p) { return double2{a[p], m[p]}; },
+                                 [&](const double2 &am, int64_t, const Vec<double, CPT> &v) {
+                                     fma_v(wa, am.x, v);
+                                     fma_v(wm, am.y, v);
+                                 });
+        Vec<double, CPT> vi = zero_v<double, CPT>();
+        if (active) {
+            stv<double, CPT>(W + row * l2 + c0, wa);
+            stv<double, CPT>(W + row * l2 + ld + c0, wm);
+            vi = ldv<double, CPT>(V + row * ld + c0);
+        }
+        __syncthreads();  // the previous pass's products are done with the stage
+        if (active) {
+            stv<double, CPT>(sv + lr * ld + c0, vi);
+            stv<double, CPT>(sw + lr * l2 + c0, wa);
+            stv<double, CPT>(sw + lr * l2 + ld + c0, wm);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < kDualGramTiles; ++s2) {
+            if (wv + s2 * nw < ntiles) {  // wave-uniform
+                int off, ta, tb;
+                tile(wv + s2 * nw, off, ta, tb);
+                const int ca = 16 * ta + c, cb = 16 * tb + c;
+                for (int k0 = 0; k0 < R; k0 += 4) {
+                    const int rr = k0 + kk;
+                    const double x = (ca < ld && rr < rows) ? sv[rr * ld + ca] : 0.0;
+                    const double y = (cb < ld && rr < rows) ? sw[rr * l2 + off + cb] : 0.0;
+                    acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[s2], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < kDualGramTiles; ++s2) {
+        if (wv + s2 * nw < ntiles) {
+            int off, ta, tb;
+            tile(wv + s2 * nw, off, ta, tb);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = 16 * ta + (lane >> 4) + 4 * u, j = 16 * tb + (lane & 15);
+                if (i < ld && j < ld) part[lb * outsz + i * l2 + off + j] = acc[s2][u];
+            }
+        }
+    }
+}
+
 // Phase 2: G[e] = sum over blocks of part[b][e]; one wavefront per element,
 // lane l sums blocks l, l+64, ..., then a fixed butterfly over the lanes.
 __global__ __launch_bounds__(256) void k_gram_reduce(int64_t nb, int outsz, int ld, int sym,
@@ -1213,6 +1313,26 @@ void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double
         hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, ld,
                        wide ? 1 : 0, part, G, status);
+}
+
+bool dual_gram_fused(int ld) { return (ld + 15) / 16 * ((2 * ld + 15) / 16) > 8; }  // the wide Gram layout
+
+void launch_dual_gram(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                      const double *m, const double *V, double *W, double *part, const int *status, int cpt) {
+    const int64_t nb = gram_blocks(n, ld);
+    DISPATCH_CPT(ld, cpt, {
+        const int rows = kDualGramWaves * (kWave / (ld / CPT));
+        KLAUNCH((k_dual_gram<CPT>), dim3((unsigned)nb), dim3(kDualGramWaves * kWave),
+                (size_t)rows * 3 * ld * sizeof(double), s,
+                n, ld, ptr, col, a, m, V, W, part, status);
+    });
+}
+
+void launch_gram_reduce(hipStream_t s, int64_t n, int ld, const double *part, double *G, const int *status) {
+    const int64_t nb = gram_blocks(n, ld);
+    const int outsz = 2 * ld * ld;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, ld,
+                       dual_gram_fused(ld) ? 1 : 0, part, G, status);
 }
 
 void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *val,
