@@ -16,6 +16,7 @@
 //                   the FP64 block V = U + x as rows finish)
 //   k_dual_spmm     W = [A V | M V] (FP64, shared pattern)
 //   k_gram          [V^T A V | V^T M V] by a two-phase deterministic reduction
+//   k_dual_gram     both of the above in one pass over the rows (wide blocks)
 //   k_final         U = P Y + V X_v on the correction level (recombination)
 #include <algorithm>
 
@@ -723,107 +724,6 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int ld, const double *_
     }
 }
 
-// Phase 1 for wide blocks (more than 8 tiles of the ld x 2ld result): the
-// workgroup stages kGramRows rows of V and W at a time in LDS (coalesced loads
-// by all threads).  V^T A V and V^T M V are symmetric, so only the 16 x 16
-// tiles on and above the diagonal of each (two grids of ti (ti + 1) / 2 tiles,
-// ti = ceil(ld / 16)) are accumulated; they are dealt round-robin to the four
-// wavefronts, which accumulate them from LDS and finally write them to
-// part[b].  The reduction fills the entries below the diagonals from their
-// mirror images.
-constexpr int kGramTilesPerWave = 8;  // covers ld <= 80 (2 x 15 tiles)
-constexpr int kGramRows = 32;
-
-__global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const double *__restrict__ V,
-                                                   const double *__restrict__ W, double *__restrict__ part,
-                                                   const int *status) {
-    extern __shared__ double stage[];  // kGramRows x ld, then kGramRows x 2 ld
-    if (status[ST_CONVERGED]) return;
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    const int64_t nb = gridDim.x, lb = xcd_block();
-    const int64_t r0 = n * lb / nb, r1 = n * (lb + 1) / nb;
-    const int l2 = 2 * ld, ti = (ld + 15) / 16, tu = ti * (ti + 1) / 2, ntiles = 2 * tu;
-    const int outsz = ld * l2;
-    const int kk = lane >> 4, c = lane & 15;
-    // tile s2 of this wavefront: grid half (A or M part), row tile, column tile >= row tile
-    int t_off[kGramTilesPerWave], t_a[kGramTilesPerWave], t_b[kGramTilesPerWave];
-#pragma unroll
-    for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
-        const int t = wv + s2 * nw, h = t < tu ? 0 : 1;
-        int u = t - h * tu, ta = 0;
-        while (ta < ti && u >= ti - ta) {
-            u -= ti - ta;
-            ++ta;
-        }
-        t_off[s2] = h * ld;
-        t_a[s2] = ta;
-        t_b[s2] = ta + u;
-    }
-    dbl4 acc[kGramTilesPerWave];
-#pragma unroll
-    for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) acc[s2] = dbl4{0.0, 0.0, 0.0, 0.0};
-    double *sv = stage, *sw = stage + kGramRows * ld;  // rows of V, then the same rows of W
-    // a chunk's rows of V and W (contiguous) are staged with all of a thread's
-    // double2 loads issued before its first store, so the whole chunk is in
-    // flight at once (ld <= kMaxWidth, ld even)
-    constexpr int kPre = kGramRows * 3 * kMaxWidth / 2 / 256;
-    auto chunk_rows = [&](int64_t base) -> int { return r1 - base < kGramRows ? (int)(r1 - base) : kGramRows; };
-    double2 pre[kPre];
-    auto fetch = [&](int64_t base) {
-        const int rows = chunk_rows(base), nv = rows * ld / 2, nt = nv + rows * l2 / 2;
-        const double2 *v2 = reinterpret_cast<const double2 *>(V + base * ld);
-        const double2 *w2 = reinterpret_cast<const double2 *>(W + base * l2);
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int e = threadIdx.x + i * 256;
-            pre[i] = e < nv ? v2[e] : (e < nt ? w2[e - nv] : make_double2(0.0, 0.0));
-        }
-    };
-    auto put = [&](int64_t base) {
-        const int rows = chunk_rows(base), nv = rows * ld / 2, nt = nv + rows * l2 / 2;
-        double2 *v2 = reinterpret_cast<double2 *>(sv);
-        double2 *w2 = reinterpret_cast<double2 *>(sw);
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int e = threadIdx.x + i * 256;
-            if (e < nv)
-                v2[e] = pre[i];
-            else if (e < nt)
-                w2[e - nv] = pre[i];
-        }
-    };
-    for (int64_t base = r0; base < r1; base += kGramRows) {
-        const int rows = chunk_rows(base);
-        fetch(base);
-        __syncthreads();  // the previous chunk is consumed
-        put(base);
-        __syncthreads();
-#pragma unroll
-        for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
-            if (wv + s2 * nw < ntiles) {  // wave-uniform
-                const int ca = 16 * t_a[s2] + c, cb = 16 * t_b[s2] + c, off = t_off[s2];
-#pragma unroll 4
-                for (int k0 = 0; k0 < kGramRows; k0 += 4) {
-                    const int rr = k0 + kk;
-                    double x = (ca < ld && rr < rows) ? sv[rr * ld + ca] : 0.0;
-                    double y = (cb < ld && rr < rows) ? sw[rr * l2 + off + cb] : 0.0;
-                    acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[s2], 0, 0, 0);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int s2 = 0; s2 < kGramTilesPerWave; ++s2) {
-        if (wv + s2 * nw < ntiles) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = 16 * t_a[s2] + (lane >> 4) + 4 * u, j = 16 * t_b[s2] + (lane & 15);
-                if (i < ld && j < ld) part[lb * outsz + i * l2 + t_off[s2] + j] = acc[s2][u];
-            }
-        }
-    }
-}
-
 // W = [A V | M V] and phase 1 of [V^T A V | V^T M V] = V^T W for wide blocks
 // in one pass over the rows, so that V and W leave memory once for both
 // products.  Workgroup b (eight wavefronts) walks the contiguous rows
@@ -832,13 +732,15 @@ __global__ __launch_bounds__(256) void k_gram_wide(int64_t n, int ld, const doub
 // over idle) and writes them out; the pass's rows of W and of V are staged in
 // LDS (at most 98 KB for ld <= 80), and the 16 x 16 tiles on and above the
 // diagonals of V^T A V and V^T M V are accumulated from there on the FP64
-// matrix cores, at most four per wavefront, dealt as in k_gram_wide, whose
-// partial layout (and reduction) this shares.  Eight wavefronts per
-// workgroup keep enough rows' gathers in flight between the barriers of a pass.
+// matrix cores, at most four per wavefront, and written to part[b] (k_gram_reduce
+// fills the entries below the diagonals from their mirror images).  Eight
+// wavefronts per workgroup, four per SIMD, keep enough rows' gathers in flight
+// between the barriers of a pass.
 constexpr int kDualGramWaves = 8;
 constexpr int kDualGramTiles = (30 + kDualGramWaves - 1) / kDualGramWaves;  // tiles per wavefront, ld <= 80
 template <int CPT>
-__global__ __launch_bounds__(kDualGramWaves * kWave) __attribute__((amdgpu_waves_per_eu(CPT == 8 ? 2 : 4))) void k_dual_gram(int64_t n, int ld, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(kDualGramWaves * kWave) __attribute__((amdgpu_waves_per_eu(CPT == 8 ? 2 : 4)))
+void k_dual_gram(int64_t n, int ld, const int32_t *__restrict__ ptr,
                                                    const int32_t *__restrict__ col, const double *__restrict__ a,
                                                    const double *__restrict__ m, const double *__restrict__ V,
                                                    double *__restrict__ W, double *__restrict__ part,
@@ -1300,19 +1202,14 @@ int64_t gram_blocks(int64_t n, int ld) {  // about 64 rows per wavefront, at mos
     return nb < 1024 ? (nb < 1 ? 1 : nb) : 1024;
 }
 
+// narrow blocks (ld <= 32); wider ones take launch_dual_gram
 void launch_gram(hipStream_t s, int64_t n, int ld, const double *V, const double *W, double *part, double *G,
                  const int *status) {
     const int64_t nb = gram_blocks(n, ld);
     const int outsz = 2 * ld * ld;
-    const int ti = (ld + 15) / 16;
-    const bool wide = ti * ((2 * ld + 15) / 16) > 8;  // ld > 32; 2 ti (ti + 1) / 2 <= 30 tiles for ld <= 80
-    if (wide)
-        hipLaunchKernelGGL(k_gram_wide, dim3((unsigned)nb), dim3(kBlock),
-                           (size_t)kGramRows * 3 * ld * sizeof(double), s, n, ld, V, W, part, status);
-    else
-        hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, ld,
-                       wide ? 1 : 0, part, G, status);
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)nb), dim3(kBlock), 0, s, n, ld, V, W, part, status);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((outsz + 3) / 4)), dim3(256), 0, s, nb, outsz, ld, 0, part, G,
+                       status);
 }
 
 bool dual_gram_fused(int ld) { return (ld + 15) / 16 * ((2 * ld + 15) / 16) > 8; }  // the wide Gram layout
