@@ -407,6 +407,24 @@ def timed_solves(ctx, steps, tol, timing):
     return time.perf_counter() - t0, lat, corr
 
 
+# A lower bound of lambda_1 from the continuous problem, where one is useful:
+# conforming P1 eigenvalues bound those of the operator from above, and the
+# Dirichlet eigenvalues of -Lap + |x|^2 on a square bound those of the whole
+# plane, whose smallest is 2.  The unit square's 2 pi^2 is exact but its solves
+# take a handful of corrections; for the L-shape and the checkerboard cube the
+# available bounds (a containing square, the smaller coefficient) lie far
+# below lambda_1.
+LAMBDA1_LOWER = {4: 2.0}
+
+
+def bench_shift(args):
+    if args.shift == "none":
+        return 0.0
+    if args.shift == "bound":
+        return 0.9 * LAMBDA1_LOWER.get(args.config, 0.0)
+    return float(args.shift)
+
+
 def prepared_context(p, wl, prec, args, stream):
     """Set up and bind a context, run `warmup` untimed solves (the first one
     also settles the block width), then choose the launch shapes."""
@@ -416,7 +434,7 @@ def prepared_context(p, wl, prec, args, stream):
     t0 = time.perf_counter()
     ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"],
                      ae.defaults(coarse_max=wl["coarse_max"], qe=args.qe, precision=prec, use_graph=args.graph,
-                                 smoother=smoother, cheb_degree=2, cheb_lo=0.25, shift_frac=args.shift_frac))
+                                 smoother=smoother, cheb_degree=2, cheb_lo=0.25, shift=bench_shift(args)))
     setup_s = time.perf_counter() - t0
     ctx.bind(stream=stream)
     for _ in range(max(1, args.warmup)):
@@ -455,9 +473,10 @@ def main():
                     help="choose the row kernels' columns per lane by timing (on-disk cache) before the timed region")
     ap.add_argument("--smoother", default="chebyshev", choices=["l1jacobi", "chebyshev", "gs"],
                     help="gs: multicolour Gauss-Seidel, forward before and backward after the coarse correction")
-    ap.add_argument("--shift-frac", type=float, default=0.9,
-                    help="shifted correction equation: sigma = this fraction of the coarsest level's smallest "
-                         "eigenvalue (0: no shift)")
+    ap.add_argument("--shift", default="bound",
+                    help="shifted correction equation: 'bound' (0.9 of the lower bound of lambda_1 the continuous "
+                         "problem gives, where it gives a useful one: the oscillator; none otherwise), 'none', or "
+                         "sigma itself")
     ap.add_argument("--requests", type=int, default=24, help="serving stream (config 5): number of requests")
     ap.add_argument("--n-hi", type=int, default=150_000, help="serving stream: largest N drawn")
     ap.add_argument("--budget-gb", type=float, default=8.0,
@@ -606,8 +625,8 @@ def main():
                    "qe": info["qe"], "levels": info["dims"].tolist(), "precision": args.precision, "tol": args.tol,
                    "smoother": {"l1jacobi": "l1-jacobi", "chebyshev": "chebyshev degree 2 on [0.25, 1]",
                                 "gs": "multicolour gauss-seidel"}[args.smoother] + " V(1,1)"
-                               + (", shift %.2f lambda_1 of the coarsest level" % args.shift_frac
-                                  if args.shift_frac else ""), "start": "nested (Algorithm 3.2)",
+                               + (", shift sigma = %g" % bench_shift(args) if bench_shift(args) else ""),
+                   "start": "nested (Algorithm 3.2)",
                    "steps_launch": ("captured hipGraph replays; the second step of each enqueued chunk of three "
                                     "or more eager and event-timed" if args.graph else "eager")},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),

@@ -98,11 +98,11 @@ typedef struct {
     double shift;       /* Remark 3.1 shift sigma of the linear equation of Algorithm 3.1:
                            (A_k - sigma M_k) u~ = (lambda - sigma) M_k u, solved by the V-cycle
                            of A_k - sigma M_k on every level (coarsest: A_n - sigma M_n).  Must
-                           lie below the smallest eigenvalue; setup rejects (EINVAL) a shift not
-                           below the coarsest level's smallest eigenvalue, which bounds it from
-                           above, or one that leaves a level's diagonal a_ii - sigma m_ii <= 0 */
-    double shift_frac;  /* if > 0 (and < 1), sigma = shift_frac * that coarsest eigenvalue, and
-                           shift must be 0 */
+                           lie below the smallest eigenvalue lambda_1, e.g. a lower bound the
+                           continuous problem gives.  The library cannot verify that: setup
+                           rejects (EINVAL) only a shift not below the coarsest level's smallest
+                           eigenvalue, an upper bound of lambda_1 that can exceed it by a large
+                           factor, or one that leaves a level's diagonal a_ii - sigma m_ii <= 0 */
 } amg_eig_opts;
 
 /* Paper defaults (Section 4.1: theta = 0.25, one V-cycle with one pre- and

@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
         ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("precision", ctypes.c_int),
         ("tol", ctypes.c_double), ("max_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
         ("qe_max", ctypes.c_int),
-        ("shift", ctypes.c_double), ("shift_frac", ctypes.c_double),
+        ("shift", ctypes.c_double),
     ]
 
 

@@ -1067,7 +1067,6 @@ void amg_eig_opts_default(amg_eig_opts *o) {
     o->use_graph = 0;
     o->qe_max = 0;
     o->shift = 0.0;
-    o->shift_frac = 0.0;
 }
 
 int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o, amg_eig_ctx **out) {

@@ -542,12 +542,11 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
     H.dn = dn;
     // shift of the linear equation (Remark 3.1): below the smallest coarsest
     // eigenvalue, an upper bound of the smallest eigenvalue of every level
-    if (!std::isfinite(o.shift) || !(o.shift_frac >= 0.0 && o.shift_frac < 1.0) ||
-        (o.shift != 0.0 && o.shift_frac != 0.0)) {
-        err = "shift must be finite, shift_frac in [0, 1), not both set";
+    if (!std::isfinite(o.shift)) {
+        err = "shift must be finite";
         return AMG_EIG_EINVAL;
     }
-    H.sigma = o.shift_frac > 0.0 ? o.shift_frac * H.lam[0] : o.shift;
+    H.sigma = o.shift;
     if (!(H.sigma < H.lam[0])) {
         err = "shift not below the smallest eigenvalue of the coarsest level";
         return AMG_EIG_EINVAL;

@@ -91,8 +91,7 @@ def test_shift_options():
     A, M = mats(p)
     o0 = Oracle(A, M, q=6, qe=8, coarse_max=150, coarse_min=26)
     lam1 = o0.lam_n[0]
-    for kw in (dict(shift=1.001 * lam1), dict(shift_frac=1.0), dict(shift_frac=-0.1),
-               dict(shift=0.1, shift_frac=0.5), dict(shift=float("nan"))):
+    for kw in (dict(shift=1.001 * lam1), dict(shift=float("nan")), dict(shift=float("inf"))):
         with pytest.raises(ae.AmgEigError) as e:
             ae.Context(p["rowptr"], p["col"], p["A"], p["M"], 6, ae.defaults(coarse_max=150, qe=8, **kw))
         assert e.value.code == ae.EINVAL, kw
