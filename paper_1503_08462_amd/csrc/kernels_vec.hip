@@ -876,79 +876,46 @@ __global__ __launch_bounds__(256) void k_final_rows(int64_t n, int ld, const int
     stv<double, CPT>(U + rm.row * ld + c0, acc);
 }
 
-// Wide blocks: U = P Y + V X_v on the correction level.  A workgroup (eight
-// wavefronts) stages X_v in LDS once, then walks its blocks of kFinalRows
-// consecutive rows: all its threads load the next block's rows of V
-// (contiguous in memory, coalesced 16-byte loads) into registers while the
-// current block's products run, and store them to LDS after it; each
-// wavefront takes 16 of the rows: V X_v as
-// 16 x 16 tiles on the FP64 matrix cores with both operands from LDS (each
-// row of V is read from memory once, whatever the number of column tiles),
-// then each lane adds the prolongation P Y for its four (row, column) entries
-// of the tile and writes them.  The first kPRow entries of the lane's four
-// rows of P are held in registers across the column tiles, so that a tile's
-// gathers of Y are independent loads issued together.
+// Wide blocks: U = P Y + V X_v on the correction level.  Each wavefront owns
+// 16 consecutive rows at a time and holds their V rows in registers, already
+// in the matrix cores' operand layout (lane l: row l mod 16, columns 4s + l / 16),
+// so V is read once whatever the number of column tiles; X_v is staged once
+// per workgroup in LDS (ld x ld) and supplies the other operand.  Per 16 x 16
+// column tile each lane then adds P Y for its four (row, column) entries: the
+// first kPRow entries of its four rows of P are held in registers across the
+// tiles, so a tile's gathers of Y are independent loads issued together.  No
+// barrier after the staging of X_v; LDS of 51 KB at ld = 80 leaves room for
+// three workgroups per CU.
 constexpr int kPRow = 4;
-constexpr int kFinalRows = 128;  // 16 rows per wavefront, eight wavefronts per workgroup
-constexpr int kFinalThreads = 512;
-__global__ __launch_bounds__(kFinalThreads) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
+constexpr int kFinalWaves = 4;
+__global__ __launch_bounds__(kFinalWaves * kWave) void k_final(int64_t n, int ld, const int32_t *__restrict__ ptr,
                                                const int32_t *__restrict__ col, const double *__restrict__ val,
                                                const double *__restrict__ Y, const double *__restrict__ V,
                                                const double *__restrict__ Xv, double *__restrict__ U,
                                                const int *status) {
-    extern __shared__ double sm[];
-    double *xv = sm;            // ld x ld
-    double *vt = sm + ld * ld;  // kFinalRows x ld: the rows of V of the current block
+    extern __shared__ double xv[];  // ld x ld
     if (status[ST_CONVERGED]) return;
     for (int e = threadIdx.x; e < ld * ld; e += blockDim.x) xv[e] = Xv[e];
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int c = lane & 15, kk = lane >> 4;
-    const int tj = (ld + 15) / 16;
-    // workgroup b owns a contiguous range of row blocks: neighbouring fine
-    // rows, whose prolongation reads the same coarse rows of Y, run on the
-    // same CU close together in time
-    const int64_t blocks = (n + kFinalRows - 1) / kFinalRows, nbk = gridDim.x, lb = xcd_block();
-    const int64_t b0 = blocks * lb / nbk, b1 = blocks * (lb + 1) / nbk;
-    // the next block's rows of V are loaded into registers while this block's
-    // products run, and stored to LDS once every wavefront is done with it
-    // (ld <= kMaxWidth, ld even: kPre double2 per thread hold a block)
-    constexpr int kPre = kFinalRows * kMaxWidth / 2 / kFinalThreads;
-    const double2 *V2 = reinterpret_cast<const double2 *>(V);
-    double2 *vt2 = reinterpret_cast<double2 *>(vt);
-    double2 pre[kPre];
-    auto block_rows = [&](int64_t blk) -> int {
-        const int64_t base = blk * kFinalRows;
-        return n - base < kFinalRows ? (int)(n - base) : kFinalRows;
-    };
-    auto fetch = [&](int64_t blk) {
-        const int n2 = block_rows(blk) * ld / 2;
-        const double2 *src = V2 + blk * kFinalRows * ld / 2;
+    const int tj = (ld + 15) / 16, ks = ld / 4;  // ld is a multiple of 4
+    // the wavefronts of workgroup b take the row tiles [T b / nb, T (b+1) / nb)
+    // in turn: neighbouring fine rows, whose prolongation reads the same coarse
+    // rows of Y, run on the same CU close together in time
+    const int64_t tiles = (n + 15) / 16, nbk = gridDim.x, lb = xcd_block();
+    const int64_t t0 = tiles * lb / nbk, t1 = tiles * (lb + 1) / nbk;
+    for (int64_t t = t0 + wv; t < t1; t += kFinalWaves) {
+        const int64_t r0 = t * 16;
+        // V rows of the tile, operand layout; rows past n read as zeros
+        double a[kMaxWidth / 4];
+        {
+            const int64_t rr = r0 + c;
+            const bool ok = rr < n;
+            const double *vr = V + (ok ? rr : 0) * ld + kk;
 #pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int e = threadIdx.x + i * kFinalThreads;
-            pre[i] = e < n2 ? src[e] : make_double2(0.0, 0.0);
+            for (int s2 = 0; s2 < kMaxWidth / 4; ++s2) a[s2] = (ok && s2 < ks) ? vr[4 * s2] : 0.0;
         }
-    };
-    auto put = [&](int64_t blk) {
-        const int n2 = block_rows(blk) * ld / 2;
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-            const int e = threadIdx.x + i * kFinalThreads;
-            if (e < n2) vt2[e] = pre[i];
-        }
-    };
-    if (b0 < b1) {
-        fetch(b0);
-        put(b0);
-    }
-    __syncthreads();  // X_v and the first block staged
-    for (int64_t blk = b0; blk < b1; ++blk) {
-        if (blk + 1 < b1) fetch(blk + 1);
-        const int64_t base = blk * kFinalRows;
-        const int rows = block_rows(blk);
-        const int w0 = 16 * wv;  // this wavefront's first row in the block
-        if (w0 < rows) {         // wave-uniform; every wavefront reaches the barriers below
-        const int64_t r0 = base + w0;
         int32_t pb[4], pe[4], pc[4][kPRow];
         double pv[4][kPRow];
 #pragma unroll
@@ -960,10 +927,10 @@ __global__ __launch_bounds__(kFinalThreads) void k_final(int64_t n, int ld, cons
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int t = 0; t < kPRow; ++t) {
-                const bool ok = pb[u] + t < pe[u];
-                pc[u][t] = ok ? col[pb[u] + t] : 0;  // padding reads row 0 of Y with weight 0
-                pv[u][t] = ok ? val[pb[u] + t] : 0.0;
+            for (int q = 0; q < kPRow; ++q) {
+                const bool ok = pb[u] + q < pe[u];
+                pc[u][q] = ok ? col[pb[u] + q] : 0;  // padding reads row 0 of Y with weight 0
+                pv[u][q] = ok ? val[pb[u] + q] : 0.0;
             }
         for (int tb = 0; tb < tj; ++tb) {
             const int j = 16 * tb + c;
@@ -972,32 +939,28 @@ __global__ __launch_bounds__(kFinalThreads) void k_final(int64_t n, int ld, cons
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int t = 0; t < kPRow; ++t) yv[u][t] = Y[(int64_t)pc[u][t] * ld + jc];
-            const dbl4 acc = mfma_tn16([&](int k, int cc) -> double {
-                                           return w0 + cc < rows ? vt[(w0 + cc) * ld + k] : 0.0;
-                                       },
-                                       [&](int k, int cc) -> double {
-                                           const int jj = 16 * tb + cc;
-                                           return jj < ld ? xv[k * ld + jj] : 0.0;
-                                       },
-                                       ld);
+                for (int q = 0; q < kPRow; ++q) yv[u][q] = Y[(int64_t)pc[u][q] * ld + jc];
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < kMaxWidth / 4; ++s2) {
+                if (s2 < ks) {
+                    const double b = j < ld ? xv[(4 * s2 + kk) * ld + j] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], b, acc, 0, 0, 0);
+                }
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t row = r0 + kk + 4 * u;
                 if (row < n && j < ld) {
                     double v = acc[u];
 #pragma unroll
-                    for (int t = 0; t < kPRow; ++t)
-                        if (pb[u] + t < pe[u]) v += pv[u][t] * yv[u][t];
-                    for (int32_t p = pb[u] + kPRow; p < pe[u]; ++p) v += val[p] * Y[(int64_t)col[p] * ld + j];
+                    for (int q = 0; q < kPRow; ++q)
+                        if (pb[u] + q < pe[u]) v += pv[u][q] * yv[u][q];
+                    for (int32_t pp = pb[u] + kPRow; pp < pe[u]; ++pp) v += val[pp] * Y[(int64_t)col[pp] * ld + j];
                     U[row * ld + j] = v;
                 }
             }
         }
-        }
-        __syncthreads();  // every wavefront is done with this block's rows of V
-        if (blk + 1 < b1) put(blk + 1);
-        __syncthreads();
     }
 }
 
@@ -1240,13 +1203,13 @@ void launch_final(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const in
                                             Y, V, Xv, U, status));
         return;
     }
-    // workgroups: each owns a contiguous range of 128-row blocks; LDS holds X_v
-    // and one block of V rows (107 KB at ld = 68, 133 KB at ld = 80: one
-    // workgroup of eight wavefronts per CU)
-    const int64_t blocks = (n + kFinalRows - 1) / kFinalRows;
-    const int64_t nb = blocks < 1024 ? blocks : 1024;
-    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kFinalThreads), (size_t)(ld * ld + kFinalRows * ld) * sizeof(double), s,
-            n, ld, ptr, col, val, Y, V, Xv, U, status);
+    // workgroups of four wavefronts, each owning a contiguous range of 16-row
+    // tiles; LDS holds X_v only
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t want = (tiles + kFinalWaves * 32 - 1) / (kFinalWaves * 32);  // about 32 tiles per wavefront
+    const int64_t nb = want < 1 ? 1 : (want > 2048 ? 2048 : want);
+    KLAUNCH(k_final, dim3((unsigned)nb), dim3(kFinalWaves * kWave), (size_t)ld * ld * sizeof(double), s, n, ld, ptr,
+            col, val, Y, V, Xv, U, status);
 }
 
 template <typename T>
