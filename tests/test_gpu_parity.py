@@ -79,7 +79,7 @@ def oracle_solve(o, tol, max_steps=400):
 
 
 def test_random_start_and_step_parity_config0():
-    """Config 1 of the benchmark set (N = 961, q = 4, seed 1): the device start
+    """The unit square with 31 x 31 interior points (N = 961, q = 4, seed 1): the device start
     block is the same SplitMix64 stream the oracle draws; Rayleigh-Ritz of the
     start and each of the first corrections agree step by step.  The width is
     fixed at q_e = q = 4 (with l1-Jacobi smoothing this block converges slower
