@@ -38,10 +38,13 @@ def _solve(p, prec, qe, force=None, tune_path=None):
     return lam, ok, pr["steps"], rep
 
 
+# q_e = 8 takes the narrow kernels; q_e = 40 the wide ones (the dual SpMM fused
+# with the Gram products, whose pass of rows grows from 24 to 96 with the
+# columns per lane while the Gram sums keep their order)
+@pytest.mark.parametrize("qe", [8, 40])
 @pytest.mark.parametrize("prec", [ae.PREC_FP64, ae.PREC_MIXED], ids=["fp64", "mixed"])
-def test_launch_shape_does_not_change_results(prec, tmp_path):
+def test_launch_shape_does_not_change_results(prec, qe, tmp_path):
     p = configs.lshape(24, q=6, jitter_seed=2)
-    qe = 8
     _say("launch shapes, L-shape N=%d, qe=%d, prec=%d" % (p["n"], qe, prec))
     ref, ok, steps, _ = _solve(p, prec, qe)
     assert ok
