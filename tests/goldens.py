@@ -28,6 +28,17 @@ def paper_table2():
     return out
 
 
+def paper_table3():
+    """{q: (lambda_q, lambda_q / lambda_{q+1} or None)} as printed in Table 3
+    (Example 3); None where the table leaves the ratio blank."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, "paper_table3.txt")):
+        if line.strip() and not line.startswith("#"):
+            q, lam, r = line.split()
+            out[int(q)] = (float(lam), None if r == "-" else float(r))
+    return out
+
+
 def oracle_eigenvalues(name):
     """(theta[qe], rho[qe], header lines) of tests/golden/oracle_<name>.txt, or
     None when that file has not been written."""

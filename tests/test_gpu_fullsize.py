@@ -24,7 +24,9 @@ import scipy.sparse as sp
 import paper_1503_08462_amd as ae
 from workloads import configs
 from tests.goldens import oracle_eigenvalues, paper_table1_ratios
-from tests.test_paper_tables import TABLE2_RATIO_TOL, TABLE2_SCALE_SPREAD_TOL, TABLE2_SCALE_TOL, table2_differences
+from tests.test_paper_tables import (EX3_ORACLE_TOL, STORED_RHO_EX3, TABLE2_RATIO_TOL, TABLE2_SCALE_SPREAD_TOL, TABLE2_SCALE_TOL,
+                                     TABLE3_RATIO_TOL, TABLE3_SCALE_SPREAD_TOL, TABLE3_SCALE_TOL, table2_differences,
+                                     table3_differences)
 
 pytestmark = pytest.mark.gpu
 
@@ -64,12 +66,12 @@ def _check_pairs(p, lam, U, tol):
     assert np.abs(G - np.eye(G.shape[0])).max() < 1e-9
 
 
-def _golden(name, q):
+def _golden(name, q, rho_max=2e-9):
     g = oracle_eigenvalues(name)
     if g is None:
         pytest.skip("tests/golden/oracle_%s.txt not written" % name)
     th, rho, head = g
-    assert rho[:q].max() <= 2e-9, "stored oracle run not converged"
+    assert rho[:q].max() <= rho_max, "stored oracle run not converged"
     return th[:q]
 
 
@@ -102,6 +104,25 @@ def test_paper_example2_full_size_table2():
     _say("Table 2: eigenvalue scale 1 %+.2e (spread %.1e), largest ratio difference %.2e" % (scale, spread, ratio_err))
     assert spread < TABLE2_SCALE_SPREAD_TOL and abs(scale) < TABLE2_SCALE_TOL
     assert ratio_err < TABLE2_RATIO_TOL
+
+
+def test_paper_example3_full_size_table3():
+    """Example 3 (K = 1e3 / 1e-3 / 1 by quadrant of (-1,1)^2, h = 1/1024): the
+    FP64 solve to the residual floor of its 1e6 contrast (rho <= 2e-6) against
+    the stored oracle run and Table 3."""
+    p = configs.quadrants(1024, q=31)
+    _say("Example 3 full size, N = %d, FP64, q = 31, q_e = 40" % p["n"])
+    lam, ok, pr, U = _solve(p, ae.PREC_FP64, 512, 40, STORED_RHO_EX3)
+    assert ok, pr
+    _check_pairs(p, lam, U, STORED_RHO_EX3)
+    ref = _golden("ex3_quadrants1024", 31, STORED_RHO_EX3)
+    err = np.abs(lam / ref - 1).max()
+    _say("max relative difference from the oracle %.2e" % err)
+    assert err < EX3_ORACLE_TOL
+    spread, scale, ratio_err = table3_differences(lam)
+    _say("Table 3: eigenvalue scale 1 %+.2e (spread %.1e), largest ratio difference %.2e" % (scale, spread, ratio_err))
+    assert spread < TABLE3_SCALE_SPREAD_TOL and abs(scale) < TABLE3_SCALE_TOL
+    assert ratio_err < TABLE3_RATIO_TOL
 
 
 @pytest.mark.parametrize("prec", [ae.PREC_MIXED, ae.PREC_FP64], ids=["mixed", "fp64"])
