@@ -21,9 +21,10 @@
  *     of the last failure on a context;
  *   - no C++ exception crosses this interface;
  *   - host arrays passed in are borrowed for the duration of the call only;
- *   - device memory is owned by the caller: the library never allocates or
+ *   - device memory is owned by the caller: the solver never allocates or
  *     frees device memory; it carves everything from the workspace given to
- *     amg_eig_bind();
+ *     amg_eig_bind() (the one exception is the standalone setup routine
+ *     amg_eig_galerkin(), which allocates and frees its own temporaries);
  *   - all device work of a context is enqueued on the stream given to
  *     amg_eig_bind(); only amg_eig_progress() and amg_eig_solve() wait on it;
  *   - one host thread at a time per context; contexts are independent.
@@ -131,6 +132,34 @@ typedef struct amg_eig_ctx amg_eig_ctx;
  * A_n not positive definite), ENOMEM.  *out is NULL on error. */
 int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o,
                   amg_eig_ctx **out);
+
+/* Galerkin coarse operators on the device (Section 2, eq. (2.5)):
+ * C_A = P^T A P and C_M = P^T M P for one prolongation P (n x nc, eqs.
+ * (2.2)-(2.4)), A and M given on one pattern.  Standalone: no context.
+ * Inputs, all device memory, borrowed for the call:
+ *   x_ptr[n+1] (int64), x_col[x_ptr[n]] (int32, in [0,n)), x_a, x_m: A and M
+ *     on their shared CSR pattern;
+ *   p_ptr[n+1], p_col (in [0,nc)), p_val: P in CSR;
+ *   pt_ptr[nc+1], pt_col (in [0,n)), pt_val: P^T in CSR, each row's columns
+ *     ascending.
+ * Outputs, device memory owned by the caller: c_ptr[nc+1] (int64) always; when
+ * the result fits (nnz <= cap), c_col[cap] (int32, ascending within a row)
+ * and c_a[cap], c_m[cap] (FP64).  *nnz (host) receives the result's nonzero
+ * count, so a call with cap = 0 and null c_col/c_a/c_m sizes the outputs.
+ * Each output entry is accumulated in the order its contributions arise (left
+ * factor's entries in storage order, then the right factor's), products and
+ * sums rounded separately: the same bits as the host setup's coarse levels.
+ * Column indices are not range-checked on the device.  Allocates and frees
+ * temporary device memory (about 20 bytes per product of T = A P and of
+ * P^T T) and waits for the stream (hipStream_t, NULL for the null stream).
+ * Column and value arrays may be null where they hold no entries.
+ * Errors: EINVAL (negative sizes, a null row-pointer or c_ptr array, cap > 0
+ * with null outputs),
+ * EWORKSPACE (nnz > cap: c_ptr and *nnz written, nothing else), EHIP. */
+int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
+                     const double *x_m, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
+                     const int64_t *pt_ptr, const int32_t *pt_col, const double *pt_val, int64_t *c_ptr,
+                     int32_t *c_col, double *c_a, double *c_m, int64_t cap, int64_t *nnz, void *hip_stream);
 
 /* Device bytes needed by amg_eig_bind(). */
 int amg_eig_footprint(const amg_eig_ctx *c, size_t *device_bytes);

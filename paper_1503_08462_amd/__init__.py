@@ -37,7 +37,7 @@ EXPORTED = [
     "amg_eig_level_matrix", "amg_eig_level_prolongation", "amg_eig_level_splitting", "amg_eig_level_colouring",
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
-    "amg_eig_tune_time", "amg_eig_bind_static",
+    "amg_eig_tune_time", "amg_eig_bind_static", "amg_eig_galerkin",
 ]
 TUNE_VCYCLE, TUNE_FP64, TUNE_FP64_WIDE = 0, 1, 2
 SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
@@ -89,6 +89,7 @@ _sig = {
     "amg_eig_set_cpt": (_i, [_vp, _i, _i, _i]),
     "amg_eig_get_cpt": (_i, [_vp, _i, _i, _vp]),
     "amg_eig_tune_time": (_i, [_vp, _i, _i, _i, _i, _vp]),
+    "amg_eig_galerkin": (_i, [_i64, _i64] + [_vp] * 14 + [_i64, _vp, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -318,6 +319,39 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def galerkin(n, nc, x_ptr, x_col, x_a, x_m, p_ptr, p_col, p_val, pt_ptr, pt_col, pt_val, stream=None):
+    """Galerkin products P^T A P and P^T M P on the device (amg_eig_galerkin).
+
+    All arguments are device tensors (int64 row pointers, int32 columns, float64
+    values) on one device; returns device tensors (c_ptr, c_col, c_a, c_m).  A
+    first call sizes the result, a second fills it."""
+    dev = x_ptr.device
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    s = ctypes.c_void_p(stream.cuda_stream)
+    ins = [x_ptr, x_col, x_a, x_m, p_ptr, p_col, p_val, pt_ptr, pt_col, pt_val]
+    want = [torch.int64, torch.int32, torch.float64, torch.float64] + [torch.int64, torch.int32, torch.float64] * 2
+    for t, d in zip(ins, want):
+        if t.device != dev or t.dtype != d or not t.is_contiguous():
+            raise ValueError("galerkin: arrays must be contiguous %s tensors on %s" % (d, dev))
+    ptrs = [ctypes.c_void_p(t.data_ptr()) for t in ins]
+    c_ptr = torch.empty(nc + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64()
+    rc = _lib.amg_eig_galerkin(n, nc, *ptrs, ctypes.c_void_p(c_ptr.data_ptr()), None, None, None, 0,
+                               ctypes.byref(nnz), s)
+    if rc not in (OK, EWORKSPACE):
+        raise AmgEigError(rc)
+    cap = nnz.value
+    c_col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    c_a = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    c_m = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    rc = _lib.amg_eig_galerkin(n, nc, *ptrs, ctypes.c_void_p(c_ptr.data_ptr()), ctypes.c_void_p(c_col.data_ptr()),
+                               ctypes.c_void_p(c_a.data_ptr()), ctypes.c_void_p(c_m.data_ptr()), cap,
+                               ctypes.byref(nnz), s)
+    if rc != OK:
+        raise AmgEigError(rc)
+    return c_ptr, c_col[:cap], c_a[:cap], c_m[:cap]
 
 
 def correct_batch(contexts, steps=1, stream=None):
