@@ -23,8 +23,9 @@
  *   - host arrays passed in are borrowed for the duration of the call only;
  *   - device memory is owned by the caller: the solver never allocates or
  *     frees device memory; it carves everything from the workspace given to
- *     amg_eig_bind() (the one exception is the standalone setup routine
- *     amg_eig_galerkin(), which allocates and frees its own temporaries);
+ *     amg_eig_bind() (the exceptions are the standalone device setup routines
+ *     amg_eig_galerkin(), amg_eig_interpolation() and amg_eig_transpose(),
+ *     which allocate and free their own temporaries);
  *   - all device work of a context is enqueued on the stream given to
  *     amg_eig_bind(); only amg_eig_progress() and amg_eig_solve() wait on it;
  *   - one host thread at a time per context; contexts are independent.
@@ -160,6 +161,44 @@ int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, const int32_t 
                      const double *x_m, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
                      const int64_t *pt_ptr, const int32_t *pt_col, const double *pt_val, int64_t *c_ptr,
                      int32_t *c_col, double *c_a, double *c_m, int64_t cap, int64_t *nnz, void *hip_stream);
+
+/* Strong couplings on the device (Section 2, eq. (2.1)): strong[p] = 1 for an
+ * entry p = (i, j) of A with j != i, a_ij < 0 and
+ * -a_ij >= theta max_{k != i, a_ik < 0} (-a_ik), else 0 (a row without
+ * negative off-diagonal entries has none).  Device arrays: x_ptr[n+1],
+ * x_col, x_a as in amg_eig_galerkin; strong[x_ptr[n]] (out, caller-owned).
+ * The same flags as the host setup's.  Asynchronous on the stream; allocates
+ * nothing.  Errors: EINVAL (n < 0, theta outside [0, 1], null x_ptr for
+ * n > 0), EHIP. */
+int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a, double theta,
+                     uint8_t *strong, void *hip_stream);
+
+/* Direct interpolation on the device (Section 2, eqs. (2.2)-(2.4)) from a C/F
+ * splitting: P (n x nc) injects the C points (coarse index = number of C
+ * points before it) and gives an F point i the weights
+ * w_ij = -alpha_i a_ij / a~_ii over its strong couplings to C points, with
+ * alpha_i = (sum of negative off-diagonal a_ij) / (sum over those couplings)
+ * and a~_ii = a_ii + (sum of positive off-diagonal a_ij); an F point whose
+ * couplings sum to zero gets an empty row.  Device inputs: A as in
+ * amg_eig_galerkin, strong[] from amg_eig_strength, cf[n] (1 = C, 0 = F).
+ * Device outputs (caller-owned): p_ptr[n+1] always; p_col[cap] (int32,
+ * ascending within a row), p_val[cap] when nnz <= cap.  *nnz and *nc (host)
+ * receive P's nonzero count and column count.  The same bits as the host
+ * setup's P.  Allocates and frees temporaries (16 bytes per row), waits for
+ * the stream.  Errors: EINVAL (negative sizes, null required arrays),
+ * EWORKSPACE (nnz > cap: p_ptr, *nnz and *nc written), EHIP. */
+int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
+                          const uint8_t *strong, const int32_t *cf, int64_t *p_ptr, int32_t *p_col, double *p_val,
+                          int64_t cap, int64_t *nnz, int64_t *nc, void *hip_stream);
+
+/* Transpose of an nr x nc CSR matrix on the device (P^T for the restriction
+ * and the Galerkin products of eq. (2.5)): pt_ptr[nc+1], pt_col[p_ptr[nr]]
+ * and pt_val[p_ptr[nr]] (caller-owned), each row's columns ascending.  Columns
+ * of P must lie in [0, nc) and be unique within a row.  Allocates and frees a
+ * counter array (8 bytes per column), waits for the stream.
+ * Errors: EINVAL (negative sizes, null row pointers), EHIP. */
+int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
+                      int64_t *pt_ptr, int32_t *pt_col, double *pt_val, void *hip_stream);
 
 /* Device bytes needed by amg_eig_bind(). */
 int amg_eig_footprint(const amg_eig_ctx *c, size_t *device_bytes);

@@ -38,6 +38,7 @@ EXPORTED = [
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
     "amg_eig_tune_time", "amg_eig_bind_static", "amg_eig_galerkin",
+    "amg_eig_strength", "amg_eig_interpolation", "amg_eig_transpose",
 ]
 TUNE_VCYCLE, TUNE_FP64, TUNE_FP64_WIDE = 0, 1, 2
 SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
@@ -90,6 +91,9 @@ _sig = {
     "amg_eig_get_cpt": (_i, [_vp, _i, _i, _vp]),
     "amg_eig_tune_time": (_i, [_vp, _i, _i, _i, _i, _vp]),
     "amg_eig_galerkin": (_i, [_i64, _i64] + [_vp] * 14 + [_i64, _vp, _vp]),
+    "amg_eig_strength": (_i, [_i64, _vp, _vp, _vp, _d, _vp, _vp]),
+    "amg_eig_interpolation": (_i, [_i64] + [_vp] * 8 + [_i64, _vp, _vp, _vp]),
+    "amg_eig_transpose": (_i, [_i64, _i64] + [_vp] * 6 + [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -352,6 +356,64 @@ def galerkin(n, nc, x_ptr, x_col, x_a, x_m, p_ptr, p_col, p_val, pt_ptr, pt_col,
     if rc != OK:
         raise AmgEigError(rc)
     return c_ptr, c_col[:cap], c_a[:cap], c_m[:cap]
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def _stream_of(dev, stream):
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def strength(x_ptr, x_col, x_a, theta=0.25, stream=None):
+    """Strong-coupling flags of eq. (2.1) on the device (amg_eig_strength): uint8 tensor per entry."""
+    n = x_ptr.numel() - 1
+    strong = torch.empty(max(x_col.numel(), 1), dtype=torch.uint8, device=x_ptr.device)
+    rc = _lib.amg_eig_strength(n, _dptr(x_ptr), _dptr(x_col), _dptr(x_a), theta, _dptr(strong),
+                               _stream_of(x_ptr.device, stream))
+    if rc != OK:
+        raise AmgEigError(rc)
+    return strong[:x_col.numel()]
+
+
+def interpolation(x_ptr, x_col, x_a, strong, cf, stream=None):
+    """Direct interpolation P of eqs. (2.2)-(2.4) on the device (amg_eig_interpolation).
+
+    Returns device tensors (p_ptr, p_col, p_val) and the coarse size."""
+    dev = x_ptr.device
+    n = x_ptr.numel() - 1
+    s = _stream_of(dev, stream)
+    p_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nnz, nc = ctypes.c_int64(), ctypes.c_int64()
+    args = [_dptr(x_ptr), _dptr(x_col), _dptr(x_a), _dptr(strong), _dptr(cf), _dptr(p_ptr)]
+    rc = _lib.amg_eig_interpolation(n, *args, None, None, 0, ctypes.byref(nnz), ctypes.byref(nc), s)
+    if rc not in (OK, EWORKSPACE):
+        raise AmgEigError(rc)
+    cap = nnz.value
+    p_col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    p_val = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    rc = _lib.amg_eig_interpolation(n, *args, _dptr(p_col), _dptr(p_val), cap, ctypes.byref(nnz),
+                                    ctypes.byref(nc), s)
+    if rc != OK:
+        raise AmgEigError(rc)
+    return p_ptr, p_col[:cap], p_val[:cap], nc.value
+
+
+def transpose(p_ptr, p_col, p_val, nc, stream=None):
+    """CSR transpose on the device (amg_eig_transpose): (pt_ptr, pt_col, pt_val)."""
+    dev = p_ptr.device
+    nr = p_ptr.numel() - 1
+    nnz = p_col.numel()
+    pt_ptr = torch.empty(nc + 1, dtype=torch.int64, device=dev)
+    pt_col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    pt_val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    rc = _lib.amg_eig_transpose(nr, nc, _dptr(p_ptr), _dptr(p_col), _dptr(p_val), _dptr(pt_ptr), _dptr(pt_col),
+                                _dptr(pt_val), _stream_of(dev, stream))
+    if rc != OK:
+        raise AmgEigError(rc)
+    return pt_ptr, pt_col[:nnz], pt_val[:nnz]
 
 
 def correct_batch(contexts, steps=1, stream=None):

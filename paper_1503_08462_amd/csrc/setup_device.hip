@@ -1,0 +1,434 @@
+// The row-parallel parts of the AMG setup of Section 2 on the device: strong
+// couplings (eq. (2.1)), direct interpolation from a C/F splitting (eqs.
+// (2.2)-(2.4)), the transpose of P, and the Galerkin coarse operators (eq.
+// (2.5)).  The C/F splitting itself (the Ruge-Stueben passes, a sequential
+// greedy choice by measure) stays on the host.  Each routine reproduces the
+// host setup's arithmetic in its order, so both give the same bits.
+//
+// Galerkin products: A_{k+1} = P^T A_k P and M_{k+1} = P^T M_k P with the same
+// prolongation P, the two products on one pattern.  A sparse-sparse product in
+// two stages, T = X P (n x n_c, for X = A_k and M_k together) and C = P^T T,
+// each row by one lane.  Every output row is accumulated in the order its
+// contributions arise: the entries of the row of the left factor in storage
+// order, and for each of them the entries of the matching row of the right
+// factor in storage order.  A new column is appended where it first appears
+// and later contributions are added to it, products and sums rounded
+// separately (no fused multiply-add).  Rows of T keep that first-appearance
+// order; rows of C are then sorted by column.
+//
+// Each lane owns a stretch of a temporary array sized by the row's product
+// count (an upper bound of its distinct columns), found by an exclusive scan.
+// A lane looks up a column by a linear search of its row so far: rows of these
+// operators hold tens to a few hundred entries, and the work is done once per
+// level at setup.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "amg_eig.h"
+
+namespace {
+
+constexpr int kRowThreads = 256;
+constexpr int kScanThreads = 1024;
+
+// ub[r] = sum over the entries (r, j) of the left factor of len(j), where
+// len(j) is the row length of the right factor: from its row pointers when
+// rlen is null, else rlen[j].
+__global__ __launch_bounds__(kRowThreads) void k_gal_bound(int64_t rows, const int64_t *lptr, const int32_t *lcol,
+                                                           const int64_t *rptr, const int64_t *rlen, int64_t *ub) {
+    const int64_t r = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (r >= rows) return;
+    int64_t s = 0;
+    for (int64_t p = lptr[r]; p < lptr[r + 1]; ++p) {
+        const int64_t j = lcol[p];
+        s += rlen ? rlen[j] : rptr[j + 1] - rptr[j];
+    }
+    ub[r] = s;
+}
+
+// out[0] = 0, out[i+1] = x_0 + ... + x_i (i < m) with x_i = in[i], or
+// x_i = (in[i] == 1) for kFlag, in one workgroup: each thread sums a
+// contiguous chunk, the chunk sums are scanned in LDS, then each thread writes
+// its chunk's running sums.
+template <class T, bool kFlag = false>
+__device__ __forceinline__ int64_t scan_term(T v) {
+    return kFlag ? (int64_t)(v == 1) : (int64_t)v;
+}
+template <class T, bool kFlag = false>
+__global__ __launch_bounds__(kScanThreads) void k_gal_scan(int64_t m, const T *in, int64_t *out) {
+    __shared__ int64_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int64_t chunk = (m + kScanThreads - 1) / kScanThreads;
+    const int64_t b = t * chunk < m ? t * chunk : m;
+    const int64_t e = b + chunk < m ? b + chunk : m;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += scan_term<T, kFlag>(in[i]);
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    if (t == 0) out[0] = 0;
+    for (int64_t i = b; i < e; ++i) {
+        run += scan_term<T, kFlag>(in[i]);
+        out[i + 1] = run;
+    }
+}
+
+// Append (c, va, vm) to the row held in col/a/m[0, len) or add to the entry of
+// column c.
+__device__ __forceinline__ void gal_accumulate(int32_t c, double va, double vm, int32_t *col, double *a, double *m,
+                                               int64_t &len) {
+#pragma clang fp contract(off)
+    for (int64_t s = 0; s < len; ++s)
+        if (col[s] == c) {
+            a[s] = a[s] + va;
+            m[s] = m[s] + vm;
+            return;
+        }
+    col[len] = c;
+    a[len] = va;
+    m[len] = vm;
+    ++len;
+}
+
+// T = [A P | M P] row by row, row i into its stretch from toff[i]; tlen[i]
+// receives its length.
+__global__ __launch_bounds__(kRowThreads) void k_gal_xp(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                        const double *xa, const double *xm, const int64_t *pptr,
+                                                        const int32_t *pcol, const double *pval, const int64_t *toff,
+                                                        int32_t *tcol, double *ta, double *tm, int64_t *tlen) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t base = toff[i];
+    int64_t len = 0;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p) {
+        const int64_t j = xcol[p];
+        const double va = xa[p], vm = xm[p];
+        for (int64_t r = pptr[j]; r < pptr[j + 1]; ++r) {
+            const double w = pval[r];
+            gal_accumulate(pcol[r], va * w, vm * w, tcol + base, ta + base, tm + base, len);
+        }
+    }
+    tlen[i] = len;
+}
+
+// C = P^T T row by row, row c into its stretch from coff[c], then sorted by
+// column (insertion sort); clen[c] receives its length.
+__global__ __launch_bounds__(kRowThreads) void k_gal_ptt(int64_t nc, const int64_t *ptptr, const int32_t *ptcol,
+                                                         const double *ptval, const int64_t *toff,
+                                                         const int64_t *tlen, const int32_t *tcol, const double *ta,
+                                                         const double *tm, const int64_t *coff, int32_t *ccol,
+                                                         double *ca, double *cm, int64_t *clen) {
+#pragma clang fp contract(off)
+    const int64_t c = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (c >= nc) return;
+    const int64_t base = coff[c];
+    int32_t *col = ccol + base;
+    double *a = ca + base, *m = cm + base;
+    int64_t len = 0;
+    for (int64_t p = ptptr[c]; p < ptptr[c + 1]; ++p) {
+        const int64_t i = ptcol[p];
+        const double w = ptval[p];
+        for (int64_t r = toff[i]; r < toff[i] + tlen[i]; ++r) gal_accumulate(tcol[r], w * ta[r], w * tm[r], col, a, m, len);
+    }
+    for (int64_t s = 1; s < len; ++s) {
+        const int32_t k = col[s];
+        const double va = a[s], vm = m[s];
+        int64_t t = s - 1;
+        while (t >= 0 && col[t] > k) {
+            col[t + 1] = col[t];
+            a[t + 1] = a[t];
+            m[t + 1] = m[t];
+            --t;
+        }
+        col[t + 1] = k;
+        a[t + 1] = va;
+        m[t + 1] = vm;
+    }
+    clen[c] = len;
+}
+
+// Row c of C from its stretch to its place c_ptr[c] in the output.
+__global__ __launch_bounds__(kRowThreads) void k_gal_compact(int64_t nc, const int64_t *coff, const int64_t *cptr,
+                                                             const int32_t *scol, const double *sa, const double *sm,
+                                                             int32_t *ocol, double *oa, double *om) {
+    const int64_t c = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (c >= nc) return;
+    const int64_t from = coff[c], to = cptr[c], len = cptr[c + 1] - cptr[c];
+    for (int64_t s = 0; s < len; ++s) {
+        ocol[to + s] = scol[from + s];
+        oa[to + s] = sa[from + s];
+        om[to + s] = sm[from + s];
+    }
+}
+
+// Strong couplings, eq. (2.1): entry (i, j), j != i, is strong when a_ij < 0
+// and -a_ij >= theta max_{k != i, a_ik < 0} (-a_ik); a row without negative
+// off-diagonal entries has none.
+__global__ __launch_bounds__(kRowThreads) void k_strength(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                          const double *xa, double theta, uint8_t *strong) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    double mx = 0.0;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p)
+        if (xcol[p] != i && xa[p] < 0.0) mx = fmax(mx, -xa[p]);
+    const double thr = theta * mx;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p)
+        strong[p] = (uint8_t)(mx != 0.0 && xcol[p] != i && xa[p] < 0.0 && -xa[p] >= thr);
+}
+
+// Row sums of direct interpolation for F row i: the diagonal, the negative and
+// positive off-diagonal entries, and the strong couplings to C points, each in
+// storage order; returns the number of strong C couplings.
+__device__ __forceinline__ int64_t interp_sums(int64_t i, const int64_t *xptr, const int32_t *xcol, const double *xa,
+                                               const uint8_t *strong, const int32_t *cf, double &diag, double &sneg,
+                                               double &spos, double &sP) {
+#pragma clang fp contract(off)
+    diag = sneg = spos = sP = 0.0;
+    int64_t cnt = 0;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p) {
+        const double v = xa[p];
+        if (xcol[p] == i) {
+            diag = diag + v;
+        } else if (v < 0.0) {
+            sneg = sneg + v;
+            if (strong[p] && cf[xcol[p]] == 1) {
+                sP = sP + v;
+                ++cnt;
+            }
+        } else if (v > 0.0) {
+            spos = spos + v;
+        }
+    }
+    return cnt;
+}
+
+// Row lengths of P: 1 for a C point; for an F point its strong C couplings,
+// none if they sum to zero.
+__global__ __launch_bounds__(kRowThreads) void k_interp_len(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                            const double *xa, const uint8_t *strong, const int32_t *cf,
+                                                            int64_t *len) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == 1) {
+        len[i] = 1;
+        return;
+    }
+    double diag, sneg, spos, sP;
+    const int64_t cnt = interp_sums(i, xptr, xcol, xa, strong, cf, diag, sneg, spos, sP);
+    len[i] = sP != 0.0 ? cnt : 0;
+}
+
+// Rows of P, eqs. (2.2)-(2.4): C points injected (coarse index cidx[i]); an F
+// point i takes w_ij = -alpha_i a_ij / a~_ii over its strong C couplings, with
+// alpha_i = (sum of negative off-diagonal a_ij) / (sum of strong C couplings)
+// and a~_ii = a_ii + (sum of positive off-diagonal a_ij).
+__global__ __launch_bounds__(kRowThreads) void k_interp_fill(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                             const double *xa, const uint8_t *strong,
+                                                             const int32_t *cf, const int64_t *cidx,
+                                                             const int64_t *pptr, int32_t *pcol, double *pval) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    int64_t q = pptr[i];
+    if (cf[i] == 1) {
+        pcol[q] = (int32_t)cidx[i];
+        pval[q] = 1.0;
+        return;
+    }
+    if (pptr[i + 1] == q) return;
+    double diag, sneg, spos, sP;
+    (void)interp_sums(i, xptr, xcol, xa, strong, cf, diag, sneg, spos, sP);
+    const double alpha = sneg / sP;
+    const double ahat = diag + spos;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p)
+        if (strong[p] && cf[xcol[p]] == 1) {
+            pcol[q] = (int32_t)cidx[xcol[p]];
+            pval[q] = -alpha * xa[p] / ahat;
+            ++q;
+        }
+}
+
+// Transpose of P: entries counted per column, placed by atomic slots, then
+// each row of P^T sorted by its column (the fine row), so the result does not
+// depend on the order of the atomics.
+__global__ __launch_bounds__(kRowThreads) void k_tr_count(int64_t nr, const int64_t *pptr, const int32_t *pcol,
+                                                          unsigned long long *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= nr) return;
+    for (int64_t p = pptr[i]; p < pptr[i + 1]; ++p) atomicAdd(cnt + pcol[p], 1ull);
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_tr_fill(int64_t nr, const int64_t *pptr, const int32_t *pcol,
+                                                         const double *pval, const int64_t *tptr,
+                                                         unsigned long long *slot, int32_t *tcol, double *tval) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= nr) return;
+    for (int64_t p = pptr[i]; p < pptr[i + 1]; ++p) {
+        const int32_t c = pcol[p];
+        const int64_t q = tptr[c] + (int64_t)atomicAdd(slot + c, 1ull);
+        tcol[q] = (int32_t)i;
+        tval[q] = pval[p];
+    }
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_tr_sort(int64_t nc, const int64_t *tptr, int32_t *tcol,
+                                                         double *tval) {
+    const int64_t c = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (c >= nc) return;
+    const int64_t b = tptr[c], e = tptr[c + 1];
+    for (int64_t s = b + 1; s < e; ++s) {
+        const int32_t k = tcol[s];
+        const double v = tval[s];
+        int64_t t = s - 1;
+        while (t >= b && tcol[t] > k) {
+            tcol[t + 1] = tcol[t];
+            tval[t + 1] = tval[t];
+            --t;
+        }
+        tcol[t + 1] = k;
+        tval[t + 1] = v;
+    }
+}
+
+inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
+
+// Temporary device arrays, freed on every return path.
+struct Temps {
+    void *p[12] = {};
+    int k = 0;
+    ~Temps() {
+        for (int i = 0; i < k; ++i) (void)hipFree(p[i]);
+    }
+    template <class T>
+    bool get(T *&out, int64_t count) {
+        out = nullptr;
+        if (count <= 0) count = 1;
+        if (hipMalloc(&p[k], (size_t)count * sizeof(T)) != hipSuccess) return false;
+        out = (T *)p[k++];
+        return true;
+    }
+};
+
+}  // namespace
+
+extern "C" int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
+                                const double *x_m, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
+                                const int64_t *pt_ptr, const int32_t *pt_col, const double *pt_val, int64_t *c_ptr,
+                                int32_t *c_col, double *c_a, double *c_m, int64_t cap, int64_t *nnz,
+                                void *hip_stream) {
+    if (n < 0 || nc < 0 || cap < 0 || !nnz || !c_ptr) return AMG_EIG_EINVAL;
+    // column and value arrays may be null when they hold no entries
+    if (n > 0 && (!x_ptr || !p_ptr)) return AMG_EIG_EINVAL;
+    if (nc > 0 && !pt_ptr) return AMG_EIG_EINVAL;
+    if (cap > 0 && (!c_col || !c_a || !c_m)) return AMG_EIG_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    *nnz = 0;
+    Temps tmp;
+    int64_t *ub_t, *toff, *tlen, *ub_c, *coff, *clen;
+    if (!tmp.get(ub_t, n) || !tmp.get(toff, n + 1) || !tmp.get(tlen, n) || !tmp.get(ub_c, nc) ||
+        !tmp.get(coff, nc + 1) || !tmp.get(clen, nc))
+        return AMG_EIG_EHIP;
+    // T = X P: bounds, offsets, rows
+    if (n > 0) k_gal_bound<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, p_ptr, nullptr, ub_t);
+    k_gal_scan<int64_t><<<1, kScanThreads, 0, st>>>(n, ub_t, toff);
+    int64_t tcap = 0;
+    if (hipMemcpyAsync(&tcap, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    int32_t *tcol;
+    double *ta, *tm;
+    if (!tmp.get(tcol, tcap) || !tmp.get(ta, tcap) || !tmp.get(tm, tcap)) return AMG_EIG_EHIP;
+    if (n > 0)
+        k_gal_xp<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, x_a, x_m, p_ptr, p_col, p_val, toff, tcol, ta,
+                                                     tm, tlen);
+    // C = P^T T: bounds, offsets, rows, row pointers
+    if (nc > 0) k_gal_bound<<<grid_of(nc), kRowThreads, 0, st>>>(nc, pt_ptr, pt_col, nullptr, tlen, ub_c);
+    k_gal_scan<int64_t><<<1, kScanThreads, 0, st>>>(nc, ub_c, coff);
+    int64_t ccap = 0;
+    if (hipMemcpyAsync(&ccap, coff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    int32_t *scol;
+    double *sa, *sm;
+    if (!tmp.get(scol, ccap) || !tmp.get(sa, ccap) || !tmp.get(sm, ccap)) return AMG_EIG_EHIP;
+    if (nc > 0)
+        k_gal_ptt<<<grid_of(nc), kRowThreads, 0, st>>>(nc, pt_ptr, pt_col, pt_val, toff, tlen, tcol, ta, tm, coff,
+                                                       scol, sa, sm, clen);
+    k_gal_scan<int64_t><<<1, kScanThreads, 0, st>>>(nc, clen, c_ptr);
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, c_ptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    *nnz = total;
+    if (total > cap) return AMG_EIG_EWORKSPACE;
+    if (nc > 0)
+        k_gal_compact<<<grid_of(nc), kRowThreads, 0, st>>>(nc, coff, c_ptr, scol, sa, sm, c_col, c_a, c_m);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return AMG_EIG_EHIP;
+    return AMG_EIG_OK;
+}
+
+extern "C" int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
+                                double theta, uint8_t *strong, void *hip_stream) {
+    if (n < 0 || !(theta >= 0.0 && theta <= 1.0)) return AMG_EIG_EINVAL;
+    if (n == 0) return AMG_EIG_OK;
+    if (!x_ptr) return AMG_EIG_EINVAL;
+    k_strength<<<grid_of(n), kRowThreads, 0, (hipStream_t)hip_stream>>>(n, x_ptr, x_col, x_a, theta, strong);
+    return hipGetLastError() == hipSuccess ? AMG_EIG_OK : AMG_EIG_EHIP;
+}
+
+extern "C" int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
+                                     const uint8_t *strong, const int32_t *cf, int64_t *p_ptr, int32_t *p_col,
+                                     double *p_val, int64_t cap, int64_t *nnz, int64_t *nc, void *hip_stream) {
+    if (n < 0 || cap < 0 || !nnz || !nc || !p_ptr) return AMG_EIG_EINVAL;
+    if (n > 0 && (!x_ptr || !cf)) return AMG_EIG_EINVAL;
+    if (cap > 0 && (!p_col || !p_val)) return AMG_EIG_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    *nnz = 0;
+    *nc = 0;
+    Temps tmp;
+    int64_t *cidx, *len;
+    if (!tmp.get(cidx, n + 1) || !tmp.get(len, n)) return AMG_EIG_EHIP;
+    k_gal_scan<int32_t, true><<<1, kScanThreads, 0, st>>>(n, cf, cidx);
+    if (n > 0) k_interp_len<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, x_a, strong, cf, len);
+    k_gal_scan<int64_t><<<1, kScanThreads, 0, st>>>(n, len, p_ptr);
+    int64_t h[2] = {0, 0};
+    if (hipMemcpyAsync(&h[0], cidx + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&h[1], p_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    *nc = h[0];
+    *nnz = h[1];
+    if (h[1] > cap) return AMG_EIG_EWORKSPACE;
+    if (n > 0)
+        k_interp_fill<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, x_a, strong, cf, cidx, p_ptr, p_col, p_val);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return AMG_EIG_EHIP;
+    return AMG_EIG_OK;
+}
+
+extern "C" int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, const int32_t *p_col,
+                                 const double *p_val, int64_t *pt_ptr, int32_t *pt_col, double *pt_val,
+                                 void *hip_stream) {
+    if (nr < 0 || nc < 0 || !pt_ptr || (nr > 0 && !p_ptr)) return AMG_EIG_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    Temps tmp;
+    unsigned long long *cnt;
+    if (!tmp.get(cnt, nc)) return AMG_EIG_EHIP;
+    if (hipMemsetAsync(cnt, 0, (size_t)(nc > 0 ? nc : 1) * sizeof(unsigned long long), st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    if (nr > 0) k_tr_count<<<grid_of(nr), kRowThreads, 0, st>>>(nr, p_ptr, p_col, cnt);
+    k_gal_scan<unsigned long long><<<1, kScanThreads, 0, st>>>(nc, cnt, pt_ptr);
+    if (hipMemsetAsync(cnt, 0, (size_t)(nc > 0 ? nc : 1) * sizeof(unsigned long long), st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    if (nr > 0) k_tr_fill<<<grid_of(nr), kRowThreads, 0, st>>>(nr, p_ptr, p_col, p_val, pt_ptr, cnt, pt_col, pt_val);
+    if (nc > 0) k_tr_sort<<<grid_of(nc), kRowThreads, 0, st>>>(nc, pt_ptr, pt_col, pt_val);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return AMG_EIG_EHIP;
+    return AMG_EIG_OK;
+}
