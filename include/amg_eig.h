@@ -24,8 +24,8 @@
  *   - device memory is owned by the caller: the solver never allocates or
  *     frees device memory; it carves everything from the workspace given to
  *     amg_eig_bind() (the exceptions are the standalone device setup routines
- *     amg_eig_galerkin(), amg_eig_interpolation() and amg_eig_transpose(),
- *     which allocate and free their own temporaries);
+ *     amg_eig_galerkin(), amg_eig_pmis(), amg_eig_interpolation() and
+ *     amg_eig_transpose(), which allocate and free their own temporaries);
  *   - all device work of a context is enqueued on the stream given to
  *     amg_eig_bind(); only amg_eig_progress() and amg_eig_solve() wait on it;
  *   - one host thread at a time per context; contexts are independent.
@@ -172,6 +172,24 @@ int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, const int32_t 
  * n > 0), EHIP. */
 int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a, double theta,
                      uint8_t *strong, void *hip_stream);
+
+/* Parallel C/F splitting on the device, for the coarsening step of Section 2
+ * (which the host setup does with the sequential Ruge-Stueben passes): PMIS,
+ * the parallel modified independent set of De Sterck, Yang and Heys (2006), on
+ * the strength graph of eq. (2.1).  Point i weighs |S_i^T| + rnd[i] (the
+ * number of points depending strongly on it plus a caller-drawn number in
+ * [0, 1)); points that no point depends on are F.  Each round every undecided
+ * point heavier (weight, then larger index) than all its undecided neighbours
+ * in the symmetrised strength graph becomes C, then every undecided point
+ * depending strongly on a C point becomes F, until none is undecided.
+ * Device inputs: x_ptr[n+1], x_col (a structurally symmetric pattern, columns
+ * ascending within a row), strong[] from amg_eig_strength, rnd[n].  Output:
+ * cf[n] (device, caller-owned; 1 = C, 0 = F); *rounds (host) the rounds
+ * taken (at most n).  Allocates and frees temporaries (1 byte per entry, 12 per
+ * row), waits for the stream after each round.
+ * Errors: EINVAL (n < 0, null arrays for n > 0), EHIP. */
+int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const uint8_t *strong, const double *rnd,
+                 int32_t *cf, int *rounds, void *hip_stream);
 
 /* Direct interpolation on the device (Section 2, eqs. (2.2)-(2.4)) from a C/F
  * splitting: P (n x nc) injects the C points (coarse index = number of C

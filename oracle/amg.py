@@ -6,6 +6,10 @@ Test infrastructure only: the eigensolver library never imports this.
   rs_splitting        Section 2.1: classical Ruge-Stueben coarsening (first pass
                       on |S_i^T|, then the second pass giving strongly
                       coupled F points a common strong C point)
+  pmis_splitting      a parallel C/F splitting (PMIS: parallel modified
+                      independent set, De Sterck, Yang and Heys 2006) on the
+                      same strength graph, the parallel coarsening that
+                      replaces the sequential Ruge-Stueben passes on a GPU
   direct_interpolation eq. (2.2)-(2.4) with P_i = S_i intersect C
   galerkin            eq. (2.5): A_{k+1} = P^T A_k P, M_{k+1} = P^T M_k P
   build_hierarchy     the level loop of Section 2.3
@@ -60,6 +64,45 @@ def rs_splitting(A, theta=0.25, second_pass=True):
     if second_pass:
         cf = native.rs_second_pass(S, cf)
     return cf, S
+
+
+def pmis_splitting(A, r, theta=0.25):
+    """C/F splitting (1 = C, 0 = F) by PMIS on the strength graph of eq. (2.1).
+
+    r holds one random number in [0, 1) per point, drawn by the caller.  Point
+    i weighs w_i = |S_i^T| + r_i, the number of points that depend strongly on
+    it plus its random part; points that no point depends on start as F, the
+    others undecided.  Each round, every undecided point whose (w_i, i) exceeds
+    (w_j, j) for all undecided neighbours j in the symmetrised strength graph
+    (j in S_i or i in S_j) becomes C, then every undecided point that depends
+    strongly on one of the new C points becomes F.  Rounds repeat until no
+    point is undecided; each round makes at least the heaviest undecided point
+    C.  Returns (cf, S, rounds).
+    """
+    n = A.shape[0]
+    S = strength(A, theta)
+    ST = S.T.tocsr()
+    ST.sort_indices()
+    G = ((S + ST) != 0).tocsr()
+    G.sort_indices()
+    w = np.diff(ST.indptr).astype(np.float64) + np.asarray(r, dtype=np.float64)
+    state = np.where(np.diff(ST.indptr) == 0, 0, -1)
+    rounds = 0
+    while (state == -1).any():
+        rounds += 1
+        undecided = [i for i in range(n) if state[i] == -1]
+        new_c = []
+        for i in undecided:
+            nbrs = [j for j in G.indices[G.indptr[i]:G.indptr[i + 1]] if j != i and state[j] == -1]
+            if all((w[j], j) < (w[i], i) for j in nbrs):
+                new_c.append(i)
+        new_set = set(new_c)
+        for i in new_c:
+            state[i] = 1
+        for i in undecided:
+            if state[i] == -1 and any(j in new_set for j in S.indices[S.indptr[i]:S.indptr[i + 1]]):
+                state[i] = 0
+    return state.astype(np.int64), S, rounds
 
 
 def direct_interpolation(A, S, cf):

@@ -38,7 +38,7 @@ EXPORTED = [
     "amg_eig_coarse_eigenvalues", "amg_eig_iterate", "amg_eig_destroy", "amg_eig_strerror",
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
     "amg_eig_tune_time", "amg_eig_bind_static", "amg_eig_galerkin",
-    "amg_eig_strength", "amg_eig_interpolation", "amg_eig_transpose",
+    "amg_eig_strength", "amg_eig_interpolation", "amg_eig_transpose", "amg_eig_pmis",
 ]
 TUNE_VCYCLE, TUNE_FP64, TUNE_FP64_WIDE = 0, 1, 2
 SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
@@ -94,6 +94,7 @@ _sig = {
     "amg_eig_strength": (_i, [_i64, _vp, _vp, _vp, _d, _vp, _vp]),
     "amg_eig_interpolation": (_i, [_i64] + [_vp] * 8 + [_i64, _vp, _vp, _vp]),
     "amg_eig_transpose": (_i, [_i64, _i64] + [_vp] * 6 + [_vp]),
+    "amg_eig_pmis": (_i, [_i64] + [_vp] * 7),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -376,6 +377,18 @@ def strength(x_ptr, x_col, x_a, theta=0.25, stream=None):
     if rc != OK:
         raise AmgEigError(rc)
     return strong[:x_col.numel()]
+
+
+def pmis(x_ptr, x_col, strong, rnd, stream=None):
+    """PMIS C/F splitting on the device (amg_eig_pmis): (cf int32 device tensor, rounds)."""
+    n = x_ptr.numel() - 1
+    cf = torch.empty(max(n, 1), dtype=torch.int32, device=x_ptr.device)
+    rounds = ctypes.c_int()
+    rc = _lib.amg_eig_pmis(n, _dptr(x_ptr), _dptr(x_col), _dptr(strong), _dptr(rnd), _dptr(cf), ctypes.byref(rounds),
+                           _stream_of(x_ptr.device, stream))
+    if rc != OK:
+        raise AmgEigError(rc)
+    return cf[:n], rounds.value
 
 
 def interpolation(x_ptr, x_col, x_a, strong, cf, stream=None):

@@ -1,9 +1,10 @@
 // The row-parallel parts of the AMG setup of Section 2 on the device: strong
 // couplings (eq. (2.1)), direct interpolation from a C/F splitting (eqs.
 // (2.2)-(2.4)), the transpose of P, and the Galerkin coarse operators (eq.
-// (2.5)).  The C/F splitting itself (the Ruge-Stueben passes, a sequential
-// greedy choice by measure) stays on the host.  Each routine reproduces the
-// host setup's arithmetic in its order, so both give the same bits.
+// (2.5)), and a parallel C/F splitting (PMIS: parallel modified independent
+// set, De Sterck, Yang and Heys 2006) in place of the sequential Ruge-Stueben
+// passes, which stay on the host.  The first four reproduce the host setup's
+// arithmetic in its order, so both give the same bits.
 //
 // Galerkin products: A_{k+1} = P^T A_k P and M_{k+1} = P^T M_k P with the same
 // prolongation P, the two products on one pattern.  A sparse-sparse product in
@@ -298,6 +299,68 @@ __global__ __launch_bounds__(kRowThreads) void k_tr_sort(int64_t nc, const int64
     }
 }
 
+// PMIS.  Per entry p = (i, j) of a structurally symmetric pattern: bit 0 =
+// i depends strongly on j, bit 1 = j depends strongly on i (the flag of the
+// mirror entry (j, i), found by binary search in row j).  w_i = |S_i^T| + r_i;
+// a point no point depends on starts F (0), the others undecided (-1).
+__global__ __launch_bounds__(kRowThreads) void k_pmis_init(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                           const uint8_t *strong, const double *rnd, uint8_t *sflag,
+                                                           double *w, int32_t *state, int32_t *isc) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    int64_t nst = 0;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p) {
+        const int32_t j = xcol[p];
+        int64_t lo = xptr[j], hi = xptr[j + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (xcol[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint8_t back = (lo < xptr[j + 1] && xcol[lo] == i && j != i) ? strong[lo] : 0;
+        sflag[p] = (uint8_t)((strong[p] ? 1 : 0) | (back ? 2 : 0));
+        nst += back ? 1 : 0;
+    }
+    w[i] = (double)nst + rnd[i];
+    state[i] = nst == 0 ? 0 : -1;
+    isc[i] = 0;
+}
+
+// An undecided point heavier (weight, then index) than every undecided
+// neighbour in the symmetrised strength graph is marked C.
+__global__ __launch_bounds__(kRowThreads) void k_pmis_select(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                             const uint8_t *sflag, const double *w,
+                                                             const int32_t *state, int32_t *isc) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n || state[i] != -1) return;
+    const double wi = w[i];
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p) {
+        const int32_t j = xcol[p];
+        if (!sflag[p] || j == i || state[j] != -1) continue;
+        if (w[j] > wi || (w[j] == wi && j > i)) return;
+    }
+    isc[i] = 1;
+}
+
+// Marked points become C; an undecided point that depends strongly on a C
+// point becomes F; the points left undecided are counted.
+__global__ __launch_bounds__(kRowThreads) void k_pmis_update(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                             const uint8_t *sflag, const int32_t *isc,
+                                                             int32_t *state, unsigned long long *left) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n || state[i] != -1) return;
+    if (isc[i]) {
+        state[i] = 1;
+        return;
+    }
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p)
+        if ((sflag[p] & 1) && isc[xcol[p]]) {
+            state[i] = 0;
+            return;
+        }
+    atomicAdd(left, 1ull);
+}
+
 inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
 
 // Temporary device arrays, freed on every return path.
@@ -431,4 +494,37 @@ extern "C" int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, c
     if (nc > 0) k_tr_sort<<<grid_of(nc), kRowThreads, 0, st>>>(nc, pt_ptr, pt_col, pt_val);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return AMG_EIG_EHIP;
     return AMG_EIG_OK;
+}
+
+extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const uint8_t *strong,
+                            const double *rnd, int32_t *cf, int *rounds, void *hip_stream) {
+    if (n < 0 || !rounds || (n > 0 && (!x_ptr || !rnd || !cf))) return AMG_EIG_EINVAL;
+    *rounds = 0;
+    if (n == 0) return AMG_EIG_OK;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int64_t nnz = 0;
+    if (hipMemcpyAsync(&nnz, x_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    Temps tmp;
+    uint8_t *sflag;
+    double *w;
+    int32_t *isc;
+    unsigned long long *left;
+    if (!tmp.get(sflag, nnz) || !tmp.get(w, n) || !tmp.get(isc, n) || !tmp.get(left, 1)) return AMG_EIG_EHIP;
+    k_pmis_init<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, strong, rnd, sflag, w, cf, isc);
+    // every round makes at least the heaviest undecided point C, so n rounds
+    // decide every point
+    for (int64_t r = 0; r < n; ++r) {
+        unsigned long long h = 0;
+        if (hipMemsetAsync(left, 0, sizeof(unsigned long long), st) != hipSuccess) return AMG_EIG_EHIP;
+        k_pmis_select<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, sflag, w, cf, isc);
+        k_pmis_update<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, sflag, isc, cf, left);
+        if (hipMemcpyAsync(&h, left, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return AMG_EIG_EHIP;
+        *rounds = (int)(r + 1);
+        if (h == 0) return hipGetLastError() == hipSuccess ? AMG_EIG_OK : AMG_EIG_EHIP;
+    }
+    return AMG_EIG_EHIP;
 }

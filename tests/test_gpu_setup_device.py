@@ -136,3 +136,107 @@ def test_interpolation_edges():
     assert ae._lib.amg_eig_strength(n, ctypes.c_void_p(x[0].data_ptr()), None, None, 1.5, None,
                                     ctypes.c_void_p(s)) == ae.EINVAL
     assert ae._lib.amg_eig_transpose(-1, 0, None, None, None, None, None, None, ctypes.c_void_p(s)) == ae.EINVAL
+
+
+def _device_hierarchy(torch, x, n, seed, coarse_max, theta=THETA, check=None):
+    """Levels built on the device only: strength, PMIS, interpolation,
+    transpose, Galerkin, until n <= coarse_max or coarsening stalls.  check(l,
+    x, strong, cf, P, Pt, xnext) is called per level with device tensors."""
+    from workloads.prng import uniform01
+    dims = [n]
+    rounds = []
+    l = 0
+    while n > coarse_max:
+        strong = ae.strength(x[0], x[1], x[2], theta)
+        rnd = _dev(torch, uniform01(seed + l, np.arange(n)), np.float64)
+        cf, r = ae.pmis(x[0], x[1], strong, rnd)
+        p_ptr, p_col, p_val, nc = ae.interpolation(x[0], x[1], x[2], strong, cf)
+        if nc == 0 or nc > 0.9 * n:
+            break
+        pt = ae.transpose(p_ptr, p_col, p_val, nc)
+        xn = list(ae.galerkin(n, nc, *x, p_ptr, p_col, p_val, *pt))
+        if check is not None:
+            check(l, x, strong, rnd, cf, (p_ptr, p_col, p_val, nc), pt, xn)
+        x, n = xn, nc
+        dims.append(n)
+        rounds.append(r)
+        l += 1
+    return dims, rounds
+
+
+PMIS_CASES = [
+    ("square48", lambda: configs.square(48, q=4)),
+    ("lshape24j", lambda: configs.lshape(24, q=10, jitter_seed=2)),
+    ("cube16", lambda: configs.cube(16, q=8)),
+    ("oscillator100", lambda: configs.oscillator(100, q=10)),
+    ("quadrants16", lambda: configs.quadrants(16, q=6)),
+]
+
+
+@pytest.mark.parametrize("name,make", PMIS_CASES, ids=[c[0] for c in PMIS_CASES])
+def test_pmis_hierarchy_on_device_matches_oracle(name, make):
+    """The whole hierarchy built on the device (PMIS in place of the host's
+    Ruge-Stueben passes); each level's steps against the oracle's on the same
+    input: strength and the splitting exactly, P within rounding, the Galerkin
+    operators within rounding of P^T A P."""
+    import torch
+    from oracle.amg import galerkin, pmis_splitting
+    p = make()
+    n = p["n"]
+
+    def check(l, x, strong, rnd, cf, P, pt, xn):
+        hp, hc, ha, hm = (t.cpu().numpy() for t in x)
+        nn = hp.size - 1
+        A = sp.csr_matrix((ha, hc, hp), shape=(nn, nn))
+        M = sp.csr_matrix((hm, hc, hp), shape=(nn, nn))
+        cf_o, S, rounds_o = pmis_splitting(A, rnd.cpu().numpy(), THETA)
+        cf_d = cf.cpu().numpy()
+        _say("pmis %s level %d: %d rows, %d C, %d rounds" % (name, l, nn, int(cf_d.sum()), rounds_o))
+        assert np.array_equal(cf_d, cf_o)
+        Pd = sp.csr_matrix((P[2].cpu().numpy(), P[1].cpu().numpy(), P[0].cpu().numpy()), shape=(nn, P[3]))
+        Po = direct_interpolation(A, S, cf_o)
+        assert Pd.shape == Po.shape and abs(Pd - Po).max() <= 1e-14 * max(1.0, abs(Po).max())
+        cp, cc, ca, cm = (t.cpu().numpy() for t in xn)
+        for vals, X in ((ca, A), (cm, M)):
+            C = sp.csr_matrix((vals, cc, cp), shape=(P[3], P[3]))
+            ref = galerkin(Pd, X)
+            assert abs(C - ref).max() <= 1e-13 * abs(ref).max()
+
+    x = [_dev(torch, p["rowptr"], np.int64), _dev(torch, p["col"], np.int32), _dev(torch, p["A"], np.float64),
+         _dev(torch, p["M"], np.float64)]
+    dims, rounds = _device_hierarchy(torch, x, n, 1000, 120, check=check)
+    _say("pmis %s: levels %s, rounds %s" % (name, dims, rounds))
+    assert len(dims) >= 3
+
+
+def test_device_setup_time_oscillator1024():
+    """Setup of the 1,046,529-row oscillator: the whole hierarchy on the device
+    (PMIS splitting) beside the host setup (Ruge-Stueben), timed; properties
+    only (every point decided, each level smaller than the last)."""
+    import time
+    import torch
+    p = configs.oscillator(1024, q=16)
+    n = p["n"]
+    _say("device setup oscillator1024: %d rows" % n)
+    x = [_dev(torch, p["rowptr"], np.int64), _dev(torch, p["col"], np.int32), _dev(torch, p["A"], np.float64),
+         _dev(torch, p["M"], np.float64)]
+    torch.cuda.synchronize()
+
+    def check(l, x, strong, rnd, cf, P, pt, xn):
+        c = cf.cpu().numpy()
+        assert set(np.unique(c).tolist()) <= {0, 1}
+
+    _device_hierarchy(torch, x, n, 1000, 512)  # warm-up (module load)
+    t0 = time.perf_counter()
+    dims, rounds = _device_hierarchy(torch, x, n, 1000, 512)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    _device_hierarchy(torch, x, n, 1000, 512, check=check)
+    assert all(a > b for a, b in zip(dims, dims[1:]))
+    t0 = time.perf_counter()
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(qe=24))
+    t_host = time.perf_counter() - t0
+    hd = [int(d) for d in ctx.info()["dims"]]
+    ctx.close()
+    _say("device setup (PMIS) %.1f ms, levels %s, rounds %s; host setup (RS, with the coarsest "
+         "eigen-decomposition) %.1f ms, levels %s" % (1e3 * t_dev, dims, rounds, 1e3 * t_host, hd))

@@ -132,3 +132,53 @@ def test_second_pass_gives_common_c_points():
             for j in Sl[i]:
                 if cf[j] == 0:
                     assert Ci & set(Sl[j]), (i, j)
+
+
+def test_pmis_1d_laplacian_picks_every_other_point():
+    """PMIS on tridiag(-1,2,-1), N = 7: interior points weigh 2 + r_i, the ends
+    1 + r_i.  With equal random parts (ties to the larger index), increasing or
+    decreasing ones, the rounds traced by hand take C = {1, 3, 5} in three
+    rounds, the textbook coarsening of the 1D Laplacian."""
+    A = _lap1d(7)
+    for r in (np.full(7, 0.5), np.arange(7) / 10.0, (6 - np.arange(7)) / 10.0):
+        cf, S, rounds = amg.pmis_splitting(A, r, 0.25)
+        assert cf.tolist() == [0, 1, 0, 1, 0, 1, 0]
+        assert rounds == 3
+
+
+def test_pmis_marks_f_along_dependence_not_influence():
+    """Asymmetric strength, traced by hand: S_0 = {1}, S_1 = {0, 2}, S_2 = {3},
+    S_3 = {2} (point 1 depends on 2, 2 does not depend on 1).  Point 2 (weight
+    2 + r_2) becomes C first; 1 and 3 depend on it and become F; 0 is then a
+    lone undecided point and becomes C: [1, 0, 1, 0] in two rounds.  Marking F
+    along the other direction (points that 2 depends on) would leave 1
+    undecided and make it C."""
+    A = sp.csr_matrix(np.array([[2.0, -1, 0, 0], [-1, 2, -0.3, 0], [0, -0.3, 11, -10], [0, 0, -10, 11]]))
+    cf, S, rounds = amg.pmis_splitting(A, np.array([0.1, 0.5, 0.0, 0.0]), 0.25)
+    assert [list(S.indices[S.indptr[i]:S.indptr[i + 1]]) for i in range(4)] == [[1], [0, 2], [3], [2]]
+    assert cf.tolist() == [1, 0, 1, 0] and rounds == 2
+
+
+def test_pmis_invariants_on_workloads():
+    """On seeded random parts: every point decided; every F point that some
+    point depends on depends strongly on a C point; the first round's C set,
+    the local maxima of the weights over the symmetrised strength graph
+    (formed here with sparse products), is contained in C."""
+    from workloads.prng import uniform01
+    for p in (configs.cube(10, q=4), configs.lshape(16, q=4, jitter_seed=1), configs.quadrants(12, q=4)):
+        A, _ = mats(p)
+        n = A.shape[0]
+        r = uniform01(77, np.arange(n))
+        cf, S, rounds = amg.pmis_splitting(A, r, 0.25)
+        assert set(np.unique(cf).tolist()) <= {0, 1} and rounds >= 1
+        nst = np.asarray(S.sum(axis=0)).ravel()
+        dep_c = np.asarray(S @ cf.astype(float)).ravel()
+        assert np.all(dep_c[(cf == 0) & (nst > 0)] > 0)
+        assert np.all(cf[nst == 0] == 0)
+        w = nst + r
+        G = ((S + S.T) != 0).tocoo()
+        beats = (w[G.col] > w[G.row]) | ((w[G.col] == w[G.row]) & (G.col > G.row))
+        beaten = np.zeros(n, bool)
+        beaten[G.row[beats & (nst[G.col] > 0)]] = True
+        first = (nst > 0) & ~beaten
+        assert first.any() and np.all(cf[first] == 1)
