@@ -69,6 +69,11 @@ extern "C" {
                                 accumulation; residual, Rayleigh-Ritz and the
                                 eigenvector block in FP64 */
 
+#define AMG_EIG_COARSEN_RS 0   /* host setup: Ruge-Stueben first and second pass (Section 2) */
+#define AMG_EIG_COARSEN_PMIS 1 /* device setup on the current device: strength, PMIS splitting,
+                                  direct interpolation, transpose and Galerkin products per level
+                                  (amg_eig_strength .. amg_eig_galerkin), levels copied back */
+
 #define AMG_EIG_INIT_NESTED 0 /* Algorithm 3.2 start from the coarsest level */
 #define AMG_EIG_INIT_RANDOM 1 /* seeded U(-1,1) block, then Rayleigh-Ritz */
 #define AMG_EIG_INIT_USER 2   /* caller's device block, then Rayleigh-Ritz */
@@ -105,12 +110,16 @@ typedef struct {
                            rejects (EINVAL) only a shift not below the coarsest level's smallest
                            eigenvalue, an upper bound of lambda_1 that can exceed it by a large
                            factor, or one that leaves a level's diagonal a_ii - sigma m_ii <= 0 */
+    int coarsening;     /* AMG_EIG_COARSEN_*: how setup splits each level into C and F points */
+    uint64_t coarsen_seed; /* PMIS only: seed of the random parts of the point weights (level k
+                           draws SplitMix64 stream coarsen_seed + k, one uniform [0,1) per point) */
 } amg_eig_opts;
 
 /* Paper defaults (Section 4.1: theta = 0.25, one V-cycle with one pre- and
  * one post-smoothing step, n_1 = n, p_k = 1 on coarse levels) plus the GPU
  * options: degree-2 Chebyshev smoothing on [0.25, 1] in D^-1 A (D the l1
- * diagonal), FP64, coarse_max 512, tol 1e-8. */
+ * diagonal), FP64, coarse_max 512, tol 1e-8, Ruge-Stueben coarsening on the
+ * host. */
 void amg_eig_opts_default(amg_eig_opts *o);
 
 /* Host CSR, borrowed for the call: rowptr[n+1] (int64, rowptr[0] = 0,
@@ -127,7 +136,10 @@ typedef struct amg_eig_ctx amg_eig_ctx;
 
 /* Build the AMG hierarchy on the host (Section 2) for the q smallest
  * eigenpairs of (A, M), plus the coarsest eigen-decomposition Z, Lambda_n with
- * Z^T M_n Z = I, Z^T A_n Z = Lambda_n.  No device call is made.
+ * Z^T M_n Z = I, Z^T A_n Z = Lambda_n.  No device call is made, except with
+ * coarsening = AMG_EIG_COARSEN_PMIS: then the levels are formed on the current
+ * device (null stream, temporaries allocated and freed) and copied back, and
+ * a HIP failure there returns EHIP.
  * Errors: EINVAL (shapes, unsorted/duplicate/out-of-range columns, q < 1,
  * qe + d_n > n, nnz >= 2^31), ENOTSPD (a_ii <= 0, m_ii < 0, coarsest M_n or
  * A_n not positive definite), ENOMEM.  *out is NULL on error. */

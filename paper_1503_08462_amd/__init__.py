@@ -27,6 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, NOT_CONVERGED, WIDENED = 0, 1, 2
 EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EWORKSPACE, EHIP, ECANCELLED, ESTATE = -1, -2, -3, -4, -5, -6, -7, -8
 SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV, SMOOTH_GAUSS_SEIDEL = 0, 1, 2
+COARSEN_RS, COARSEN_PMIS = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 INIT_NESTED, INIT_RANDOM, INIT_USER = 0, 1, 2
 
@@ -53,6 +54,7 @@ class Opts(ctypes.Structure):
         ("tol", ctypes.c_double), ("max_steps", ctypes.c_int), ("use_graph", ctypes.c_int),
         ("qe_max", ctypes.c_int),
         ("shift", ctypes.c_double),
+        ("coarsening", ctypes.c_int), ("coarsen_seed", ctypes.c_uint64),
     ]
 
 

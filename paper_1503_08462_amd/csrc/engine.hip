@@ -1067,6 +1067,8 @@ void amg_eig_opts_default(amg_eig_opts *o) {
     o->use_graph = 0;
     o->qe_max = 0;
     o->shift = 0.0;
+    o->coarsening = AMG_EIG_COARSEN_RS;
+    o->coarsen_seed = 0;
 }
 
 int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o, amg_eig_ctx **out) {

@@ -60,6 +60,14 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
 bool dense_sygv(int n, const std::vector<double> &A, const std::vector<double> &M, std::vector<double> &lam,
                 std::vector<double> &Z);
 
+// Coarsen on the device with PMIS (setup_device.hip): from H.lv.back() on,
+// while H.lv.size() < max_levels and the last level has more than coarse_max
+// rows, form strength, splitting, P, P^T and the next level on the current
+// device and append it (cf, P, Pt of each coarsened level filled); a splitting
+// with fewer than cmin or more than 0.9 n C points ends the loop.  Returns an
+// amg_eig status code.
+int device_coarsen(Hierarchy &H, const amg_eig_opts &o, int64_t cmin, std::string &err);
+
 // Choose the block width by the guard rule on approximate eigenvalues.
 int guard_width(const std::vector<double> &lam, int q, double gap, int cap);
 

@@ -494,8 +494,16 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
     }
     const int qcap = o.qe > 0 ? o.qe : 2 * q + 8;
     const int64_t cmin = o.coarse_min > 0 ? o.coarse_min : std::max<int64_t>(2 * qcap + 2, 16);
+    if (o.coarsening != AMG_EIG_COARSEN_RS && o.coarsening != AMG_EIG_COARSEN_PMIS) {
+        err = "invalid coarsening";
+        return AMG_EIG_EINVAL;
+    }
+    if (o.coarsening == AMG_EIG_COARSEN_PMIS) {
+        rc = device_coarsen(H, o, cmin, err);
+        if (rc) return rc;
+    }
     std::vector<uint8_t> strong;
-    while ((int)H.lv.size() < o.max_levels && H.lv.back().n > o.coarse_max) {
+    while (o.coarsening == AMG_EIG_COARSEN_RS && (int)H.lv.size() < o.max_levels && H.lv.back().n > o.coarse_max) {
         Level &L = H.lv.back();
         strong_flags(L, o.theta, strong);
         std::vector<int32_t> cf;

@@ -25,8 +25,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
+#include <vector>
 
 #include "amg_eig.h"
+#include "internal.h"
 
 namespace {
 
@@ -528,3 +531,128 @@ extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_co
     }
     return AMG_EIG_EHIP;
 }
+
+namespace amgeig {
+namespace {
+
+// Device copy of a host array, freed with the object.
+template <class T>
+struct DevArr {
+    T *p = nullptr;
+    int64_t n = 0;
+    DevArr() = default;
+    DevArr(const DevArr &) = delete;
+    DevArr &operator=(const DevArr &) = delete;
+    ~DevArr() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    bool alloc(int64_t count) {
+        reset();
+        n = count;
+        return hipMalloc(&p, (size_t)(count > 0 ? count : 1) * sizeof(T)) == hipSuccess;
+    }
+    bool up(const std::vector<T> &v) {
+        return alloc((int64_t)v.size()) &&
+               (v.empty() || hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess);
+    }
+    bool down(std::vector<T> &v, int64_t count) const {
+        v.resize((size_t)count);
+        return count == 0 || hipMemcpy(v.data(), p, (size_t)count * sizeof(T), hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    void swap(DevArr &o) {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+    }
+};
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k of the stream
+// seeded with s is the MurmurHash3 variant-13 finaliser of s + (k+1) * gamma;
+// a uniform double in [0, 1) from its top 53 bits.
+double splitmix_uniform(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace
+
+int device_coarsen(Hierarchy &H, const amg_eig_opts &o, int64_t cmin, std::string &err) {
+    auto hip_fail = [&](const char *what) {
+        err = std::string("device coarsening: ") + what + " failed";
+        (void)hipGetLastError();
+        return AMG_EIG_EHIP;
+    };
+    DevArr<int64_t> xp, pp, ptp, cp;
+    DevArr<int32_t> xc, cf, pc, ptc, cc;
+    DevArr<double> xa, xm, rnd, pv, ptv, ca, cm;
+    DevArr<uint8_t> strong;
+    {
+        const Level &L = H.lv.back();
+        if (!xp.up(L.ptr) || !xc.up(L.col) || !xa.up(L.a) || !xm.up(L.m)) return hip_fail("upload");
+    }
+    while ((int)H.lv.size() < o.max_levels && H.lv.back().n > o.coarse_max) {
+        const size_t k = H.lv.size() - 1;
+        const int64_t n = H.lv[k].n;
+        int rc;
+        if (!strong.alloc(xc.n)) return hip_fail("allocation");
+        rc = amg_eig_strength(n, xp.p, xc.p, xa.p, o.theta, strong.p, nullptr);
+        if (rc) return rc == AMG_EIG_EHIP ? hip_fail("strength") : rc;
+        std::vector<double> r((size_t)n);
+        for (int64_t i = 0; i < n; ++i) r[(size_t)i] = splitmix_uniform(o.coarsen_seed + (uint64_t)k, (uint64_t)i);
+        if (!rnd.up(r) || !cf.alloc(n)) return hip_fail("upload");
+        int rounds = 0;
+        rc = amg_eig_pmis(n, xp.p, xc.p, strong.p, rnd.p, cf.p, &rounds, nullptr);
+        if (rc) return rc == AMG_EIG_EHIP ? hip_fail("PMIS") : rc;
+        int64_t pnnz = 0, nc = 0;
+        if (!pp.alloc(n + 1)) return hip_fail("allocation");
+        rc = amg_eig_interpolation(n, xp.p, xc.p, xa.p, strong.p, cf.p, pp.p, nullptr, nullptr, 0, &pnnz, &nc,
+                                   nullptr);
+        if (rc != AMG_EIG_OK && rc != AMG_EIG_EWORKSPACE) return rc == AMG_EIG_EHIP ? hip_fail("interpolation") : rc;
+        if (nc < cmin || (double)nc > 0.9 * (double)n || nc == 0) break;
+        if (!pc.alloc(pnnz) || !pv.alloc(pnnz)) return hip_fail("allocation");
+        rc = amg_eig_interpolation(n, xp.p, xc.p, xa.p, strong.p, cf.p, pp.p, pc.p, pv.p, pnnz, &pnnz, &nc, nullptr);
+        if (rc) return rc == AMG_EIG_EHIP ? hip_fail("interpolation") : rc;
+        if (!ptp.alloc(nc + 1) || !ptc.alloc(pnnz) || !ptv.alloc(pnnz)) return hip_fail("allocation");
+        rc = amg_eig_transpose(n, nc, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, nullptr);
+        if (rc) return rc == AMG_EIG_EHIP ? hip_fail("transpose") : rc;
+        int64_t cnnz = 0;
+        if (!cp.alloc(nc + 1)) return hip_fail("allocation");
+        rc = amg_eig_galerkin(n, nc, xp.p, xc.p, xa.p, xm.p, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, cp.p, nullptr,
+                              nullptr, nullptr, 0, &cnnz, nullptr);
+        if (rc != AMG_EIG_OK && rc != AMG_EIG_EWORKSPACE) return rc == AMG_EIG_EHIP ? hip_fail("Galerkin") : rc;
+        if (cnnz >= ((int64_t)1 << 31)) {
+            err = "device coarsening: a coarse level has 2^31 or more entries";
+            return AMG_EIG_EINVAL;
+        }
+        if (!cc.alloc(cnnz) || !ca.alloc(cnnz) || !cm.alloc(cnnz)) return hip_fail("allocation");
+        rc = amg_eig_galerkin(n, nc, xp.p, xc.p, xa.p, xm.p, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, cp.p, cc.p, ca.p,
+                              cm.p, cnnz, &cnnz, nullptr);
+        if (rc) return rc == AMG_EIG_EHIP ? hip_fail("Galerkin") : rc;
+        // copy the splitting, P, P^T and the new level back
+        Level &L = H.lv[k];
+        L.P.nr = n;
+        L.P.nc = nc;
+        L.Pt.nr = nc;
+        L.Pt.nc = n;
+        Level next;
+        next.n = nc;
+        if (!cf.down(L.cf, n) || !pp.down(L.P.ptr, n + 1) || !pc.down(L.P.col, pnnz) || !pv.down(L.P.val, pnnz) ||
+            !ptp.down(L.Pt.ptr, nc + 1) || !ptc.down(L.Pt.col, pnnz) || !ptv.down(L.Pt.val, pnnz) ||
+            !cp.down(next.ptr, nc + 1) || !cc.down(next.col, cnnz) || !ca.down(next.a, cnnz) ||
+            !cm.down(next.m, cnnz))
+            return hip_fail("download");
+        H.lv.push_back(std::move(next));
+        xp.swap(cp);
+        xc.swap(cc);
+        xa.swap(ca);
+        xm.swap(cm);
+    }
+    return AMG_EIG_OK;
+}
+
+}  // namespace amgeig
