@@ -181,3 +181,15 @@ def test_joint_batch_calls_reject_unbound_members_on_the_host():
     ae.init_batch_joint([])
     ae.correct_batch_joint([], 1)
     ctx.close()
+
+
+def test_setup_rejects_unknown_coarsening_without_device():
+    """coarsening accepts only the host Ruge-Stueben passes (0, the default)
+    and the device PMIS setup (1); another value is refused before any device
+    call."""
+    p = configs.config(0)
+    o = ae.defaults()
+    assert o.coarsening == ae.COARSEN_RS and o.coarsen_seed == 0
+    with pytest.raises(ae.AmgEigError) as e:
+        ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(coarsening=5))
+    assert e.value.code == ae.EINVAL
