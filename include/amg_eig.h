@@ -24,8 +24,9 @@
  *   - device memory is owned by the caller: the solver never allocates or
  *     frees device memory; it carves everything from the workspace given to
  *     amg_eig_bind() (the exceptions are the standalone device setup routines
- *     amg_eig_galerkin(), amg_eig_pmis(), amg_eig_interpolation() and
- *     amg_eig_transpose(), which allocate and free their own temporaries);
+ *     amg_eig_galerkin(), amg_eig_pmis(), amg_eig_interpolation(),
+ *     amg_eig_transpose() and amg_eig_dense_sygv(), which allocate and free
+ *     their own temporaries);
  *   - all device work of a context is enqueued on the stream given to
  *     amg_eig_bind(); only amg_eig_progress() and amg_eig_solve() wait on it;
  *   - one host thread at a time per context; contexts are independent.
@@ -72,7 +73,8 @@ extern "C" {
 #define AMG_EIG_COARSEN_RS 0   /* host setup: Ruge-Stueben first and second pass (Section 2) */
 #define AMG_EIG_COARSEN_PMIS 1 /* device setup on the current device: strength, PMIS splitting,
                                   direct interpolation, transpose and Galerkin products per level
-                                  (amg_eig_strength .. amg_eig_galerkin), levels copied back */
+                                  (amg_eig_strength .. amg_eig_galerkin), levels copied back, and
+                                  the coarsest eigen-decomposition by amg_eig_dense_sygv */
 
 #define AMG_EIG_INIT_NESTED 0 /* Algorithm 3.2 start from the coarsest level */
 #define AMG_EIG_INIT_RANDOM 1 /* seeded U(-1,1) block, then Rayleigh-Ritz */
@@ -229,6 +231,22 @@ int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int32_t *x_col,
  * Errors: EINVAL (negative sizes, null row pointers), EHIP. */
 int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
                       int64_t *pt_ptr, int32_t *pt_col, double *pt_val, void *hip_stream);
+
+/* Dense symmetric-definite eigen-decomposition on the device, for the
+ * coarsest level of the hierarchy (the coarsest eigen-solve that starts
+ * Algorithm 3.2 and gives the exact coarsest solve): A z = lambda M z with
+ * Z^T M Z = I, eigenvalues ascending.  Cholesky M = L L^T, cyclic Jacobi on
+ * L^-1 A L^-T in the parallel round-robin ordering until the off-diagonal
+ * Frobenius norm is below n * 2^-52 of the whole (at most 40 sweeps), then
+ * Z = L^-T V.  Device arrays, row-major: A[n*n] and M[n*n] symmetric (read
+ * only), lam[n] and Z[n*n] (column j = eigenvector j) written.  *sweeps (host,
+ * may be NULL) receives the Jacobi sweeps.  Allocates and frees three n x n
+ * temporaries, waits for the stream; thousands of small launches (for setup,
+ * not for a solve loop).  Errors: EINVAL (n < 1 or n > 4096, null arrays),
+ * ENOTSPD (a Cholesky pivot of M not positive), EBREAKDOWN (no convergence in
+ * 40 sweeps), EHIP. */
+int amg_eig_dense_sygv(int64_t n, const double *A, const double *M, double *lam, double *Z, int *sweeps,
+                       void *hip_stream);
 
 /* Device bytes needed by amg_eig_bind(). */
 int amg_eig_footprint(const amg_eig_ctx *c, size_t *device_bytes);

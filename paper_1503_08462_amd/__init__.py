@@ -40,6 +40,7 @@ EXPORTED = [
     "amg_eig_last_error", "amg_eig_timing", "amg_eig_site_stats", "amg_eig_set_cpt", "amg_eig_get_cpt",
     "amg_eig_tune_time", "amg_eig_bind_static", "amg_eig_galerkin",
     "amg_eig_strength", "amg_eig_interpolation", "amg_eig_transpose", "amg_eig_pmis",
+    "amg_eig_dense_sygv",
 ]
 TUNE_VCYCLE, TUNE_FP64, TUNE_FP64_WIDE = 0, 1, 2
 SITES = ["residual", "presmooth", "postsmooth", "dualspmm", "gram", "restrict", "final", "small"]
@@ -97,6 +98,7 @@ _sig = {
     "amg_eig_interpolation": (_i, [_i64] + [_vp] * 8 + [_i64, _vp, _vp, _vp]),
     "amg_eig_transpose": (_i, [_i64, _i64] + [_vp] * 6 + [_vp]),
     "amg_eig_pmis": (_i, [_i64] + [_vp] * 7),
+    "amg_eig_dense_sygv": (_i, [_i64] + [_vp] * 6),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -391,6 +393,24 @@ def pmis(x_ptr, x_col, strong, rnd, stream=None):
     if rc != OK:
         raise AmgEigError(rc)
     return cf[:n], rounds.value
+
+
+def dense_sygv(A, M, stream=None):
+    """A z = lambda M z on the device (amg_eig_dense_sygv) for n x n float64
+    device tensors: (lam, Z, sweeps), Z^T M Z = I, eigenvalues ascending."""
+    n = A.shape[0]
+    dev = A.device
+    for t in (A, M):
+        if t.shape != (n, n) or t.dtype != torch.float64 or t.device != dev or not t.is_contiguous():
+            raise ValueError("dense_sygv: A and M must be contiguous n x n float64 tensors on one device")
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    Z = torch.empty((n, n), dtype=torch.float64, device=dev)
+    sweeps = ctypes.c_int()
+    rc = _lib.amg_eig_dense_sygv(n, _dptr(A), _dptr(M), _dptr(lam), _dptr(Z), ctypes.byref(sweeps),
+                                 _stream_of(dev, stream))
+    if rc != OK:
+        raise AmgEigError(rc)
+    return lam, Z, sweeps.value
 
 
 def interpolation(x_ptr, x_col, x_a, strong, cf, stream=None):

@@ -68,6 +68,10 @@ bool dense_sygv(int n, const std::vector<double> &A, const std::vector<double> &
 // amg_eig status code.
 int device_coarsen(Hierarchy &H, const amg_eig_opts &o, int64_t cmin, std::string &err);
 
+// dense_sygv on the current device (amg_eig_dense_sygv); returns a status code.
+int device_sygv(int n, const std::vector<double> &A, const std::vector<double> &M, std::vector<double> &lam,
+                std::vector<double> &Z, std::string &err);
+
 // Choose the block width by the guard rule on approximate eigenvalues.
 int guard_width(const std::vector<double> &lam, int q, double gap, int cap);
 

@@ -539,7 +539,10 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
             Ad[(size_t)i * dn + j] = Ad[(size_t)j * dn + i] = sa;
             Md[(size_t)i * dn + j] = Md[(size_t)j * dn + i] = sm;
         }
-    if (!dense_sygv(dn, Ad, Md, H.lam, H.Z)) {
+    if (o.coarsening == AMG_EIG_COARSEN_PMIS) {
+        rc = device_sygv(dn, Ad, Md, H.lam, H.Z, err);
+        if (rc) return rc;
+    } else if (!dense_sygv(dn, Ad, Md, H.lam, H.Z)) {
         err = "coarsest mass matrix not positive definite";
         return AMG_EIG_ENOTSPD;
     }

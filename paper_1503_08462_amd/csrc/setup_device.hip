@@ -364,6 +364,210 @@ __global__ __launch_bounds__(kRowThreads) void k_pmis_update(int64_t n, const in
     atomicAdd(left, 1ull);
 }
 
+// ---------------------------------------------------------------------
+// Dense symmetric-definite eigen-decomposition A z = lambda M z of the
+// coarsest level: Cholesky M = L L^T, C = L^-1 A L^-T, cyclic Jacobi on C in
+// the round-robin (circle) ordering, whose m/2 rotations of a step act on
+// disjoint index pairs and are applied together (rows, then columns), then
+// Z = L^-T V.  Row-major n x n arrays; one launch per elimination or Jacobi
+// phase, each over many workgroups.
+
+// Cholesky pivot of column k: sqrt(L_kk), or a flag and 1 when not positive.
+__global__ void k_chol_pivot(int64_t n, int64_t k, double *L, int *status) {
+    const double d = L[k * n + k];
+    if (!(d > 0.0)) {
+        *status = 1;
+        L[k * n + k] = 1.0;
+    } else {
+        L[k * n + k] = sqrt(d);
+    }
+}
+
+// L_ik /= L_kk for i > k.
+__global__ __launch_bounds__(kRowThreads) void k_chol_col(int64_t n, int64_t k, double *L) {
+    const int64_t i = k + 1 + (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    L[i * n + k] = L[i * n + k] / L[k * n + k];
+}
+
+// Trailing update of the lower triangle: L_ij -= L_ik L_jk for k < j <= i.
+__global__ __launch_bounds__(kRowThreads) void k_chol_trail(int64_t n, int64_t k, double *L) {
+    const int64_t m = n - k - 1;
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= m * m) return;
+    const int64_t i = k + 1 + t / m, j = k + 1 + t % m;
+    if (j > i) return;
+    L[i * n + j] = L[i * n + j] - L[i * n + k] * L[j * n + k];
+}
+
+// Forward substitution step k of W = L^-1 W: W_k. /= L_kk.
+__global__ __launch_bounds__(kRowThreads) void k_fwd_row(int64_t n, int64_t k, const double *L, double *W) {
+    const int64_t j = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (j >= n) return;
+    W[k * n + j] = W[k * n + j] / L[k * n + k];
+}
+
+// W_i. -= L_ik W_k. for i > k.
+__global__ __launch_bounds__(kRowThreads) void k_fwd_elim(int64_t n, int64_t k, const double *L, double *W) {
+    const int64_t m = n - k - 1;
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= m * n) return;
+    const int64_t i = k + 1 + t / n, j = t % n;
+    W[i * n + j] = W[i * n + j] - L[i * n + k] * W[k * n + j];
+}
+
+// Backward substitution step k of Z = L^-T Z: Z_k. /= L_kk, then
+// Z_i. -= L_ki Z_k. for i < k (two launches).
+__global__ __launch_bounds__(kRowThreads) void k_bwd_elim(int64_t n, int64_t k, const double *L, double *Z) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= k * n) return;
+    const int64_t i = t / n, j = t % n;
+    Z[i * n + j] = Z[i * n + j] - L[k * n + i] * Z[k * n + j];
+}
+
+// out_ij = X_ji.
+__global__ __launch_bounds__(kRowThreads) void k_transpose_sq(int64_t n, const double *X, double *out) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= n * n) return;
+    const int64_t i = t / n, j = t % n;
+    out[i * n + j] = X[j * n + i];
+}
+
+// out = (X + X^T) / 2.
+__global__ __launch_bounds__(kRowThreads) void k_symmetrise(int64_t n, const double *X, double *out) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= n * n) return;
+    const int64_t i = t / n, j = t % n;
+    out[i * n + j] = 0.5 * (X[i * n + j] + X[j * n + i]);
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_identity(int64_t n, double *V) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= n * n) return;
+    V[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
+// Pair k of step s of the circle method over m (even) indices: index 0 stays,
+// the others rotate; r_t = 1 + (t + s) mod (m - 1); pairs (0, r_0) and
+// (r_t, r_{m-1-t}), t = 1 .. m/2 - 1.  Returns p < q.
+__device__ __forceinline__ void jacobi_pair(int64_t m, int64_t s, int64_t k, int64_t &p, int64_t &q) {
+    int64_t a, b;
+    if (k == 0) {
+        a = 0;
+        b = 1 + s % (m - 1);
+    } else {
+        a = 1 + (k + s) % (m - 1);
+        b = 1 + (m - 1 - k + s) % (m - 1);
+    }
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+// Rotation of each pair zeroing C_pq (symmetric Schur decomposition of the
+// 2 x 2 block): tau = (C_qq - C_pp) / (2 C_pq), t = sign(tau) / (|tau| +
+// sqrt(1 + tau^2)), c = 1 / sqrt(1 + t^2), s = t c.  Pairs with the padding
+// index n, or C_pq = 0, get c = 1, s = 0.
+__global__ __launch_bounds__(kRowThreads) void k_jac_angles(int64_t n, int64_t m, int64_t step, const double *C,
+                                                            double *cs) {
+    const int64_t k = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (k >= m / 2) return;
+    int64_t p, q;
+    jacobi_pair(m, step, k, p, q);
+    double c = 1.0, sn = 0.0;
+    if (q < n) {
+        const double apq = C[p * n + q];
+        if (apq != 0.0) {
+            const double tau = (C[q * n + q] - C[p * n + p]) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+        }
+    }
+    cs[2 * k] = c;
+    cs[2 * k + 1] = sn;
+}
+
+// Rows p, q of C <- J^T C for every pair (disjoint rows).
+__global__ __launch_bounds__(kRowThreads) void k_jac_rows(int64_t n, int64_t m, int64_t step, const double *cs,
+                                                          double *C) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= (m / 2) * n) return;
+    const int64_t k = t / n, j = t % n;
+    int64_t p, q;
+    jacobi_pair(m, step, k, p, q);
+    if (q >= n) return;
+    const double c = cs[2 * k], sn = cs[2 * k + 1];
+    const double x = C[p * n + j], y = C[q * n + j];
+    C[p * n + j] = c * x - sn * y;
+    C[q * n + j] = sn * x + c * y;
+}
+
+// Columns p, q of C <- C J and V <- V J for every pair (disjoint columns).
+__global__ __launch_bounds__(kRowThreads) void k_jac_cols(int64_t n, int64_t m, int64_t step, const double *cs,
+                                                          double *C, double *V) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= (m / 2) * n) return;
+    const int64_t k = t % (m / 2), i = t / (m / 2);
+    int64_t p, q;
+    jacobi_pair(m, step, k, p, q);
+    if (q >= n) return;
+    const double c = cs[2 * k], sn = cs[2 * k + 1];
+    double x = C[i * n + p], y = C[i * n + q];
+    C[i * n + p] = c * x - sn * y;
+    C[i * n + q] = sn * x + c * y;
+    x = V[i * n + p];
+    y = V[i * n + q];
+    V[i * n + p] = c * x - sn * y;
+    V[i * n + q] = sn * x + c * y;
+}
+
+// Sums of squares of the off-diagonal entries and of all entries of C, in
+// one workgroup.
+__global__ __launch_bounds__(kScanThreads) void k_offnorm(int64_t n, const double *C, double *out) {
+    __shared__ double so[kScanThreads], sa[kScanThreads];
+    double o = 0.0, a = 0.0;
+    for (int64_t t = threadIdx.x; t < n * n; t += kScanThreads) {
+        const double v = C[t] * C[t];
+        a += v;
+        if (t / n != t % n) o += v;
+    }
+    so[threadIdx.x] = o;
+    sa[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            so[threadIdx.x] += so[threadIdx.x + w];
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = so[0];
+        out[1] = sa[0];
+    }
+}
+
+// Eigenvalues ascending (ties by index) and the matching columns of Z.
+__global__ __launch_bounds__(kRowThreads) void k_eig_rank(int64_t n, const double *C, double *lam, int64_t *rank) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n) return;
+    const double d = C[i * n + i];
+    int64_t r = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double e = C[j * n + j];
+        r += (e < d || (e == d && j < i)) ? 1 : 0;
+    }
+    rank[i] = r;
+    lam[r] = d;
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_eig_cols(int64_t n, const double *V, const int64_t *rank, double *Z) {
+    const int64_t t = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (t >= n * n) return;
+    const int64_t i = t / n, j = t % n;
+    Z[i * n + rank[j]] = V[i * n + j];
+}
+
 inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
 
 // Temporary device arrays, freed on every return path.
@@ -532,6 +736,87 @@ extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_co
     return AMG_EIG_EHIP;
 }
 
+extern "C" int amg_eig_dense_sygv(int64_t n, const double *A, const double *M, double *lam, double *Z, int *sweeps,
+                                  void *hip_stream) {
+    if (n < 1 || n > 4096 || !A || !M || !lam || !Z) return AMG_EIG_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (sweeps) *sweeps = 0;
+    Temps tmp;
+    double *L, *C, *W, *cs, *nrm;
+    int64_t *rank;
+    int *status;
+    const int64_t m = n + (n & 1);
+    if (!tmp.get(L, n * n) || !tmp.get(C, n * n) || !tmp.get(W, n * n) || !tmp.get(cs, m) || !tmp.get(nrm, 2) ||
+        !tmp.get(rank, n) || !tmp.get(status, 1))
+        return AMG_EIG_EHIP;
+    const size_t bytes = (size_t)(n * n) * sizeof(double);
+    if (hipMemsetAsync(status, 0, sizeof(int), st) != hipSuccess ||
+        hipMemcpyAsync(L, M, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(W, A, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    const unsigned gnn = grid_of(n * n);
+    // M = L L^T (lower triangle of L)
+    for (int64_t k = 0; k < n; ++k) {
+        k_chol_pivot<<<1, 1, 0, st>>>(n, k, L, status);
+        if (k + 1 < n) {
+            k_chol_col<<<grid_of(n - k - 1), kRowThreads, 0, st>>>(n, k, L);
+            k_chol_trail<<<grid_of((n - k - 1) * (n - k - 1)), kRowThreads, 0, st>>>(n, k, L);
+        }
+    }
+    // C = L^-1 A L^-T: W = L^-1 A, then (L^-1 W^T)^T, symmetrised
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t k = 0; k < n; ++k) {
+            k_fwd_row<<<grid_of(n), kRowThreads, 0, st>>>(n, k, L, W);
+            if (k + 1 < n) k_fwd_elim<<<grid_of((n - k - 1) * n), kRowThreads, 0, st>>>(n, k, L, W);
+        }
+        k_transpose_sq<<<gnn, kRowThreads, 0, st>>>(n, W, C);
+        if (pass == 0 && hipMemcpyAsync(W, C, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return AMG_EIG_EHIP;
+    }
+    k_symmetrise<<<gnn, kRowThreads, 0, st>>>(n, C, W);
+    std::swap(C, W);
+    k_identity<<<gnn, kRowThreads, 0, st>>>(n, W);  // W now holds V
+    // cyclic Jacobi, at most 40 sweeps, until the off-diagonal part is below
+    // n eps of the Frobenius norm
+    constexpr int kMaxSweeps = 40;
+    int done = 0, sw = 0;
+    int hstatus = 0;
+    for (sw = 0; sw < kMaxSweeps && n > 1; ++sw) {
+        double h[2];
+        k_offnorm<<<1, kScanThreads, 0, st>>>(n, C, nrm);
+        if (hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return AMG_EIG_EHIP;
+        if (hstatus) return AMG_EIG_ENOTSPD;
+        // rounding leaves off-diagonal entries of order eps |C|, so the bound
+        // grows with n
+        const double tolr = (double)n * 2.220446049250313e-16;
+        if (!(h[0] > tolr * tolr * h[1])) {
+            done = 1;
+            break;
+        }
+        for (int64_t step = 0; step < m - 1; ++step) {
+            k_jac_angles<<<grid_of(m / 2), kRowThreads, 0, st>>>(n, m, step, C, cs);
+            k_jac_rows<<<grid_of((m / 2) * n), kRowThreads, 0, st>>>(n, m, step, cs, C);
+            k_jac_cols<<<grid_of((m / 2) * n), kRowThreads, 0, st>>>(n, m, step, cs, C, W);
+        }
+    }
+    if (n == 1) done = 1;
+    if (sweeps) *sweeps = sw;
+    if (!done) return AMG_EIG_EBREAKDOWN;
+    // Z = L^-T V (in W), then eigenvalues ascending with their columns
+    for (int64_t k = n - 1; k >= 0; --k) {
+        k_fwd_row<<<grid_of(n), kRowThreads, 0, st>>>(n, k, L, W);
+        if (k > 0) k_bwd_elim<<<grid_of(k * n), kRowThreads, 0, st>>>(n, k, L, W);
+    }
+    k_eig_rank<<<grid_of(n), kRowThreads, 0, st>>>(n, C, lam, rank);
+    k_eig_cols<<<gnn, kRowThreads, 0, st>>>(n, W, rank, Z);
+    if (hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        return AMG_EIG_EHIP;
+    return hstatus ? AMG_EIG_ENOTSPD : AMG_EIG_OK;
+}
+
 namespace amgeig {
 namespace {
 
@@ -651,6 +936,34 @@ int device_coarsen(Hierarchy &H, const amg_eig_opts &o, int64_t cmin, std::strin
         xc.swap(cc);
         xa.swap(ca);
         xm.swap(cm);
+    }
+    return AMG_EIG_OK;
+}
+
+}  // namespace amgeig
+
+namespace amgeig {
+
+int device_sygv(int n, const std::vector<double> &A, const std::vector<double> &M, std::vector<double> &lam,
+                std::vector<double> &Z, std::string &err) {
+    DevArr<double> da, dm, dl, dz;
+    if (!da.up(A) || !dm.up(M) || !dl.alloc(n) || !dz.alloc((int64_t)n * n)) {
+        err = "device eigen-decomposition: allocation or upload failed";
+        return AMG_EIG_EHIP;
+    }
+    int sweeps = 0;
+    const int rc = amg_eig_dense_sygv(n, da.p, dm.p, dl.p, dz.p, &sweeps, nullptr);
+    if (rc == AMG_EIG_ENOTSPD) {
+        err = "coarsest mass matrix not positive definite";
+        return rc;
+    }
+    if (rc) {
+        err = "device eigen-decomposition of the coarsest level failed";
+        return rc;
+    }
+    if (!dl.down(lam, n) || !dz.down(Z, (int64_t)n * n)) {
+        err = "device eigen-decomposition: download failed";
+        return AMG_EIG_EHIP;
     }
     return AMG_EIG_OK;
 }
