@@ -9,7 +9,9 @@ Test infrastructure only: the eigensolver library never imports this.
   pmis_splitting      a parallel C/F splitting (PMIS: parallel modified
                       independent set, De Sterck, Yang and Heys 2006) on the
                       same strength graph, the parallel coarsening that
-                      replaces the sequential Ruge-Stueben passes on a GPU
+                      replaces the sequential Ruge-Stueben passes on a GPU,
+                      optionally followed by a parallel form of the RS
+                      second pass (pmis_second_pass)
   direct_interpolation eq. (2.2)-(2.4) with P_i = S_i intersect C
   galerkin            eq. (2.5): A_{k+1} = P^T A_k P, M_{k+1} = P^T M_k P
   build_hierarchy     the level loop of Section 2.3
@@ -66,7 +68,38 @@ def rs_splitting(A, theta=0.25, second_pass=True):
     return cf, S
 
 
-def pmis_splitting(A, r, theta=0.25):
+def pmis_second_pass(S, cf, w):
+    """Parallel form of the Ruge-Stueben second pass on a splitting cf.
+
+    A conflict is a pair of F points (i, j) with j in S_i that share no C point
+    strongly influencing both (S_i cap S_j cap C empty).  Each round, for every
+    conflict the heavier point of the pair, by (w, index), becomes C; rounds
+    repeat until no conflict is left.  Returns (cf, rounds).
+    """
+    n = S.shape[0]
+    cf = np.array(cf, dtype=np.int64)
+    rounds = 0
+    while True:
+        promote = set()
+        for i in range(n):
+            if cf[i] != 0:
+                continue
+            Si = S.indices[S.indptr[i]:S.indptr[i + 1]]
+            Ci = set(int(k) for k in Si if cf[k] == 1)
+            for j in Si:
+                if cf[j] != 0 or j == i:
+                    continue
+                Sj = S.indices[S.indptr[j]:S.indptr[j + 1]]
+                if not any(int(k) in Ci for k in Sj):
+                    promote.add(i if (w[i], i) > (w[j], j) else int(j))
+        if not promote:
+            return cf, rounds
+        rounds += 1
+        for k in promote:
+            cf[k] = 1
+
+
+def pmis_splitting(A, r, theta=0.25, second_pass=False):
     """C/F splitting (1 = C, 0 = F) by PMIS on the strength graph of eq. (2.1).
 
     r holds one random number in [0, 1) per point, drawn by the caller.  Point
@@ -77,7 +110,8 @@ def pmis_splitting(A, r, theta=0.25):
     (j in S_i or i in S_j) becomes C, then every undecided point that depends
     strongly on one of the new C points becomes F.  Rounds repeat until no
     point is undecided; each round makes at least the heaviest undecided point
-    C.  Returns (cf, S, rounds).
+    C.  With second_pass, pmis_second_pass follows on the same weights (its
+    rounds are not counted).  Returns (cf, S, rounds).
     """
     n = A.shape[0]
     S = strength(A, theta)
@@ -102,7 +136,10 @@ def pmis_splitting(A, r, theta=0.25):
         for i in undecided:
             if state[i] == -1 and any(j in new_set for j in S.indices[S.indptr[i]:S.indptr[i + 1]]):
                 state[i] = 0
-    return state.astype(np.int64), S, rounds
+    cf = state.astype(np.int64)
+    if second_pass:
+        cf, _ = pmis_second_pass(S, cf, w)
+    return cf, S, rounds
 
 
 def direct_interpolation(A, S, cf):

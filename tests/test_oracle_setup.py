@@ -182,3 +182,37 @@ def test_pmis_invariants_on_workloads():
         beaten[G.row[beats & (nst[G.col] > 0)]] = True
         first = (nst > 0) & ~beaten
         assert first.any() and np.all(cf[first] == 1)
+
+
+def test_pmis_second_pass_promotes_the_heavier_of_a_conflict():
+    """Path 0-1-2-3 with cf = [C, F, F, C]: F points 1 and 2 depend on each
+    other and share no strong C point (S_1 cap C = {0}, S_2 cap C = {3}), so the
+    heavier of the two becomes C; afterwards no conflict is left."""
+    A = _lap1d(4)
+    S = amg.strength(A, 0.25)
+    cf = np.array([1, 0, 0, 1])
+    out, rounds = amg.pmis_second_pass(S, cf, np.array([1.0, 2.1, 2.7, 1.0]))
+    assert out.tolist() == [1, 0, 1, 1] and rounds == 1
+    out, rounds = amg.pmis_second_pass(S, cf, np.array([1.0, 2.9, 2.7, 1.0]))
+    assert out.tolist() == [1, 1, 0, 1] and rounds == 1
+    out, rounds = amg.pmis_second_pass(S, np.array([0, 1, 0, 1]), np.ones(4))
+    assert out.tolist() == [0, 1, 0, 1] and rounds == 0
+
+
+def test_pmis_second_pass_leaves_no_conflict():
+    """After the second pass every F point j in S_i of an F point i shares a
+    strong C point with it (checked with sparse products: (S_C S_C^T)_ij > 0
+    for S_C = S restricted to C columns), and the first pass's C points stay C."""
+    from workloads.prng import uniform01
+    for p in (configs.cube(10, q=4), configs.lshape(16, q=4, jitter_seed=1), configs.oscillator(30, q=4)):
+        A, _ = mats(p)
+        n = A.shape[0]
+        r = uniform01(3, np.arange(n))
+        cf1, S, _ = amg.pmis_splitting(A, r, 0.25)
+        cf2, _, _ = amg.pmis_splitting(A, r, 0.25, second_pass=True)
+        assert np.all(cf2[cf1 == 1] == 1) and cf2.sum() >= cf1.sum()
+        SC = S @ sp.diags((cf2 == 1).astype(float))
+        common = (SC @ SC.T).toarray()
+        Ff = S.tocoo()
+        sel = (cf2[Ff.row] == 0) & (cf2[Ff.col] == 0) & (Ff.row != Ff.col)
+        assert np.all(common[Ff.row[sel], Ff.col[sel]] > 0)
