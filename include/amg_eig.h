@@ -71,7 +71,8 @@ extern "C" {
                                 eigenvector block in FP64 */
 
 #define AMG_EIG_COARSEN_RS 0   /* host setup: Ruge-Stueben first and second pass (Section 2) */
-#define AMG_EIG_COARSEN_PMIS 1 /* device setup on the current device: strength, PMIS splitting,
+#define AMG_EIG_COARSEN_PMIS 1 /* device setup on the current device: strength, PMIS splitting
+                                  with the parallel second pass,
                                   direct interpolation, transpose and Galerkin products per level
                                   (amg_eig_strength .. amg_eig_galerkin), levels copied back, and
                                   the coarsest eigen-decomposition by amg_eig_dense_sygv */
@@ -196,14 +197,17 @@ int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *x_col, cons
  * point heavier (weight, then larger index) than all its undecided neighbours
  * in the symmetrised strength graph becomes C, then every undecided point
  * depending strongly on a C point becomes F, until none is undecided.
+ * With second_pass != 0 a parallel form of the Ruge-Stueben second pass
+ * follows: while two F points i, j (j in S_i) share no C point that
+ * influences both strongly, the heavier of each such pair becomes C.
  * Device inputs: x_ptr[n+1], x_col (a structurally symmetric pattern, columns
  * ascending within a row), strong[] from amg_eig_strength, rnd[n].  Output:
  * cf[n] (device, caller-owned; 1 = C, 0 = F); *rounds (host) the rounds
- * taken (at most n).  Allocates and frees temporaries (1 byte per entry, 12 per
- * row), waits for the stream after each round.
+ * taken by the first pass (at most n).  Allocates and frees temporaries (1 byte
+ * per entry, 12 per row), waits for the stream after each round.
  * Errors: EINVAL (n < 0, null arrays for n > 0), EHIP. */
 int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const uint8_t *strong, const double *rnd,
-                 int32_t *cf, int *rounds, void *hip_stream);
+                 int second_pass, int32_t *cf, int *rounds, void *hip_stream);
 
 /* Direct interpolation on the device (Section 2, eqs. (2.2)-(2.4)) from a C/F
  * splitting: P (n x nc) injects the C points (coarse index = number of C

@@ -97,7 +97,7 @@ _sig = {
     "amg_eig_strength": (_i, [_i64, _vp, _vp, _vp, _d, _vp, _vp]),
     "amg_eig_interpolation": (_i, [_i64] + [_vp] * 8 + [_i64, _vp, _vp, _vp]),
     "amg_eig_transpose": (_i, [_i64, _i64] + [_vp] * 6 + [_vp]),
-    "amg_eig_pmis": (_i, [_i64] + [_vp] * 7),
+    "amg_eig_pmis": (_i, [_i64] + [_vp] * 4 + [_i] + [_vp] * 3),
     "amg_eig_dense_sygv": (_i, [_i64] + [_vp] * 6),
 }
 for _name, (_res, _args) in _sig.items():
@@ -383,12 +383,14 @@ def strength(x_ptr, x_col, x_a, theta=0.25, stream=None):
     return strong[:x_col.numel()]
 
 
-def pmis(x_ptr, x_col, strong, rnd, stream=None):
-    """PMIS C/F splitting on the device (amg_eig_pmis): (cf int32 device tensor, rounds)."""
+def pmis(x_ptr, x_col, strong, rnd, second_pass=False, stream=None):
+    """PMIS C/F splitting on the device (amg_eig_pmis), optionally with the
+    parallel second pass: (cf int32 device tensor, first-pass rounds)."""
     n = x_ptr.numel() - 1
     cf = torch.empty(max(n, 1), dtype=torch.int32, device=x_ptr.device)
     rounds = ctypes.c_int()
-    rc = _lib.amg_eig_pmis(n, _dptr(x_ptr), _dptr(x_col), _dptr(strong), _dptr(rnd), _dptr(cf), ctypes.byref(rounds),
+    rc = _lib.amg_eig_pmis(n, _dptr(x_ptr), _dptr(x_col), _dptr(strong), _dptr(rnd), int(bool(second_pass)), _dptr(cf),
+                           ctypes.byref(rounds),
                            _stream_of(x_ptr.device, stream))
     if rc != OK:
         raise AmgEigError(rc)

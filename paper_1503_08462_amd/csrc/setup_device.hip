@@ -568,6 +568,48 @@ __global__ __launch_bounds__(kRowThreads) void k_eig_cols(int64_t n, const doubl
     Z[i * n + rank[j]] = V[i * n + j];
 }
 
+// Second pass after PMIS: for each F point i and each F point j it depends
+// on strongly, a conflict when no C point influences both strongly; the
+// heavier point of each conflicting pair (weight, then index) is marked.
+__device__ __forceinline__ bool strong_entry(const int64_t *xptr, const int32_t *xcol, const uint8_t *sflag,
+                                             int64_t j, int32_t k) {
+    int64_t lo = xptr[j], hi = xptr[j + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (xcol[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < xptr[j + 1] && xcol[lo] == k && (sflag[lo] & 1);
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_pmis2_mark(int64_t n, const int64_t *xptr, const int32_t *xcol,
+                                                            const uint8_t *sflag, const double *w, const int32_t *cf,
+                                                            int32_t *mark) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n || cf[i] != 0) return;
+    for (int64_t p = xptr[i]; p < xptr[i + 1]; ++p) {
+        const int32_t j = xcol[p];
+        if (!(sflag[p] & 1) || j == i || cf[j] != 0) continue;
+        bool shared = false;
+        for (int64_t r = xptr[i]; r < xptr[i + 1] && !shared; ++r) {
+            const int32_t k = xcol[r];
+            if ((sflag[r] & 1) && cf[k] == 1 && strong_entry(xptr, xcol, sflag, j, k)) shared = true;
+        }
+        if (shared) continue;
+        const bool i_heavier = w[i] > w[j] || (w[i] == w[j] && i > j);
+        mark[i_heavier ? i : j] = 1;
+    }
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_pmis2_apply(int64_t n, int32_t *mark, int32_t *cf,
+                                                             unsigned long long *moved) {
+    const int64_t i = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
+    if (i >= n || !mark[i]) return;
+    mark[i] = 0;
+    cf[i] = 1;
+    atomicAdd(moved, 1ull);
+}
+
 inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
 
 // Temporary device arrays, freed on every return path.
@@ -704,7 +746,7 @@ extern "C" int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, c
 }
 
 extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const uint8_t *strong,
-                            const double *rnd, int32_t *cf, int *rounds, void *hip_stream) {
+                            const double *rnd, int second_pass, int32_t *cf, int *rounds, void *hip_stream) {
     if (n < 0 || !rounds || (n > 0 && (!x_ptr || !rnd || !cf))) return AMG_EIG_EINVAL;
     *rounds = 0;
     if (n == 0) return AMG_EIG_OK;
@@ -731,6 +773,20 @@ extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_co
             hipStreamSynchronize(st) != hipSuccess)
             return AMG_EIG_EHIP;
         *rounds = (int)(r + 1);
+        if (h == 0) break;
+    }
+    if (!second_pass) return hipGetLastError() == hipSuccess ? AMG_EIG_OK : AMG_EIG_EHIP;
+    // second pass: every round promotes at least one F point, so n rounds
+    // leave no conflict (isc is free again and serves as the marks)
+    if (hipMemsetAsync(isc, 0, (size_t)n * sizeof(int32_t), st) != hipSuccess) return AMG_EIG_EHIP;
+    for (int64_t r = 0; r <= n; ++r) {
+        unsigned long long h = 0;
+        if (hipMemsetAsync(left, 0, sizeof(unsigned long long), st) != hipSuccess) return AMG_EIG_EHIP;
+        k_pmis2_mark<<<grid_of(n), kRowThreads, 0, st>>>(n, x_ptr, x_col, sflag, w, cf, isc);
+        k_pmis2_apply<<<grid_of(n), kRowThreads, 0, st>>>(n, isc, cf, left);
+        if (hipMemcpyAsync(&h, left, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return AMG_EIG_EHIP;
         if (h == 0) return hipGetLastError() == hipSuccess ? AMG_EIG_OK : AMG_EIG_EHIP;
     }
     return AMG_EIG_EHIP;
@@ -891,7 +947,7 @@ int device_coarsen(Hierarchy &H, const amg_eig_opts &o, int64_t cmin, std::strin
         for (int64_t i = 0; i < n; ++i) r[(size_t)i] = splitmix_uniform(o.coarsen_seed + (uint64_t)k, (uint64_t)i);
         if (!rnd.up(r) || !cf.alloc(n)) return hip_fail("upload");
         int rounds = 0;
-        rc = amg_eig_pmis(n, xp.p, xc.p, strong.p, rnd.p, cf.p, &rounds, nullptr);
+        rc = amg_eig_pmis(n, xp.p, xc.p, strong.p, rnd.p, 1, cf.p, &rounds, nullptr);
         if (rc) return rc == AMG_EIG_EHIP ? hip_fail("PMIS") : rc;
         int64_t pnnz = 0, nc = 0;
         if (!pp.alloc(n + 1)) return hip_fail("allocation");

@@ -1,5 +1,5 @@
 """Solves on a hierarchy set up on the device (coarsening = PMIS: strength,
-PMIS splitting, direct interpolation, transpose and Galerkin products formed on
+PMIS splitting with the parallel second pass, direct interpolation, transpose and Galerkin products formed on
 the GPU level by level).  The hierarchy changes, the eigenpairs of (A, M) do
 not: the converged eigenvalues match dense LAPACK (or shift-invert Lanczos)
 and the eigenvectors span the same subspaces; the library's first splitting
@@ -46,7 +46,7 @@ def test_solve_on_device_hierarchy(name, make, cm, dense):
     # the first level's splitting is the oracle's PMIS on the same random parts
     rp, ci, a, _ = ctx.level_matrix(0)
     A0 = sp.csr_matrix((a, ci, rp), shape=(n, n))
-    cf_o, _, _ = pmis_splitting(A0, uniform01(SEED, np.arange(n)), opts.theta)
+    cf_o, _, _ = pmis_splitting(A0, uniform01(SEED, np.arange(n)), opts.theta, second_pass=True)
     assert np.array_equal(ctx.splitting(0), cf_o)
     ctx.bind()
     U = torch.zeros((n, q), dtype=torch.float64, device="cuda")

@@ -138,7 +138,7 @@ def test_interpolation_edges():
     assert ae._lib.amg_eig_transpose(-1, 0, None, None, None, None, None, None, ctypes.c_void_p(s)) == ae.EINVAL
 
 
-def _device_hierarchy(torch, x, n, seed, coarse_max, theta=THETA, check=None):
+def _device_hierarchy(torch, x, n, seed, coarse_max, theta=THETA, check=None, second_pass=False):
     """Levels built on the device only: strength, PMIS, interpolation,
     transpose, Galerkin, until n <= coarse_max or coarsening stalls.  check(l,
     x, strong, cf, P, Pt, xnext) is called per level with device tensors."""
@@ -149,7 +149,7 @@ def _device_hierarchy(torch, x, n, seed, coarse_max, theta=THETA, check=None):
     while n > coarse_max:
         strong = ae.strength(x[0], x[1], x[2], theta)
         rnd = _dev(torch, uniform01(seed + l, np.arange(n)), np.float64)
-        cf, r = ae.pmis(x[0], x[1], strong, rnd)
+        cf, r = ae.pmis(x[0], x[1], strong, rnd, second_pass=second_pass)
         p_ptr, p_col, p_val, nc = ae.interpolation(x[0], x[1], x[2], strong, cf)
         if nc == 0 or nc > 0.9 * n:
             break
@@ -173,8 +173,9 @@ PMIS_CASES = [
 ]
 
 
+@pytest.mark.parametrize("second_pass", [False, True], ids=["pmis", "pmis2"])
 @pytest.mark.parametrize("name,make", PMIS_CASES, ids=[c[0] for c in PMIS_CASES])
-def test_pmis_hierarchy_on_device_matches_oracle(name, make):
+def test_pmis_hierarchy_on_device_matches_oracle(name, make, second_pass):
     """The whole hierarchy built on the device (PMIS in place of the host's
     Ruge-Stueben passes); each level's steps against the oracle's on the same
     input: strength and the splitting exactly, P within rounding, the Galerkin
@@ -189,7 +190,7 @@ def test_pmis_hierarchy_on_device_matches_oracle(name, make):
         nn = hp.size - 1
         A = sp.csr_matrix((ha, hc, hp), shape=(nn, nn))
         M = sp.csr_matrix((hm, hc, hp), shape=(nn, nn))
-        cf_o, S, rounds_o = pmis_splitting(A, rnd.cpu().numpy(), THETA)
+        cf_o, S, rounds_o = pmis_splitting(A, rnd.cpu().numpy(), THETA, second_pass=second_pass)
         cf_d = cf.cpu().numpy()
         _say("pmis %s level %d: %d rows, %d C, %d rounds" % (name, l, nn, int(cf_d.sum()), rounds_o))
         assert np.array_equal(cf_d, cf_o)
@@ -204,7 +205,7 @@ def test_pmis_hierarchy_on_device_matches_oracle(name, make):
 
     x = [_dev(torch, p["rowptr"], np.int64), _dev(torch, p["col"], np.int32), _dev(torch, p["A"], np.float64),
          _dev(torch, p["M"], np.float64)]
-    dims, rounds = _device_hierarchy(torch, x, n, 1000, 120, check=check)
+    dims, rounds = _device_hierarchy(torch, x, n, 1000, 120, check=check, second_pass=second_pass)
     _say("pmis %s: levels %s, rounds %s" % (name, dims, rounds))
     assert len(dims) >= 3
 
@@ -231,6 +232,11 @@ def test_device_setup_time_oscillator1024():
     dims, rounds = _device_hierarchy(torch, x, n, 1000, 512)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dims2, rounds2 = _device_hierarchy(torch, x, n, 1000, 512, second_pass=True)
+    torch.cuda.synchronize()
+    t_dev2 = time.perf_counter() - t0
+    _say("device setup (PMIS with the second pass) %.1f ms, levels %s" % (1e3 * t_dev2, dims2))
     _device_hierarchy(torch, x, n, 1000, 512, check=check)
     assert all(a > b for a, b in zip(dims, dims[1:]))
     t0 = time.perf_counter()
