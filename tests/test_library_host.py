@@ -193,3 +193,26 @@ def test_setup_rejects_unknown_coarsening_without_device():
     with pytest.raises(ae.AmgEigError) as e:
         ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(coarsening=5))
     assert e.value.code == ae.EINVAL
+
+
+def test_device_setup_entry_points_check_arguments_on_the_host():
+    """The device setup calls refuse malformed sizes and missing arrays before
+    any device work, and accept empty problems without touching the device."""
+    lib = ae._lib
+    nnz, nc = ctypes.c_int64(), ctypes.c_int64()
+    rounds = ctypes.c_int(-1)
+    assert lib.amg_eig_galerkin(-1, 0, *([None] * 14), 0, ctypes.byref(nnz), None) == ae.EINVAL
+    assert lib.amg_eig_galerkin(4, 2, *([None] * 14), 0, ctypes.byref(nnz), None) == ae.EINVAL
+    assert lib.amg_eig_strength(-1, None, None, None, 0.25, None, None) == ae.EINVAL
+    assert lib.amg_eig_strength(0, None, None, None, 0.25, None, None) == ae.OK
+    assert lib.amg_eig_strength(3, None, None, None, 0.25, None, None) == ae.EINVAL
+    assert lib.amg_eig_pmis(-1, None, None, None, None, 1, None, ctypes.byref(rounds), None) == ae.EINVAL
+    assert lib.amg_eig_pmis(0, None, None, None, None, 1, None, ctypes.byref(rounds), None) == ae.OK
+    assert rounds.value == 0
+    assert lib.amg_eig_pmis(5, None, None, None, None, 0, None, ctypes.byref(rounds), None) == ae.EINVAL
+    assert lib.amg_eig_interpolation(-1, *([None] * 8), 0, ctypes.byref(nnz), ctypes.byref(nc), None) == ae.EINVAL
+    assert lib.amg_eig_interpolation(3, *([None] * 8), 0, ctypes.byref(nnz), ctypes.byref(nc), None) == ae.EINVAL
+    assert lib.amg_eig_transpose(-1, 0, *([None] * 6), None) == ae.EINVAL
+    assert lib.amg_eig_transpose(2, 2, *([None] * 6), None) == ae.EINVAL
+    for n in (0, 4097):
+        assert lib.amg_eig_dense_sygv(n, *([None] * 5), None) == ae.EINVAL
