@@ -70,3 +70,31 @@ def test_solve_on_device_hierarchy(name, make, cm, dense):
     Ug = U.cpu().numpy()
     assert np.abs(Ug.T @ (M @ Ug) - np.eye(q)).max() < 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("variant", ["mixed", "gauss_seidel"])
+def test_solve_on_device_hierarchy_variants(variant):
+    """The device-built hierarchy under the other forms of the correction: the
+    FP32 V-cycle under the FP64 residual, and the multicolour Gauss-Seidel
+    smoother (its colouring is taken on the device-built levels)."""
+    import torch
+    p = configs.lshape(40, q=8, jitter_seed=3)
+    q, n = p["q"], p["n"]
+    kw = dict(coarse_max=300, coarsening=ae.COARSEN_PMIS, coarsen_seed=SEED + 1)
+    if variant == "mixed":
+        kw["precision"] = ae.PREC_MIXED
+    else:
+        kw["smoother"] = ae.SMOOTH_GAUSS_SEIDEL
+    ctx = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], q, ae.defaults(**kw))
+    ctx.bind()
+    U = torch.zeros((n, q), dtype=torch.float64, device="cuda")
+    lam, ok = ctx.solve(tol=1e-9, max_steps=300, U_out=U)
+    torch.cuda.synchronize()
+    assert ok
+    _say("pmis %s: levels %s, %d corrections" % (variant, ctx.info()["dims"].tolist(), ctx.progress()["steps"]))
+    ref = reference_eigenvalues(p, q)
+    assert np.abs(lam / ref - 1).max() < 1e-9
+    _, M = mats(p)
+    Ug = U.cpu().numpy()
+    assert np.abs(Ug.T @ (M @ Ug) - np.eye(q)).max() < 1e-12
+    ctx.close()
