@@ -169,9 +169,10 @@ int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_e
  * Column indices are not range-checked on the device.  Allocates and frees
  * temporary device memory (about 20 bytes per product of T = A P and of
  * P^T T) and waits for the stream (hipStream_t, NULL for the null stream).
- * Column and value arrays may be null where they hold no entries.
- * Errors: EINVAL (negative sizes, a null row-pointer or c_ptr array, cap > 0
- * with null outputs),
+ * Column and value arrays may be null where they hold no entries (the
+ * nonzero counts are read from the row pointers first).
+ * Errors: EINVAL (negative sizes, a null row-pointer or c_ptr array, a null
+ * array that holds entries, cap > 0 with null outputs),
  * EWORKSPACE (nnz > cap: c_ptr and *nnz written, nothing else), EHIP. */
 int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
                      const double *x_m, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
@@ -184,7 +185,7 @@ int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, const int32_t 
  * negative off-diagonal entries has none).  Device arrays: x_ptr[n+1],
  * x_col, x_a as in amg_eig_galerkin; strong[x_ptr[n]] (out, caller-owned).
  * The same flags as the host setup's.  Asynchronous on the stream; allocates
- * nothing.  Errors: EINVAL (n < 0, theta outside [0, 1], null x_ptr for
+ * nothing.  Errors: EINVAL (n < 0, theta outside [0, 1], a null array for
  * n > 0), EHIP. */
 int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a, double theta,
                      uint8_t *strong, void *hip_stream);
@@ -206,7 +207,8 @@ int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *x_col, cons
  * cf[n] (device, caller-owned; 1 = C, 0 = F); *rounds (host) the rounds
  * taken by the first pass (at most n).  Allocates and frees temporaries (1 byte
  * per entry, 12 per row), waits for the stream after each round.
- * Errors: EINVAL (n < 0, null arrays for n > 0), EHIP. */
+ * Errors: EINVAL (n < 0, null arrays for n > 0; x_col and strong may be null
+ * only when the pattern has no entries), EHIP. */
 int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const uint8_t *strong, const double *rnd,
                  int second_pass, int32_t *cf, int *rounds, void *hip_stream);
 
@@ -222,7 +224,8 @@ int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const ui
  * ascending within a row), p_val[cap] when nnz <= cap.  *nnz and *nc (host)
  * receive P's nonzero count and column count.  The same bits as the host
  * setup's P.  Allocates and frees temporaries (16 bytes per row), waits for
- * the stream.  Errors: EINVAL (negative sizes, null required arrays),
+ * the stream.  Errors: EINVAL (negative sizes, null required arrays; x_col,
+ * x_a and strong may be null only when A has no entries),
  * EWORKSPACE (nnz > cap: p_ptr, *nnz and *nc written), EHIP. */
 int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int32_t *x_col, const double *x_a,
                           const uint8_t *strong, const int32_t *cf, int64_t *p_ptr, int32_t *p_col, double *p_val,
@@ -233,7 +236,8 @@ int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int32_t *x_col,
  * and pt_val[p_ptr[nr]] (caller-owned), each row's columns ascending.  Columns
  * of P must lie in [0, nc) and be unique within a row.  Allocates and frees a
  * counter array (8 bytes per column), waits for the stream.
- * Errors: EINVAL (negative sizes, null row pointers), EHIP. */
+ * Errors: EINVAL (negative sizes, null row pointers, a null column or value
+ * array while P has entries), EHIP. */
 int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, const int32_t *p_col, const double *p_val,
                       int64_t *pt_ptr, int32_t *pt_col, double *pt_val, void *hip_stream);
 

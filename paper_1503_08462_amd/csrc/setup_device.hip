@@ -610,6 +610,17 @@ __global__ __launch_bounds__(kRowThreads) void k_pmis2_apply(int64_t n, int32_t 
     atomicAdd(moved, 1ull);
 }
 
+// Last entry of a device row-pointer array (its nonzero count), read with a
+// wait on the stream; -1 if the copy fails.
+int64_t device_nnz(const int64_t *ptr, int64_t rows, hipStream_t st) {
+    int64_t v = 0;
+    if (rows <= 0 || !ptr) return 0;
+    if (hipMemcpyAsync(&v, ptr + rows, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return -1;
+    return v;
+}
+
 inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
 
 // Temporary device arrays, freed on every return path.
@@ -643,6 +654,12 @@ extern "C" int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, con
     if (cap > 0 && (!c_col || !c_a || !c_m)) return AMG_EIG_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
     *nnz = 0;
+    {
+        const int64_t xn = device_nnz(x_ptr, n, st), pn = device_nnz(p_ptr, n, st), tn = device_nnz(pt_ptr, nc, st);
+        if (xn < 0 || pn < 0 || tn < 0) return AMG_EIG_EHIP;
+        if ((xn > 0 && (!x_col || !x_a || !x_m)) || (pn > 0 && (!p_col || !p_val)) || (tn > 0 && (!pt_col || !pt_val)))
+            return AMG_EIG_EINVAL;
+    }
     Temps tmp;
     int64_t *ub_t, *toff, *tlen, *ub_c, *coff, *clen;
     if (!tmp.get(ub_t, n) || !tmp.get(toff, n + 1) || !tmp.get(tlen, n) || !tmp.get(ub_c, nc) ||
@@ -691,7 +708,7 @@ extern "C" int amg_eig_strength(int64_t n, const int64_t *x_ptr, const int32_t *
                                 double theta, uint8_t *strong, void *hip_stream) {
     if (n < 0 || !(theta >= 0.0 && theta <= 1.0)) return AMG_EIG_EINVAL;
     if (n == 0) return AMG_EIG_OK;
-    if (!x_ptr) return AMG_EIG_EINVAL;
+    if (!x_ptr || !x_col || !x_a || !strong) return AMG_EIG_EINVAL;
     k_strength<<<grid_of(n), kRowThreads, 0, (hipStream_t)hip_stream>>>(n, x_ptr, x_col, x_a, theta, strong);
     return hipGetLastError() == hipSuccess ? AMG_EIG_OK : AMG_EIG_EHIP;
 }
@@ -705,6 +722,11 @@ extern "C" int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int3
     hipStream_t st = (hipStream_t)hip_stream;
     *nnz = 0;
     *nc = 0;
+    {
+        const int64_t xn = device_nnz(x_ptr, n, st);
+        if (xn < 0) return AMG_EIG_EHIP;
+        if (xn > 0 && (!x_col || !x_a || !strong)) return AMG_EIG_EINVAL;
+    }
     Temps tmp;
     int64_t *cidx, *len;
     if (!tmp.get(cidx, n + 1) || !tmp.get(len, n)) return AMG_EIG_EHIP;
@@ -730,6 +752,11 @@ extern "C" int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, c
                                  void *hip_stream) {
     if (nr < 0 || nc < 0 || !pt_ptr || (nr > 0 && !p_ptr)) return AMG_EIG_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
+    {
+        const int64_t pn = device_nnz(p_ptr, nr, st);
+        if (pn < 0) return AMG_EIG_EHIP;
+        if (pn > 0 && (!p_col || !p_val || !pt_col || !pt_val)) return AMG_EIG_EINVAL;
+    }
     Temps tmp;
     unsigned long long *cnt;
     if (!tmp.get(cnt, nc)) return AMG_EIG_EHIP;
@@ -755,6 +782,7 @@ extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_co
     if (hipMemcpyAsync(&nnz, x_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return AMG_EIG_EHIP;
+    if (nnz > 0 && (!x_col || !strong)) return AMG_EIG_EINVAL;
     Temps tmp;
     uint8_t *sflag;
     double *w;
