@@ -387,24 +387,28 @@ def load_traffic(kernel, workload_tag):
 
 def timed_solves(ctx, steps, tol, timing):
     """`steps` whole solves (nested start, corrections to tol) between device
-    synchronisations; returns (elapsed s, per-solve latencies, corrections)."""
+    synchronisations; returns (elapsed s, per-solve latencies, corrections, the
+    last solve's eigenvalues and relative residuals)."""
     import torch
     if timing:
         ctx.timing(True)
     lat, corr = [], []
+    lam = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
         ctx.init(0)
-        _, ok = ctx.solve(tol, 400)
+        lam, ok = ctx.solve(tol, 400)
         lat.append(time.perf_counter() - t)
         pr = ctx.progress()
         if not ok:
             raise SystemExit("solve did not converge: %s" % pr)
         corr.append(pr["steps"])
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, lat, corr
+    elapsed = time.perf_counter() - t0
+    rho = np.asarray(ctx.progress()["rho"], dtype=float)[:len(lam)] if lam is not None else None
+    return elapsed, lat, corr, (np.asarray(lam, dtype=float) if lam is not None else None, rho)
 
 
 # A lower bound of lambda_1 from the continuous problem, where one is useful:
@@ -528,7 +532,7 @@ def main():
     stream = torch.cuda.Stream()
     ctx, setup_s, tuning = prepared_context(p, wl, prec, args, stream)
     info = ctx.info()
-    elapsed, lat, steps = timed_solves(ctx, args.steps, args.tol, True)
+    elapsed, lat, steps, (lam_mixed, rho_mixed) = timed_solves(ctx, args.steps, args.tol, True)
     stats = ctx.site_stats()
     ctx.timing(False)
     if args.copy_calibration:
@@ -546,10 +550,13 @@ def main():
     fp64 = None
     if args.fp64_steps > 0 and prec == ae.PREC_MIXED:
         c64, _, _ = prepared_context(p, wl, ae.PREC_FP64, args, stream)
-        e64, lat64, steps64 = timed_solves(c64, args.fp64_steps, args.tol, False)
+        e64, lat64, steps64, (lam64, _) = timed_solves(c64, args.fp64_steps, args.tol, False)
         fp64 = {"value": q * args.fp64_steps / e64, "unit": "eigenpairs/s", "ms_per_step": e64 / args.fp64_steps * 1e3,
                 "steps": args.fp64_steps, "qe": c64.info()["qe"], "corrections_per_solve": float(np.mean(steps64)),
                 "note": "the same solves with every kernel in FP64 (single instance), timed the same way"}
+        if lam_mixed is not None and lam64 is not None:
+            # per-eigenpair agreement of the mixed-precision solve with the FP64 one
+            fp64["max_rel_eigenvalue_diff_vs_mixed"] = float(np.max(np.abs(lam_mixed / lam64 - 1.0)))
         c64.close()
         c64.workspace = None
 
@@ -632,6 +639,7 @@ def main():
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "corrections_per_solve": float(np.mean(steps)),
+        "max_rho": float(np.max(rho_mixed)) if rho_mixed is not None and rho_mixed.size else None,
         "setup_s": setup_s,
         "fp64_single_instance": fp64,
         "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
