@@ -49,8 +49,9 @@ def guard_count(lam, q, gap=1e-2, cap=None):
 class Oracle:
     def __init__(self, A, M, q, qe=None, theta=0.25, coarse_max=512, coarse_min=None, max_levels=25,
                  smoother="gs", nu_pre=1, nu_post=1, cheb_degree=2, cheb_lo=0.25,
-                 guard_gap=1e-2, shift=0.0):
+                 guard_gap=1e-2, shift=0.0, cycles=1):
         self.q = q
+        self.cycles = int(cycles)  # m of Algorithm 3.1: AMG cycles per correction
         cmin = coarse_min if coarse_min is not None else 2 * (qe if qe else q) + 2
         self.levels = amg.build_hierarchy(A, M, theta, coarse_max, cmin, max_levels)
         self.lam_n, self.Z = amg.coarse_eigen(self.levels)
@@ -168,11 +169,14 @@ class Oracle:
         return mu, U
 
     def correction(self, k, lam, U):
-        """Algorithm 3.1 (m = 1): AMGCorrection(n, k, {lam, U}); with a shift
-        sigma the right-hand side is (lam - sigma) M_k u (Remark 3.1)."""
+        """Algorithm 3.1: AMGCorrection(n, k, {lam, U}), m = self.cycles AMG
+        cycles on the linear equation (3.1) from the initial value U, eq. (3.2);
+        with a shift sigma the right-hand side is (lam - sigma) M_k u (Remark 3.1)."""
         L = self.levels[k]
         rhs = (L.M @ U) * (lam - self.shift)[None, :]
-        V = self.vcycle(k, rhs, U)
+        V = U
+        for _ in range(self.cycles):
+            V = self.vcycle(k, rhs, V)
         return self.rayleigh_ritz(k, V)
 
     # -------------------------------------------------------------- residuals

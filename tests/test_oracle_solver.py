@@ -213,3 +213,25 @@ def test_eig_pencil_range_restriction_on_dependent_basis():
     assert np.abs(V.T @ (M @ V) - np.eye(5)).max() < 1e-9
     assert ref[5] / ref[4] - 1 > 1e-2  # the 5-dimensional subspace is isolated
     assert sin_angle_M(B1 @ Y[:, :5], V, M) < 1e-7
+
+
+@pytest.mark.parametrize("shift", [0.0, 15.0])
+def test_many_cycles_approach_the_exact_linear_solve(shift):
+    """m AMG cycles of Algorithm 3.1 from the initial value U (eq. (3.2)) form a
+    convergent iteration for the linear equation (3.1), so with m large the
+    correction equals the Rayleigh-Ritz step on the exact solution
+    (A - sigma M)^-1 (lambda - sigma) M U, formed here by a sparse direct solve;
+    one cycle stays far from it."""
+    import scipy.sparse.linalg as spla
+    p = configs.square(24, q=4)
+    A, M = mats(p)
+    kw = dict(q=4, qe=4, coarse_max=60, smoother="gs", shift=shift)
+    o1, o80 = Oracle(A, M, **kw), Oracle(A, M, cycles=80, **kw)
+    lam, U = o1.nested_start()
+    rhs = (M @ U) * (lam - shift)[None, :]
+    V = spla.spsolve((A - shift * M).tocsc(), rhs)
+    mu_exact, U_exact = o1.rayleigh_ritz(0, V)
+    mu80, U80 = o80.correction(0, lam, U)
+    mu1, _ = o1.correction(0, lam, U)
+    assert np.abs(mu80 / mu_exact - 1).max() < 1e-11
+    assert np.abs(mu1 / mu_exact - 1).max() > 1e3 * np.abs(mu80 / mu_exact - 1).max()
