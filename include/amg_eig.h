@@ -116,10 +116,12 @@ typedef struct {
     int coarsening;     /* AMG_EIG_COARSEN_*: how setup splits each level into C and F points */
     uint64_t coarsen_seed; /* PMIS only: seed of the random parts of the point weights (level k
                            draws SplitMix64 stream coarsen_seed + k, one uniform [0,1) per point) */
+    int vcycles;        /* m of Algorithm 3.1, eq. (3.2): AMG cycles on the linear equation per
+                           correction, each from the previous iterate (1 .. 16; paper default 1) */
 } amg_eig_opts;
 
-/* Paper defaults (Section 4.1: theta = 0.25, one V-cycle with one pre- and
- * one post-smoothing step, n_1 = n, p_k = 1 on coarse levels) plus the GPU
+/* Paper defaults (Section 4.1: theta = 0.25, one V-cycle (m = 1) with one
+ * pre- and one post-smoothing step, n_1 = n, p_k = 1 on coarse levels) plus the GPU
  * options: degree-2 Chebyshev smoothing on [0.25, 1] in D^-1 A (D the l1
  * diagonal), FP64, coarse_max 512, tol 1e-8, Ruge-Stueben coarsening on the
  * host. */

@@ -56,6 +56,7 @@ class Opts(ctypes.Structure):
         ("qe_max", ctypes.c_int),
         ("shift", ctypes.c_double),
         ("coarsening", ctypes.c_int), ("coarsen_seed", ctypes.c_uint64),
+        ("vcycles", ctypes.c_int),
     ]
 
 

@@ -489,7 +489,7 @@ double site_bytes(const amg_eig_ctx *c, int site) {
 // colours), or backward in place on the prolongated block in r (then V = U + r
 // row by row when final).
 template <typename T>
-void gs_sweep(amg_eig_ctx *c, int l, bool backward, bool final) {
+void gs_sweep(amg_eig_ctx *c, int l, bool backward, bool final, const double *base = nullptr) {
     DevLevel &d = c->dl[l];
     const Level &lv = c->H.lv[l];
     const int nc = (int)lv.coff.size() - 1;
@@ -498,8 +498,8 @@ void gs_sweep(amg_eig_ctx *c, int l, bool backward, bool final) {
         const int64_t r0 = lv.coff[k], nr = lv.coff[k + 1] - r0;
         if (backward)
             launch_gs_colour<T>(c->stream, final, nr, c->ld, d.gs_ptr + r0, d.gs_col, (const T *)d.gs_val,
-                                (const T *)d.gs_diag + r0, d.gs_rows + r0, (const T *)d.b, (T *)d.r, c->U, c->V,
-                                c->status, d.cpt[0]);
+                                (const T *)d.gs_diag + r0, d.gs_rows + r0, (const T *)d.b, (T *)d.r,
+                                base ? base : c->U, c->V, c->status, d.cpt[0]);
         else
             launch_gs_colour<T>(c->stream, false, nr, c->ld, d.gs_lptr + r0, d.gs_lcol, (const T *)d.gs_lval,
                                 (const T *)d.gs_diag + r0, d.gs_rows + r0, (const T *)d.b, (T *)d.x, nullptr,
@@ -513,7 +513,8 @@ void gs_sweep(amg_eig_ctx *c, int l, bool backward, bool final) {
 // V = U + x when final_at_k, else x.  Returns the block that holds x on level
 // k (dl[k].x, or dl[k].r after the Gauss-Seidel post-smoothing).
 template <typename T>
-void *vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
+void *vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k, const double *base = nullptr) {
+    if (!base) base = c->U;
     const int L = (int)c->dl.size(), ld = c->ld;
     hipStream_t s = c->stream;
     const int *st = c->status;
@@ -561,7 +562,7 @@ void *vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
             launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)xc, (const T *)d.x,
                                 (T *)d.r, st, d.cpt[0]);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l);
-            gs_sweep<T>(c, l, true, final_at_k && l == k);
+            gs_sweep<T>(c, l, true, final_at_k && l == k, base);
         } else if (cheb) {
             // y = x + P x_{l+1} into r (free after the restriction), then x = smoothed y
             launch_prolong_x<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x, (const T *)d.x,
@@ -570,23 +571,38 @@ void *vcycle_levels(amg_eig_ctx *c, int k, int bottom, bool final_at_k) {
                                  (const T *)d.r, (T *)d.t, lo, st, d.cpt[0]);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l, true);
             launch_cheb_post2<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val,
-                                 (const T *)d.dinv, (const T *)d.r, (const T *)d.t, (T *)d.x, c->U, c->V, lo, st,
+                                 (const T *)d.dinv, (const T *)d.r, (const T *)d.t, (T *)d.x, base, c->V, lo, st,
                                  d.cpt[0]);
         } else {
             launch_prolong_add<T>(s, d.n, ld, d.p_ptr, d.p_col, (const T *)d.p_val, (const T *)e.x,
                                   (const T *)d.dinv, (const T *)d.b, (T *)d.r, st, d.cpt[0]);
             SiteScope sc(c, AMG_EIG_SITE_POSTSMOOTH, l, true);
             launch_smooth_post<T>(s, final_at_k && l == k, d.n, ld, d.v_ptr, d.v_col, (const T *)d.v_val, (const T *)d.dinv,
-                                  (const T *)d.b, (const T *)d.r, (T *)d.x, c->U, c->V, st, d.cpt[0]);
+                                  (const T *)d.b, (const T *)d.r, (T *)d.x, base, c->V, st, d.cpt[0]);
         }
     }
     return gs && k < bottom ? c->dl[k].r : c->dl[k].x;
 }
 
 template <typename T>
-void vcycle(amg_eig_ctx *c, int k) {
+void vcycle(amg_eig_ctx *c, int k, const double *base = nullptr) {
     const int bottom = (c->tail >= 0 && k < c->tail) ? c->tail : (int)c->dl.size() - 1;
-    (void)vcycle_levels<T>(c, k, bottom, true);
+    (void)vcycle_levels<T>(c, k, bottom, true, base);
+}
+
+// Cycles 2 .. m of one correction (eq. (3.2) with m > 1): the previous
+// iterate V is copied to the head of W (free until the dual SpMM), the
+// right-hand side of the next cycle is the residual of the linear equation at
+// it, and the V-cycle's last post-smoothing writes V = copy + x.
+template <typename T>
+void further_cycles(amg_eig_ctx *c, int k) {
+    DevLevel &d = c->dl[k];
+    for (int i = 1; i < c->o.vcycles; ++i) {
+        launch_copy_f64(c->stream, d.n * c->ld, c->V, c->W);
+        launch_residual_cycle<T>(c->stream, d.n, c->ld, d.u_ptr, d.u_col, d.u_a, d.u_m, c->U, c->W, c->theta,
+                                 c->H.sigma, (T *)d.b, c->status, d.cpt[1]);
+        vcycle<T>(c, k, c->W);
+    }
 }
 
 // Bt (stored transposed) = the V-cycle from the tail level, one identity block
@@ -722,9 +738,11 @@ void correction_front(amg_eig_ctx *c, int k, bool with_gemm = true) {
     if (c->mixed) {
         residual<float>(c, k, k == 0);
         vcycle<float>(c, k);
+        further_cycles<float>(c, k);
     } else {
         residual<double>(c, k, k == 0);
         vcycle<double>(c, k);
+        further_cycles<double>(c, k);
     }
     rr_front(c, k, with_gemm);
 }
@@ -1069,6 +1087,7 @@ void amg_eig_opts_default(amg_eig_opts *o) {
     o->shift = 0.0;
     o->coarsening = AMG_EIG_COARSEN_RS;
     o->coarsen_seed = 0;
+    o->vcycles = 1;
 }
 
 int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_eig_opts *o, amg_eig_ctx **out) {

@@ -25,6 +25,12 @@ template <typename TO>
 void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
                      const double *m, const double *U, const double *theta, TO *R, double *part, const int *status,
                      int cpt = 0);
+// right-hand side of a further cycle of one correction:
+// R = (Theta - sigma) M U - (A - sigma M) V (working precision T)
+template <typename T>
+void launch_residual_cycle(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                           const double *m, const double *U, const double *V, const double *theta, double sigma, T *R,
+                           const int *status, int cpt);
 // the norms rho_j and the convergence flag from the partial sums of launch_residual
 void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
                             double *rho, int q, double tol, int *status, int check, int cpt = 0);

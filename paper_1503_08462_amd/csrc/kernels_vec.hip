@@ -213,6 +213,34 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, int ld, const int32
     }
 }
 
+// Right-hand side of a further AMG cycle of the same correction (m > 1 in
+// eq. (3.2)): R = (Theta - sigma) M U - (A - sigma M) V, the residual of the
+// linear equation (3.1) (shifted by sigma, Remark 3.1) at the current iterate
+// V, its right-hand side formed from the iterate U the correction started
+// from.  Shared pattern of A and M, FP64 products, output in the working
+// precision.
+template <typename TO, int CPT>
+__global__ __launch_bounds__(256) void k_residual_cycle(int64_t n, int ld, const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ col, const double *__restrict__ a,
+                                                        const double *__restrict__ m, const double *__restrict__ U,
+                                                        const double *__restrict__ V, const double *__restrict__ theta,
+                                                        double sigma, TO *__restrict__ R, const int *status) {
+    if (status[ST_CONVERGED]) return;
+    RowMap rm(ld, CPT, n);
+    const int c0 = rm.sub * CPT;
+    Vec<double, CPT> mu = zero_v<double, CPT>(), av = zero_v<double, CPT>();
+    gather_wave<double, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, U, ld, c0, [&](int32_t p) { return m[p]; },
+                             [&](const double &w, int64_t, const Vec<double, CPT> &x) { fma_v(mu, w, x); });
+    gather_wave<double, CPT>(rm.row, rm.sub, rm.tpr, rm.active, n, ptr, col, V, ld, c0,
+                             [&](int32_t p) { return a[p] - sigma * m[p]; },
+                             [&](const double &w, int64_t, const Vec<double, CPT> &x) { fma_v(av, w, x); });
+    if (!rm.active) return;
+    Vec<TO, CPT> out;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) out.v[c] = (TO)((theta[c0 + c] - sigma) * mu.v[c] - av.v[c]);
+    stv<TO, CPT>(R + rm.row * ld + c0, out);
+}
+
 // Residual norms: one workgroup per sum fin[e] = sum over blocks of
 // part[b][e] (threads strided over blocks, fixed-order tree), then the last
 // workgroup to finish forms rho_j = sqrt(sum R_j^2) / (|theta_j| sqrt(sum (MU)_j^2))
@@ -1098,6 +1126,14 @@ void launch_residual(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const
                                              ptr, col, a, m, U, theta, R, blocks, status));
 }
 
+template <typename TO>
+void launch_residual_cycle(hipStream_t s, int64_t n, int ld, const int32_t *ptr, const int32_t *col, const double *a,
+                           const double *m, const double *U, const double *V, const double *theta, double sigma, TO *R,
+                           const int *status, int cpt) {
+    DISPATCH_CPT(ld, cpt, KLAUNCH((k_residual_cycle<TO, CPT>), dim3((unsigned)row_blocks(n, ld, CPT)), dim3(kBlock),
+                                  0, s, n, ld, ptr, col, a, m, U, V, theta, sigma, R, status));
+}
+
 void launch_residual_finish(hipStream_t s, int64_t n, int ld, double *part, unsigned *counter, const double *theta,
                             double *rho, int q, double tol, int *status, int check, int cpt) {
     const int64_t nb = residual_blocks(n, ld, cpt);
@@ -1353,6 +1389,9 @@ void launch_fill_i32(hipStream_t s, int count, int value, int *dst) {
     template void launch_gs_colour<T>(hipStream_t, bool, int64_t, int, const int32_t *, const int32_t *, const T *,   \
                                       const T *, const int32_t *, const T *, T *, const double *, double *,          \
                                       const int *, int);                                                             \
+    template void launch_residual_cycle<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *,              \
+                                           const double *, const double *, const double *, const double *,            \
+                                           const double *, double, T *, const int *, int);                            \
     template void launch_residual<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *, const double *,    \
                                      const double *, const double *, const double *, T *, double *, const int *,      \
                                      int);                                                                            \

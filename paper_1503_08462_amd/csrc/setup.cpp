@@ -494,6 +494,10 @@ int build_hierarchy(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg
     }
     const int qcap = o.qe > 0 ? o.qe : 2 * q + 8;
     const int64_t cmin = o.coarse_min > 0 ? o.coarse_min : std::max<int64_t>(2 * qcap + 2, 16);
+    if (o.vcycles < 1 || o.vcycles > 16) {
+        err = "vcycles must lie in 1 .. 16";
+        return AMG_EIG_EINVAL;
+    }
     if (o.coarsening != AMG_EIG_COARSEN_RS && o.coarsening != AMG_EIG_COARSEN_PMIS) {
         err = "invalid coarsening";
         return AMG_EIG_EINVAL;
