@@ -623,9 +623,11 @@ int64_t device_nnz(const int64_t *ptr, int64_t rows, hipStream_t st) {
 
 inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
 
-// Temporary device arrays, freed on every return path.
+// Temporary device arrays (at most kMaxTemps per call), freed on every return
+// path.
+constexpr int kMaxTemps = 12;
 struct Temps {
-    void *p[12] = {};
+    void *p[kMaxTemps] = {};
     int k = 0;
     ~Temps() {
         for (int i = 0; i < k; ++i) (void)hipFree(p[i]);
@@ -633,6 +635,7 @@ struct Temps {
     template <class T>
     bool get(T *&out, int64_t count) {
         out = nullptr;
+        if (k == kMaxTemps) return false;
         if (count <= 0) count = 1;
         if (hipMalloc(&p[k], (size_t)count * sizeof(T)) != hipSuccess) return false;
         out = (T *)p[k++];
