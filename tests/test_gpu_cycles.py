@@ -86,3 +86,39 @@ def test_vcycles_out_of_range_refused():
         with pytest.raises(ae.AmgEigError) as e:
             ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(vcycles=m))
         assert e.value.code == ae.EINVAL
+
+
+def test_m_cycles_graph_and_joint_equal_eager_solo():
+    """With m = 2 cycles a captured step replays the eager step bit for bit, and
+    a joint batch of two requests on two streams (amg_eig_correct_batch_joint)
+    gives bitwise the iterates of the same requests corrected one by one."""
+    torch = _torch()
+    probs = [(configs.lshape(24, q=6, jitter_seed=4), dict(coarse_max=200, qe=8, precision=ae.PREC_MIXED)),
+             (configs.oscillator(40, q=6), dict(coarse_max=150, qe=8, precision=ae.PREC_FP64))]
+
+    def ctx_for(p, kw, graph, stream):
+        c = ae.Context(p["rowptr"], p["col"], p["A"], p["M"], p["q"], ae.defaults(use_graph=graph, vcycles=2, **kw))
+        c.bind(stream=stream)
+        c.init(ae.INIT_NESTED)
+        return c
+
+    def state(c):
+        qe = c.info()["qe"]
+        return c.progress()["theta"].copy(), c.iterate().cpu().numpy()[:, :qe].copy()
+
+    _say("m = 2: eager, captured and joint steps")
+    eager = [ctx_for(p, kw, 0, torch.cuda.Stream()) for p, kw in probs]
+    graph = [ctx_for(p, kw, 1, torch.cuda.Stream()) for p, kw in probs]
+    joint = [ctx_for(p, kw, 0, torch.cuda.Stream()) for p, kw in probs]
+    for c in eager + graph:
+        c.correct(4)
+    ae.correct_batch_joint(joint, 4)
+    torch.cuda.synchronize()
+    for e, g, j in zip(eager, graph, joint):
+        te, ue = state(e)
+        tg, ug = state(g)
+        tj, uj = state(j)
+        assert np.array_equal(te, tg) and np.array_equal(ue, ug)
+        assert np.array_equal(te, tj) and np.array_equal(ue, uj)
+    for c in eager + graph + joint:
+        c.close()
