@@ -170,7 +170,11 @@ int amg_eig_setup(const amg_eig_csr *A, const amg_eig_csr *M, int q, const amg_e
  * sums rounded separately: the same bits as the host setup's coarse levels.
  * Column indices are not range-checked on the device.  Allocates and frees
  * temporary device memory (about 20 bytes per product of T = A P and of
- * P^T T) and waits for the stream (hipStream_t, NULL for the null stream).
+ * P^T T) stream-ordered on the given stream (hipMallocAsync / hipFreeAsync,
+ * so other streams are not synchronised) and waits for that stream
+ * (hipStream_t, NULL for the null stream).  The same holds for the
+ * temporaries of amg_eig_pmis, amg_eig_interpolation, amg_eig_transpose and
+ * amg_eig_dense_sygv.
  * Column and value arrays may be null where they hold no entries (the
  * nonzero counts are read from the row pointers first).
  * Errors: EINVAL (negative sizes, a null row-pointer or c_ptr array, a null

@@ -623,21 +623,24 @@ int64_t device_nnz(const int64_t *ptr, int64_t rows, hipStream_t st) {
 
 inline unsigned grid_of(int64_t rows) { return (unsigned)((rows + kRowThreads - 1) / kRowThreads); }
 
-// Temporary device arrays (at most kMaxTemps per call), freed on every return
-// path.
+// Temporary device arrays (at most kMaxTemps per call), stream-ordered on the
+// call's stream, so that a setup call does not synchronise the device while
+// other streams work; freed on every return path.
 constexpr int kMaxTemps = 12;
 struct Temps {
+    hipStream_t st;
     void *p[kMaxTemps] = {};
     int k = 0;
+    explicit Temps(hipStream_t s) : st(s) {}
     ~Temps() {
-        for (int i = 0; i < k; ++i) (void)hipFree(p[i]);
+        for (int i = 0; i < k; ++i) (void)hipFreeAsync(p[i], st);
     }
     template <class T>
     bool get(T *&out, int64_t count) {
         out = nullptr;
         if (k == kMaxTemps) return false;
         if (count <= 0) count = 1;
-        if (hipMalloc(&p[k], (size_t)count * sizeof(T)) != hipSuccess) return false;
+        if (hipMallocAsync(&p[k], (size_t)count * sizeof(T), st) != hipSuccess) return false;
         out = (T *)p[k++];
         return true;
     }
@@ -663,7 +666,7 @@ extern "C" int amg_eig_galerkin(int64_t n, int64_t nc, const int64_t *x_ptr, con
         if ((xn > 0 && (!x_col || !x_a || !x_m)) || (pn > 0 && (!p_col || !p_val)) || (tn > 0 && (!pt_col || !pt_val)))
             return AMG_EIG_EINVAL;
     }
-    Temps tmp;
+    Temps tmp(st);
     int64_t *ub_t, *toff, *tlen, *ub_c, *coff, *clen;
     if (!tmp.get(ub_t, n) || !tmp.get(toff, n + 1) || !tmp.get(tlen, n) || !tmp.get(ub_c, nc) ||
         !tmp.get(coff, nc + 1) || !tmp.get(clen, nc))
@@ -730,7 +733,7 @@ extern "C" int amg_eig_interpolation(int64_t n, const int64_t *x_ptr, const int3
         if (xn < 0) return AMG_EIG_EHIP;
         if (xn > 0 && (!x_col || !x_a || !strong)) return AMG_EIG_EINVAL;
     }
-    Temps tmp;
+    Temps tmp(st);
     int64_t *cidx, *len;
     if (!tmp.get(cidx, n + 1) || !tmp.get(len, n)) return AMG_EIG_EHIP;
     k_gal_scan<int32_t, true><<<1, kScanThreads, 0, st>>>(n, cf, cidx);
@@ -760,7 +763,7 @@ extern "C" int amg_eig_transpose(int64_t nr, int64_t nc, const int64_t *p_ptr, c
         if (pn < 0) return AMG_EIG_EHIP;
         if (pn > 0 && (!p_col || !p_val || !pt_col || !pt_val)) return AMG_EIG_EINVAL;
     }
-    Temps tmp;
+    Temps tmp(st);
     unsigned long long *cnt;
     if (!tmp.get(cnt, nc)) return AMG_EIG_EHIP;
     if (hipMemsetAsync(cnt, 0, (size_t)(nc > 0 ? nc : 1) * sizeof(unsigned long long), st) != hipSuccess)
@@ -786,7 +789,7 @@ extern "C" int amg_eig_pmis(int64_t n, const int64_t *x_ptr, const int32_t *x_co
         hipStreamSynchronize(st) != hipSuccess)
         return AMG_EIG_EHIP;
     if (nnz > 0 && (!x_col || !strong)) return AMG_EIG_EINVAL;
-    Temps tmp;
+    Temps tmp(st);
     uint8_t *sflag;
     double *w;
     int32_t *isc;
@@ -828,7 +831,7 @@ extern "C" int amg_eig_dense_sygv(int64_t n, const double *A, const double *M, d
     if (n < 1 || n > 4096 || !A || !M || !lam || !Z) return AMG_EIG_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
     if (sweeps) *sweeps = 0;
-    Temps tmp;
+    Temps tmp(st);
     double *L, *C, *W, *cs, *nrm;
     int64_t *rank;
     int *status;
