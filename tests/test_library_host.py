@@ -216,3 +216,29 @@ def test_device_setup_entry_points_check_arguments_on_the_host():
     assert lib.amg_eig_transpose(2, 2, *([None] * 6), None) == ae.EINVAL
     for n in (0, 4097):
         assert lib.amg_eig_dense_sygv(n, *([None] * 5), None) == ae.EINVAL
+
+
+def test_options_struct_layout_matches_the_binding(tmp_path):
+    """The ctypes mirrors of amg_eig_opts and amg_eig_csr have the C structs'
+    sizes and field offsets (a C program built with gcc against
+    include/amg_eig.h prints them), so they cross the boundary intact."""
+    import subprocess
+    fields = [f[0] for f in ae.Opts._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"amg_eig.h\"\nint main(void) {\n"
+                   "  printf(\"size %zu\\n\", sizeof(amg_eig_opts));\n"
+                   + "".join("  printf(\"%s %%zu\\n\", offsetof(amg_eig_opts, %s));\n" % (f, f) for f in fields)
+                   + "  printf(\"csr_size %zu\\n\", sizeof(amg_eig_csr));\n"
+                   + "".join("  printf(\"csr_%s %%zu\\n\", offsetof(amg_eig_csr, %s));\n" % (f, f)
+                             for f, _ in ae.Csr._fields_)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(ae.Opts)
+    for f in fields:
+        assert int(out[f]) == getattr(ae.Opts, f).offset, f
+    assert int(out["csr_size"]) == ctypes.sizeof(ae.Csr)
+    for f, _ in ae.Csr._fields_:
+        assert int(out["csr_" + f]) == getattr(ae.Csr, f).offset, f
