@@ -143,9 +143,9 @@ typedef struct amg_eig_ctx amg_eig_ctx;
  * eigenpairs of (A, M), plus the coarsest eigen-decomposition Z, Lambda_n with
  * Z^T M_n Z = I, Z^T A_n Z = Lambda_n.  No device call is made, except with
  * coarsening = AMG_EIG_COARSEN_PMIS: then the levels are formed on the current
- * device (null stream, temporaries allocated and freed, so the device is
- * synchronised: best done before other contexts start solving) and copied
- * back, and a HIP failure there returns EHIP.
+ * device (on a non-blocking stream of its own with stream-ordered arrays, so
+ * other streams are not synchronised) and copied back, and a HIP failure
+ * there returns EHIP.
  * Errors: EINVAL (shapes, unsorted/duplicate/out-of-range columns, q < 1,
  * qe + d_n > n, nnz >= 2^31), ENOTSPD (a_ii <= 0, m_ii < 0, coarsest M_n or
  * A_n not positive definite), ENOMEM.  *out is NULL on error. */

@@ -910,36 +910,58 @@ extern "C" int amg_eig_dense_sygv(int64_t n, const double *A, const double *M, d
 namespace amgeig {
 namespace {
 
-// Device copy of a host array, freed with the object.
+// Device copy of a host array, stream-ordered on the stream it was allocated
+// on and freed with the object.
 template <class T>
 struct DevArr {
     T *p = nullptr;
     int64_t n = 0;
+    hipStream_t st = nullptr;
     DevArr() = default;
     DevArr(const DevArr &) = delete;
     DevArr &operator=(const DevArr &) = delete;
     ~DevArr() { reset(); }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, st);
         p = nullptr;
         n = 0;
     }
-    bool alloc(int64_t count) {
+    bool alloc(int64_t count, hipStream_t s) {
         reset();
+        st = s;
         n = count;
-        return hipMalloc(&p, (size_t)(count > 0 ? count : 1) * sizeof(T)) == hipSuccess;
+        return hipMallocAsync((void **)&p, (size_t)(count > 0 ? count : 1) * sizeof(T), s) == hipSuccess;
     }
-    bool up(const std::vector<T> &v) {
-        return alloc((int64_t)v.size()) &&
-               (v.empty() || hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess);
+    bool up(const std::vector<T> &v, hipStream_t s) {
+        return alloc((int64_t)v.size(), s) &&
+               (v.empty() ||
+                (hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s) == hipSuccess &&
+                 hipStreamSynchronize(s) == hipSuccess));
     }
     bool down(std::vector<T> &v, int64_t count) const {
         v.resize((size_t)count);
-        return count == 0 || hipMemcpy(v.data(), p, (size_t)count * sizeof(T), hipMemcpyDeviceToHost) == hipSuccess;
+        return count == 0 ||
+               (hipMemcpyAsync(v.data(), p, (size_t)count * sizeof(T), hipMemcpyDeviceToHost, st) == hipSuccess &&
+                hipStreamSynchronize(st) == hipSuccess);
     }
     void swap(DevArr &o) {
         std::swap(p, o.p);
         std::swap(n, o.n);
+        std::swap(st, o.st);
+    }
+};
+
+// A non-blocking stream of default priority owned by one setup call: the
+// arrays declared after it free themselves on it first, then it is drained
+// and destroyed.
+struct OwnStream {
+    hipStream_t s = nullptr;
+    bool create() { return hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess; }
+    ~OwnStream() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
     }
 };
 
@@ -962,51 +984,54 @@ int device_coarsen(Hierarchy &H, const amg_eig_opts &o, int64_t cmin, std::strin
         (void)hipGetLastError();
         return AMG_EIG_EHIP;
     };
+    OwnStream os;
+    if (!os.create()) return hip_fail("stream creation");
+    hipStream_t st = os.s;
     DevArr<int64_t> xp, pp, ptp, cp;
     DevArr<int32_t> xc, cf, pc, ptc, cc;
     DevArr<double> xa, xm, rnd, pv, ptv, ca, cm;
     DevArr<uint8_t> strong;
     {
         const Level &L = H.lv.back();
-        if (!xp.up(L.ptr) || !xc.up(L.col) || !xa.up(L.a) || !xm.up(L.m)) return hip_fail("upload");
+        if (!xp.up(L.ptr, st) || !xc.up(L.col, st) || !xa.up(L.a, st) || !xm.up(L.m, st)) return hip_fail("upload");
     }
     while ((int)H.lv.size() < o.max_levels && H.lv.back().n > o.coarse_max) {
         const size_t k = H.lv.size() - 1;
         const int64_t n = H.lv[k].n;
         int rc;
-        if (!strong.alloc(xc.n)) return hip_fail("allocation");
-        rc = amg_eig_strength(n, xp.p, xc.p, xa.p, o.theta, strong.p, nullptr);
+        if (!strong.alloc(xc.n, st)) return hip_fail("allocation");
+        rc = amg_eig_strength(n, xp.p, xc.p, xa.p, o.theta, strong.p, st);
         if (rc) return rc == AMG_EIG_EHIP ? hip_fail("strength") : rc;
         std::vector<double> r((size_t)n);
         for (int64_t i = 0; i < n; ++i) r[(size_t)i] = splitmix_uniform(o.coarsen_seed + (uint64_t)k, (uint64_t)i);
-        if (!rnd.up(r) || !cf.alloc(n)) return hip_fail("upload");
+        if (!rnd.up(r, st) || !cf.alloc(n, st)) return hip_fail("upload");
         int rounds = 0;
-        rc = amg_eig_pmis(n, xp.p, xc.p, strong.p, rnd.p, 1, cf.p, &rounds, nullptr);
+        rc = amg_eig_pmis(n, xp.p, xc.p, strong.p, rnd.p, 1, cf.p, &rounds, st);
         if (rc) return rc == AMG_EIG_EHIP ? hip_fail("PMIS") : rc;
         int64_t pnnz = 0, nc = 0;
-        if (!pp.alloc(n + 1)) return hip_fail("allocation");
+        if (!pp.alloc(n + 1, st)) return hip_fail("allocation");
         rc = amg_eig_interpolation(n, xp.p, xc.p, xa.p, strong.p, cf.p, pp.p, nullptr, nullptr, 0, &pnnz, &nc,
-                                   nullptr);
+                                   st);
         if (rc != AMG_EIG_OK && rc != AMG_EIG_EWORKSPACE) return rc == AMG_EIG_EHIP ? hip_fail("interpolation") : rc;
         if (nc < cmin || (double)nc > 0.9 * (double)n || nc == 0) break;
-        if (!pc.alloc(pnnz) || !pv.alloc(pnnz)) return hip_fail("allocation");
-        rc = amg_eig_interpolation(n, xp.p, xc.p, xa.p, strong.p, cf.p, pp.p, pc.p, pv.p, pnnz, &pnnz, &nc, nullptr);
+        if (!pc.alloc(pnnz, st) || !pv.alloc(pnnz, st)) return hip_fail("allocation");
+        rc = amg_eig_interpolation(n, xp.p, xc.p, xa.p, strong.p, cf.p, pp.p, pc.p, pv.p, pnnz, &pnnz, &nc, st);
         if (rc) return rc == AMG_EIG_EHIP ? hip_fail("interpolation") : rc;
-        if (!ptp.alloc(nc + 1) || !ptc.alloc(pnnz) || !ptv.alloc(pnnz)) return hip_fail("allocation");
-        rc = amg_eig_transpose(n, nc, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, nullptr);
+        if (!ptp.alloc(nc + 1, st) || !ptc.alloc(pnnz, st) || !ptv.alloc(pnnz, st)) return hip_fail("allocation");
+        rc = amg_eig_transpose(n, nc, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, st);
         if (rc) return rc == AMG_EIG_EHIP ? hip_fail("transpose") : rc;
         int64_t cnnz = 0;
-        if (!cp.alloc(nc + 1)) return hip_fail("allocation");
+        if (!cp.alloc(nc + 1, st)) return hip_fail("allocation");
         rc = amg_eig_galerkin(n, nc, xp.p, xc.p, xa.p, xm.p, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, cp.p, nullptr,
-                              nullptr, nullptr, 0, &cnnz, nullptr);
+                              nullptr, nullptr, 0, &cnnz, st);
         if (rc != AMG_EIG_OK && rc != AMG_EIG_EWORKSPACE) return rc == AMG_EIG_EHIP ? hip_fail("Galerkin") : rc;
         if (cnnz >= ((int64_t)1 << 31)) {
             err = "device coarsening: a coarse level has 2^31 or more entries";
             return AMG_EIG_EINVAL;
         }
-        if (!cc.alloc(cnnz) || !ca.alloc(cnnz) || !cm.alloc(cnnz)) return hip_fail("allocation");
+        if (!cc.alloc(cnnz, st) || !ca.alloc(cnnz, st) || !cm.alloc(cnnz, st)) return hip_fail("allocation");
         rc = amg_eig_galerkin(n, nc, xp.p, xc.p, xa.p, xm.p, pp.p, pc.p, pv.p, ptp.p, ptc.p, ptv.p, cp.p, cc.p, ca.p,
-                              cm.p, cnnz, &cnnz, nullptr);
+                              cm.p, cnnz, &cnnz, st);
         if (rc) return rc == AMG_EIG_EHIP ? hip_fail("Galerkin") : rc;
         // copy the splitting, P, P^T and the new level back
         Level &L = H.lv[k];
@@ -1036,13 +1061,19 @@ namespace amgeig {
 
 int device_sygv(int n, const std::vector<double> &A, const std::vector<double> &M, std::vector<double> &lam,
                 std::vector<double> &Z, std::string &err) {
+    OwnStream os;
+    if (!os.create()) {
+        err = "device eigen-decomposition: stream creation failed";
+        return AMG_EIG_EHIP;
+    }
+    hipStream_t st = os.s;
     DevArr<double> da, dm, dl, dz;
-    if (!da.up(A) || !dm.up(M) || !dl.alloc(n) || !dz.alloc((int64_t)n * n)) {
+    if (!da.up(A, st) || !dm.up(M, st) || !dl.alloc(n, st) || !dz.alloc((int64_t)n * n, st)) {
         err = "device eigen-decomposition: allocation or upload failed";
         return AMG_EIG_EHIP;
     }
     int sweeps = 0;
-    const int rc = amg_eig_dense_sygv(n, da.p, dm.p, dl.p, dz.p, &sweeps, nullptr);
+    const int rc = amg_eig_dense_sygv(n, da.p, dm.p, dl.p, dz.p, &sweeps, st);
     if (rc == AMG_EIG_ENOTSPD) {
         err = "coarsest mass matrix not positive definite";
         return rc;
