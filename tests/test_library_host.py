@@ -242,3 +242,23 @@ def test_options_struct_layout_matches_the_binding(tmp_path):
     assert int(out["csr_size"]) == ctypes.sizeof(ae.Csr)
     for f, _ in ae.Csr._fields_:
         assert int(out["csr_" + f]) == getattr(ae.Csr, f).offset, f
+
+
+def test_product_path_never_reaches_the_oracle():
+    """The package (binding, autotuner, serving loop, HIP and C++ sources)
+    names no module or file of the oracle, and importing it leaves the oracle
+    unloaded: every step of a solve runs in libamg_eig.so."""
+    import subprocess
+    import sys
+    pkg = os.path.join(ROOT, "paper_1503_08462_amd")
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
+                assert "liboracle" not in text and "oracle/csrc" not in text, f
+    code = "import sys; import paper_1503_08462_amd; print(any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules))"
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    assert out.stdout.strip() == "False"
